@@ -1,0 +1,303 @@
+"""ctypes shim over the FP64 CPU oracle (oracle.c) plus the numpy MLP oracle.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+benchmark's CPU-baseline leg, never by the product library.  Arrays go in and
+come out as numpy; every routine is documented where it is defined in C.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_D = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_F = np.ctypeslib.ndpointer(dtype=np.float32, flags="C_CONTIGUOUS")
+_I32 = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_I64 = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_U64 = np.ctypeslib.ndpointer(dtype=np.uint64, flags="C_CONTIGUOUS")
+
+
+class Grid(C.Structure):
+    _fields_ = [("G", C.c_int32), ("h", C.c_double), ("origin", C.c_double * 3),
+                ("tau", C.c_double), ("band", C.c_double)]
+
+
+class Cam(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double),
+                ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class Noise(C.Structure):
+    _fields_ = [("a", C.c_double), ("c", C.c_double), ("z0", C.c_double),
+                ("sigma2_pose", C.POINTER(C.c_double)), ("sigma2_model", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "liboracle.so")
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        L.orc_morton_encode.restype = C.c_uint64
+        L.orc_morton_encode.argtypes = [C.c_int32] * 3
+        L.orc_morton_decode.argtypes = [C.c_uint64] + [C.POINTER(C.c_int32)] * 3
+        L.orc_tsdf_voxel.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, C.c_int32,
+                                     C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32)]
+        L.orc_tsdf_dense.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, _D, _I32]
+        L.orc_band.restype = C.c_int64
+        L.orc_band.argtypes = [C.POINTER(Grid), _D, _I32, C.c_int64, C.c_void_p, C.c_void_p,
+                               C.c_void_p]
+        L.orc_neighbours.argtypes = [C.c_int32, _U64, C.c_int64, _I32, _I32]
+        L.orc_assemble.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D,
+                                   C.POINTER(Noise), _U64, C.c_int64, _D, _D, C.c_void_p]
+        L.orc_precision_diag.argtypes = [C.c_int64, _D, _I32, C.c_double, C.c_double, C.c_double, _D]
+        L.orc_anchor_rhs.argtypes = [C.c_int64, _D, _I32, _D, C.c_double, _D]
+        L.orc_apply_Q.argtypes = [C.c_int64, _I32, _D, C.c_double, _D, _D]
+        L.orc_pcg.argtypes = [C.c_int64, _I32, _D, C.c_double, _D, C.c_void_p, C.c_double,
+                              C.c_int32, _D, C.POINTER(Report)]
+        L.orc_splitmix_output.restype = C.c_uint64
+        L.orc_splitmix_output.argtypes = [C.c_uint64, C.c_uint64]
+        L.orc_probe_sign.restype = C.c_int32
+        L.orc_probe_sign.argtypes = [C.c_uint64, C.c_int32, C.c_int64]
+        L.orc_hutchinson.argtypes = [C.c_int64, _I32, _D, C.c_double, C.c_int32, C.c_uint64,
+                                     C.c_double, C.c_int32, _D, C.c_void_p]
+        L.orc_quantize_variance.argtypes = [C.c_int64, _D, _I64]
+        L.orc_nbv_ray.restype = C.c_int64
+        L.orc_nbv_ray.argtypes = [C.POINTER(Grid), _U64, C.c_int64, _D, _I64, _D, _D, C.c_void_p]
+        L.orc_nbv_candidate.restype = C.c_int64
+        L.orc_nbv_candidate.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _I64,
+                                        _D]
+        L.orc_nbv_argmax.restype = C.c_int32
+        L.orc_nbv_argmax.argtypes = [C.c_int32, _I64]
+        L.orc_features.argtypes = [C.c_int64, C.c_int32, C.c_double, _D, _I32, _I32, _I32, _D, _D,
+                                   _D]
+        _lib = L
+    return _lib
+
+
+# ---------------------------------------------------------------- helpers
+def grid(G, h, origin, tau, band) -> Grid:
+    g = Grid()
+    g.G, g.h, g.tau, g.band = int(G), float(h), float(tau), float(band)
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+    return g
+
+
+def cam(c) -> Cam:
+    out = Cam()
+    out.width, out.height = int(c.width), int(c.height)
+    out.fx, out.fy, out.cx, out.cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+    return out
+
+
+def grid_of(w) -> Grid:
+    """Oracle grid for a synthetic workload object (G, h, origin, tau, band)."""
+    return grid(w.G, w.h, w.origin, w.tau, w.band)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def morton_encode(i, j, k) -> int:
+    return int(lib().orc_morton_encode(int(i), int(j), int(k)))
+
+
+def morton_decode(key):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().orc_morton_decode(C.c_uint64(int(key)), C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value
+
+
+def tsdf_voxel(g: Grid, cm: Cam, depth, c2w, i, j, k):
+    t, w = C.c_double(), C.c_int32()
+    depth = _c(depth, np.float32)
+    lib().orc_tsdf_voxel(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64),
+                         int(i), int(j), int(k), C.byref(t), C.byref(w))
+    return t.value, w.value
+
+
+def tsdf_dense(g: Grid, cm: Cam, depth, c2w):
+    """Dense coarse TSDF and weights, arrays indexed [k][j][i]."""
+    depth = _c(depth, np.float32)
+    G = g.G
+    tsdf = np.zeros(G * G * G, dtype=np.float64)
+    w = np.zeros(G * G * G, dtype=np.int32)
+    lib().orc_tsdf_dense(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64), tsdf, w)
+    return tsdf.reshape(G, G, G), w.reshape(G, G, G)
+
+
+def band(g: Grid, tsdf_dense, w_dense):
+    t = _c(tsdf_dense, np.float64).reshape(-1)
+    w = _c(w_dense, np.int32).reshape(-1)
+    n = lib().orc_band(C.byref(g), t, w, 0, None, None, None)
+    keys = np.zeros(max(n, 1), dtype=np.uint64)
+    bt = np.zeros(max(n, 1), dtype=np.float64)
+    bw = np.zeros(max(n, 1), dtype=np.int32)
+    lib().orc_band(C.byref(g), t, w, n, keys.ctypes.data, bt.ctypes.data, bw.ctypes.data)
+    return keys[:n], bt[:n], bw[:n]
+
+
+def neighbours(G, keys):
+    keys = _c(keys, np.uint64)
+    N = keys.shape[0]
+    nbr = np.zeros((max(N, 1), 6), dtype=np.int32)
+    deg = np.zeros(max(N, 1), dtype=np.int32)
+    lib().orc_neighbours(int(G), keys, N, nbr, deg)
+    return nbr[:N], deg[:N]
+
+
+def assemble(g: Grid, cm: Cam, depth, c2w, keys, noise=(0.0012, 0.0019, 0.4), sigma2_pose=None,
+             sigma2_model=0.0, with_acc=False):
+    depth = _c(depth, np.float32)
+    keys = _c(keys, np.uint64)
+    N = keys.shape[0]
+    nz = Noise()
+    nz.a, nz.c, nz.z0 = (float(v) for v in noise)
+    nz.sigma2_model = float(sigma2_model)
+    pose_arr = None
+    if sigma2_pose is not None:
+        pose_arr = _c(sigma2_pose, np.float64)
+        nz.sigma2_pose = pose_arr.ctypes.data_as(C.POINTER(C.c_double))
+    Lam = np.zeros(max(N, 1), dtype=np.float64)
+    b = np.zeros(max(N, 1), dtype=np.float64)
+    acc = np.zeros((max(N, 1), 5), dtype=np.float64) if with_acc else None
+    lib().orc_assemble(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64),
+                       C.byref(nz), keys, N, Lam, b, acc.ctypes.data if with_acc else None)
+    if with_acc:
+        return Lam[:N], b[:N], acc[:N]
+    return Lam[:N], b[:N]
+
+
+def precision_diag(Lam, deg, lam, eps, lam_b=0.0):
+    Lam = _c(Lam, np.float64)
+    out = np.zeros(max(Lam.shape[0], 1), dtype=np.float64)
+    lib().orc_precision_diag(Lam.shape[0], Lam, _c(deg, np.int32), float(lam), float(eps),
+                             float(lam_b), out)
+    return out[:Lam.shape[0]]
+
+
+def anchor_rhs(b, deg, tsdf, lam_b):
+    b = _c(b, np.float64)
+    out = np.zeros(max(b.shape[0], 1), dtype=np.float64)
+    lib().orc_anchor_rhs(b.shape[0], b, _c(deg, np.int32), _c(tsdf, np.float64), float(lam_b), out)
+    return out[:b.shape[0]]
+
+
+def apply_Q(nbr, diag, lam, p):
+    p = _c(p, np.float64)
+    q = np.zeros(max(p.shape[0], 1), dtype=np.float64)
+    lib().orc_apply_Q(p.shape[0], _c(nbr, np.int32), _c(diag, np.float64), float(lam), p, q)
+    return q[:p.shape[0]]
+
+
+def pcg(nbr, diag, lam, rhs, tol, max_iter=10000, x0=None):
+    rhs = _c(rhs, np.float64)
+    N = rhs.shape[0]
+    x = np.zeros(max(N, 1), dtype=np.float64)
+    rep = Report()
+    x0a = _c(x0, np.float64) if x0 is not None else None
+    lib().orc_pcg(N, _c(nbr, np.int32), _c(diag, np.float64), float(lam), rhs,
+                  x0a.ctypes.data if x0a is not None else None, float(tol), int(max_iter), x,
+                  C.byref(rep))
+    return x[:N], {"iters": rep.iters, "status": rep.status, "rel_res": rep.rel_res}
+
+
+def splitmix_output(start, n) -> int:
+    return int(lib().orc_splitmix_output(C.c_uint64(int(start)), C.c_uint64(int(n))))
+
+
+def probe_sign(seed, k, i) -> int:
+    return int(lib().orc_probe_sign(C.c_uint64(int(seed)), int(k), int(i)))
+
+
+def probes(seed, K, N):
+    """Rademacher probe matrix z[N][K] (int8) from the oracle's generator."""
+    L = lib()
+    z = np.empty((N, K), dtype=np.int8)
+    for k in range(K):
+        for i in range(N):
+            z[i, k] = L.orc_probe_sign(C.c_uint64(int(seed)), k, i)
+    return z
+
+
+def hutchinson(nbr, diag, lam, K, seed, tol, max_iter=10000, with_iters=False):
+    diag = _c(diag, np.float64)
+    N = diag.shape[0]
+    s = np.zeros(max(N, 1), dtype=np.float64)
+    its = np.zeros(max(K, 1), dtype=np.int32)
+    lib().orc_hutchinson(N, _c(nbr, np.int32), diag, float(lam), int(K), C.c_uint64(int(seed)),
+                         float(tol), int(max_iter), s, its.ctypes.data)
+    if with_iters:
+        return s[:N], its[:K]
+    return s[:N]
+
+
+def quantize_variance(s):
+    s = _c(s, np.float64)
+    q = np.zeros(max(s.shape[0], 1), dtype=np.int64)
+    lib().orc_quantize_variance(s.shape[0], s, q)
+    return q[:s.shape[0]]
+
+
+def nbv_ray(g: Grid, keys, mu, q, o, d):
+    steps = C.c_int64(0)
+    sc = lib().orc_nbv_ray(C.byref(g), _c(keys, np.uint64), len(keys), _c(mu, np.float64),
+                           _c(q, np.int64), _c(o, np.float64), _c(d, np.float64), C.byref(steps))
+    return int(sc), int(steps.value)
+
+
+def nbv_scores(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
+    keys = _c(keys, np.uint64)
+    mu = _c(mu, np.float64)
+    q = _c(q, np.int64)
+    cands = _c(cands, np.float64).reshape(-1, 12)
+    idx = range(cands.shape[0]) if which is None else which
+    return np.array([lib().orc_nbv_candidate(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
+                                             np.ascontiguousarray(cands[c]))
+                     for c in idx], dtype=np.int64)
+
+
+def nbv_argmax(scores) -> int:
+    s = _c(scores, np.int64)
+    return int(lib().orc_nbv_argmax(s.shape[0], s))
+
+
+def features(T, h, tsdf, w, nbr, deg, Lam, acc):
+    tsdf = _c(tsdf, np.float64)
+    N = tsdf.shape[0]
+    out = np.zeros((max(N, 1), 12), dtype=np.float64)
+    lib().orc_features(N, int(T), float(h), tsdf, _c(w, np.int32), _c(nbr, np.int32),
+                       _c(deg, np.int32), _c(Lam, np.float64), _c(acc, np.float64), out)
+    return out[:N]
+
+
+def full_pipeline(wl, with_acc=False):
+    """Band, neighbours, assembly and precision diagonal of a synthetic workload."""
+    g = grid_of(wl)
+    cm = cam(wl.cam)
+    td, wd = tsdf_dense(g, cm, wl.depth, wl.poses)
+    keys, bt, bw = band(g, td, wd)
+    nbr, deg = neighbours(wl.G, keys)
+    res = assemble(g, cm, wl.depth, wl.poses, keys, noise=wl.noise, with_acc=with_acc)
+    Lam, b = res[0], res[1]
+    diag = precision_diag(Lam, deg, wl.lam, wl.eps, wl.lam_b)
+    rhs = anchor_rhs(b, deg, bt, wl.lam_b)
+    out = dict(grid=g, cam=cm, tsdf_dense=td, w_dense=wd, keys=keys, tsdf=bt, w=bw, nbr=nbr,
+               deg=deg, Lambda=Lam, b=b, diag=diag, rhs=rhs)
+    if with_acc:
+        out["acc"] = res[2]
+    return out

@@ -1,0 +1,129 @@
+"""Analytic signed-distance scenes used to render synthetic depth.
+
+The scene is only a source of ground-truth depth; the fused field never calls
+these functions.  SDFs are evaluated in float64 with torch so that the renderer
+can run on the CPU (small test scenes) or on a GPU (full-size workloads).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+import torch
+
+
+def _random_rotation(rng: np.random.Generator) -> np.ndarray:
+    q = rng.standard_normal(4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w)],
+        [2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w)],
+        [2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)],
+    ])
+
+
+@dataclasses.dataclass
+class Sphere:
+    centre: np.ndarray
+    radius: float
+
+    def bound(self) -> float:
+        return self.radius
+
+    def sdf(self, p: torch.Tensor) -> torch.Tensor:
+        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
+        return torch.linalg.vector_norm(p - c, dim=-1) - self.radius
+
+
+@dataclasses.dataclass
+class RoundedBox:
+    centre: np.ndarray
+    rot: np.ndarray          # local -> world rotation
+    half: np.ndarray         # half extents (including the rounding)
+    rounding: float
+
+    def bound(self) -> float:
+        return float(np.linalg.norm(self.half))
+
+    def sdf(self, p: torch.Tensor) -> torch.Tensor:
+        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
+        rot = torch.as_tensor(self.rot, dtype=p.dtype, device=p.device)
+        q = (p - c) @ rot  # world -> local
+        b = torch.as_tensor(self.half - self.rounding, dtype=p.dtype, device=p.device)
+        d = q.abs() - b
+        outside = torch.linalg.vector_norm(d.clamp(min=0.0), dim=-1)
+        inside = d.max(dim=-1).values.clamp(max=0.0)
+        return outside + inside - self.rounding
+
+
+@dataclasses.dataclass
+class Torus:
+    centre: np.ndarray
+    rot: np.ndarray
+    major: float
+    minor: float
+
+    def bound(self) -> float:
+        return self.major + self.minor
+
+    def sdf(self, p: torch.Tensor) -> torch.Tensor:
+        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
+        rot = torch.as_tensor(self.rot, dtype=p.dtype, device=p.device)
+        q = (p - c) @ rot
+        ring = torch.sqrt(q[..., 0] ** 2 + q[..., 2] ** 2) - self.major
+        return torch.sqrt(ring * ring + q[..., 1] ** 2) - self.minor
+
+
+@dataclasses.dataclass
+class Scene:
+    prims: List[object]
+
+    def bound(self) -> float:
+        return max(float(np.linalg.norm(p.centre)) + p.bound() for p in self.prims)
+
+    def sdf(self, p: torch.Tensor) -> torch.Tensor:
+        d = self.prims[0].sdf(p)
+        for prim in self.prims[1:]:
+            d = torch.minimum(d, prim.sdf(p))
+        return d
+
+
+def single_sphere(radius: float = 0.30, centre=(0.0, 0.0, 0.0)) -> Scene:
+    return Scene([Sphere(np.asarray(centre, dtype=np.float64), float(radius))])
+
+
+def random_union(seed: int, n_spheres: int = 3, n_boxes: int = 1, n_tori: int = 1,
+                 size_lo: float = 0.05, size_hi: float = 0.25, half_cube: float = 0.5) -> Scene:
+    """Union of spheres, rounded boxes and tori with seeded sizes and poses.
+
+    Sizes are uniform in [size_lo, size_hi]: sphere radius, box half extents,
+    torus major radius.  The box rounding is 0.2 x its smallest half extent and
+    the torus minor radius is U(0.2, 0.5) x its major radius.  Each primitive's
+    bounding sphere lies inside the cube [-half_cube, half_cube]^3.
+    """
+    rng = np.random.default_rng((0xB5F, int(seed)))
+    prims: List[object] = []
+
+    def centre_for(bound: float) -> np.ndarray:
+        lim = max(half_cube - bound, 0.0)
+        return rng.uniform(-lim, lim, size=3)
+
+    for _ in range(n_spheres):
+        r = rng.uniform(size_lo, size_hi)
+        prims.append(Sphere(centre_for(r), float(r)))
+    for _ in range(n_boxes):
+        half = rng.uniform(size_lo, size_hi, size=3)
+        rot = _random_rotation(rng)
+        box = RoundedBox(np.zeros(3), rot, half, 0.2 * float(half.min()))
+        box.centre = centre_for(box.bound())
+        prims.append(box)
+    for _ in range(n_tori):
+        major = rng.uniform(size_lo, size_hi)
+        minor = rng.uniform(0.2, 0.5) * major
+        rot = _random_rotation(rng)
+        tor = Torus(np.zeros(3), rot, float(major), float(minor))
+        tor.centre = centre_for(tor.bound())
+        prims.append(tor)
+    return Scene(prims)
