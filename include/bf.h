@@ -1,0 +1,254 @@
+/*
+ * bf.h - C ABI of the MI355X (gfx950) BayesFusion-SDF narrow-band solver.
+ *
+ * The library computes, on one GPU, the probabilistic signed-distance fusion of
+ * the paper "BayesFusion-SDF: Probabilistic Signed Distance Fusion with View
+ * Planning on CPU" (arXiv 2602.19697): coarse TSDF and narrow band (Sec. 3.3,
+ * eq. 1), observation assembly under a heteroscedastic noise model (Sec. 3.5,
+ * eqs. 3-5), the GMRF posterior precision Q = Lambda_obs + lambda L + eps I and
+ * its mean (Sec. 3.6, eqs. 7-11), the Hutchinson estimate of diag(Q^-1)
+ * (Sec. 3.7, eq. 12) and next-best-view scoring (Sec. 3.8, eq. 13).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Units are metres.  A pose is the row-major 3x4 camera-to-world matrix
+ *    [R | t] (T_{w<-c} of Sec. 3.1); cameras follow the pinhole model with x
+ *    right, y down, z forward and integer pixel centres.  Depth is camera-z
+ *    depth (eq. 2), float32, with 0 meaning "no return".
+ *  - Pointers named *_dev are device pointers on the context's device; the
+ *    caller owns them.  Pointers named *_host are host memory.  Struct
+ *    arguments are read during the call only.
+ *  - Every call is ordered on the context's HIP stream.  Calls that write a
+ *    host out-parameter (a count, a report, an argmax) synchronise that stream
+ *    before returning; all others are asynchronous.
+ *  - Every call returns a bf_status.  On failure the context's message
+ *    (bf_last_error) says what went wrong; outputs are then unspecified unless
+ *    the call's comment says otherwise.  No C++ exception crosses the ABI.
+ *  - Band and system objects are opaque, own their device arrays and are
+ *    released with bf_band_free / bf_system_free on the context that made them.
+ *    Arrays exposed by the *_view calls stay valid until that free.
+ *  - A band of zero voxels is valid: later calls launch nothing and succeed.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum bf_status {
+  BF_OK = 0,
+  BF_ERR_INVALID_ARG = 1,    /* bad size, NULL pointer, NaN/negative depth, ... */
+  BF_ERR_OOM = 2,            /* device allocation failed */
+  BF_ERR_CAPACITY = 3,       /* hash table could not place every band voxel */
+  BF_ERR_BREAKDOWN = 4,      /* CG met p.Qp <= 0 or a non-finite scalar */
+  BF_ERR_NOT_CONVERGED = 5,  /* max_iter reached; result and report are written */
+  BF_ERR_HIP = 6             /* a HIP runtime call failed */
+} bf_status;
+
+typedef struct bf_ctx bf_ctx;
+typedef struct bf_band bf_band;
+typedef struct bf_system bf_system;
+
+/* Regular grid of G^3 voxels of edge h whose low corner is `origin`; voxel
+ * (i,j,k) has centre origin + (index + 1/2) h.  tau is the TSDF truncation
+ * distance and `band` the half-width of the narrow band (eq. 1 with
+ * alpha*tau = band), both in metres.  G <= 2048. */
+typedef struct bf_grid {
+  int32_t G;
+  double h;
+  double origin[3];
+  double tau;
+  double band;
+} bf_grid;
+
+typedef struct bf_camera {
+  int32_t width, height;
+  double fx, fy, cx, cy;
+} bf_camera;
+
+/* Observation variance of eq. (5): sigma^2 = sigma_depth(D)^2 + sigma2_pose[t]
+ * + sigma2_model with sigma_depth(D) = a + c (D - z0)^2 of the measured depth.
+ * sigma2_pose_dev is a device array [T] or NULL (all zero). */
+typedef struct bf_noise {
+  double a, c, z0;
+  const double* sigma2_pose_dev;
+  double sigma2_model;
+} bf_noise;
+
+/* GMRF prior of eqs. (6)-(7): lambda weights the 6-neighbour Laplacian of the
+ * band (unit edge weights), eps >= 0 adds eps*I, and lambda_b >= 0 anchors the
+ * band boundary (voxels with fewer than 6 band neighbours) to the TSDF. */
+typedef struct bf_prior {
+  double lambda, eps, lambda_b;
+} bf_prior;
+
+enum { BF_PREC_FP64 = 0, BF_PREC_MIXED = 1 };
+enum { BF_BAND_KEEP_DENSE = 1 };
+enum { BF_UTILITY_SUM_VAR = 0, BF_UTILITY_VAR_REDUCTION = 1 };
+
+/* CG stopping rule: ||rhs - Q x|| <= tol ||rhs|| with the residual recomputed
+ * in FP64 before stopping.  precision: BF_PREC_FP64 runs every vector
+ * operation in double; BF_PREC_MIXED runs the matrix-vector products and
+ * vector updates in float with double dot products, alpha/beta and an FP64
+ * residual-correction loop.  use_x0 != 0 starts from the values in x_dev.
+ * check_every: host convergence polls, 0 = automatic. */
+typedef struct bf_solve_opts {
+  double tol;
+  int32_t max_iter;
+  int32_t precision;
+  int32_t use_x0;
+  int32_t check_every;
+} bf_solve_opts;
+
+typedef struct bf_solve_report {
+  int32_t iters;            /* CG iterations (the largest over probe columns) */
+  int32_t status;           /* bf_status of the solve */
+  int32_t refinements;      /* FP64 residual corrections taken (mixed precision) */
+  int32_t used_warm_start;  /* 1 if the supplied start was kept */
+  double rel_res;           /* final FP64 ||rhs - Q x|| / ||rhs|| (max over columns) */
+  double seconds;           /* device time of the solve */
+  int64_t col_iters;        /* iterations summed over right-hand sides (probe columns) */
+} bf_solve_report;
+
+/* Hutchinson probes of eq. (12): K Rademacher vectors z_k with z_k[i] = -1 when
+ * the top bit of output i of SplitMix64 started at u_k is set (else +1), u_k
+ * being output k of SplitMix64 started at `seed`.  K in {1..64}. */
+typedef struct bf_probe_opts {
+  int32_t K;
+  int32_t precision;
+  uint64_t seed;
+  double tol;
+  int32_t max_iter;
+} bf_probe_opts;
+
+typedef struct bf_band_arrays {
+  int64_t n;               /* band voxel count N */
+  int32_t dense_side;      /* P = smallest power of two >= G */
+  const uint64_t* keys;    /* [N] Morton keys, strictly ascending: bit 3b = bit b of i,
+                              bit 3b+1 = bit b of j, bit 3b+2 = bit b of k */
+  const double* tsdf;      /* [N] coarse TSDF */
+  const int32_t* w;        /* [N] number of views fused */
+  const int32_t* nbr;      /* [N][6] band index of the -x,+x,-y,+y,-z,+z neighbour or -1 */
+  const int32_t* deg;      /* [N] number of band neighbours */
+  const double* dense_tsdf;   /* [P^3] Morton-ordered dense TSDF, or NULL */
+  const int32_t* dense_w;     /* [P^3] Morton-ordered dense weights, or NULL */
+} bf_band_arrays;
+
+typedef struct bf_system_arrays {
+  int64_t n;
+  const double* Lambda;    /* [N] diagonal of A^T W A (eq. 10) */
+  const double* b;         /* [N] A^T W y (eq. 11) */
+  const double* rhs;       /* [N] h = A^T W y + b0 (anchor term included) */
+  const double* diag;      /* [N] diagonal of Q */
+  const float* diag32;     /* [N] diag rounded to float */
+  const double* acc;       /* [N][5] n_obs, sum y, sum y^2, sum sigma, min sigma */
+} bf_system_arrays;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that orders its work on
+ * `hip_stream` (a hipStream_t, NULL = the null stream).  The context owns a
+ * reusable device workspace and a pinned host staging buffer. */
+bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream);
+bf_status bf_destroy(bf_ctx* ctx);
+/* Change the stream later calls are ordered on. */
+bf_status bf_set_stream(bf_ctx* ctx, void* hip_stream);
+/* Message of the last failure on this context ("" if none); owned by ctx. */
+const char* bf_last_error(const bf_ctx* ctx);
+/* Library version string, static storage. */
+const char* bf_version(void);
+
+/* ---------------------------------------------------------------- band */
+
+/* Sec. 3.3-3.4, eq. (1), Algorithm 1 steps 1-2.  Fuses the T depth maps
+ * depth_dev [T][H][W] with poses c2w_dev [T][3][4] into a coarse TSDF over the
+ * whole grid (unit weight per view; a view counts when the projective distance
+ * D - Z of the nearest pixel is >= -tau, and contributes min(D - Z, tau)),
+ * then activates B = { v : W(v) > 0 and |TSDF(v)| <= band } in ascending
+ * Morton order, builds the key -> index hash and the 6-neighbour table.
+ * flags: BF_BAND_KEEP_DENSE keeps the dense grid in the band object.
+ * Writes *out (new band) and *n_out (host; synchronises).  Errors:
+ * INVALID_ARG for bad sizes or depth that is NaN, infinite or negative;
+ * CAPACITY if the hash overflows; OOM; HIP. */
+bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
+                        const float* depth_dev, const double* c2w_dev, uint32_t flags,
+                        bf_band** out, int64_t* n_out);
+bf_status bf_band_view(const bf_band* band, bf_band_arrays* out);
+bf_status bf_band_free(bf_ctx* ctx, bf_band* band);
+
+/* ---------------------------------------------------------------- system */
+
+/* Sec. 3.5-3.6, eqs. (3)-(5), (8)-(11), Algorithm 1 steps 3-4.  Voxel-centric
+ * observation rows: each band voxel gets one observation per accepted view
+ * (same acceptance as the TSDF), y = min(D - Z, tau) with weight 1/sigma^2.
+ * Builds Lambda, b, the anchored right-hand side and diag(Q) =
+ * Lambda + lambda deg + eps (+ lambda_b on the boundary); the off-diagonal
+ * entries -lambda on band edges are implicit.  Writes *out. */
+bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, int32_t T,
+                      const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                      const bf_prior* prior, bf_system** out);
+bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out);
+bf_status bf_system_free(bf_ctx* ctx, bf_system* sys);
+
+/* q_dev = Q p_dev for device vectors of N doubles (eq. 10). */
+bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double* p_dev, double* q_dev);
+
+/* ---------------------------------------------------------------- solves */
+
+/* Sec. 3.6, eq. (11), Algorithm 1 step 5: Jacobi-preconditioned CG for
+ * Q x = rhs with rhs_dev [N] (NULL = the system's right-hand side h).  x_dev
+ * [N] receives the posterior mean (and holds the start if opts->use_x0).
+ * rep (host, may be NULL) is filled; synchronises.  Returns NOT_CONVERGED
+ * (with x and report written) when max_iter is reached, BREAKDOWN when
+ * p.Qp <= 0 or non-finite. */
+bf_status bf_pcg_solve(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
+                       const double* rhs_dev, double* x_dev, bf_solve_report* rep);
+
+/* Sec. 3.7, eq. (12), Algorithm 1 step 6: s_dev [N] = (1/K) sum_k z_k * u_k
+ * with Q u_k = z_k, all K probe solves run together as one block CG whose
+ * columns keep their own alpha/beta and stop independently.  logvar_dev
+ * [N] (NULL = none) is a predicted log of diag(Q^-1) * diag(Q); when given,
+ * each probe solve starts from u = exp(logvar) z / diag.  Synchronises. */
+bf_status bf_diag_estimate(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* opts,
+                           const float* logvar_dev, double* s_dev, bf_solve_report* rep);
+
+/* ---------------------------------------------------------------- NBV */
+
+/* Sec. 3.8, eq. (13), Algorithm 1 step 8.  Scores n_cand candidate poses
+ * cand_c2w_dev [n][3][4] by casting one ray per pixel of ray_cam through the
+ * grid (voxel walk, lowest axis first on ties) and summing, over the band
+ * voxels crossed up to and including the first with mu <= 0, the quantised
+ * variance q_v = rint(s_v / max(s) * 2^32) (BF_UTILITY_SUM_VAR) or the
+ * quantised expected reduction s_v^2 / (s_v + sigma(Z)^2) scaled the same way
+ * (BF_UTILITY_VAR_REDUCTION, Z = the voxel's depth in the candidate view).
+ * scores_dev [n] int64 receives the exact integer utilities; *best_host the
+ * lowest index attaining the maximum (synchronises).  noise is used by the
+ * variance-reduction utility only (may be NULL otherwise). */
+bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
+                       const double* s_dev, int32_t n_cand, const double* cand_c2w_dev,
+                       const bf_camera* ray_cam, int32_t utility, const bf_noise* noise,
+                       int64_t* scores_dev, int32_t* best_host);
+
+/* ---------------------------------------------------------------- instrumentation */
+
+/* Per-kernel device time, accumulated while timing is on: the library
+ * brackets each hot kernel launch with HIP events on the context stream. */
+typedef struct bf_kernel_time {
+  char name[48];
+  int64_t launches;
+  double total_ms;
+} bf_kernel_time;
+
+bf_status bf_set_timing(bf_ctx* ctx, int32_t enable);
+/* Synchronises, aggregates the recorded launches by kernel name into out
+ * [cap] (host), writes the number of names to *n_out and clears the record. */
+bf_status bf_get_timings(bf_ctx* ctx, bf_kernel_time* out, int32_t cap, int32_t* n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BF_H */

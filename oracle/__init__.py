@@ -38,6 +38,11 @@ class Noise(C.Structure):
                 ("sigma2_pose", C.POINTER(C.c_double)), ("sigma2_model", C.c_double)]
 
 
+class Utility(C.Structure):
+    _fields_ = [("utility", C.c_int32), ("a", C.c_double), ("c", C.c_double), ("z0", C.c_double),
+                ("s", C.c_void_p), ("smax", C.c_double)]
+
+
 class Report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double)]
 
@@ -79,6 +84,9 @@ def lib():
         L.orc_nbv_candidate.restype = C.c_int64
         L.orc_nbv_candidate.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _I64,
                                         _D]
+        L.orc_nbv_candidate_u.restype = C.c_int64
+        L.orc_nbv_candidate_u.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D,
+                                          _I64, C.POINTER(Utility), _D]
         L.orc_nbv_argmax.restype = C.c_int32
         L.orc_nbv_argmax.argtypes = [C.c_int32, _I64]
         L.orc_features.argtypes = [C.c_int64, C.c_int32, C.c_double, _D, _I32, _I32, _I32, _D, _D,
@@ -268,6 +276,25 @@ def nbv_scores(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
     idx = range(cands.shape[0]) if which is None else which
     return np.array([lib().orc_nbv_candidate(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
                                              np.ascontiguousarray(cands[c]))
+                     for c in idx], dtype=np.int64)
+
+
+def nbv_scores_var_reduction(g: Grid, ray_cam: Cam, keys, mu, s, cands, noise=(0.0012, 0.0019, 0.4),
+                             which=None):
+    """Candidate utilities with the expected-variance-reduction utility."""
+    keys = _c(keys, np.uint64)
+    mu = _c(mu, np.float64)
+    s = _c(s, np.float64)
+    u = Utility()
+    u.utility = 1
+    u.a, u.c, u.z0 = (float(v) for v in noise)
+    u.s = s.ctypes.data
+    u.smax = float(max(0.0, float(np.max(s)) if len(s) else 0.0))
+    q = np.zeros(max(len(s), 1), dtype=np.int64)
+    cands = _c(cands, np.float64).reshape(-1, 12)
+    idx = range(cands.shape[0]) if which is None else which
+    return np.array([lib().orc_nbv_candidate_u(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
+                                               C.byref(u), np.ascontiguousarray(cands[c]))
                      for c in idx], dtype=np.int64)
 
 

@@ -421,8 +421,13 @@ void orc_quantize_variance(int64_t N, const double* s, int64_t* q) {
 /* The next boundary on axis a is computed directly from the voxel index:   */
 /* t_a = (origin_a + (i_a + [d_a > 0]) h - o_a) / d_a (as a product with    */
 /* 1/d_a); the smallest t_a is stepped, the lowest axis first on ties.      */
-int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
-                    const int64_t* q, const double* o, const double* d, int64_t* steps_out) {
+/* Utility 0 sums q_v.  Utility 1 sums, per crossed band voxel, the         */
+/* quantised expected variance reduction of one new observation taken at    */
+/* the voxel's depth Z in the candidate view: s^2 / (s + sigma(Z)^2) for    */
+/* s > 0, scaled by 2^32 / max(s) and rounded to an integer.                */
+int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
+                      const int64_t* q, const orc_utility* u, const double* P, const double* o,
+                      const double* d, int64_t* steps_out) {
   int32_t G = g->G;
   double inv[3];
   double tnear = 0.0, tfar = INFINITY;
@@ -462,7 +467,20 @@ int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const do
     ++steps;
     int64_t v = find_key(keys, N, orc_morton_encode(idx[0], idx[1], idx[2]));
     if (v >= 0) {
-      score += q[v];
+      if (u == NULL || u->utility == 0) {
+        score += q[v];
+      } else {
+        double x = g->origin[0] + ((double)idx[0] + 0.5) * g->h;
+        double y = g->origin[1] + ((double)idx[1] + 0.5) * g->h;
+        double z = g->origin[2] + ((double)idx[2] + 0.5) * g->h;
+        double dx = x - P[3], dy = y - P[7], dz = z - P[11];
+        double Z = (P[2] * dx + P[6] * dy) + P[10] * dz;
+        double e = Z - u->z0;
+        double sd = u->a + u->c * (e * e);
+        double sv = u->s[v];
+        double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
+        score += u->smax > 0.0 ? (int64_t)rint((term / u->smax) * 4294967296.0) : 0;
+      }
       if (mu[v] <= 0.0) break;
     }
     int a = 0;
@@ -476,10 +494,16 @@ int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const do
   return score;
 }
 
+int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
+                    const int64_t* q, const double* o, const double* d, int64_t* steps_out) {
+  return orc_nbv_ray_u(g, keys, N, mu, q, NULL, NULL, o, d, steps_out);
+}
+
 /* One candidate pose: rays through every pixel centre of ray_cam, with the */
 /* unnormalised direction R ((col - cx)/fx, (row - cy)/fy, 1).              */
-int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
-                          const double* mu, const int64_t* q, const double* P) {
+int64_t orc_nbv_candidate_u(const orc_grid* g, const orc_cam* cam, const uint64_t* keys,
+                            int64_t N, const double* mu, const int64_t* q, const orc_utility* u,
+                            const double* P) {
   int64_t total = 0;
   double o[3] = {P[3], P[7], P[11]};
   for (int32_t row = 0; row < cam->height; ++row)
@@ -490,9 +514,14 @@ int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* cam, const uint64_t*
       d[0] = (P[0] * a + P[1] * b) + P[2];
       d[1] = (P[4] * a + P[5] * b) + P[6];
       d[2] = (P[8] * a + P[9] * b) + P[10];
-      total += orc_nbv_ray(g, keys, N, mu, q, o, d, NULL);
+      total += orc_nbv_ray_u(g, keys, N, mu, q, u, P, o, d, NULL);
     }
   return total;
+}
+
+int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                          const double* mu, const int64_t* q, const double* P) {
+  return orc_nbv_candidate_u(g, cam, keys, N, mu, q, NULL, P);
 }
 
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores) {

@@ -76,7 +76,20 @@ void orc_hutchinson(int64_t N, const int32_t* nbr, const double* diag, double la
                     uint64_t seed, double tol, int32_t max_iter, double* s_out,
                     int32_t* iters_out /* [K] or NULL */);
 
+typedef struct {
+  int32_t utility;    /* 0: sum of quantised variance, 1: expected variance reduction */
+  double a, c, z0;    /* sensor model sigma(Z) = a + c (Z - z0)^2 (utility 1) */
+  const double* s;    /* [N] variance (utility 1) */
+  double smax;        /* max(0, max s) (utility 1) */
+} orc_utility;
+
 void orc_quantize_variance(int64_t N, const double* s, int64_t* q);
+int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
+                      const int64_t* q, const orc_utility* u, const double* P, const double* o,
+                      const double* d, int64_t* steps_out);
+int64_t orc_nbv_candidate_u(const orc_grid* g, const orc_cam* cam, const uint64_t* keys,
+                            int64_t N, const double* mu, const int64_t* q, const orc_utility* u,
+                            const double* P);
 int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
                     const int64_t* q, const double* o, const double* d, int64_t* steps_out);
 int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* ray_cam, const uint64_t* keys,

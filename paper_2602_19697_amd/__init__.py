@@ -1,0 +1,265 @@
+"""Python binding of the gfx950 BayesFusion-SDF library (libbf.so).
+
+Argument marshalling only: torch supplies device memory and the stream, every
+step of the method runs in the library's HIP kernels.  Function names follow
+the C ABI in include/bf.h (bf_build_band, bf_assemble, bf_pcg_solve,
+bf_diag_estimate, bf_nbv_score, ...).  Importing this package does not load
+the library; the first Context does, and fails loudly if it is not built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+
+import torch
+
+from . import _lib as L
+
+__all__ = ["Context", "Band", "System", "BFError", "L"]
+
+
+class BFError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if not t.is_contiguous():
+        raise ValueError("contiguous tensor expected")
+    return t.data_ptr()
+
+
+class _DevArray:
+    """Minimal __cuda_array_interface__ view of library-owned device memory."""
+
+    def __init__(self, ptr, shape, typestr):
+        self.__cuda_array_interface__ = {"data": (int(ptr), False), "shape": tuple(shape),
+                                         "typestr": typestr, "version": 2, "strides": None}
+
+
+_TYPESTR = {torch.float64: "<f8", torch.float32: "<f4", torch.int32: "<i4", torch.int64: "<i8",
+            torch.uint64: "<u8"}
+
+
+_hip = None
+
+
+def _hip_memcpy_d2d(dst: int, src: int, nbytes: int, stream) -> None:
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+        _hip.hipMemcpyAsync.restype = C.c_int
+    st = _hip.hipMemcpyAsync(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 3,
+                             C.c_void_p(stream.cuda_stream))
+    if st != 0:
+        raise RuntimeError(f"hipMemcpyAsync failed ({st})")
+
+
+def _view(ptr, shape, dtype, device, copy=False):
+    """Tensor over library-owned device memory (aliasing), or a stream-ordered copy."""
+    if not ptr or any(s == 0 for s in shape):
+        return torch.empty(shape, dtype=dtype, device=device)
+    if not copy:
+        try:
+            return torch.as_tensor(_DevArray(ptr, shape, _TYPESTR[dtype]), device=device)
+        except Exception:
+            pass
+    out = torch.empty(shape, dtype=dtype, device=device)
+    _hip_memcpy_d2d(out.data_ptr(), ptr, out.numel() * out.element_size(),
+                    torch.cuda.current_stream(device))
+    return out
+
+
+def grid_struct(G, h, origin, tau, band) -> L.bf_grid:
+    g = L.bf_grid()
+    g.G, g.h, g.tau, g.band = int(G), float(h), float(tau), float(band)
+    for a in range(3):
+        g.origin[a] = float(origin[a])
+    return g
+
+
+def camera_struct(cam) -> L.bf_camera:
+    c = L.bf_camera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    return c
+
+
+def noise_struct(a=0.0012, c=0.0019, z0=0.4, sigma2_pose=None, sigma2_model=0.0) -> L.bf_noise:
+    n = L.bf_noise()
+    n.a, n.c, n.z0, n.sigma2_model = float(a), float(c), float(z0), float(sigma2_model)
+    n.sigma2_pose_dev = _ptr(sigma2_pose)
+    return n
+
+
+@dataclasses.dataclass
+class Band:
+    ctx: "Context"
+    handle: C.c_void_p
+    n: int
+
+    def arrays(self) -> dict:
+        a = L.bf_band_arrays()
+        self.ctx._check(self.ctx.lib.bf_band_view(self.handle, C.byref(a)))
+        dev, n = self.ctx.device, int(a.n)
+        out = {"keys": _view(a.keys, (n,), torch.uint64, dev),
+               "tsdf": _view(a.tsdf, (n,), torch.float64, dev),
+               "w": _view(a.w, (n,), torch.int32, dev),
+               "nbr": _view(a.nbr, (n, 6), torch.int32, dev),
+               "deg": _view(a.deg, (n,), torch.int32, dev),
+               "dense_side": int(a.dense_side)}
+        P3 = int(a.dense_side) ** 3
+        if a.dense_tsdf:
+            out["dense_tsdf"] = _view(a.dense_tsdf, (P3,), torch.float64, dev)
+            out["dense_w"] = _view(a.dense_w, (P3,), torch.int32, dev)
+        return out
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.bf_band_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+@dataclasses.dataclass
+class System:
+    ctx: "Context"
+    handle: C.c_void_p
+    n: int
+    band: Band
+
+    def arrays(self) -> dict:
+        a = L.bf_system_arrays()
+        self.ctx._check(self.ctx.lib.bf_system_view(self.handle, C.byref(a)))
+        dev, n = self.ctx.device, int(a.n)
+        return {"Lambda": _view(a.Lambda, (n,), torch.float64, dev),
+                "b": _view(a.b, (n,), torch.float64, dev),
+                "rhs": _view(a.rhs, (n,), torch.float64, dev),
+                "diag": _view(a.diag, (n,), torch.float64, dev),
+                "diag32": _view(a.diag32, (n,), torch.float32, dev),
+                "acc": _view(a.acc, (n, 5), torch.float64, dev)}
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.bf_system_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+class Context:
+    """One bf_ctx on a torch CUDA (HIP) device, ordered on torch's current stream."""
+
+    def __init__(self, device="cuda:0", stream=None):
+        self.lib = L.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the library runs on a GPU device")
+        idx = self.device.index if self.device.index is not None else torch.cuda.current_device()
+        self.device = torch.device("cuda", idx)
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = s
+        h = C.c_void_p()
+        st = self.lib.bf_create(C.byref(h), idx, C.c_void_p(s.cuda_stream))
+        if st != 0:
+            raise BFError(st, "bf_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.bf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow=()):
+        if st != 0 and st not in allow:
+            raise BFError(st, self.lib.bf_last_error(self.handle).decode())
+        return st
+
+    # ---------------------------------------------------------- instrumentation
+    def bf_set_timing(self, enable: bool):
+        self._check(self.lib.bf_set_timing(self.handle, 1 if enable else 0))
+
+    def bf_get_timings(self) -> dict:
+        """{kernel name: (launches, total ms)} since the last call (synchronises)."""
+        cap = 64
+        arr = (L.bf_kernel_time * cap)()
+        n = C.c_int32()
+        self._check(self.lib.bf_get_timings(self.handle, arr, cap, C.byref(n)))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+    # ---------------------------------------------------------- band
+    def bf_build_band(self, grid: L.bf_grid, cam, depth, poses, keep_dense=False) -> Band:
+        T = int(depth.shape[0]) if depth is not None else 0
+        h = C.c_void_p()
+        n = C.c_int64()
+        self._check(self.lib.bf_build_band(self.handle, C.byref(grid), C.byref(camera_struct(cam)), T,
+                                           _ptr(depth), _ptr(poses),
+                                           L.BF_BAND_KEEP_DENSE if keep_dense else 0, C.byref(h),
+                                           C.byref(n)))
+        return Band(self, h, int(n.value))
+
+    # ---------------------------------------------------------- system
+    def bf_assemble(self, band: Band, cam, depth, poses, noise: L.bf_noise, lam, eps,
+                    lam_b=0.0) -> System:
+        pr = L.bf_prior()
+        pr.lam, pr.eps, pr.lambda_b = float(lam), float(eps), float(lam_b)
+        h = C.c_void_p()
+        self._check(self.lib.bf_assemble(self.handle, band.handle, C.byref(camera_struct(cam)),
+                                         int(depth.shape[0]), _ptr(depth), _ptr(poses), C.byref(noise),
+                                         C.byref(pr), C.byref(h)))
+        return System(self, h, band.n, band)
+
+    def bf_apply_Q(self, sys: System, p):
+        q = torch.empty_like(p)
+        self._check(self.lib.bf_apply_Q(self.handle, sys.handle, _ptr(p), _ptr(q)))
+        return q
+
+    def bf_features(self, sys: System):
+        f = torch.empty((sys.n, 12), dtype=torch.float32, device=self.device)
+        self._check(self.lib.bf_features(self.handle, sys.handle, _ptr(f)))
+        return f
+
+    # ---------------------------------------------------------- solves
+    def bf_pcg_solve(self, sys: System, tol, max_iter=10000, precision=L.BF_PREC_FP64, x0=None,
+                     rhs=None, check_every=0, out=None, allow_fail=False):
+        o = L.bf_solve_opts()
+        o.tol, o.max_iter, o.precision = float(tol), int(max_iter), int(precision)
+        o.use_x0 = 1 if x0 is not None else 0
+        o.check_every = int(check_every)
+        x = out if out is not None else torch.empty(sys.n, dtype=torch.float64, device=self.device)
+        if x0 is not None and x0.data_ptr() != x.data_ptr():
+            x.copy_(x0)
+        rep = L.bf_solve_report()
+        st = self.lib.bf_pcg_solve(self.handle, sys.handle, C.byref(o), _ptr(rhs), _ptr(x), C.byref(rep))
+        self._check(st, allow=(L.BF_ERR_NOT_CONVERGED, L.BF_ERR_BREAKDOWN) if allow_fail else ())
+        return x, rep.as_dict()
+
+    def bf_diag_estimate(self, sys: System, K, seed, tol, max_iter=10000, precision=L.BF_PREC_FP64,
+                         logvar=None, out=None, allow_fail=False):
+        o = L.bf_probe_opts()
+        o.K, o.precision, o.seed, o.tol, o.max_iter = int(K), int(precision), int(seed), float(tol), int(max_iter)
+        s = out if out is not None else torch.empty(sys.n, dtype=torch.float64, device=self.device)
+        rep = L.bf_solve_report()
+        st = self.lib.bf_diag_estimate(self.handle, sys.handle, C.byref(o), _ptr(logvar), _ptr(s), C.byref(rep))
+        self._check(st, allow=(L.BF_ERR_NOT_CONVERGED, L.BF_ERR_BREAKDOWN) if allow_fail else ())
+        return s, rep.as_dict()
+
+    # ---------------------------------------------------------- NBV
+    def bf_nbv_score(self, band: Band, mu, s, cands, ray_cam, utility=L.BF_UTILITY_SUM_VAR, noise=None):
+        n = int(cands.shape[0])
+        scores = torch.empty(n, dtype=torch.int64, device=self.device)
+        best = C.c_int32(-1)
+        self._check(self.lib.bf_nbv_score(self.handle, band.handle, _ptr(mu), _ptr(s), n, _ptr(cands),
+                                          C.byref(camera_struct(ray_cam)), int(utility),
+                                          C.byref(noise) if noise is not None else None,
+                                          _ptr(scores), C.byref(best)))
+        return scores, int(best.value)

@@ -1,0 +1,219 @@
+// Context, error plumbing, allocation and object views of the C ABI.
+#include "bf_internal.h"
+
+#include <cstdlib>
+#include <cstring>
+
+bf_status bf_fail(bf_ctx* ctx, bf_status st, const char* fmt, ...) {
+  if (ctx) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ctx->err, sizeof(ctx->err), fmt, ap);
+    va_end(ap);
+  }
+  return st;
+}
+
+bf_status bf_dev_alloc(bf_ctx* ctx, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return BF_OK;
+  hipError_t e = hipMallocAsync(p, bytes, ctx->stream);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return bf_fail(ctx, BF_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes,
+                   hipGetErrorString(e));
+  }
+  return BF_OK;
+}
+
+void bf_dev_free(bf_ctx* ctx, void* p) {
+  if (p) (void)hipFreeAsync(p, ctx->stream);
+}
+
+bf_status bf_ws(bf_ctx* ctx, int slot, size_t bytes, void** out) {
+  if (ctx->ws_bytes[slot] < bytes) {
+    bf_dev_free(ctx, ctx->ws[slot]);
+    ctx->ws[slot] = nullptr;
+    ctx->ws_bytes[slot] = 0;
+    size_t want = bytes + bytes / 8 + 4096;
+    BF_TRY(bf_dev_alloc(ctx, &ctx->ws[slot], want));
+    ctx->ws_bytes[slot] = want;
+  }
+  *out = ctx->ws[slot];
+  return BF_OK;
+}
+
+bf_status bf_pinned(bf_ctx* ctx, size_t bytes, void** out) {
+  if (ctx->pinned_bytes < bytes) {
+    if (ctx->pinned) {
+      BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+      BF_HIP(ctx, hipHostFree(ctx->pinned));
+    }
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    size_t want = bytes < 4096 ? 4096 : bytes;
+    BF_HIP(ctx, hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+    ctx->pinned_bytes = want;
+  }
+  *out = ctx->pinned;
+  return BF_OK;
+}
+
+bf_status bf_launch_check(bf_ctx* ctx, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return bf_fail(ctx, BF_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+  return BF_OK;
+}
+
+hipEvent_t bf_event_get(bf_ctx* ctx) {
+  if (!ctx->pool.empty()) {
+    hipEvent_t e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+void bf_timing_stop(bf_ctx* ctx, const char* name, hipEvent_t start) {
+  hipEvent_t b = bf_event_get(ctx);
+  (void)hipEventRecord(b, ctx->stream);
+  ctx->recs.push_back({name, start, b});
+}
+
+extern "C" {
+
+bf_status bf_set_timing(bf_ctx* ctx, int32_t enable) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  ctx->timing = enable ? 1 : 0;
+  return BF_OK;
+}
+
+bf_status bf_get_timings(bf_ctx* ctx, bf_kernel_time* out, int32_t cap, int32_t* n_out) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, n_out && (cap == 0 || out), "bf_get_timings: NULL argument");
+  BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int32_t n = 0;
+  for (auto& r : ctx->recs) {
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    int32_t slot = -1;
+    for (int32_t i = 0; i < n && i < cap; ++i)
+      if (strncmp(out[i].name, r.name, sizeof(out[i].name)) == 0) slot = i;
+    if (slot < 0 && n < cap) {
+      slot = n++;
+      memset(&out[slot], 0, sizeof(bf_kernel_time));
+      strncpy(out[slot].name, r.name, sizeof(out[slot].name) - 1);
+    }
+    if (slot >= 0) {
+      out[slot].launches += 1;
+      out[slot].total_ms += ms;
+    }
+    ctx->pool.push_back(r.a);
+    ctx->pool.push_back(r.b);
+  }
+  ctx->recs.clear();
+  *n_out = n;
+  return BF_OK;
+}
+
+const char* bf_version(void) { return "bayesfusion-gfx950 0.1"; }
+
+bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream) {
+  if (!out) return BF_ERR_INVALID_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BF_ERR_INVALID_ARG;
+  if (hipSetDevice(device) != hipSuccess) return BF_ERR_HIP;
+  bf_ctx* ctx = new (std::nothrow) bf_ctx();
+  if (!ctx) return BF_ERR_OOM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
+  *out = ctx;
+  return BF_OK;
+}
+
+bf_status bf_destroy(bf_ctx* ctx) {
+  if (!ctx) return BF_OK;
+  (void)hipSetDevice(ctx->device);
+  for (int s = 0; s < bf_ctx::WS_COUNT; ++s) bf_dev_free(ctx, ctx->ws[s]);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& r : ctx->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  delete ctx;
+  return BF_OK;
+}
+
+bf_status bf_set_stream(bf_ctx* ctx, void* hip_stream) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return BF_OK;
+}
+
+const char* bf_last_error(const bf_ctx* ctx) { return ctx ? ctx->err : "null context"; }
+
+bf_status bf_band_view(const bf_band* band, bf_band_arrays* out) {
+  if (!band || !out) return BF_ERR_INVALID_ARG;
+  out->n = band->n;
+  out->dense_side = band->P;
+  out->keys = band->keys;
+  out->tsdf = band->tsdf;
+  out->w = band->w;
+  out->nbr = band->nbr;
+  out->deg = band->deg;
+  out->dense_tsdf = band->dense_tsdf;
+  out->dense_w = band->dense_w;
+  return BF_OK;
+}
+
+bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  if (!band) return BF_OK;
+  bf_dev_free(ctx, band->keys);
+  bf_dev_free(ctx, band->tsdf);
+  bf_dev_free(ctx, band->w);
+  bf_dev_free(ctx, band->nbr);
+  bf_dev_free(ctx, band->deg);
+  bf_dev_free(ctx, band->hkeys);
+  bf_dev_free(ctx, band->hvals);
+  bf_dev_free(ctx, band->dense_tsdf);
+  bf_dev_free(ctx, band->dense_w);
+  delete band;
+  return BF_OK;
+}
+
+bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out) {
+  if (!sys || !out) return BF_ERR_INVALID_ARG;
+  out->n = sys->n;
+  out->Lambda = sys->Lambda;
+  out->b = sys->b;
+  out->rhs = sys->rhs;
+  out->diag = sys->diag;
+  out->diag32 = sys->diag32;
+  out->acc = sys->acc;
+  return BF_OK;
+}
+
+bf_status bf_system_free(bf_ctx* ctx, bf_system* sys) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  if (!sys) return BF_OK;
+  bf_dev_free(ctx, sys->Lambda);
+  bf_dev_free(ctx, sys->b);
+  bf_dev_free(ctx, sys->rhs);
+  bf_dev_free(ctx, sys->diag);
+  bf_dev_free(ctx, sys->dinv);
+  bf_dev_free(ctx, sys->diag32);
+  bf_dev_free(ctx, sys->dinv32);
+  bf_dev_free(ctx, sys->acc);
+  delete sys;
+  return BF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,203 @@
+// Observation assembly and posterior precision (Sec. 3.5-3.6, eqs. 3-5 and
+// 8-11; Algorithm 1 steps 3-4), the explicit Q p product, and the per-voxel
+// features of the learned warm start.
+//
+// Observation rows are voxel-centric (a_i = e_v): every band voxel receives
+// one observation per view that sees it, so A^T W A is the diagonal Lambda and
+// A^T W y the vector b.  One thread per band voxel walks the views in order;
+// the FP64 operation order is fixed so Lambda, b and diag(Q) are reproducible
+// bit for bit.
+#include "bf_internal.h"
+
+namespace {
+
+struct noise_k {
+  double a, c, z0, model;
+  const double* pose;  // [T] or null
+};
+
+__global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32_t T,
+                                                  const float* __restrict__ depth,
+                                                  const double* __restrict__ poses, noise_k nz,
+                                                  const uint64_t* __restrict__ keys,
+                                                  const double* __restrict__ tsdf,
+                                                  const int32_t* __restrict__ deg, int64_t n,
+                                                  double lam, double eps, double lam_b,
+                                                  double* __restrict__ Lambda, double* __restrict__ b,
+                                                  double* __restrict__ rhs, double* __restrict__ diag,
+                                                  double* __restrict__ dinv, float* __restrict__ diag32,
+                                                  float* __restrict__ dinv32, double* __restrict__ acc) {
+#pragma clang fp contract(off)
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const int32_t i = (int32_t)bf_compact3(key), j = (int32_t)bf_compact3(key >> 1),
+                k = (int32_t)bf_compact3(key >> 2);
+  const int64_t plane = (int64_t)c.W * c.H;
+  double L = 0.0, B = 0.0, cnt = 0.0, sy = 0.0, syy = 0.0, ss = 0.0, smin = INFINITY;
+  for (int32_t t = 0; t < T; ++t) {
+    double D, Z;
+    if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
+    const double d = D - Z;
+    if (d < -g.tau) continue;
+    const double y = d < g.tau ? d : g.tau;
+    const double e = D - nz.z0;
+    const double sd = nz.a + nz.c * (e * e);
+    double var = sd * sd + (nz.pose ? nz.pose[t] : 0.0);
+    var = var + nz.model;
+    const double w = 1.0 / var;
+    L = L + w;
+    B = B + w * y;
+    cnt = cnt + 1.0;
+    sy = sy + y;
+    syy = syy + y * y;
+    ss = ss + sd;
+    smin = sd < smin ? sd : smin;
+  }
+  const int32_t dg = deg[v];
+  double dq = L + lam * (double)dg;
+  dq = dq + eps;
+  double h = B;
+  if (lam_b != 0.0 && dg < 6) {
+    dq = dq + lam_b;
+    h = h + lam_b * tsdf[v];
+  }
+  Lambda[v] = L;
+  b[v] = B;
+  rhs[v] = h;
+  diag[v] = dq;
+  const double inv = 1.0 / dq;
+  dinv[v] = inv;
+  diag32[v] = (float)dq;
+  dinv32[v] = (float)inv;
+  double* a = acc + v * 5;
+  a[0] = cnt;
+  a[1] = sy;
+  a[2] = syy;
+  a[3] = ss;
+  a[4] = cnt > 0.0 ? smin : 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_apply_Q(const int32_t* __restrict__ nbr,
+                                                 const double* __restrict__ diag, double lam,
+                                                 const double* __restrict__ p, double* __restrict__ q,
+                                                 int64_t n) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const int32_t* nb = nbr + v * 6;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {
+    const int32_t u = nb[t];
+    if (u >= 0) s += p[u];
+  }
+  q[v] = diag[v] * p[v] - lam * s;
+}
+
+// Features of the learned warm start, lengths in units of h (see bf_features).
+__global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h,
+                                                  const double* __restrict__ tsdf,
+                                                  const int32_t* __restrict__ w,
+                                                  const int32_t* __restrict__ nbr,
+                                                  const int32_t* __restrict__ deg,
+                                                  const double* __restrict__ Lambda,
+                                                  const double* __restrict__ acc,
+                                                  float* __restrict__ feat) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double* a = acc + v * 5;
+  const double cnt = a[0];
+  const double my = cnt > 0.0 ? a[1] / cnt : 0.0;
+  const double vy = cnt > 0.0 ? a[2] / cnt - my * my : 0.0;
+  const double ms = cnt > 0.0 ? a[3] / cnt : 0.0;
+  const double tv = tsdf[v];
+  float* f = feat + v * 12;
+  f[0] = (float)(tv / h);
+  f[1] = (float)log(1.0 + (double)w[v]);
+  f[2] = (float)((double)deg[v] / 6.0);
+  f[3] = (float)(cnt / (double)T);
+  f[4] = (float)(my / h);
+  f[5] = (float)(vy / (h * h));
+  f[6] = (float)(ms / h);
+  f[7] = (float)(a[4] / h);
+  f[8] = (float)log(Lambda[v] * (h * h) + 1.0);
+  const int32_t* nb = nbr + v * 6;
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    const int32_t m = nb[2 * ax], p = nb[2 * ax + 1];
+    const double tm = m >= 0 ? tsdf[m] : tv;
+    const double tp = p >= 0 ? tsdf[p] : tv;
+    f[9 + ax] = (float)((tp - tm) / (2.0 * h));
+  }
+}
+
+}  // namespace
+
+extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, int32_t T,
+                                 const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                                 const bf_prior* prior, bf_system** out) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, band && cam && noise && prior && out, "bf_assemble: NULL argument");
+  *out = nullptr;
+  BF_CHECK(ctx, T >= 0, "bf_assemble: T < 0");
+  BF_CHECK(ctx, T == 0 || band->n == 0 || (depth_dev && c2w_dev && cam->width > 0 && cam->height > 0),
+           "bf_assemble: bad camera or NULL depth/poses");
+  BF_CHECK(ctx, prior->lambda >= 0.0 && prior->eps >= 0.0 && prior->lambda_b >= 0.0,
+           "bf_assemble: lambda, eps and lambda_b must be >= 0");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  bf_system* sys = new (std::nothrow) bf_system();
+  if (!sys) return bf_fail(ctx, BF_ERR_OOM, "bf_assemble: host allocation");
+  sys->n = band->n;
+  sys->band = band;
+  sys->lambda = prior->lambda;
+  sys->eps = prior->eps;
+  sys->lambda_b = prior->lambda_b;
+  sys->T = T;
+  const int64_t N = band->n;
+  auto fail = [&](bf_status st) {
+    bf_system_free(ctx, sys);
+    return st;
+  };
+  if (N > 0) {
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->Lambda, N * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->b, N * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->rhs, N * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag, N * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv, N * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag32, N * 4)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv32, N * 4)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->acc, N * 40)) return fail(s);
+    bf_grid_k gk{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
+    bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+    noise_k nz{noise->a, noise->c, noise->z0, noise->sigma2_model, noise->sigma2_pose_dev};
+    BF_LAUNCH(ctx, "assemble", k_assemble, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, gk, ck, T,
+                       depth_dev, c2w_dev, nz, band->keys, band->tsdf, band->deg, N, prior->lambda,
+                       prior->eps, prior->lambda_b, sys->Lambda, sys->b, sys->rhs, sys->diag, sys->dinv,
+                       sys->diag32, sys->dinv32, sys->acc);
+    if (bf_status s = bf_launch_check(ctx, "k_assemble")) return fail(s);
+  }
+  *out = sys;
+  return BF_OK;
+}
+
+extern "C" bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double* p_dev, double* q_dev) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys, "bf_apply_Q: NULL system");
+  if (sys->n == 0) return BF_OK;
+  BF_CHECK(ctx, p_dev && q_dev && p_dev != q_dev, "bf_apply_Q: bad vectors");
+  hipLaunchKernelGGL(k_apply_Q, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, ctx->stream,
+                     sys->band->nbr, sys->diag, sys->lambda, p_dev, q_dev, sys->n);
+  return bf_launch_check(ctx, "k_apply_Q");
+}
+
+extern "C" bf_status bf_features(bf_ctx* ctx, const bf_system* sys, float* feat_dev) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys, "bf_features: NULL system");
+  if (sys->n == 0) return BF_OK;
+  BF_CHECK(ctx, feat_dev && sys->T > 0, "bf_features: NULL output or system without views");
+  const bf_band* band = sys->band;
+  BF_LAUNCH(ctx, "features", k_features, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, sys->n,
+                     sys->T, band->h, band->tsdf, band->w, band->nbr, band->deg, sys->Lambda, sys->acc,
+                     feat_dev);
+  return bf_launch_check(ctx, "k_features");
+}

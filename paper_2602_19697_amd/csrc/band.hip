@@ -1,0 +1,314 @@
+// Coarse TSDF bootstrap, narrow-band activation in Morton order, key->index
+// hash and 6-neighbour table (Sec. 3.3-3.4, eq. 1; Algorithm 1 steps 1-2).
+//
+// Layout: the dense coarse TSDF lives on a P^3 cube (P = next power of two
+// >= G) indexed by Morton code m, so walking m = 0..P^3-1 visits voxels in
+// key order and a block-wise stream compaction emits the band already sorted.
+// Morton-local voxels also project to nearby pixels, which keeps the depth
+// gathers of a block inside a few cache lines.
+#include "bf_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 4;                    // voxels per thread per block tile
+constexpr int kTile = kThreads * kItems;     // Morton codes per block
+
+__global__ __launch_bounds__(256) void k_validate_depth(const float* __restrict__ depth, int64_t n,
+                                                        int* __restrict__ flag) {
+  int bad = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = depth[i];
+    if (!(d >= 0.0f) || d == INFINITY) bad = 1;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+// One block tile of Morton codes: fuse every view into the coarse TSDF of each
+// voxel (unit weights, truncation, occlusion test), store the dense grid and
+// count the band predicate |TSDF| <= band, W > 0.
+__global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
+                                                    const float* __restrict__ depth,
+                                                    const double* __restrict__ poses,
+                                                    uint64_t total, double* __restrict__ dense_t,
+                                                    int32_t* __restrict__ dense_w,
+                                                    uint32_t* __restrict__ counts) {
+#pragma clang fp contract(off)
+  __shared__ uint32_t wave_cnt[kThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  const int64_t plane = (int64_t)c.W * c.H;
+  uint32_t cnt = 0;
+  for (int it = 0; it < kItems; ++it) {
+    const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
+    if (m >= total) break;
+    const int32_t i = (int32_t)bf_compact3(m), j = (int32_t)bf_compact3(m >> 1),
+                  k = (int32_t)bf_compact3(m >> 2);
+    double tsdf = 0.0;
+    int32_t W = 0;
+    if (i < g.G && j < g.G && k < g.G) {
+      double S = 0.0;
+      for (int32_t t = 0; t < T; ++t) {
+        double D, Z;
+        if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
+        const double d = D - Z;
+        if (d < -g.tau) continue;
+        S = S + (d < g.tau ? d : g.tau);
+        W = W + 1;
+      }
+      if (W > 0) tsdf = S / (double)W;
+    }
+    dense_t[m] = tsdf;
+    dense_w[m] = W;
+    cnt += (W > 0 && fabs(tsdf) <= g.band) ? 1u : 0u;
+  }
+  // block count (integer: any order is exact)
+  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if ((threadIdx.x & 63) == 0) wave_cnt[threadIdx.x >> 6] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += wave_cnt[w];
+    counts[blockIdx.x] = s;
+  }
+}
+
+// Exclusive scan of the per-block counts in one block of 1024 threads; writes
+// offsets[nb] and the total to *n_total.
+__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ counts, int64_t nb,
+                                                      uint64_t* __restrict__ offsets,
+                                                      uint64_t* __restrict__ n_total) {
+  __shared__ uint64_t part[1024];
+  const int64_t chunk = bf_cdiv(nb, 1024);
+  const int64_t lo = threadIdx.x * chunk;
+  const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
+  uint64_t s = 0;
+  for (int64_t b = lo; b < hi; ++b) s += counts[b];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 chunk sums
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint64_t run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  for (int64_t b = lo; b < hi; ++b) {
+    offsets[b] = run;
+    run += counts[b];
+  }
+  if (threadIdx.x == 1023) *n_total = part[1023];
+}
+
+// Scatter of the band voxels of one block tile in Morton order.
+__global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double band,
+                                                      const double* __restrict__ dense_t,
+                                                      const int32_t* __restrict__ dense_w,
+                                                      const uint64_t* __restrict__ offsets,
+                                                      uint64_t* __restrict__ keys,
+                                                      double* __restrict__ tsdf,
+                                                      int32_t* __restrict__ w) {
+  __shared__ uint32_t wave_cnt[kThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  uint64_t out = offsets[blockIdx.x];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int it = 0; it < kItems; ++it) {
+    const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
+    double t = 0.0;
+    int32_t W = 0;
+    if (m < total) {
+      t = dense_t[m];
+      W = dense_w[m];
+    }
+    const bool sel = m < total && W > 0 && fabs(t) <= band;
+    const uint64_t mask = __ballot(sel);
+    const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) wave_cnt[wid] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t before = 0, row = 0;
+    for (int v = 0; v < kThreads / 64; ++v) {
+      if (v < wid) before += wave_cnt[v];
+      row += wave_cnt[v];
+    }
+    if (sel) {
+      const uint64_t o = out + before + rank;
+      keys[o] = m;
+      tsdf[o] = t;
+      w[o] = W;
+    }
+    out += row;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n,
+                                                     uint64_t* __restrict__ hkeys,
+                                                     int32_t* __restrict__ hvals, int log2cap,
+                                                     uint64_t max_probe, int* __restrict__ flag) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const uint64_t mask = (1ull << log2cap) - 1ull;
+  uint64_t slot = bf_hash_slot(key, log2cap);
+  for (uint64_t p = 0; p < max_probe; ++p) {
+    const unsigned long long prev =
+        atomicCAS((unsigned long long*)&hkeys[slot], (unsigned long long)kBfEmptyKey,
+                  (unsigned long long)key);
+    if (prev == kBfEmptyKey || prev == key) {
+      hvals[slot] = (int32_t)v;
+      return;
+    }
+    slot = (slot + 1) & mask;
+  }
+  atomicOr(flag, 2);
+}
+
+__global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__ keys, int64_t n,
+                                                    int32_t G, const uint64_t* __restrict__ hkeys,
+                                                    const int32_t* __restrict__ hvals, int log2cap,
+                                                    uint64_t max_probe, int32_t* __restrict__ nbr,
+                                                    int32_t* __restrict__ deg) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const int32_t c[3] = {(int32_t)bf_compact3(key), (int32_t)bf_compact3(key >> 1),
+                        (int32_t)bf_compact3(key >> 2)};
+  int32_t d = 0;
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    int32_t q[3] = {c[0], c[1], c[2]};
+    q[s >> 1] += (s & 1) ? 1 : -1;
+    int32_t idx = -1;
+    if (q[s >> 1] >= 0 && q[s >> 1] < G)
+      idx = bf_hash_find(hkeys, hvals, log2cap, max_probe, bf_morton(q[0], q[1], q[2]));
+    nbr[v * 6 + s] = idx;
+    d += idx >= 0;
+  }
+  deg[v] = d;
+}
+
+}  // namespace
+
+extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
+                                   const float* depth_dev, const double* c2w_dev, uint32_t flags,
+                                   bf_band** out, int64_t* n_out) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, grid && cam && out && n_out, "bf_build_band: NULL argument");
+  *out = nullptr;
+  *n_out = 0;
+  BF_CHECK(ctx, grid->G >= 1 && grid->G <= 2048, "bf_build_band: G=%d outside [1, 2048]", grid->G);
+  BF_CHECK(ctx, grid->h > 0.0 && grid->tau >= 0.0 && grid->band >= 0.0,
+           "bf_build_band: h must be > 0, tau and band >= 0");
+  BF_CHECK(ctx, T >= 0, "bf_build_band: T < 0");
+  BF_CHECK(ctx, T == 0 || (cam->width > 0 && cam->height > 0 && depth_dev && c2w_dev),
+           "bf_build_band: bad camera size or NULL depth/poses");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+
+  bf_band* band = new (std::nothrow) bf_band();
+  if (!band) return bf_fail(ctx, BF_ERR_OOM, "bf_build_band: host allocation");
+  band->G = grid->G;
+  band->h = grid->h;
+  for (int a = 0; a < 3; ++a) band->origin[a] = grid->origin[a];
+  band->tau = grid->tau;
+  band->band = grid->band;
+  int l2 = 0;
+  while ((1 << l2) < grid->G) ++l2;
+  band->P = 1 << l2;
+  band->log2P = l2;
+  const uint64_t total = (uint64_t)band->P * band->P * band->P;
+  const int64_t nblocks = (int64_t)((total + kTile - 1) / kTile);
+
+  auto fail = [&](bf_status st) {
+    bf_band_free(ctx, band);
+    return st;
+  };
+
+  // flags[0]: depth invalid, flags[1]: hash overflow; then the band count
+  void* scan_ws = nullptr;
+  const size_t scan_bytes = 64 + nblocks * (sizeof(uint32_t) + sizeof(uint64_t)) + 64;
+  if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
+  int* dflags = (int*)scan_ws;
+  uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
+  uint32_t* counts = (uint32_t*)((char*)scan_ws + 64);
+  uint64_t* offsets = (uint64_t*)((char*)scan_ws + 64 + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64);
+  if (hipMemsetAsync(scan_ws, 0, 64, ctx->stream) != hipSuccess)
+    return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
+
+  double* dense_t = nullptr;
+  int32_t* dense_w = nullptr;
+  if (flags & BF_BAND_KEEP_DENSE) {
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->dense_tsdf, total * sizeof(double))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->dense_w, total * sizeof(int32_t))) return fail(s);
+    dense_t = band->dense_tsdf;
+    dense_w = band->dense_w;
+  } else {
+    if (bf_status s = bf_ws(ctx, bf_ctx::WS_DENSE_T, total * sizeof(double), (void**)&dense_t)) return fail(s);
+    if (bf_status s = bf_ws(ctx, bf_ctx::WS_DENSE_W, total * sizeof(int32_t), (void**)&dense_w)) return fail(s);
+  }
+
+  const int64_t npix = (int64_t)T * cam->width * cam->height;
+  if (npix > 0) {
+    const int vb = (int)std::min<int64_t>(bf_cdiv(npix, 256), 8192);
+    BF_LAUNCH(ctx, "validate_depth", k_validate_depth, dim3(vb), dim3(256), 0, depth_dev, npix, dflags);
+    if (bf_status s = bf_launch_check(ctx, "k_validate_depth")) return fail(s);
+  }
+  bf_grid_k gk{grid->G, grid->h, grid->origin[0], grid->origin[1], grid->origin[2], grid->tau, grid->band};
+  bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+  BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
+                     depth_dev, c2w_dev, total, dense_t, dense_w, counts);
+  if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
+  BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal);
+  if (bf_status s = bf_launch_check(ctx, "k_scan_counts")) return fail(s);
+
+  void* pin = nullptr;
+  if (bf_status s = bf_pinned(ctx, 64, &pin)) return fail(s);
+  if (hipMemcpyAsync(pin, scan_ws, 24, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->stream) != hipSuccess)
+    return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: count read-back failed"));
+  if (((int*)pin)[0] & 1)
+    return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth holds NaN, inf or negative values"));
+  const uint64_t N = *(uint64_t*)((char*)pin + 16);
+  if (N >= (1ull << 31) - 1) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing", (unsigned long long)N));
+  band->n = (int64_t)N;
+
+  if (N > 0) {
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->keys, N * sizeof(uint64_t))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->tsdf, N * sizeof(double))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->w, N * sizeof(int32_t))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->nbr, N * 6 * sizeof(int32_t))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->deg, N * sizeof(int32_t))) return fail(s);
+    BF_LAUNCH(ctx, "band_scatter", k_band_scatter, dim3((unsigned)nblocks), dim3(kThreads), 0, total,
+                       grid->band, dense_t, dense_w, offsets, band->keys, band->tsdf, band->w);
+    if (bf_status s = bf_launch_check(ctx, "k_band_scatter")) return fail(s);
+
+    int log2cap = 6;
+    while ((1ull << log2cap) < 2 * N) ++log2cap;
+    band->hcap = 1ull << log2cap;
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->hkeys, band->hcap * sizeof(uint64_t))) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->hvals, band->hcap * sizeof(int32_t))) return fail(s);
+    const int fb = (int)std::min<uint64_t>((band->hcap + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_u64, dim3(fb), dim3(256), 0, ctx->stream, band->hkeys, band->hcap, kBfEmptyKey);
+    const unsigned nb = (unsigned)bf_cdiv((int64_t)N, 256);
+    const uint64_t max_probe = getenv("BF_DEBUG_HASH_PROBES") ? strtoull(getenv("BF_DEBUG_HASH_PROBES"), nullptr, 10)
+                                                               : band->hcap;
+    BF_LAUNCH(ctx, "hash_insert", k_hash_insert, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->hkeys,
+                       band->hvals, log2cap, max_probe, dflags);
+    BF_LAUNCH(ctx, "neighbours", k_neighbours, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, grid->G,
+                       band->hkeys, band->hvals, log2cap, band->hcap, band->nbr, band->deg);
+    if (bf_status s = bf_launch_check(ctx, "hash/neighbours")) return fail(s);
+    if (hipMemcpyAsync(pin, scan_ws, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: flag read-back failed"));
+    if (((int*)pin)[0] & 2) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: hash table overflow"));
+  }
+  *out = band;
+  *n_out = band->n;
+  return BF_OK;
+}

@@ -1,0 +1,373 @@
+// Jacobi-preconditioned conjugate gradients for the posterior mean
+// (Sec. 3.6, eq. 11; Algorithm 1 step 5).
+//
+// Q = diag(Q) - lambda * adjacency(band) is never assembled: the product is a
+// 7-point stencil through the neighbour table.  Each iteration is two
+// streaming kernels whose last-arriving block turns the block partials into
+// the CG scalars on the device, so the host never waits inside an iteration:
+//   A: p = z + beta p_old (own row and, on the fly, each neighbour), q = Q p,
+//      partial p.q  ->  alpha = rho / p.q (breakdown check)
+//   B: x += alpha p, r -= alpha q, z = r / diag, partials r.z and r.r
+//      -> beta, or a request for an FP64 true-residual check
+// Precision V = double runs everything in FP64.  V = float (mixed) keeps the
+// vectors and the stencil in float while the dot products, alpha/beta and the
+// residual test stay FP64; its correction c is folded into the FP64 solution
+// and the residual recomputed in FP64 whenever the float residual has fallen
+// 1e6-fold (or below the tolerance); the float solve then restarts on the FP64
+// residual (mixed-precision iterative refinement).
+// Reductions are deterministic: fixed-order wave butterflies, a fixed block
+// tree and a fixed-order sum of the block partials.
+#include "bf_internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct PcgState {
+  double rho, alpha, beta, tol2b, bnorm2, rr, rr_true, rho_new, inner2, rr_ref;
+  int32_t iters, done, check, status, last, refinements, max_iter, replace_every;
+  uint32_t counter, pad_;
+};
+
+enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
+
+__global__ void k_state_init(PcgState* st, double tol, int32_t max_iter, int32_t replace_every, double inner) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    PcgState s{};
+    s.tol2b = tol * tol;  // scaled by ||rhs||^2 once known
+    s.max_iter = max_iter;
+    s.replace_every = replace_every;
+    s.inner2 = inner * inner;
+    *st = s;
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_fill(V* __restrict__ p, int64_t n, V v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Sum the per-block partials [nb][W] in a fixed order inside the last block.
+template <int W>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int nb, double* out,
+                                                double* lds) {
+  double acc[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) acc[w] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int w = 0; w < W; ++w) acc[w] += part[b * W + w];
+#pragma unroll
+  for (int w = 0; w < W; ++w) out[w] = bf_block_sum(acc[w], lds);
+}
+
+// A: direction update fused with the stencil product and p.q.
+template <typename V>
+__global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                               const V* __restrict__ diag, V lam, const V* __restrict__ z,
+                                               const V* __restrict__ p_old, V* __restrict__ p_new,
+                                               V* __restrict__ q, int64_t n, double* __restrict__ part) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (st->done) return;
+  const V beta = (V)st->beta;
+  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double pq = 0.0;
+  if (v < n) {
+    const int32_t* nb = nbr + v * 6;
+    V s = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int32_t u = nb[t];
+      if (u >= 0) s += z[u] + beta * p_old[u];
+    }
+    const V pv = z[v] + beta * p_old[v];
+    const V qv = diag[v] * pv - lam * s;
+    p_new[v] = pv;
+    q[v] = qv;
+    pq = (double)pv * (double)qv;
+  }
+  pq = bf_block_sum(pq, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = pq;
+  if (!bf_last_block(&st->counter, &flag)) return;
+  double tot;
+  reduce_partials<1>(part, gridDim.x, &tot, lds);
+  if (threadIdx.x == 0) {
+    st->counter = 0;
+    if (!(tot > 0.0) || !isfinite(tot)) {
+      st->status = BF_ERR_BREAKDOWN;
+      st->done = 1;
+    } else {
+      st->alpha = st->rho / tot;
+    }
+  }
+}
+
+// B: solution/residual update, preconditioned residual and the two dots.
+template <typename V>
+__global__ __launch_bounds__(256) void k_pcg_B(PcgState* __restrict__ st, const V* __restrict__ dinv,
+                                               const V* __restrict__ p, const V* __restrict__ q,
+                                               V* __restrict__ x, V* __restrict__ r, V* __restrict__ z,
+                                               int64_t n, double* __restrict__ part) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (st->done) return;
+  const V alpha = (V)st->alpha;
+  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double rz = 0.0, rr = 0.0;
+  if (v < n) {
+    x[v] = x[v] + alpha * p[v];
+    const V rv = r[v] - alpha * q[v];
+    const V zv = rv * dinv[v];
+    r[v] = rv;
+    z[v] = zv;
+    rz = (double)rv * (double)zv;
+    rr = (double)rv * (double)rv;
+  }
+  rz = bf_block_sum(rz, lds);
+  rr = bf_block_sum(rr, lds);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rz;
+    part[2 * blockIdx.x + 1] = rr;
+  }
+  if (!bf_last_block(&st->counter, &flag)) return;
+  double tot[2];
+  reduce_partials<2>(part, gridDim.x, tot, lds);
+  if (threadIdx.x == 0) {
+    st->counter = 0;
+    st->iters += 1;
+    st->rr = tot[1];
+    const bool at_max = st->iters >= st->max_iter;
+    const bool periodic = st->replace_every > 0 && (st->iters % st->replace_every) == 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+      st->status = BF_ERR_BREAKDOWN;
+      st->done = 1;
+    } else if (tot[1] <= fmax(st->tol2b, st->inner2 * st->rr_ref) || at_max || periodic) {
+      st->check = 1;
+      st->last = at_max ? 1 : 0;
+      st->rho_new = tot[0];
+    } else {
+      st->beta = tot[0] / st->rho;
+      st->rho = tot[0];
+    }
+  }
+}
+
+// Mixed precision: fold the float correction into the FP64 solution.
+__global__ __launch_bounds__(256) void k_fold(const PcgState* __restrict__ st, int force, double* __restrict__ x64,
+                                              float* __restrict__ c, int64_t n) {
+  if (!force && (st->done || !st->check)) return;
+  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  if (v < n) {
+    x64[v] = x64[v] + (double)c[v];
+    c[v] = 0.0f;
+  }
+}
+
+// True residual r = rhs - Q x in FP64 (INIT: start of the solve; CHECK:
+// confirm convergence / replace the recursive residual; REPORT: norm only).
+template <typename V>
+__global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int mode,
+                                                  const int32_t* __restrict__ nbr,
+                                                  const double* __restrict__ diag, double lam,
+                                                  const double* __restrict__ rhs,
+                                                  const double* __restrict__ x, const V* __restrict__ dinv,
+                                                  V* __restrict__ r, V* __restrict__ z, int64_t n,
+                                                  double* __restrict__ part) {
+  __shared__ double lds[16];
+  __shared__ int flag;
+  if (mode == MODE_CHECK && (st->done || !st->check)) return;
+  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  double rr = 0.0, rz = 0.0, bb = 0.0;
+  if (v < n) {
+    const double hv = rhs[v];
+    double res = hv;
+    if (x) {
+      const int32_t* nb = nbr + v * 6;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int32_t u = nb[t];
+        if (u >= 0) s += x[u];
+      }
+      res = hv - (diag[v] * x[v] - lam * s);
+    }
+    rr = res * res;
+    bb = hv * hv;
+    if (mode != MODE_REPORT) {
+      const V rv = (V)res;
+      const V zv = rv * dinv[v];
+      r[v] = rv;
+      z[v] = zv;
+      rz = (double)rv * (double)zv;
+    }
+  }
+  rr = bf_block_sum(rr, lds);
+  rz = bf_block_sum(rz, lds);
+  bb = bf_block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = rr;
+    part[3 * blockIdx.x + 1] = rz;
+    part[3 * blockIdx.x + 2] = bb;
+  }
+  if (!bf_last_block(&st->counter, &flag)) return;
+  double tot[3];
+  reduce_partials<3>(part, gridDim.x, tot, lds);
+  if (threadIdx.x != 0) return;
+  st->counter = 0;
+  st->rr_true = tot[0];
+  if (mode == MODE_REPORT) return;
+  if (mode == MODE_INIT) {
+    st->bnorm2 = tot[2];
+    st->tol2b = st->tol2b * tot[2];
+    if (tot[2] == 0.0 || tot[0] <= st->tol2b) {
+      st->done = 1;
+      return;
+    }
+    st->rho = tot[1];
+    st->beta = 0.0;
+    st->rr_ref = tot[0];
+    if (st->max_iter <= 0) {
+      st->status = BF_ERR_NOT_CONVERGED;
+      st->done = 1;
+    }
+    return;
+  }
+  st->refinements += 1;
+  if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+    st->status = BF_ERR_BREAKDOWN;
+    st->done = 1;
+  } else if (tot[0] <= st->tol2b) {
+    st->done = 1;
+  } else if (st->last) {
+    st->status = BF_ERR_NOT_CONVERGED;
+    st->done = 1;
+  } else {
+    // FP64: continue CG from the replaced residual.  Mixed: the float
+    // correction has been folded; restart the inner solve on the new residual
+    // (iterative refinement), since float drift breaks the conjugacy.
+    st->beta = st->inner2 > 0.0 ? 0.0 : tot[1] / st->rho;
+    st->rho = tot[1];
+    st->rr_ref = tot[0];
+    st->check = 0;
+  }
+}
+
+template <typename V>
+bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, const double* rhs, double* x,
+                  bf_solve_report* rep) {
+  const int64_t N = sys->n;
+  const int nb = (int)bf_cdiv(N, kThreads);
+  const bool mixed = sizeof(V) == 4;
+  // workspace: state | partials [nb][3] | r z p0 p1 q (V) | c (float, mixed)
+  const size_t st_bytes = 256;
+  const size_t part_bytes = ((size_t)nb * 3 * 8 + 255) / 256 * 256;
+  const size_t vec_bytes = ((size_t)N * sizeof(V) + 255) / 256 * 256;
+  const size_t c_bytes = mixed ? ((size_t)N * 4 + 255) / 256 * 256 : 0;
+  char* ws = nullptr;
+  BF_TRY(bf_ws(ctx, bf_ctx::WS_PCG, st_bytes + part_bytes + 5 * vec_bytes + c_bytes, (void**)&ws));
+  PcgState* st = (PcgState*)ws;
+  double* part = (double*)(ws + st_bytes);
+  V* r = (V*)(ws + st_bytes + part_bytes);
+  V* z = (V*)((char*)r + vec_bytes);
+  V* p0 = (V*)((char*)z + vec_bytes);
+  V* p1 = (V*)((char*)p0 + vec_bytes);
+  V* q = (V*)((char*)p1 + vec_bytes);
+  float* c = mixed ? (float*)((char*)q + vec_bytes) : nullptr;
+  const V* diagV = mixed ? (const V*)sys->diag32 : (const V*)sys->diag;
+  const V* dinvV = mixed ? (const V*)sys->dinv32 : (const V*)sys->dinv;
+  V* xin = mixed ? (V*)c : (V*)x;
+  const int replace_every = 0;
+  // Mixed: each inner float solve reduces its residual 1e6-fold before an FP64 check.
+  const double inner = mixed ? 1e-6 : 0.0;
+  const int fb = std::min(nb, 4096);
+
+  hipEvent_t e0, e1;
+  BF_HIP(ctx, hipEventCreate(&e0));
+  BF_HIP(ctx, hipEventCreate(&e1));
+  BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, ctx->stream, st, o->tol, o->max_iter, replace_every,
+                     inner);
+  if (!o->use_x0) hipLaunchKernelGGL(k_fill<double>, dim3(fb), dim3(256), 0, ctx->stream, x, N, 0.0);
+  hipLaunchKernelGGL(k_fill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N, (V)0);
+  if (mixed) hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, ctx->stream, c, N, 0.0f);
+  BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
+                     sys->band->nbr, sys->diag, sys->lambda, rhs, o->use_x0 ? (const double*)x : nullptr, dinvV,
+                     r, z, N, part);
+  BF_TRY(bf_launch_check(ctx, "pcg init"));
+
+  PcgState* hs = nullptr;
+  BF_TRY(bf_pinned(ctx, sizeof(PcgState), (void**)&hs));
+  int it = 0;
+  int next = o->check_every > 0 ? o->check_every : 3;
+  V* pa = p0;
+  V* pb = p1;
+  const V lamV = (V)sys->lambda;
+  for (;;) {
+    const int upto = std::min(next, o->max_iter);
+    for (; it < upto; ++it) {
+      BF_LAUNCH(ctx, "pcg_A", k_pcg_A<V>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, z,
+                         pa, pb, q, N, part);
+      BF_LAUNCH(ctx, "pcg_B", k_pcg_B<V>, dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, z, N,
+                         part);
+      if (mixed)
+        BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 0, x, c, N);
+      BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
+                         sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+      std::swap(pa, pb);
+    }
+    BF_TRY(bf_launch_check(ctx, "pcg iteration"));
+    BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
+    BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (hs->done || it >= o->max_iter) break;
+    next = o->check_every > 0 ? it + o->check_every : it + std::max(it, 4);
+  }
+  if (mixed) BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
+  BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
+                     sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+  BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+  BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
+  BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  float ms = 0.0f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bf_status status = (bf_status)hs->status;
+  if (status == BF_OK && !hs->done) status = BF_ERR_NOT_CONVERGED;
+  if (hs->bnorm2 == 0.0) {  // Q x = 0 has the solution x = 0
+    hipLaunchKernelGGL(k_fill<double>, dim3(fb), dim3(256), 0, ctx->stream, x, N, 0.0);
+    BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
+  if (rep) {
+    rep->iters = hs->iters;
+    rep->status = status;
+    rep->refinements = mixed ? hs->refinements : 0;
+    rep->used_warm_start = o->use_x0 ? 1 : 0;
+    rep->rel_res = hs->bnorm2 > 0.0 ? sqrt(hs->rr_true / hs->bnorm2) : 0.0;
+    rep->seconds = ms * 1e-3;
+    rep->col_iters = hs->iters;
+  }
+  if (status == BF_ERR_BREAKDOWN) return bf_fail(ctx, status, "bf_pcg_solve: breakdown (p.Qp <= 0 or non-finite)");
+  if (status == BF_ERR_NOT_CONVERGED)
+    return bf_fail(ctx, status, "bf_pcg_solve: not converged after %d iterations", hs->iters);
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" bf_status bf_pcg_solve(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
+                                  const double* rhs_dev, double* x_dev, bf_solve_report* rep) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys && opts, "bf_pcg_solve: NULL argument");
+  BF_CHECK(ctx, opts->tol >= 0.0 && opts->max_iter >= 0, "bf_pcg_solve: tol and max_iter must be >= 0");
+  BF_CHECK(ctx, opts->precision == BF_PREC_FP64 || opts->precision == BF_PREC_MIXED,
+           "bf_pcg_solve: unknown precision %d", opts->precision);
+  if (rep) *rep = bf_solve_report{};
+  if (sys->n == 0) return BF_OK;
+  BF_CHECK(ctx, x_dev, "bf_pcg_solve: NULL x");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  const double* rhs = rhs_dev ? rhs_dev : sys->rhs;
+  if (opts->precision == BF_PREC_FP64) return run_pcg<double>(ctx, sys, opts, rhs, x_dev, rep);
+  return run_pcg<float>(ctx, sys, opts, rhs, x_dev, rep);
+}

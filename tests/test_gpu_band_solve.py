@@ -1,0 +1,173 @@
+"""GPU (gfx950) parity of the band, assembly and PCG against the FP64 oracle.
+
+Band keys, TSDF, weights, neighbour table, Lambda, b and diag(Q) are compared
+bit for bit; the posterior mean within the relative-L2 tolerances 1e-6 (FP64)
+and 1e-4 (mixed precision).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from tests import gpu_common as gc  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2602_19697_amd as bf
+    c = bf.Context(gc.DEV)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("name", ["tiny", "sphere64"])
+def test_band_bitexact(ctx, name):
+    wl = gc.workload(name)
+    ref = gc.oracle_ref(name)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, keep_dense=True)
+    a = band.arrays()
+    print(f"[{name}] N gpu={band.n} oracle={len(ref['keys'])}", flush=True)
+    assert band.n == len(ref["keys"])
+    assert np.array_equal(a["keys"].cpu().numpy(), ref["keys"])
+    assert np.array_equal(a["tsdf"].cpu().numpy(), ref["tsdf"])
+    assert np.array_equal(a["w"].cpu().numpy(), ref["w"])
+    assert np.array_equal(a["nbr"].cpu().numpy(), ref["nbr"])
+    assert np.array_equal(a["deg"].cpu().numpy(), ref["deg"])
+    # dense coarse TSDF over the whole grid, bit for bit
+    pos = gc.morton_to_linear(wl.G, a["dense_side"])
+    dt = a["dense_tsdf"].cpu().numpy()[pos]
+    dw = a["dense_w"].cpu().numpy()[pos]
+    assert np.array_equal(dw, ref["w_dense"].ravel())
+    assert np.array_equal(dt, ref["tsdf_dense"].ravel())
+    sys_.free()
+    band.free()
+
+
+@pytest.mark.parametrize("name", ["tiny", "sphere64"])
+def test_assembly_bitexact(ctx, name):
+    wl = gc.workload(name)
+    ref = gc.oracle_ref(name)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    s = sys_.arrays()
+    assert np.array_equal(s["Lambda"].cpu().numpy(), ref["Lambda"])
+    assert np.array_equal(s["b"].cpu().numpy(), ref["b"])
+    assert np.array_equal(s["rhs"].cpu().numpy(), ref["rhs"])
+    assert np.array_equal(s["diag"].cpu().numpy(), ref["diag"])
+    assert np.array_equal(s["acc"].cpu().numpy(), ref["acc"])
+    sys_.free()
+    band.free()
+
+
+def test_assembly_anchor_bitexact(ctx):
+    import oracle as O
+    wl = gc.workload("sphere64")
+    ref = gc.oracle_ref("sphere64")
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, lam_b=250.0)
+    s = sys_.arrays()
+    diag = O.precision_diag(ref["Lambda"], ref["deg"], wl.lam, wl.eps, 250.0)
+    rhs = O.anchor_rhs(ref["b"], ref["deg"], ref["tsdf"], 250.0)
+    assert np.array_equal(s["diag"].cpu().numpy(), diag)
+    assert np.array_equal(s["rhs"].cpu().numpy(), rhs)
+    sys_.free()
+    band.free()
+
+
+def test_apply_Q_matches_oracle(ctx):
+    import oracle as O
+    wl = gc.workload("sphere64")
+    ref = gc.oracle_ref("sphere64")
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    p = np.random.default_rng(0).standard_normal(band.n)
+    q = ctx.bf_apply_Q(sys_, torch.from_numpy(p).to(gc.DEV)).cpu().numpy()
+    q_ref = O.apply_Q(ref["nbr"], ref["diag"], wl.lam, p)
+    assert gc.rel_l2(q, q_ref) <= 1e-15
+    sys_.free()
+    band.free()
+
+
+@pytest.mark.parametrize("name,lam,tol", [("tiny", 10.0, 1e-8), ("sphere64", 10.0, 1e-8),
+                                          ("sphere64", 1e5, 1e-8), ("sphere64", 1e6, 1e-10)])
+def test_pcg_fp64(ctx, name, lam, tol):
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    wl = gc.workload(name)
+    ref = gc.oracle_ref(name)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, lam=lam)
+    diag = O.precision_diag(ref["Lambda"], ref["deg"], lam, wl.eps)
+    mu_ref, rep_ref = O.pcg(ref["nbr"], diag, lam, ref["rhs"], tol)
+    mu, rep = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_FP64)
+    err = gc.rel_l2(mu.cpu().numpy(), mu_ref)
+    print(f"[{name} lam={lam}] iters gpu={rep['iters']} oracle={rep_ref['iters']} rel_res={rep['rel_res']:.2e} err={err:.2e}")
+    assert rep["status"] == 0 and rep["rel_res"] <= tol
+    assert err <= 1e-6
+    # the same run twice is bitwise identical (deterministic reductions)
+    mu2, _ = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_FP64)
+    assert torch.equal(mu, mu2)
+    sys_.free()
+    band.free()
+
+
+@pytest.mark.parametrize("name,lam,tol", [("sphere64", 10.0, 1e-6), ("sphere64", 1e5, 1e-6),
+                                          ("sphere64", 1e6, 1e-8)])
+def test_pcg_mixed(ctx, name, lam, tol):
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    wl = gc.workload(name)
+    ref = gc.oracle_ref(name)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, lam=lam)
+    diag = O.precision_diag(ref["Lambda"], ref["deg"], lam, wl.eps)
+    mu_ref, _ = O.pcg(ref["nbr"], diag, lam, ref["rhs"], 1e-12)
+    mu, rep = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_MIXED)
+    err = gc.rel_l2(mu.cpu().numpy(), mu_ref)
+    print(f"[mixed {name} lam={lam}] iters={rep['iters']} refinements={rep['refinements']} rel_res={rep['rel_res']:.2e} err={err:.2e}")
+    assert rep["status"] == 0 and rep["rel_res"] <= tol
+    assert err <= 1e-4
+    sys_.free()
+    band.free()
+
+
+def test_pcg_warm_start_and_zero_rhs(ctx):
+    import paper_2602_19697_amd as bf
+    wl = gc.workload("tiny")
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    mu, rep = ctx.bf_pcg_solve(sys_, 1e-10)
+    mu2, rep2 = ctx.bf_pcg_solve(sys_, 1e-8, x0=mu)
+    assert rep2["iters"] == 0 and torch.equal(mu, mu2)
+    zero = torch.zeros(band.n, dtype=torch.float64, device=gc.DEV)
+    x, rep3 = ctx.bf_pcg_solve(sys_, 1e-8, rhs=zero, x0=mu)
+    assert rep3["iters"] == 0 and torch.count_nonzero(x).item() == 0
+    _, rep4 = ctx.bf_pcg_solve(sys_, 1e-14, max_iter=1, allow_fail=True)
+    assert rep4["status"] == bf.L.BF_ERR_NOT_CONVERGED and rep4["iters"] == 1
+    sys_.free()
+    band.free()
+
+
+def test_invalid_depth_rejected(ctx):
+    import paper_2602_19697_amd as bf
+    wl = gc.workload("tiny")
+    depth, poses = gc.to_dev(wl)
+    depth[0, 3, 3] = float("nan")
+    g = bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band)
+    with pytest.raises(bf.BFError) as e:
+        ctx.bf_build_band(g, wl.cam, depth, poses)
+    assert e.value.status == bf.L.BF_ERR_INVALID_ARG
+    depth[0, 3, 3] = -1.0
+    with pytest.raises(bf.BFError):
+        ctx.bf_build_band(g, wl.cam, depth, poses)
+
+
+def test_empty_band(ctx):
+    import paper_2602_19697_amd as bf
+    wl = gc.workload("tiny")
+    depth, poses = gc.to_dev(wl)
+    depth.zero_()
+    g = bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band)
+    band = ctx.bf_build_band(g, wl.cam, depth, poses)
+    assert band.n == 0
+    sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, bf.noise_struct(), wl.lam, wl.eps)
+    x, rep = ctx.bf_pcg_solve(sys_, 1e-8)
+    assert x.numel() == 0 and rep["iters"] == 0
+    sys_.free()
+    band.free()
