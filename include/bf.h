@@ -233,6 +233,44 @@ bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
                        const bf_camera* ray_cam, int32_t utility, const bf_noise* noise,
                        int64_t* scores_dev, int32_t* best_host);
 
+/* ---------------------------------------------------------------- learned warm start */
+/* The paper names learned priors as future work (Sec. 6-7).  This extension
+ * proposes starting points only; every solve still runs CG to its tolerance.
+ * Network: 12 features -> 64 -> 64 -> 64 -> 2 with SiLU, BF16 weights on the
+ * matrix cores with FP32 accumulation.  params_dev is a float32 device vector
+ * of BF_MLP_PARAMS values: W1[64][12] b1[64] W2[64][64] b2[64] W3[64][64]
+ * b3[64] W4[2][64] b4[2] (BF_MLP_TRAIN trainable values), then the fixed
+ * input standardisation in_mean[12] in_std[12] and output scaling
+ * out_mean[2] out_std[2].  Outputs: o0 = (mu - rhs/diag) / h (the mean's
+ * correction to the Jacobi estimate, in voxels) and o1 = log(s * diag) (the
+ * variance relative to 1/diag). */
+enum { BF_MLP_TRAIN = 9282, BF_MLP_PARAMS = 9310 };
+
+/* feat_dev [N][12] float: TSDF/h, log(1+W), deg/6, n_obs/T, mean y/h,
+ * var y/h^2, mean sigma/h, min sigma/h, log(1 + Lambda h^2), and the TSDF
+ * central differences along x, y, z over 2h (own value where a band
+ * neighbour is absent). */
+bf_status bf_features(bf_ctx* ctx, const bf_system* sys, float* feat_dev);
+/* out_dev [n][2] = network outputs (physical units) for feat_dev [n][12]. */
+bf_status bf_mlp_forward(bf_ctx* ctx, const float* params_dev, const float* feat_dev, int64_t n,
+                         float* out_dev);
+/* Features -> network -> x0_dev [N] = rhs/diag + h*o0 (mean start) and
+ * logvar_dev [N] = o1 (probe start for bf_diag_estimate); either may be NULL. */
+bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const float* params_dev,
+                        const float* feat_dev, double* x0_dev, float* logvar_dev);
+/* Gradient of L = 1/(2M) sum_m |o_m - t_m|^2 (outputs and targets in the
+ * standardised units (t - out_mean) / out_std) over the batch rows idx_dev[M]
+ * of feat_dev [nrows][12] / target_dev [nrows][2]; rows outside [0, nrows)
+ * are skipped.  grad_dev [BF_MLP_TRAIN]; loss_dev (device float, may be NULL). */
+bf_status bf_mlp_grad(bf_ctx* ctx, const float* params_dev, const float* feat_dev,
+                      const float* target_dev, int64_t nrows, const int32_t* idx_dev, int64_t M,
+                      float* grad_dev, float* loss_dev);
+/* One Adam step (Kingma & Ba 2015, bias-corrected, step >= 1) on the
+ * trainable part of params_dev with moment vectors m_dev, v_dev. */
+bf_status bf_adam_step(bf_ctx* ctx, float* params_dev, float* m_dev, float* v_dev,
+                       const float* grad_dev, int32_t step, float lr, float beta1, float beta2,
+                       float eps);
+
 /* ---------------------------------------------------------------- instrumentation */
 
 /* Per-kernel device time, accumulated while timing is on: the library

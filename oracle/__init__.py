@@ -61,6 +61,8 @@ def lib():
                                      C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                      C.POINTER(C.c_int32)]
         L.orc_tsdf_dense.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, _D, _I32]
+        L.orc_tsdf_points.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, C.c_int64,
+                                      _I32, _D, _I32]
         L.orc_band.restype = C.c_int64
         L.orc_band.argtypes = [C.POINTER(Grid), _D, _I32, C.c_int64, C.c_void_p, C.c_void_p,
                                C.c_void_p]
@@ -136,6 +138,17 @@ def tsdf_voxel(g: Grid, cm: Cam, depth, c2w, i, j, k):
     lib().orc_tsdf_voxel(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64),
                          int(i), int(j), int(k), C.byref(t), C.byref(w))
     return t.value, w.value
+
+
+def tsdf_points(g: Grid, cm: Cam, depth, c2w, ijk):
+    """Coarse TSDF and weight of the voxels ijk [n][3] (single thread)."""
+    depth = _c(depth, np.float32)
+    ijk = _c(ijk, np.int32).reshape(-1, 3)
+    n = ijk.shape[0]
+    t = np.zeros(max(n, 1), dtype=np.float64)
+    w = np.zeros(max(n, 1), dtype=np.int32)
+    lib().orc_tsdf_points(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64), n, ijk, t, w)
+    return t[:n], w[:n]
 
 
 def tsdf_dense(g: Grid, cm: Cam, depth, c2w):

@@ -112,6 +112,13 @@ void orc_tsdf_dense(const orc_grid* g, const orc_cam* cam, int32_t T, const floa
       }
 }
 
+/* Coarse TSDF of a list of voxels ijk [n][3] (single thread). */
+void orc_tsdf_points(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
+                     const double* c2w, int64_t n, const int32_t* ijk, double* tsdf, int32_t* w) {
+  for (int64_t p = 0; p < n; ++p)
+    orc_tsdf_voxel(g, cam, T, depth, c2w, ijk[3 * p], ijk[3 * p + 1], ijk[3 * p + 2], &tsdf[p], &w[p]);
+}
+
 /* ------------------------------------------------------------------ */
 /* Narrow-band activation, eq. (1): B = { v : W(v) > 0, |TSDF(v)| <= band }.*/
 /* The band is listed in ascending Morton key (sorted with qsort).      */

@@ -53,6 +53,8 @@ void orc_tsdf_voxel(const orc_grid* g, const orc_cam* cam, int32_t T, const floa
                     const double* c2w, int32_t i, int32_t j, int32_t k, double* tsdf, int32_t* w);
 void orc_tsdf_dense(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
                     const double* c2w, double* tsdf, int32_t* w);
+void orc_tsdf_points(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
+                     const double* c2w, int64_t n, const int32_t* ijk, double* tsdf, int32_t* w);
 int64_t orc_band(const orc_grid* g, const double* tsdf_dense, const int32_t* w_dense, int64_t cap,
                  uint64_t* keys, double* tsdf, int32_t* w);
 void orc_neighbours(int32_t G, const uint64_t* keys, int64_t N, int32_t* nbr, int32_t* deg);

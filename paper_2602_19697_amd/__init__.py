@@ -228,6 +228,29 @@ class Context:
         self._check(self.lib.bf_features(self.handle, sys.handle, _ptr(f)))
         return f
 
+    # ---------------------------------------------------------- learned warm start
+    def bf_mlp_forward(self, params, feat):
+        out = torch.empty((feat.shape[0], 2), dtype=torch.float32, device=self.device)
+        self._check(self.lib.bf_mlp_forward(self.handle, _ptr(params), _ptr(feat), int(feat.shape[0]), _ptr(out)))
+        return out
+
+    def bf_warm_start(self, sys: System, params, feat, mean=True, logvar=True):
+        x0 = torch.empty(sys.n, dtype=torch.float64, device=self.device) if mean else None
+        lv = torch.empty(sys.n, dtype=torch.float32, device=self.device) if logvar else None
+        self._check(self.lib.bf_warm_start(self.handle, sys.handle, _ptr(params), _ptr(feat), _ptr(x0), _ptr(lv)))
+        return x0, lv
+
+    def bf_mlp_grad(self, params, feat, target, idx, grad=None, loss=None):
+        grad = grad if grad is not None else torch.empty(L.BF_MLP_TRAIN, dtype=torch.float32, device=self.device)
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=self.device)
+        self._check(self.lib.bf_mlp_grad(self.handle, _ptr(params), _ptr(feat), _ptr(target), int(feat.shape[0]),
+                                         _ptr(idx), int(idx.shape[0]), _ptr(grad), _ptr(loss)))
+        return grad, loss
+
+    def bf_adam_step(self, params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self._check(self.lib.bf_adam_step(self.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), int(step),
+                                          float(lr), float(beta1), float(beta2), float(eps)))
+
     # ---------------------------------------------------------- solves
     def bf_pcg_solve(self, sys: System, tol, max_iter=10000, precision=L.BF_PREC_FP64, x0=None,
                      rhs=None, check_every=0, out=None, allow_fail=False):

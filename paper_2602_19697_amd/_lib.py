@@ -22,6 +22,8 @@ BF_PREC_MIXED = 1
 BF_BAND_KEEP_DENSE = 1
 BF_UTILITY_SUM_VAR = 0
 BF_UTILITY_VAR_REDUCTION = 1
+BF_MLP_TRAIN = 9282
+BF_MLP_PARAMS = 9310
 
 
 class bf_grid(C.Structure):
@@ -102,6 +104,10 @@ SIGNATURES = {
                                    C.POINTER(bf_solve_report)]),
     "bf_nbv_score": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(bf_camera), C.c_int32,
                                C.POINTER(bf_noise), P, C.POINTER(C.c_int32)]),
+    "bf_mlp_forward": (C.c_int, [P, P, P, C.c_int64, P]),
+    "bf_warm_start": (C.c_int, [P, P, P, P, P, P]),
+    "bf_mlp_grad": (C.c_int, [P, P, P, P, C.c_int64, P, C.c_int64, P, P]),
+    "bf_adam_step": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]),
     "bf_set_timing": (C.c_int, [P, C.c_int32]),
     "bf_get_timings": (C.c_int, [P, C.POINTER(bf_kernel_time), C.c_int32, C.POINTER(C.c_int32)]),
 }

@@ -185,6 +185,7 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   bf_dev_free(ctx, band->hvals);
   bf_dev_free(ctx, band->dense_tsdf);
   bf_dev_free(ctx, band->dense_w);
+  bf_dev_free(ctx, band->bricks);
   delete band;
   return BF_OK;
 }

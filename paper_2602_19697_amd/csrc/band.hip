@@ -194,6 +194,17 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__
   deg[v] = d;
 }
 
+__global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__ keys, int64_t n, int shift,
+                                                    int nbrick, uint32_t* __restrict__ bits) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const uint32_t bi = bf_compact3(key) >> shift, bj = bf_compact3(key >> 1) >> shift,
+                 bk = bf_compact3(key >> 2) >> shift;
+  const uint32_t bit = (bk * nbrick + bj) * nbrick + bi;
+  atomicOr(&bits[bit >> 5], 1u << (bit & 31));
+}
+
 }  // namespace
 
 extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
@@ -302,6 +313,18 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
                        band->hvals, log2cap, max_probe, dflags);
     BF_LAUNCH(ctx, "neighbours", k_neighbours, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, grid->G,
                        band->hkeys, band->hvals, log2cap, band->hcap, band->nbr, band->deg);
+    // brick occupancy bitmap for the ray walker: brick edge 2^shift with at
+    // most 64 bricks per axis
+    int shift = 2;
+    while ((band->P >> shift) > 64) ++shift;
+    band->brick_shift = shift;
+    band->nbrick = std::max(1, band->P >> shift);
+    const size_t words = ((size_t)band->nbrick * band->nbrick * band->nbrick + 31) / 32;
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->bricks, words * 4)) return fail(s);
+    if (hipMemsetAsync(band->bricks, 0, words * 4, ctx->stream) != hipSuccess)
+      return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
+    BF_LAUNCH(ctx, "brick_bits", k_brick_bits, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, shift, band->nbrick,
+              band->bricks);
     if (bf_status s = bf_launch_check(ctx, "hash/neighbours")) return fail(s);
     if (hipMemcpyAsync(pin, scan_ws, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)

@@ -24,7 +24,7 @@ struct BState {
   double inner2;
   int32_t active[kMaxK], check[kMaxK], last[kMaxK], iters[kMaxK], status[kMaxK];
   int32_t nactive, any_check, max_iter, replace_every, K, refinements;
-  uint32_t counter, pad_;
+  int32_t pad_[2];
 };
 
 enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
@@ -57,7 +57,6 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, i
     st->replace_every = replace_every;
     st->K = K;
     st->refinements = 0;
-    st->counter = 0;
   }
 }
 
@@ -84,30 +83,18 @@ __device__ __forceinline__ void col_block_sum(double (&v)[NQ], double* lds /*[4]
     }
 }
 
-// Last block: column sums over all block partials part[nb][NQ][KC]; result
-// for column c in tot[q] of thread c (< KC).
+// Column c's sums over all block partials part[nb][NQ][KC], computed by one
+// workgroup per column in a fixed order; the result is returned to every
+// thread of the workgroup.
 template <int KC, int NQ>
-__device__ __forceinline__ void col_partials_sum(const double* __restrict__ part, int nb, double (&tot)[NQ],
+__device__ __forceinline__ void col_partials_sum(const double* __restrict__ part, int nb, int c, double (&tot)[NQ],
                                                  double* lds) {
-  constexpr int G = kThreads / KC;
-  const int c = threadIdx.x % KC, g = threadIdx.x / KC;
-  double acc[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  for (int b = g; b < nb; b += G)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += part[((size_t)b * NQ + q) * KC + c];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) lds[(q * G + g) * KC + c] = acc[q];
-  __syncthreads();
-  if (threadIdx.x < KC)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = 0.0;
-      for (int gg = 0; gg < G; ++gg) s += lds[(q * G + gg) * KC + threadIdx.x];
-      tot[q] = s;
-    }
+  for (int q = 0; q < NQ; ++q) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[((size_t)b * NQ + q) * KC + c];
+    tot[q] = bf_block_sum(acc, lds);
+  }
 }
 
 template <int KC, int NQ>
@@ -124,7 +111,6 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
                                             const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
                                             int64_t n, double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
-  __shared__ int flag;
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
   constexpr int RS = kThreads / KC;
@@ -154,20 +140,26 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   }
   col_block_sum<KC, 1>(v1, lds);
   store_partials<KC, 1>(part, v1);
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// Per-column alpha from A's block partials (one workgroup per column).
+template <int KC>
+__global__ __launch_bounds__(256) void k_bscal_A(BState* __restrict__ st, const double* __restrict__ part, int nb) {
+  __shared__ double lds[16];
+  const int c = blockIdx.x;
+  if (c == 0 && threadIdx.x == 0) st->any_check = 0;  // consumed by the previous check, if any
+  if (!st->active[c]) return;
   double tot[1];
-  col_partials_sum<KC, 1>(part, gridDim.x, tot, lds);
-  if (threadIdx.x < KC && st->active[threadIdx.x]) {
-    const int cc = threadIdx.x;
+  col_partials_sum<KC, 1>(part, nb, c, tot, lds);
+  if (threadIdx.x == 0) {
     if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-      st->status[cc] = BF_ERR_BREAKDOWN;
-      st->active[cc] = 0;
+      st->status[c] = BF_ERR_BREAKDOWN;
+      st->active[c] = 0;
       atomicSub(&st->nactive, 1);
     } else {
-      st->alpha[cc] = st->rho[cc] / tot[0];
+      st->alpha[c] = st->rho[c] / tot[0];
     }
   }
-  if (threadIdx.x == 0) st->counter = 0;
 }
 
 // B: x += alpha p, r -= alpha q, zz = r / diag, partials r.zz and r.r.
@@ -177,7 +169,6 @@ __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __
                                             V* __restrict__ r, V* __restrict__ zz, int64_t n,
                                             double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
-  __shared__ int flag;
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
   constexpr int RS = kThreads / KC;
@@ -202,35 +193,33 @@ __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __
   }
   col_block_sum<KC, 2>(v2, lds);
   store_partials<KC, 2>(part, v2);
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// Per-column beta or residual-check request from B's block partials.
+template <int KC>
+__global__ __launch_bounds__(256) void k_bscal_B(BState* __restrict__ st, const double* __restrict__ part, int nb) {
+  __shared__ double lds[16];
+  const int c = blockIdx.x;
+  if (!st->active[c]) return;
   double tot[2];
-  col_partials_sum<KC, 2>(part, gridDim.x, tot, lds);
-  __shared__ int any;
-  if (threadIdx.x == 0) any = 0;
-  __syncthreads();
-  if (threadIdx.x < KC && st->active[threadIdx.x]) {
-    const int cc = threadIdx.x;
-    const int it = st->iters[cc] + 1;
-    st->iters[cc] = it;
+  col_partials_sum<KC, 2>(part, nb, c, tot, lds);
+  if (threadIdx.x == 0) {
+    const int it = st->iters[c] + 1;
+    st->iters[c] = it;
     const bool at_max = it >= st->max_iter;
     const bool periodic = st->replace_every > 0 && (it % st->replace_every) == 0;
     if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-      st->status[cc] = BF_ERR_BREAKDOWN;
-      st->active[cc] = 0;
+      st->status[c] = BF_ERR_BREAKDOWN;
+      st->active[c] = 0;
       atomicSub(&st->nactive, 1);
-    } else if (tot[1] <= fmax(st->tol2b[cc], st->inner2 * st->rr_ref[cc]) || at_max || periodic) {
-      st->check[cc] = 1;
-      st->last[cc] = at_max ? 1 : 0;
-      atomicOr(&any, 1);
+    } else if (tot[1] <= fmax(st->tol2b[c], st->inner2 * st->rr_ref[c]) || at_max || periodic) {
+      st->check[c] = 1;
+      st->last[c] = at_max ? 1 : 0;
+      atomicOr(&st->any_check, 1);
     } else {
-      st->beta[cc] = tot[0] / st->rho[cc];
-      st->rho[cc] = tot[0];
+      st->beta[c] = tot[0] / st->rho[c];
+      st->rho[c] = tot[0];
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    st->any_check = any;
-    st->counter = 0;
   }
 }
 
@@ -263,7 +252,6 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
                                                 V* __restrict__ r, V* __restrict__ zz, int64_t n,
                                                 double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
-  __shared__ int flag;
   if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
   const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
   constexpr int RS = kThreads / KC;
@@ -318,55 +306,57 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   }
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, v3);
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// Per-column decisions after an FP64 residual (one workgroup per column).
+template <int KC>
+__global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mode, const double* __restrict__ part,
+                                                 int nb) {
+  __shared__ double lds[16];
+  const int cc = blockIdx.x;
+  if (mode == MODE_CHECK && !(st->active[cc] && st->check[cc])) return;
+  if (mode == MODE_REPORT && cc >= st->K) return;
+  if (mode == MODE_INIT && !st->active[cc]) return;
   double tot[3];
-  col_partials_sum<KC, 3>(part, gridDim.x, tot, lds);
-  if (threadIdx.x < KC) {
-    const int cc = threadIdx.x;
-    if (mode == MODE_REPORT) {
-      if (cc < st->K) st->rr_true[cc] = tot[0];
-    } else if (mode == MODE_INIT) {
-      if (st->active[cc]) {
-        st->bnorm2[cc] = tot[2];
-        st->tol2b[cc] *= tot[2];
-        st->rr_true[cc] = tot[0];
-        if (tot[2] == 0.0 || tot[0] <= st->tol2b[cc] || st->max_iter <= 0) {
-          if (!(tot[2] == 0.0 || tot[0] <= st->tol2b[cc])) st->status[cc] = BF_ERR_NOT_CONVERGED;
-          st->active[cc] = 0;
-          atomicSub(&st->nactive, 1);
-        } else {
-          st->rho[cc] = tot[1];
-          st->beta[cc] = 0.0;
-          st->rr_ref[cc] = tot[0];
-        }
-      }
-    } else if (st->active[cc] && st->check[cc]) {
-      st->rr_true[cc] = tot[0];
-      atomicAdd(&st->refinements, 1);
-      if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-        st->status[cc] = BF_ERR_BREAKDOWN;
-        st->active[cc] = 0;
-        atomicSub(&st->nactive, 1);
-      } else if (tot[0] <= st->tol2b[cc]) {
-        st->active[cc] = 0;
-        atomicSub(&st->nactive, 1);
-      } else if (st->last[cc]) {
-        st->status[cc] = BF_ERR_NOT_CONVERGED;
-        st->active[cc] = 0;
-        atomicSub(&st->nactive, 1);
-      } else {
-        // FP64 continues CG from the replaced residual; mixed restarts the
-        // float solve on the FP64 residual (iterative refinement).
-        st->beta[cc] = st->inner2 > 0.0 ? 0.0 : tot[1] / st->rho[cc];
-        st->rho[cc] = tot[1];
-        st->rr_ref[cc] = tot[0];
-      }
-      st->check[cc] = 0;
+  col_partials_sum<KC, 3>(part, nb, cc, tot, lds);
+  if (threadIdx.x != 0) return;
+  if (mode == MODE_REPORT) {
+    st->rr_true[cc] = tot[0];
+  } else if (mode == MODE_INIT) {
+    st->bnorm2[cc] = tot[2];
+    st->tol2b[cc] *= tot[2];
+    st->rr_true[cc] = tot[0];
+    if (tot[2] == 0.0 || tot[0] <= st->tol2b[cc] || st->max_iter <= 0) {
+      if (!(tot[2] == 0.0 || tot[0] <= st->tol2b[cc])) st->status[cc] = BF_ERR_NOT_CONVERGED;
+      st->active[cc] = 0;
+      atomicSub(&st->nactive, 1);
+    } else {
+      st->rho[cc] = tot[1];
+      st->beta[cc] = 0.0;
+      st->rr_ref[cc] = tot[0];
     }
-  }
-  if (threadIdx.x == 0) {
-    st->any_check = 0;
-    st->counter = 0;
+  } else {
+    st->rr_true[cc] = tot[0];
+    atomicAdd(&st->refinements, 1);
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+      st->status[cc] = BF_ERR_BREAKDOWN;
+      st->active[cc] = 0;
+      atomicSub(&st->nactive, 1);
+    } else if (tot[0] <= st->tol2b[cc]) {
+      st->active[cc] = 0;
+      atomicSub(&st->nactive, 1);
+    } else if (st->last[cc]) {
+      st->status[cc] = BF_ERR_NOT_CONVERGED;
+      st->active[cc] = 0;
+      atomicSub(&st->nactive, 1);
+    } else {
+      // FP64 continues CG from the replaced residual; mixed restarts the
+      // float solve on the FP64 residual (iterative refinement).
+      st->beta[cc] = st->inner2 > 0.0 ? 0.0 : tot[1] / st->rho[cc];
+      st->rho[cc] = tot[1];
+      st->rr_ref[cc] = tot[0];
+    }
+    st->check[cc] = 0;
   }
 }
 
@@ -426,6 +416,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cc, N * KC, 0.0f);
   BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->band->nbr,
                      sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
+  BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
   BF_TRY(bf_pinned(ctx, sizeof(BState), (void**)&hs));
@@ -437,11 +428,14 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     for (; it < upto; ++it) {
       BF_LAUNCH(ctx, "block_A", (k_bA<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
                          zz, pa, pb, q, N, part);
+      BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N,
                          part);
+      BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cc, N);
       BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
                          sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+      BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "block pcg iteration"));
@@ -457,6 +451,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // final FP64 residual of every probe column for the report
   BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
                      sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+  BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
   BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   float ms = 0.0f;

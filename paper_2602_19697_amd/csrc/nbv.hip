@@ -18,10 +18,11 @@ namespace {
 constexpr int kThreads = 256;
 constexpr double kScale = 4294967296.0;  // 2^32
 
-__global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64_t n, double* __restrict__ part,
-                                             double* __restrict__ out, unsigned int* __restrict__ counter) {
-  __shared__ double lds[16];
-  __shared__ int flag;
+// max(0, max_v s_v): non-negative doubles order like their bit patterns, so an
+// integer atomic max on the bits is exact and order independent.
+__global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64_t n,
+                                             unsigned long long* __restrict__ out_bits) {
+  __shared__ double lds[kThreads / 64];
   double m = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
     m = fmax(m, s[i]);
@@ -31,14 +32,7 @@ __global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64
   if (threadIdx.x == 0) {
     double b = 0.0;
     for (int w = 0; w < kThreads / 64; ++w) b = fmax(b, lds[w]);
-    part[blockIdx.x] = b;
-  }
-  if (!bf_last_block(counter, &flag)) return;
-  if (threadIdx.x == 0) {
-    double b = 0.0;
-    for (unsigned i = 0; i < gridDim.x; ++i) b = fmax(b, part[i]);
-    *out = b;
-    *counter = 0;
+    atomicMax(out_bits, (unsigned long long)__double_as_longlong(b));
   }
 }
 
@@ -58,13 +52,17 @@ struct ray_k {
   uint64_t hcap;
   int utility;
   double na, nc, nz0;  // sensor model for the variance-reduction utility
+  int brick_shift, nbrick;
+  int64_t tiles_per_cand, ntiles;
 };
+
+constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
 
 // Walk of one ray; returns the ray's integer utility.
 __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t row, int32_t col,
                         const uint64_t* __restrict__ hkeys, const int32_t* __restrict__ hvals,
                         const double* __restrict__ mu, const double* __restrict__ s, const int64_t* __restrict__ q,
-                        double smax) {
+                        double smax, const uint32_t* __restrict__ bricks) {
 #pragma clang fp contract(off)
   const bf_grid_k& g = R.g;
   const double o[3] = {P[3], P[7], P[11]};
@@ -111,7 +109,12 @@ __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t ro
   int64_t score = 0;
   const int64_t max_steps = 3 * (int64_t)g.G + 3;
   for (int64_t it = 0; it < max_steps; ++it) {
-    const int32_t v = bf_hash_find(hkeys, hvals, R.log2cap, R.hcap, bf_morton(idx[0], idx[1], idx[2]));
+    // only voxels of occupied bricks can be band voxels: look those up
+    const uint32_t bit = (((uint32_t)idx[2] >> R.brick_shift) * R.nbrick + ((uint32_t)idx[1] >> R.brick_shift)) *
+                             R.nbrick + ((uint32_t)idx[0] >> R.brick_shift);
+    const int32_t v = ((bricks[bit >> 5] >> (bit & 31)) & 1u)
+                          ? bf_hash_find(hkeys, hvals, R.log2cap, R.hcap, bf_morton(idx[0], idx[1], idx[2]))
+                          : -1;
     if (v >= 0) {
       if (R.utility == BF_UTILITY_SUM_VAR) {
         score += q[v];
@@ -140,29 +143,39 @@ __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t ro
   return score;
 }
 
-// grid: (ray tiles, candidates); one thread per ray.
+// Persistent grid over (candidate, ray tile) work items; one thread per ray.
+// Every workgroup stages the brick bitmap in LDS once.
 __global__ __launch_bounds__(256) void k_nbv_rays(ray_k R, const double* __restrict__ cands,
                                                   const uint64_t* __restrict__ hkeys,
                                                   const int32_t* __restrict__ hvals, const double* __restrict__ mu,
                                                   const double* __restrict__ s, const int64_t* __restrict__ q,
                                                   const double* __restrict__ smax_p,
+                                                  const uint32_t* __restrict__ bricks_g,
                                                   unsigned long long* __restrict__ scores) {
+  __shared__ uint32_t bricks[kMaxBrickWords];
   __shared__ long long lds[kThreads / 64];
-  const int cand = blockIdx.y;
-  const int64_t npix = (int64_t)R.cam.W * R.cam.H;
-  const int64_t pix = blockIdx.x * (int64_t)kThreads + threadIdx.x;
-  long long sc = 0;
-  if (pix < npix) {
-    const int32_t row = (int32_t)(pix / R.cam.W), col = (int32_t)(pix % R.cam.W);
-    sc = walk(R, cands + 12 * (int64_t)cand, row, col, hkeys, hvals, mu, s, q, *smax_p);
-  }
-  for (int off = 32; off > 0; off >>= 1) sc += __shfl_xor(sc, off, 64);
-  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = sc;
+  const int words = (R.nbrick * R.nbrick * R.nbrick + 31) / 32;
+  for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
   __syncthreads();
-  if (threadIdx.x == 0) {
-    long long t = 0;
-    for (int w = 0; w < kThreads / 64; ++w) t += lds[w];
-    atomicAdd(&scores[cand], (unsigned long long)t);  // two's complement: exact for signed sums
+  const double smax = *smax_p;
+  const int64_t npix = (int64_t)R.cam.W * R.cam.H;
+  for (int64_t tile = blockIdx.x; tile < R.ntiles; tile += gridDim.x) {
+    const int64_t cand = tile / R.tiles_per_cand;
+    const int64_t pix = (tile % R.tiles_per_cand) * kThreads + threadIdx.x;
+    long long sc = 0;
+    if (pix < npix) {
+      const int32_t row = (int32_t)(pix / R.cam.W), col = (int32_t)(pix % R.cam.W);
+      sc = walk(R, cands + 12 * cand, row, col, hkeys, hvals, mu, s, q, smax, bricks);
+    }
+    for (int off = 32; off > 0; off >>= 1) sc += __shfl_xor(sc, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = sc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      long long t = 0;
+      for (int w = 0; w < kThreads / 64; ++w) t += lds[w];
+      atomicAdd(&scores[cand], (unsigned long long)t);  // two's complement: exact for signed sums
+    }
   }
 }
 
@@ -214,20 +227,18 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   BF_CHECK(ctx, cand_c2w_dev && scores_dev, "bf_nbv_score: NULL candidates or scores");
   BF_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t N = band->n;
-  // workspace: counter | smax | best | partials [nb] | q [N]
+  // workspace: smax | best | q [N]
   const int nbm = (int)std::max<int64_t>(1, std::min<int64_t>(bf_cdiv(N, kThreads), 1024));
   char* ws = nullptr;
-  BF_TRY(bf_ws(ctx, bf_ctx::WS_NBV, 256 + nbm * 8 + N * 8 + 256, (void**)&ws));
-  unsigned int* counter = (unsigned int*)ws;
-  double* smax = (double*)(ws + 8);
-  int32_t* dbest = (int32_t*)(ws + 16);
-  double* part = (double*)(ws + 256);
-  int64_t* q = (int64_t*)(ws + 256 + ((nbm * 8 + 255) / 256) * 256);
-  BF_HIP(ctx, hipMemsetAsync(ws, 0, 24, ctx->stream));
+  BF_TRY(bf_ws(ctx, bf_ctx::WS_NBV, 256 + N * 8, (void**)&ws));
+  double* smax = (double*)ws;
+  int32_t* dbest = (int32_t*)(ws + 8);
+  int64_t* q = (int64_t*)(ws + 256);
+  BF_HIP(ctx, hipMemsetAsync(ws, 0, 16, ctx->stream));
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, ctx->stream, scores_dev, n_cand);
   if (N > 0) {
     BF_CHECK(ctx, mu_dev && s_dev, "bf_nbv_score: NULL mu or s");
-    hipLaunchKernelGGL(k_max, dim3(nbm), dim3(kThreads), 0, ctx->stream, s_dev, N, part, smax, counter);
+    hipLaunchKernelGGL(k_max, dim3(nbm), dim3(kThreads), 0, ctx->stream, s_dev, N, (unsigned long long*)smax);
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)bf_cdiv(N, kThreads)), dim3(kThreads), 0, ctx->stream, s_dev, N,
                        smax, q);
     int l2 = 0;
@@ -244,9 +255,13 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
       R.nz0 = noise->z0;
     }
     const int64_t npix = (int64_t)ray_cam->width * ray_cam->height;
-    dim3 grid((unsigned)bf_cdiv(npix, kThreads), (unsigned)n_cand);
-    BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays, grid, dim3(kThreads), 0, R, cand_c2w_dev, band->hkeys, band->hvals,
-                       mu_dev, s_dev, q, smax, (unsigned long long*)scores_dev);
+    R.brick_shift = band->brick_shift;
+    R.nbrick = band->nbrick;
+    R.tiles_per_cand = bf_cdiv(npix, kThreads);
+    R.ntiles = R.tiles_per_cand * n_cand;
+    const unsigned grid = (unsigned)std::min<int64_t>(R.ntiles, 16 * (int64_t)ctx->cu_count);
+    BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev, band->hkeys,
+              band->hvals, mu_dev, s_dev, q, smax, band->bricks, (unsigned long long*)scores_dev);
   }
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, ctx->stream, scores_dev, n_cand, dbest);
   BF_TRY(bf_launch_check(ctx, "nbv"));

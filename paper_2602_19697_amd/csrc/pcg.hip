@@ -16,7 +16,10 @@
 // 1e6-fold (or below the tolerance); the float solve then restarts on the FP64
 // residual (mixed-precision iterative refinement).
 // Reductions are deterministic: fixed-order wave butterflies, a fixed block
-// tree and a fixed-order sum of the block partials.
+// tree and a fixed-order sum of the block partials.  The scalar step runs in
+// its own one-workgroup kernel: a "last block done" epilogue would need a
+// device-scope release fence in every workgroup, which on this chip writes
+// back the XCD's L2 each time.
 #include "bf_internal.h"
 
 namespace {
@@ -26,7 +29,7 @@ constexpr int kThreads = 256;
 struct PcgState {
   double rho, alpha, beta, tol2b, bnorm2, rr, rr_true, rho_new, inner2, rr_ref;
   int32_t iters, done, check, status, last, refinements, max_iter, replace_every;
-  uint32_t counter, pad_;
+  int32_t pad_[2];
 };
 
 enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
@@ -69,7 +72,6 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
                                                const V* __restrict__ p_old, V* __restrict__ p_new,
                                                V* __restrict__ q, int64_t n, double* __restrict__ part) {
   __shared__ double lds[16];
-  __shared__ int flag;
   if (st->done) return;
   const V beta = (V)st->beta;
   const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
@@ -90,11 +92,16 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
   }
   pq = bf_block_sum(pq, lds);
   if (threadIdx.x == 0) part[blockIdx.x] = pq;
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// alpha = rho / p.q from A's block partials (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void k_pcg_alpha(PcgState* __restrict__ st, const double* __restrict__ part,
+                                                   int nb) {
+  __shared__ double lds[16];
+  if (st->done) return;
   double tot;
-  reduce_partials<1>(part, gridDim.x, &tot, lds);
+  reduce_partials<1>(part, nb, &tot, lds);
   if (threadIdx.x == 0) {
-    st->counter = 0;
     if (!(tot > 0.0) || !isfinite(tot)) {
       st->status = BF_ERR_BREAKDOWN;
       st->done = 1;
@@ -111,7 +118,6 @@ __global__ __launch_bounds__(256) void k_pcg_B(PcgState* __restrict__ st, const 
                                                V* __restrict__ x, V* __restrict__ r, V* __restrict__ z,
                                                int64_t n, double* __restrict__ part) {
   __shared__ double lds[16];
-  __shared__ int flag;
   if (st->done) return;
   const V alpha = (V)st->alpha;
   const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
@@ -131,11 +137,16 @@ __global__ __launch_bounds__(256) void k_pcg_B(PcgState* __restrict__ st, const 
     part[2 * blockIdx.x] = rz;
     part[2 * blockIdx.x + 1] = rr;
   }
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// beta, or a request for an FP64 residual check, from B's block partials.
+__global__ __launch_bounds__(256) void k_pcg_beta(PcgState* __restrict__ st, const double* __restrict__ part,
+                                                  int nb) {
+  __shared__ double lds[16];
+  if (st->done) return;
   double tot[2];
-  reduce_partials<2>(part, gridDim.x, tot, lds);
+  reduce_partials<2>(part, nb, tot, lds);
   if (threadIdx.x == 0) {
-    st->counter = 0;
     st->iters += 1;
     st->rr = tot[1];
     const bool at_max = st->iters >= st->max_iter;
@@ -176,7 +187,6 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
                                                   V* __restrict__ r, V* __restrict__ z, int64_t n,
                                                   double* __restrict__ part) {
   __shared__ double lds[16];
-  __shared__ int flag;
   if (mode == MODE_CHECK && (st->done || !st->check)) return;
   const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   double rr = 0.0, rz = 0.0, bb = 0.0;
@@ -211,11 +221,16 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
     part[3 * blockIdx.x + 1] = rz;
     part[3 * blockIdx.x + 2] = bb;
   }
-  if (!bf_last_block(&st->counter, &flag)) return;
+}
+
+// Decisions after an FP64 residual: stop, or continue / restart from it.
+__global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__ st, int mode,
+                                                          const double* __restrict__ part, int nb) {
+  __shared__ double lds[16];
+  if (mode == MODE_CHECK && (st->done || !st->check)) return;
   double tot[3];
-  reduce_partials<3>(part, gridDim.x, tot, lds);
+  reduce_partials<3>(part, nb, tot, lds);
   if (threadIdx.x != 0) return;
-  st->counter = 0;
   st->rr_true = tot[0];
   if (mode == MODE_REPORT) return;
   if (mode == MODE_INIT) {
@@ -295,6 +310,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
                      sys->band->nbr, sys->diag, sys->lambda, rhs, o->use_x0 ? (const double*)x : nullptr, dinvV,
                      r, z, N, part);
+  BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "pcg init"));
 
   PcgState* hs = nullptr;
@@ -309,12 +325,15 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     for (; it < upto; ++it) {
       BF_LAUNCH(ctx, "pcg_A", k_pcg_A<V>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, z,
                          pa, pb, q, N, part);
+      BF_LAUNCH(ctx, "pcg_scalars", k_pcg_alpha, dim3(1), dim3(256), 0, st, part, nb);
       BF_LAUNCH(ctx, "pcg_B", k_pcg_B<V>, dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, z, N,
                          part);
+      BF_LAUNCH(ctx, "pcg_scalars", k_pcg_beta, dim3(1), dim3(256), 0, st, part, nb);
       if (mixed)
         BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 0, x, c, N);
       BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
                          sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+      BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "pcg iteration"));
@@ -326,6 +345,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   if (mixed) BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
   BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
                      sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+  BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
   BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
   BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
