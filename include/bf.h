@@ -233,6 +233,38 @@ bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
                        const bf_camera* ray_cam, int32_t utility, const bf_noise* noise,
                        int64_t* scores_dev, int32_t* best_host);
 
+/* ---------------------------------------------------------------- batched solves */
+/* Many systems (scenes of uneven band size) solved in ONE persistent launch:
+ * the work list is every system's row tiles in the schedule's order, walked by
+ * a grid of co-resident workgroups that meet at grid barriers between CG
+ * phases; every system and probe column keeps its own scalars and stopping
+ * test, and converged systems leave the work list.  Results equal the
+ * single-system calls up to the order of the dot-product reductions. */
+enum { BF_ORDER_SCENE_MAJOR = 0, BF_ORDER_INTERLEAVED = 1, BF_ORDER_LARGEST_FIRST = 2 };
+typedef struct bf_schedule {
+  int32_t rows_per_tile;  /* band rows per work item, 16..4096 */
+  int32_t blocks_per_cu;  /* persistent workgroups per CU (0 = as many as fit) */
+  int32_t order;          /* BF_ORDER_* tile order across systems */
+  int32_t xcd_aware;      /* 1: contiguous runs of tiles stay on one XCD's workgroups */
+} bf_schedule;
+
+/* Hutchinson probes (as bf_diag_estimate, no warm start) for n_sys systems;
+ * s_dev[i] receives system i's estimate, reps[i] (host, may be NULL) its
+ * report.  sched NULL = a default schedule.  Synchronises. */
+bf_status bf_diag_estimate_batched(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
+                                   const bf_probe_opts* opts, const bf_schedule* sched,
+                                   double* const* s_dev, bf_solve_report* reps);
+/* Posterior means (as bf_pcg_solve from x = 0 with each system's rhs). */
+bf_status bf_pcg_solve_batched(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
+                               const bf_solve_opts* opts, const bf_schedule* sched,
+                               double* const* x_dev, bf_solve_report* reps);
+/* Times every candidate schedule (rows per tile x blocks per CU x order x
+ * XCD mapping) on the batched probe solve and returns the fastest in *best;
+ * json (host, may be NULL) receives every candidate's time as a JSON array. */
+bf_status bf_autotune_batch(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
+                            const bf_probe_opts* opts, double* const* s_dev, bf_schedule* best,
+                            char* json, size_t json_len);
+
 /* ---------------------------------------------------------------- learned warm start */
 /* The paper names learned priors as future work (Sec. 6-7).  This extension
  * proposes starting points only; every solve still runs CG to its tolerance.

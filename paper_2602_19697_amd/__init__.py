@@ -228,6 +228,54 @@ class Context:
         self._check(self.lib.bf_features(self.handle, sys.handle, _ptr(f)))
         return f
 
+    # ---------------------------------------------------------- batched solves
+    @staticmethod
+    def schedule(rows_per_tile=256, blocks_per_cu=0, order=L.BF_ORDER_SCENE_MAJOR, xcd_aware=1):
+        s = L.bf_schedule()
+        s.rows_per_tile, s.blocks_per_cu, s.order, s.xcd_aware = rows_per_tile, blocks_per_cu, order, xcd_aware
+        return s
+
+    def _batch_args(self, systems, outs):
+        n = len(systems)
+        sys_arr = (C.c_void_p * n)(*[s.handle.value if isinstance(s.handle, C.c_void_p) else s.handle
+                                     for s in systems])
+        out_arr = (C.c_void_p * n)(*[o.data_ptr() for o in outs])
+        reps = (L.bf_solve_report * n)()
+        return n, sys_arr, out_arr, reps
+
+    def bf_diag_estimate_batched(self, systems, K, seed, tol, max_iter=10000, precision=L.BF_PREC_MIXED,
+                                 schedule=None, allow_fail=False):
+        o = L.bf_probe_opts()
+        o.K, o.precision, o.seed, o.tol, o.max_iter = int(K), int(precision), int(seed), float(tol), int(max_iter)
+        outs = [torch.empty(s.n, dtype=torch.float64, device=self.device) for s in systems]
+        n, sa, oa, reps = self._batch_args(systems, outs)
+        st = self.lib.bf_diag_estimate_batched(self.handle, sa, n, C.byref(o),
+                                               C.byref(schedule) if schedule is not None else None, oa, reps)
+        self._check(st, allow=(L.BF_ERR_NOT_CONVERGED, L.BF_ERR_BREAKDOWN) if allow_fail else ())
+        return outs, [r.as_dict() for r in reps]
+
+    def bf_pcg_solve_batched(self, systems, tol, max_iter=10000, precision=L.BF_PREC_MIXED, schedule=None,
+                             allow_fail=False):
+        o = L.bf_solve_opts()
+        o.tol, o.max_iter, o.precision, o.use_x0, o.check_every = float(tol), int(max_iter), int(precision), 0, 0
+        outs = [torch.empty(s.n, dtype=torch.float64, device=self.device) for s in systems]
+        n, sa, oa, reps = self._batch_args(systems, outs)
+        st = self.lib.bf_pcg_solve_batched(self.handle, sa, n, C.byref(o),
+                                           C.byref(schedule) if schedule is not None else None, oa, reps)
+        self._check(st, allow=(L.BF_ERR_NOT_CONVERGED, L.BF_ERR_BREAKDOWN) if allow_fail else ())
+        return outs, [r.as_dict() for r in reps]
+
+    def bf_autotune_batch(self, systems, K, seed, tol, max_iter=10000, precision=L.BF_PREC_MIXED):
+        import json as _json
+        o = L.bf_probe_opts()
+        o.K, o.precision, o.seed, o.tol, o.max_iter = int(K), int(precision), int(seed), float(tol), int(max_iter)
+        outs = [torch.empty(s.n, dtype=torch.float64, device=self.device) for s in systems]
+        n, sa, oa, _ = self._batch_args(systems, outs)
+        best = L.bf_schedule()
+        buf = C.create_string_buffer(1 << 16)
+        self._check(self.lib.bf_autotune_batch(self.handle, sa, n, C.byref(o), oa, C.byref(best), buf, len(buf)))
+        return best, _json.loads(buf.value.decode())
+
     # ---------------------------------------------------------- learned warm start
     def bf_mlp_forward(self, params, feat):
         out = torch.empty((feat.shape[0], 2), dtype=torch.float32, device=self.device)

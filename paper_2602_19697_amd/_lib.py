@@ -22,6 +22,9 @@ BF_PREC_MIXED = 1
 BF_BAND_KEEP_DENSE = 1
 BF_UTILITY_SUM_VAR = 0
 BF_UTILITY_VAR_REDUCTION = 1
+BF_ORDER_SCENE_MAJOR = 0
+BF_ORDER_INTERLEAVED = 1
+BF_ORDER_LARGEST_FIRST = 2
 BF_MLP_TRAIN = 9282
 BF_MLP_PARAMS = 9310
 
@@ -64,6 +67,14 @@ class bf_probe_opts(C.Structure):
                 ("tol", C.c_double), ("max_iter", C.c_int32)]
 
 
+class bf_schedule(C.Structure):
+    _fields_ = [("rows_per_tile", C.c_int32), ("blocks_per_cu", C.c_int32), ("order", C.c_int32),
+                ("xcd_aware", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class bf_band_arrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("dense_side", C.c_int32), ("keys", C.c_void_p),
                 ("tsdf", C.c_void_p), ("w", C.c_void_p), ("nbr", C.c_void_p), ("deg", C.c_void_p),
@@ -104,6 +115,12 @@ SIGNATURES = {
                                    C.POINTER(bf_solve_report)]),
     "bf_nbv_score": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(bf_camera), C.c_int32,
                                C.POINTER(bf_noise), P, C.POINTER(C.c_int32)]),
+    "bf_diag_estimate_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_probe_opts), C.POINTER(bf_schedule),
+                                           P, C.POINTER(bf_solve_report)]),
+    "bf_pcg_solve_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_solve_opts), C.POINTER(bf_schedule), P,
+                                       C.POINTER(bf_solve_report)]),
+    "bf_autotune_batch": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_probe_opts), P, C.POINTER(bf_schedule),
+                                    C.c_char_p, C.c_size_t]),
     "bf_mlp_forward": (C.c_int, [P, P, P, C.c_int64, P]),
     "bf_warm_start": (C.c_int, [P, P, P, P, P, P]),
     "bf_mlp_grad": (C.c_int, [P, P, P, P, C.c_int64, P, C.c_int64, P, P]),

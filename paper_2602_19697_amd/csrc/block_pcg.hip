@@ -4,107 +4,26 @@
 // Layout: block vectors are row-major [N][KC] (KC = K rounded up to 16, 32 or
 // 64), so one band voxel's K values are contiguous: the stencil gathers of a
 // neighbour row are coalesced and the neighbour table and diagonal are read
-// once per row for all K columns.  A thread owns one column, a workgroup a
-// tile of rows; every column keeps its own FP64 alpha, beta and stopping test
-// (independent CGs sharing each matrix pass).  Probes z_k are never stored:
-// the SplitMix64 counter hash regenerates them in registers wherever the
-// right-hand side is needed.  Precision as in the single right-hand-side
-// solver: FP64, or float vectors with FP64 scalars, FP64 folds/residuals and
-// restarted float solves (mixed-precision iterative refinement).
-#include "bf_internal.h"
+// once per row for all K columns.  Every column keeps its own FP64 alpha, beta
+// and stopping test (independent CGs sharing each matrix pass).  Probes z_k
+// are never stored: the SplitMix64 counter hash regenerates them in registers
+// wherever the right-hand side is needed.  Precision as in the single
+// right-hand-side solver: FP64, or float vectors with FP64 scalars, FP64
+// folds/residuals and restarted float solves (mixed-precision iterative
+// refinement).  The per-tile work and the per-column decisions live in
+// block_tiles.h and are shared with the persistent multi-scene solver.
+#include "block_tiles.h"
 
 namespace {
 
-constexpr int kThreads = 256;
+using namespace bt;
 constexpr int kRowsPerTile = 64;
-constexpr int kMaxK = 64;
 
-struct BState {
-  double rho[kMaxK], alpha[kMaxK], beta[kMaxK], tol2b[kMaxK], rr_true[kMaxK], bnorm2[kMaxK], rr_ref[kMaxK];
-  double inner2;
-  int32_t active[kMaxK], check[kMaxK], last[kMaxK], iters[kMaxK], status[kMaxK];
-  int32_t nactive, any_check, max_iter, replace_every, K, refinements;
-  int32_t pad_[2];
-};
-
-enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
-
-// SplitMix64 output n (0-based) of the generator started at `start`.
-__device__ __forceinline__ uint64_t splitmix_out(uint64_t start, uint64_t n) {
-  uint64_t z = start + (n + 1ull) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-__device__ __forceinline__ double probe(uint64_t col_seed, int64_t i) {
-  return (splitmix_out(col_seed, (uint64_t)i) >> 63) ? -1.0 : 1.0;
+__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner) {
+  state_init(st, K, tol, max_iter, inner);
 }
 
-__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, int32_t replace_every,
-                              double inner) {
-  const int c = threadIdx.x;
-  if (c < kMaxK) {
-    st->rho[c] = st->alpha[c] = st->beta[c] = st->rr_true[c] = st->bnorm2[c] = st->rr_ref[c] = 0.0;
-    st->tol2b[c] = tol * tol;
-    st->active[c] = c < K ? 1 : 0;
-    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = 0;
-  }
-  if (c == 0) {
-    st->inner2 = inner * inner;
-    st->nactive = K;
-    st->any_check = 0;
-    st->max_iter = max_iter;
-    st->replace_every = replace_every;
-    st->K = K;
-    st->refinements = 0;
-  }
-}
-
-// Per-column block reduction of NQ quantities; afterwards threads c < KC hold
-// the block's column sums in out[q] (fixed order).
-template <int KC, int NQ>
-__device__ __forceinline__ void col_block_sum(double (&v)[NQ], double* lds /*[4][NQ][64]*/) {
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-#pragma unroll
-    for (int off = KC; off < 64; off <<= 1) v[q] += __shfl_xor(v[q], off, 64);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane < KC)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) lds[(wid * NQ + q) * 64 + lane] = v[q];
-  __syncthreads();
-  if (threadIdx.x < KC)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      double s = 0.0;
-      for (int w = 0; w < kThreads / 64; ++w) s += lds[(w * NQ + q) * 64 + threadIdx.x];
-      v[q] = s;
-    }
-}
-
-// Column c's sums over all block partials part[nb][NQ][KC], computed by one
-// workgroup per column in a fixed order; the result is returned to every
-// thread of the workgroup.
-template <int KC, int NQ>
-__device__ __forceinline__ void col_partials_sum(const double* __restrict__ part, int nb, int c, double (&tot)[NQ],
-                                                 double* lds) {
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    double acc = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[((size_t)b * NQ + q) * KC + c];
-    tot[q] = bf_block_sum(acc, lds);
-  }
-}
-
-template <int KC, int NQ>
-__device__ __forceinline__ void store_partials(double* __restrict__ part, double (&v)[NQ]) {
-  if (threadIdx.x < KC)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) part[((size_t)blockIdx.x * NQ + q) * KC + threadIdx.x] = v[q];
-}
-
-// A: p = zz + beta p_old (with neighbours on the fly), q = Q p, partial p.q.
+// A: p = zz + beta p_old, q = Q p, per-column partial p.q.
 template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                             const V* __restrict__ diag, V lam, const V* __restrict__ zz,
@@ -112,34 +31,14 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
                                             int64_t n, double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
-  const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
-  constexpr int RS = kThreads / KC;
-  const bool act = st->active[c] != 0;
-  const V beta = (V)st->beta[c];
+  const int c = threadIdx.x % KC;
   double v1[1] = {0.0};
-  if (act) {
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x) {
-      for (int s = rsub; s < kRowsPerTile; s += RS) {
-        const int64_t v = tile * kRowsPerTile + s;
-        if (v >= n) break;
-        const int32_t* nb = nbr + v * 6;
-        V acc = 0;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-          const int32_t u = nb[t];
-          if (u >= 0) acc += zz[(int64_t)u * KC + c] + beta * p_old[(int64_t)u * KC + c];
-        }
-        const int64_t e = v * KC + c;
-        const V pv = zz[e] + beta * p_old[e];
-        const V qv = diag[v] * pv - lam * acc;
-        p_new[e] = pv;
-        q[e] = qv;
-        v1[0] += (double)pv * (double)qv;
-      }
-    }
-  }
+  if (st->active[c])
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
+      tile_A<V, KC>(c, (V)st->beta[c], nbr, diag, lam, zz, p_old, p_new, q, tile * kRowsPerTile,
+                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v1[0]);
   col_block_sum<KC, 1>(v1, lds);
-  store_partials<KC, 1>(part, v1);
+  store_partials<KC, 1>(part, blockIdx.x, v1);
 }
 
 // Per-column alpha from A's block partials (one workgroup per column).
@@ -151,18 +50,10 @@ __global__ __launch_bounds__(256) void k_bscal_A(BState* __restrict__ st, const 
   if (!st->active[c]) return;
   double tot[1];
   col_partials_sum<KC, 1>(part, nb, c, tot, lds);
-  if (threadIdx.x == 0) {
-    if (!(tot[0] > 0.0) || !isfinite(tot[0])) {
-      st->status[c] = BF_ERR_BREAKDOWN;
-      st->active[c] = 0;
-      atomicSub(&st->nactive, 1);
-    } else {
-      st->alpha[c] = st->rho[c] / tot[0];
-    }
-  }
+  if (threadIdx.x == 0) decide_A(st, c, tot[0], nullptr);
 }
 
-// B: x += alpha p, r -= alpha q, zz = r / diag, partials r.zz and r.r.
+// B: x += alpha p, r -= alpha q, zz = r / diag, per-column partials r.zz, r.r.
 template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __restrict__ dinv,
                                             const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
@@ -170,29 +61,14 @@ __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __
                                             double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
-  const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
-  constexpr int RS = kThreads / KC;
-  const bool act = st->active[c] != 0;
-  const V alpha = (V)st->alpha[c];
+  const int c = threadIdx.x % KC;
   double v2[2] = {0.0, 0.0};
-  if (act) {
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x) {
-      for (int s = rsub; s < kRowsPerTile; s += RS) {
-        const int64_t v = tile * kRowsPerTile + s;
-        if (v >= n) break;
-        const int64_t e = v * KC + c;
-        x[e] = x[e] + alpha * p[e];
-        const V rv = r[e] - alpha * q[e];
-        const V zv = rv * dinv[v];
-        r[e] = rv;
-        zz[e] = zv;
-        v2[0] += (double)rv * (double)zv;
-        v2[1] += (double)rv * (double)rv;
-      }
-    }
-  }
+  if (st->active[c])
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
+      tile_B<V, KC>(c, (V)st->alpha[c], dinv, p, q, x, r, zz, tile * kRowsPerTile,
+                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v2[0], v2[1]);
   col_block_sum<KC, 2>(v2, lds);
-  store_partials<KC, 2>(part, v2);
+  store_partials<KC, 2>(part, blockIdx.x, v2);
 }
 
 // Per-column beta or residual-check request from B's block partials.
@@ -203,47 +79,21 @@ __global__ __launch_bounds__(256) void k_bscal_B(BState* __restrict__ st, const 
   if (!st->active[c]) return;
   double tot[2];
   col_partials_sum<KC, 2>(part, nb, c, tot, lds);
-  if (threadIdx.x == 0) {
-    const int it = st->iters[c] + 1;
-    st->iters[c] = it;
-    const bool at_max = it >= st->max_iter;
-    const bool periodic = st->replace_every > 0 && (it % st->replace_every) == 0;
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-      st->status[c] = BF_ERR_BREAKDOWN;
-      st->active[c] = 0;
-      atomicSub(&st->nactive, 1);
-    } else if (tot[1] <= fmax(st->tol2b[c], st->inner2 * st->rr_ref[c]) || at_max || periodic) {
-      st->check[c] = 1;
-      st->last[c] = at_max ? 1 : 0;
-      atomicOr(&st->any_check, 1);
-    } else {
-      st->beta[c] = tot[0] / st->rho[c];
-      st->rho[c] = tot[0];
-    }
-  }
+  if (threadIdx.x == 0) decide_B(st, c, tot[0], tot[1], nullptr, nullptr);
 }
 
 // Mixed precision: fold the float corrections of checked columns into x64.
 template <int KC>
 __global__ __launch_bounds__(256) void k_bfold(const BState* __restrict__ st, int force, double* __restrict__ x64,
-                                               float* __restrict__ cc, int64_t n) {
+                                               float* __restrict__ cf, int64_t n) {
   if (!force && (st->nactive == 0 || !st->any_check)) return;
-  const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
-  constexpr int RS = kThreads / KC;
+  const int c = threadIdx.x % KC;
   if (!force && !(st->active[c] && st->check[c])) return;
   for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
-    for (int s = rsub; s < kRowsPerTile; s += RS) {
-      const int64_t v = tile * kRowsPerTile + s;
-      if (v >= n) break;
-      const int64_t e = v * KC + c;
-      x64[e] = x64[e] + (double)cc[e];
-      cc[e] = 0.0f;
-    }
+    tile_fold<KC>(c, x64, cf, tile * kRowsPerTile, std::min<int64_t>(n, (tile + 1) * kRowsPerTile));
 }
 
-// True residual r = z - Q x in FP64 for the checked columns (INIT: every
-// active column, optionally from the warm start u0 = exp(logvar) z / diag,
-// which is written to x64).
+// FP64 residual r = z - Q x for the checked columns (INIT: every active column).
 template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mode, const int32_t* __restrict__ nbr,
                                                 const double* __restrict__ diag, double lam,
@@ -253,59 +103,17 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
                                                 double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
   if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
-  const int c = threadIdx.x % KC, rsub = threadIdx.x / KC;
-  constexpr int RS = kThreads / KC;
-  const bool act = mode == MODE_REPORT ? c < st->K :
-                   (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
+  const int c = threadIdx.x % KC;
+  const bool act = mode == MODE_REPORT ? c < st->K
+                                       : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   double v3[3] = {0.0, 0.0, 0.0};
-  if (act) {
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x) {
-      for (int s = rsub; s < kRowsPerTile; s += RS) {
-        const int64_t v = tile * kRowsPerTile + s;
-        if (v >= n) break;
-        const int64_t e = v * KC + c;
-        const double zv = probe(cs, v);
-        double res = zv;
-        if (mode == MODE_INIT) {
-          if (logvar) {
-            const int32_t* nb = nbr + v * 6;
-            double acc = 0.0;
-#pragma unroll
-            for (int t = 0; t < 6; ++t) {
-              const int32_t u = nb[t];
-              if (u >= 0) acc += exp((double)logvar[u]) * probe(cs, u) / diag[u];
-            }
-            const double x0 = exp((double)logvar[v]) * zv / diag[v];
-            x64[e] = x0;
-            res = zv - (diag[v] * x0 - lam * acc);
-          } else {
-            x64[e] = 0.0;
-          }
-        } else {
-          const int32_t* nb = nbr + v * 6;
-          double acc = 0.0;
-#pragma unroll
-          for (int t = 0; t < 6; ++t) {
-            const int32_t u = nb[t];
-            if (u >= 0) acc += x64[(int64_t)u * KC + c];
-          }
-          res = zv - (diag[v] * x64[e] - lam * acc);
-        }
-        v3[0] += res * res;
-        v3[2] += zv * zv;
-        if (mode != MODE_REPORT) {
-          const V rv = (V)res;
-          const V zzv = rv * dinv[v];
-          r[e] = rv;
-          zz[e] = zzv;
-          v3[1] += (double)rv * (double)zzv;
-        }
-      }
-    }
-  }
+  if (act)
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
+      tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile,
+                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v3);
   col_block_sum<KC, 3>(v3, lds);
-  store_partials<KC, 3>(part, v3);
+  store_partials<KC, 3>(part, blockIdx.x, v3);
 }
 
 // Per-column decisions after an FP64 residual (one workgroup per column).
@@ -313,62 +121,20 @@ template <int KC>
 __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mode, const double* __restrict__ part,
                                                  int nb) {
   __shared__ double lds[16];
-  const int cc = blockIdx.x;
-  if (mode == MODE_CHECK && !(st->active[cc] && st->check[cc])) return;
-  if (mode == MODE_REPORT && cc >= st->K) return;
-  if (mode == MODE_INIT && !st->active[cc]) return;
+  const int c = blockIdx.x;
+  if (mode == MODE_CHECK && !(st->active[c] && st->check[c])) return;
+  if (mode == MODE_REPORT && c >= st->K) return;
+  if (mode == MODE_INIT && !st->active[c]) return;
   double tot[3];
-  col_partials_sum<KC, 3>(part, nb, cc, tot, lds);
-  if (threadIdx.x != 0) return;
-  if (mode == MODE_REPORT) {
-    st->rr_true[cc] = tot[0];
-  } else if (mode == MODE_INIT) {
-    st->bnorm2[cc] = tot[2];
-    st->tol2b[cc] *= tot[2];
-    st->rr_true[cc] = tot[0];
-    if (tot[2] == 0.0 || tot[0] <= st->tol2b[cc] || st->max_iter <= 0) {
-      if (!(tot[2] == 0.0 || tot[0] <= st->tol2b[cc])) st->status[cc] = BF_ERR_NOT_CONVERGED;
-      st->active[cc] = 0;
-      atomicSub(&st->nactive, 1);
-    } else {
-      st->rho[cc] = tot[1];
-      st->beta[cc] = 0.0;
-      st->rr_ref[cc] = tot[0];
-    }
-  } else {
-    st->rr_true[cc] = tot[0];
-    atomicAdd(&st->refinements, 1);
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
-      st->status[cc] = BF_ERR_BREAKDOWN;
-      st->active[cc] = 0;
-      atomicSub(&st->nactive, 1);
-    } else if (tot[0] <= st->tol2b[cc]) {
-      st->active[cc] = 0;
-      atomicSub(&st->nactive, 1);
-    } else if (st->last[cc]) {
-      st->status[cc] = BF_ERR_NOT_CONVERGED;
-      st->active[cc] = 0;
-      atomicSub(&st->nactive, 1);
-    } else {
-      // FP64 continues CG from the replaced residual; mixed restarts the
-      // float solve on the FP64 residual (iterative refinement).
-      st->beta[cc] = st->inner2 > 0.0 ? 0.0 : tot[1] / st->rho[cc];
-      st->rho[cc] = tot[1];
-      st->rr_ref[cc] = tot[0];
-    }
-    st->check[cc] = 0;
-  }
+  col_partials_sum<KC, 3>(part, nb, c, tot, lds);
+  if (threadIdx.x == 0) decide_R(st, c, mode, tot, nullptr);
 }
 
-// s_v = (1/K) sum_k z_k[v] u_k[v], columns in ascending order.
 template <int KC>
 __global__ __launch_bounds__(256) void k_hutch_final(const double* __restrict__ x64, uint64_t seed, int K,
                                                      int64_t n, double* __restrict__ s_out) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  double s = 0.0;
-  for (int k = 0; k < K; ++k) s += probe(splitmix_out(seed, (uint64_t)k), v) * x64[v * KC + k];
-  s_out[v] = s / (double)K;
+  if (v < n) s_out[v] = hutch_row<KC>(x64, seed, K, v);
 }
 
 template <typename V>
@@ -399,8 +165,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   V* p0 = (V*)((char*)zz + vec);
   V* p1 = (V*)((char*)p0 + vec);
   V* q = (V*)((char*)p1 + vec);
-  float* cc = mixed ? (float*)((char*)q + vec) : nullptr;
-  V* xin = mixed ? (V*)cc : (V*)x64;
+  float* cf = mixed ? (float*)((char*)q + vec) : nullptr;
+  V* xin = mixed ? (V*)cf : (V*)x64;
   const V* diagV = mixed ? (const V*)sys->diag32 : (const V*)sys->diag;
   const V* dinvV = mixed ? (const V*)sys->dinv32 : (const V*)sys->dinv;
   const V lamV = (V)sys->lambda;
@@ -410,12 +176,12 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   BF_HIP(ctx, hipEventCreate(&e0));
   BF_HIP(ctx, hipEventCreate(&e1));
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
-  hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter, 0,
+  hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
                      mixed ? 1e-6 : 0.0);
   hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
-  if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cc, N * KC, 0.0f);
+  if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->band->nbr,
-                     sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
+            sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
@@ -426,15 +192,14 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   for (;;) {
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
-      BF_LAUNCH(ctx, "block_A", (k_bA<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
-                         zz, pa, pb, q, N, part);
+      BF_LAUNCH(ctx, "block_A", (k_bA<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, zz, pa,
+                pb, q, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
-      BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N,
-                         part);
+      BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
-      if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cc, N);
+      if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
       BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
-                         sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+                sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       std::swap(pa, pb);
     }
@@ -444,13 +209,13 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     if (hs->nactive == 0 || it >= o->max_iter) break;
     next = it + std::max(it, 4);
   }
-  if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cc, N);
-  BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, x64, o->seed,
-                     o->K, N, s_out);
+  if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
+  BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, x64, o->seed, o->K,
+            N, s_out);
   BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
   // final FP64 residual of every probe column for the report
   BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
-                     sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+            sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
   BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));

@@ -1,0 +1,285 @@
+// Building blocks of the K-column block CG for the Hutchinson probes
+// (Sec. 3.7, eq. 12), shared by the single-system kernels and the persistent
+// multi-scene kernel: per-column solver state, the in-register Rademacher
+// probes, the per-tile work of each CG phase and the per-column decisions.
+//
+// Block vectors are row-major [N][KC] (KC = 16, 32 or 64 >= K).  A thread owns
+// one column c = threadIdx.x % KC and rows rsub, rsub + 256/KC, ... of a tile,
+// so each row's KC values and each neighbour row's KC values are read as one
+// coalesced segment while the neighbour table and diagonal are read once per
+// row for all columns.
+#pragma once
+
+#include "bf_internal.h"
+
+namespace bt {
+
+constexpr int kThreads = 256;
+constexpr int kMaxK = 64;
+
+enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
+
+struct BState {
+  double rho[kMaxK], alpha[kMaxK], beta[kMaxK], tol2b[kMaxK], rr_true[kMaxK], bnorm2[kMaxK], rr_ref[kMaxK];
+  double inner2;
+  int32_t active[kMaxK], check[kMaxK], last[kMaxK], iters[kMaxK], status[kMaxK];
+  int32_t nactive, any_check, max_iter, replace_every, K, refinements;
+  int32_t pad_[2];
+};
+
+// SplitMix64 output n (0-based) of the generator started at `start`.
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t start, uint64_t n) {
+  uint64_t z = start + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+// z_k[i] = -1 if the top bit of output i of the generator started at u_k is set.
+__device__ __forceinline__ double probe(uint64_t col_seed, int64_t i) {
+  return (splitmix_out(col_seed, (uint64_t)i) >> 63) ? -1.0 : 1.0;
+}
+
+__device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_t max_iter, double inner) {
+  const int c = threadIdx.x;
+  if (c < kMaxK) {
+    st->rho[c] = st->alpha[c] = st->beta[c] = st->rr_true[c] = st->bnorm2[c] = st->rr_ref[c] = 0.0;
+    st->tol2b[c] = tol * tol;
+    st->active[c] = c < K ? 1 : 0;
+    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = 0;
+  }
+  if (c == 0) {
+    st->inner2 = inner * inner;
+    st->nactive = K;
+    st->any_check = 0;
+    st->max_iter = max_iter;
+    st->replace_every = 0;
+    st->K = K;
+    st->refinements = 0;
+  }
+}
+
+// Per-column sum over the workgroup in a fixed order; threads c < KC end with
+// the column totals.  lds holds >= 4*NQ*64 doubles.
+template <int KC, int NQ>
+__device__ __forceinline__ void col_block_sum(double (&v)[NQ], double* lds) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+#pragma unroll
+    for (int off = KC; off < 64; off <<= 1) v[q] += __shfl_xor(v[q], off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane < KC)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) lds[(wid * NQ + q) * 64 + lane] = v[q];
+  __syncthreads();
+  if (threadIdx.x < KC)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      double s = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) s += lds[(w * NQ + q) * 64 + threadIdx.x];
+      v[q] = s;
+    }
+}
+
+template <int KC, int NQ>
+__device__ __forceinline__ void store_partials(double* __restrict__ part, int64_t slot, double (&v)[NQ]) {
+  if (threadIdx.x < KC)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) part[((size_t)slot * NQ + q) * KC + threadIdx.x] = v[q];
+}
+
+// Column c's sums over `nb` partial slots, by one whole workgroup in a fixed
+// order; every thread receives the totals.
+template <int KC, int NQ>
+__device__ __forceinline__ void col_partials_sum(const double* __restrict__ part, int64_t nb, int c,
+                                                 double (&tot)[NQ], double* lds) {
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) acc += part[((size_t)b * NQ + q) * KC + c];
+    tot[q] = bf_block_sum(acc, lds);
+  }
+}
+
+// ---------------------------------------------------------------- tile work
+// A: p = zz + beta p_old (neighbours on the fly), q = Q p; acc += p.q.
+template <typename V, int KC>
+__device__ __forceinline__ void tile_A(int c, V beta, const int32_t* __restrict__ nbr, const V* __restrict__ diag, V lam,
+                                       const V* __restrict__ zz, const V* __restrict__ p_old, V* __restrict__ p_new,
+                                       V* __restrict__ q, int64_t r0, int64_t r1, double& acc1) {
+  constexpr int RS = kThreads / KC;
+  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+    const int32_t* nb = nbr + v * 6;
+    V s = 0;
+#pragma unroll
+    for (int t = 0; t < 6; ++t) {
+      const int32_t u = nb[t];
+      if (u >= 0) s += zz[(int64_t)u * KC + c] + beta * p_old[(int64_t)u * KC + c];
+    }
+    const int64_t e = v * KC + c;
+    const V pv = zz[e] + beta * p_old[e];
+    const V qv = diag[v] * pv - lam * s;
+    p_new[e] = pv;
+    q[e] = qv;
+    acc1 += (double)pv * (double)qv;
+  }
+}
+
+// B: x += alpha p, r -= alpha q, zz = r / diag; acc += r.zz, r.r.
+template <typename V, int KC>
+__device__ __forceinline__ void tile_B(int c, V alpha, const V* __restrict__ dinv, const V* __restrict__ p,
+                                       const V* __restrict__ q, V* __restrict__ x, V* __restrict__ r,
+                                       V* __restrict__ zz, int64_t r0, int64_t r1, double& rz, double& rr) {
+  constexpr int RS = kThreads / KC;
+  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+    const int64_t e = v * KC + c;
+    x[e] = x[e] + alpha * p[e];
+    const V rv = r[e] - alpha * q[e];
+    const V zv = rv * dinv[v];
+    r[e] = rv;
+    zz[e] = zv;
+    rz += (double)rv * (double)zv;
+    rr += (double)rv * (double)rv;
+  }
+}
+
+// Mixed precision: x64 += c (float correction), c = 0.
+template <int KC>
+__device__ __forceinline__ void tile_fold(int c, double* __restrict__ x64, float* __restrict__ cf, int64_t r0,
+                                          int64_t r1) {
+  constexpr int RS = kThreads / KC;
+  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+    const int64_t e = v * KC + c;
+    x64[e] = x64[e] + (double)cf[e];
+    cf[e] = 0.0f;
+  }
+}
+
+// FP64 residual r = z - Q x (INIT: x = 0 or the warm start exp(logvar) z / diag,
+// written to x64).  acc: r.r, r.zz (stored precision), z.z.
+template <typename V, int KC>
+__device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const int32_t* __restrict__ nbr,
+                                           const double* __restrict__ diag, double lam,
+                                           const float* __restrict__ logvar, double* __restrict__ x64,
+                                           const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
+                                           int64_t r0, int64_t r1, double (&v3)[3]) {
+  constexpr int RS = kThreads / KC;
+  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+    const int64_t e = v * KC + c;
+    const double zv = probe(cs, v);
+    double res = zv;
+    if (mode == MODE_INIT) {
+      if (logvar) {
+        const int32_t* nb = nbr + v * 6;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+          const int32_t u = nb[t];
+          if (u >= 0) acc += exp((double)logvar[u]) * probe(cs, u) / diag[u];
+        }
+        const double x0 = exp((double)logvar[v]) * zv / diag[v];
+        x64[e] = x0;
+        res = zv - (diag[v] * x0 - lam * acc);
+      } else {
+        x64[e] = 0.0;
+      }
+    } else {
+      const int32_t* nb = nbr + v * 6;
+      double acc = 0.0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int32_t u = nb[t];
+        if (u >= 0) acc += x64[(int64_t)u * KC + c];
+      }
+      res = zv - (diag[v] * x64[e] - lam * acc);
+    }
+    v3[0] += res * res;
+    v3[2] += zv * zv;
+    if (mode != MODE_REPORT) {
+      const V rv = (V)res;
+      const V zzv = rv * dinv[v];
+      r[e] = rv;
+      zz[e] = zzv;
+      v3[1] += (double)rv * (double)zzv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- decisions
+// Executed by one thread per column; *nactive_all (may be null) mirrors the
+// count of active columns across all systems of a batch.
+__device__ __forceinline__ void deactivate(BState* st, int c, int status, int* nactive_all) {
+  if (status) st->status[c] = status;
+  st->active[c] = 0;
+  atomicSub(&st->nactive, 1);
+  if (nactive_all) atomicSub(nactive_all, 1);
+}
+
+__device__ __forceinline__ void decide_A(BState* st, int c, double pq, int* nactive_all) {
+  if (!(pq > 0.0) || !isfinite(pq)) deactivate(st, c, BF_ERR_BREAKDOWN, nactive_all);
+  else st->alpha[c] = st->rho[c] / pq;
+}
+
+__device__ __forceinline__ void decide_B(BState* st, int c, double rz, double rr, int* nactive_all, int* any_all) {
+  const int it = st->iters[c] + 1;
+  st->iters[c] = it;
+  const bool at_max = it >= st->max_iter;
+  const bool periodic = st->replace_every > 0 && (it % st->replace_every) == 0;
+  if (!isfinite(rz) || !isfinite(rr)) {
+    deactivate(st, c, BF_ERR_BREAKDOWN, nactive_all);
+  } else if (rr <= fmax(st->tol2b[c], st->inner2 * st->rr_ref[c]) || at_max || periodic) {
+    st->check[c] = 1;
+    st->last[c] = at_max ? 1 : 0;
+    atomicOr(&st->any_check, 1);
+    if (any_all) atomicOr(any_all, 1);
+  } else {
+    st->beta[c] = rz / st->rho[c];
+    st->rho[c] = rz;
+  }
+}
+
+__device__ __forceinline__ void decide_R(BState* st, int c, int mode, const double (&tot)[3], int* nactive_all) {
+  if (mode == MODE_REPORT) {
+    st->rr_true[c] = tot[0];
+  } else if (mode == MODE_INIT) {
+    st->bnorm2[c] = tot[2];
+    st->tol2b[c] *= tot[2];
+    st->rr_true[c] = tot[0];
+    if (tot[2] == 0.0 || tot[0] <= st->tol2b[c]) {
+      deactivate(st, c, 0, nactive_all);
+    } else if (st->max_iter <= 0) {
+      deactivate(st, c, BF_ERR_NOT_CONVERGED, nactive_all);
+    } else {
+      st->rho[c] = tot[1];
+      st->beta[c] = 0.0;
+      st->rr_ref[c] = tot[0];
+    }
+  } else {
+    st->rr_true[c] = tot[0];
+    atomicAdd(&st->refinements, 1);
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) {
+      deactivate(st, c, BF_ERR_BREAKDOWN, nactive_all);
+    } else if (tot[0] <= st->tol2b[c]) {
+      deactivate(st, c, 0, nactive_all);
+    } else if (st->last[c]) {
+      deactivate(st, c, BF_ERR_NOT_CONVERGED, nactive_all);
+    } else {
+      // FP64 continues CG from the replaced residual; mixed restarts the
+      // float solve on the FP64 residual (iterative refinement).
+      st->beta[c] = st->inner2 > 0.0 ? 0.0 : tot[1] / st->rho[c];
+      st->rho[c] = tot[1];
+      st->rr_ref[c] = tot[0];
+    }
+    st->check[c] = 0;
+  }
+}
+
+// s_v = (1/K) sum_k z_k[v] u_k[v], columns in ascending order.
+template <int KC>
+__device__ __forceinline__ double hutch_row(const double* __restrict__ x64, uint64_t seed, int K, int64_t v) {
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) s += probe(splitmix_out(seed, (uint64_t)k), v) * x64[v * KC + k];
+  return s / (double)K;
+}
+
+}  // namespace bt
