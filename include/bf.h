@@ -234,18 +234,23 @@ bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
                        int64_t* scores_dev, int32_t* best_host);
 
 /* ---------------------------------------------------------------- batched solves */
-/* Many systems (scenes of uneven band size) solved in ONE persistent launch:
- * the work list is every system's row tiles in the schedule's order, walked by
- * a grid of co-resident workgroups that meet at grid barriers between CG
- * phases; every system and probe column keeps its own scalars and stopping
- * test, and converged systems leave the work list.  Results equal the
- * single-system calls up to the order of the dot-product reductions. */
+/* Many systems (scenes of uneven band size) solved together: the work list is
+ * every system's row tiles in the schedule's order.  Persistent: one
+ * cooperative launch whose co-resident workgroups walk the list phase by
+ * phase and meet at grid barriers between CG phases.  Phased: one launch per
+ * CG phase over the whole list.  Every system and probe column keeps its own
+ * scalars and stopping test, and converged systems leave the work list.
+ * Results equal the single-system calls up to the order of the dot-product
+ * reductions. */
 enum { BF_ORDER_SCENE_MAJOR = 0, BF_ORDER_INTERLEAVED = 1, BF_ORDER_LARGEST_FIRST = 2 };
 typedef struct bf_schedule {
   int32_t rows_per_tile;  /* band rows per work item, 16..4096 */
-  int32_t blocks_per_cu;  /* persistent workgroups per CU (0 = as many as fit) */
+  int32_t blocks_per_cu;  /* workgroups per CU, 0..16 (persistent: 0 = as many as fit;
+                             phased: 0 = 4) */
   int32_t order;          /* BF_ORDER_* tile order across systems */
   int32_t xcd_aware;      /* 1: contiguous runs of tiles stay on one XCD's workgroups */
+  int32_t persistent;     /* 1: one cooperative launch with grid barriers (probe solves
+                             only); 0: one launch per CG phase, host polls convergence */
 } bf_schedule;
 
 /* Hutchinson probes (as bf_diag_estimate, no warm start) for n_sys systems;
@@ -254,12 +259,13 @@ typedef struct bf_schedule {
 bf_status bf_diag_estimate_batched(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
                                    const bf_probe_opts* opts, const bf_schedule* sched,
                                    double* const* s_dev, bf_solve_report* reps);
-/* Posterior means (as bf_pcg_solve from x = 0 with each system's rhs). */
+/* Posterior means (as bf_pcg_solve from x = 0 with each system's rhs).  Runs
+ * phased only: a schedule with persistent = 1 is rejected (BF_ERR_INVALID_ARG). */
 bf_status bf_pcg_solve_batched(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
                                const bf_solve_opts* opts, const bf_schedule* sched,
                                double* const* x_dev, bf_solve_report* reps);
-/* Times every candidate schedule (rows per tile x blocks per CU x order x
- * XCD mapping) on the batched probe solve and returns the fastest in *best;
+/* Times every candidate schedule (launch kind x rows per tile x blocks per CU
+ * x order x XCD mapping) on the batched probe solve and returns the fastest in *best;
  * json (host, may be NULL) receives every candidate's time as a JSON array. */
 bf_status bf_autotune_batch(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sys,
                             const bf_probe_opts* opts, double* const* s_dev, bf_schedule* best,

@@ -230,9 +230,10 @@ class Context:
 
     # ---------------------------------------------------------- batched solves
     @staticmethod
-    def schedule(rows_per_tile=256, blocks_per_cu=0, order=L.BF_ORDER_SCENE_MAJOR, xcd_aware=1):
+    def schedule(rows_per_tile=256, blocks_per_cu=0, order=L.BF_ORDER_SCENE_MAJOR, xcd_aware=1, persistent=1):
         s = L.bf_schedule()
         s.rows_per_tile, s.blocks_per_cu, s.order, s.xcd_aware = rows_per_tile, blocks_per_cu, order, xcd_aware
+        s.persistent = persistent
         return s
 
     def _batch_args(self, systems, outs):

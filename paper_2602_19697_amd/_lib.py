@@ -69,7 +69,7 @@ class bf_probe_opts(C.Structure):
 
 class bf_schedule(C.Structure):
     _fields_ = [("rows_per_tile", C.c_int32), ("blocks_per_cu", C.c_int32), ("order", C.c_int32),
-                ("xcd_aware", C.c_int32)]
+                ("xcd_aware", C.c_int32), ("persistent", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

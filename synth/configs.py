@@ -95,6 +95,17 @@ def batch_sphere(s: int, device="cpu") -> Workload:
                            8, 1.0, s, device=device, probes=64, tol=1e-6, probe_seed=s)
 
 
+def train_sphere(s: int, device="cpu") -> Workload:
+    """Sphere scene with a seeded radius in [0.15, 0.35] m and voxel edge in
+    [12, 20] mm, 8 ring views at 160x120 (training scenes of the warm start)."""
+    rng = np.random.default_rng((0x7EA1, int(s)))
+    radius = float(rng.uniform(0.15, 0.35))
+    h = float(rng.uniform(0.012, 0.020))
+    G = int(math.ceil(0.96 / h))
+    return sphere_workload(f"trainsphere{s}", G, h, 3, 4, Camera.centred(160, 120, 150.0, 150.0), 8, 1.0, s,
+                           radius=radius, device=device, probes=64, tol=1e-6)
+
+
 def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
     if name == "tiny":
         return sphere_workload("tiny", 32, 0.03, 3, 4, Camera.centred(80, 60, 75.0, 75.0), 4, 1.0,
@@ -113,6 +124,8 @@ def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
                               tol=1e-6, probes=32)
     if name.startswith("batchsphere"):
         return batch_sphere(int(name[len("batchsphere"):]), device=device)
+    if name.startswith("trainsphere"):
+        return train_sphere(int(name[len("trainsphere"):]), device=device)
     raise KeyError(name)
 
 
