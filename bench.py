@@ -39,6 +39,44 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the roofline kernel, from two rocprofv3 --pmc runs of this
+# bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
+# counters read for a plain copy of known size (bench.py --copy-calibration).
+# The figures hold only for the kernel source they were taken from.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+COPY_BYTES = 1 << 30
+
+
+def copy_calibration():
+    """A plain device copy of COPY_BYTES (reads and writes that many bytes)."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counters, or None if
+    there are none for it or its source changed since they were taken."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    entry = rec.get("kernels", {}).get(kernel)
+    if entry is None:
+        return None
+    with open(os.path.join(ROOT, entry["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != entry["source_sha256"]:
+            return None
+    fetch = entry["fetch_kib_per_dispatch"] * 1024 * rec["copy"]["fetch_factor"]
+    write = entry["write_kib_per_dispatch"] * 1024 * rec["copy"]["write_factor"]
+    return fetch + write
+
+
 def algorithmic_work(name, N, K, T, G, P, fp64=True):
     """(amount, unit, bound) of one launch of a timed kernel."""
     s = 8 if fp64 else 4
@@ -76,11 +114,22 @@ def run_gpu(args):
     ctx = bf.Context(dev)
     K = args.probes
 
+    prec = bf.L.BF_PREC_FP64 if args.precision == "fp64" else bf.L.BF_PREC_MIXED
+    params = None
+    if args.learned:
+        if not os.path.exists(WEIGHTS):
+            raise SystemExit(f"--learned needs the trained weights at {WEIGHTS}")
+        params = torch.from_numpy(np.load(WEIGHTS)).to(dev)
+
     def step():
         band = ctx.bf_build_band(grid, wl.cam, depth, poses)
         sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, noise, wl.lam, wl.eps)
-        mu, rep = ctx.bf_pcg_solve(sys_, args.tol, precision=bf.L.BF_PREC_FP64)
-        s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=bf.L.BF_PREC_FP64)
+        if params is not None:  # learned start: features -> network -> x0 and log-variance
+            x0, lv = ctx.bf_warm_start(sys_, params, ctx.bf_features(sys_))
+        else:
+            x0 = lv = None
+        mu, rep = ctx.bf_pcg_solve(sys_, args.tol, precision=prec, x0=x0)
+        s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
@@ -138,50 +187,153 @@ def run_gpu(args):
                 dominant=dominant)
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2602_19697_amd", "weights", "warm_start_lam10.npy")
+
+
+def _timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+    torch.cuda.synchronize()
+    return r, 1e3 * (time.perf_counter() - t0) / reps
+
+
 def time_to_tol(g, args):
-    """Plain FP64 (mean + K sequential probe solves from zero) vs one mixed
-    mean solve + one mixed K-column block solve."""
+    """Mean plus K-probe variance to relative residual 1e-6 on the bench scene:
+    plain FP64 (mean PCG + K sequential one-probe solves, all from zero)
+    against the block FP64 solve, the block mixed solve, and the learned start
+    (features + network, then mixed PCG from x0 and the mixed block solve from
+    the predicted log-variance)."""
     import torch
     import paper_2602_19697_amd as bf
     ctx, wl = g["ctx"], g["wl"]
     band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
     sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], g["noise"], wl.lam, wl.eps)
     K, tol = args.probes, 1e-6
+    FP64, MIXED = bf.L.BF_PREC_FP64, bf.L.BF_PREC_MIXED
 
     def plain():
-        _, r = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_FP64)
-        its = r["iters"]
+        _, r = ctx.bf_pcg_solve(sys_, tol, precision=FP64)
+        its = [r["iters"], 0]
         for k in range(K):
-            _, pr = ctx.bf_diag_estimate(sys_, 1, 1000 + k, tol, precision=bf.L.BF_PREC_FP64)
-            its += pr["iters"]
+            _, pr = ctx.bf_diag_estimate(sys_, 1, 1000 + k, tol, precision=FP64)
+            its[1] += pr["iters"]
         return its
 
-    def batched_mixed():
-        _, r = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_MIXED)
-        _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=bf.L.BF_PREC_MIXED)
-        return r["iters"] + pr["iters"]
+    def block(prec):
+        def run():
+            _, r = ctx.bf_pcg_solve(sys_, tol, precision=prec)
+            _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)
+            return [r["iters"], pr["col_iters"]]
+        return run
 
-    def batched_fp64():
-        _, r = ctx.bf_pcg_solve(sys_, tol, precision=bf.L.BF_PREC_FP64)
-        _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=bf.L.BF_PREC_FP64)
-        return r["iters"] + pr["iters"]
+    variants = [("plain_fp64", plain), ("batched_fp64", block(FP64)), ("batched_mixed", block(MIXED))]
+    params = None
+    if os.path.exists(WEIGHTS):
+        params = torch.from_numpy(np.load(WEIGHTS)).to(ctx.device)
 
-    out = {}
-    for name, fn in (("plain_fp64", plain), ("batched_fp64", batched_fp64), ("batched_mixed", batched_mixed)):
-        fn()
-        torch.cuda.synchronize()
-        reps = 3
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            its = fn()
-        torch.cuda.synchronize()
-        out[name + "_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+        def learned():
+            f = ctx.bf_features(sys_)
+            x0, lv = ctx.bf_warm_start(sys_, params, f)
+            _, r = ctx.bf_pcg_solve(sys_, tol, precision=MIXED, x0=x0)
+            _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED, logvar=lv)
+            return [r["iters"], pr["col_iters"]]
+        variants.append(("learned_batched_mixed", learned))
+    out = {"tol": tol, "probes": K}
+    for name, fn in variants:
+        its, ms = _timed(fn)
+        out[name + "_ms"] = ms
+        out[name + "_iters"] = {"mean": its[0], "probe_columns": its[1]}
     out["speedup_batching"] = out["plain_fp64_ms"] / out["batched_fp64_ms"]
     out["speedup_precision"] = out["batched_fp64_ms"] / out["batched_mixed_ms"]
-    out["speedup_total"] = out["plain_fp64_ms"] / out["batched_mixed_ms"]
-    out["learned"] = None
+    out["speedup_batched_mixed"] = out["plain_fp64_ms"] / out["batched_mixed_ms"]
+    if params is not None:
+        out["speedup_total"] = out["plain_fp64_ms"] / out["learned_batched_mixed_ms"]
+        out["speedup_learned"] = out["batched_mixed_ms"] / out["learned_batched_mixed_ms"]
+    # error of the mixed results against the FP64 ones on the GPU
+    mu64, _ = ctx.bf_pcg_solve(sys_, 1e-10, precision=FP64)
+    s64, _ = ctx.bf_diag_estimate(sys_, K, 0, 1e-10, precision=FP64)
+    mu32, _ = ctx.bf_pcg_solve(sys_, tol, precision=MIXED)
+    s32, _ = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED)
+    out["mixed_rel_err_vs_fp64"] = {"mean": float(torch.linalg.norm(mu32 - mu64) / torch.linalg.norm(mu64)),
+                                    "variance": float(torch.linalg.norm(s32 - s64) / torch.linalg.norm(s64))}
     sys_.free()
     band.free()
+    return out
+
+
+def batch_section(g, args):
+    """Many scenes of uneven size: args.batch_scenes sphere scenes whose band
+    sizes are log-uniform in [2e4, 8e5], mean + 64-probe variance, to 1e-6.
+    The autotuner picks the schedule on the batch itself; then the batched
+    mixed solve is timed against the same work done scene by scene in plain
+    FP64 and batched in FP64."""
+    import torch
+    import paper_2602_19697_amd as bf
+    from synth import make_workload
+    ctx, dev = g["ctx"], g["ctx"].device
+    FP64, MIXED = bf.L.BF_PREC_FP64, bf.L.BF_PREC_MIXED
+    K, tol = args.batch_probes, 1e-6
+    t0 = time.time()
+    scenes = []
+    for s in range(args.batch_scenes):
+        wl = make_workload(f"batchsphere{s}", device=dev)
+        depth = torch.from_numpy(np.ascontiguousarray(wl.depth)).to(dev)
+        poses = torch.from_numpy(np.ascontiguousarray(wl.poses)).to(dev)
+        band = ctx.bf_build_band(bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band), wl.cam, depth, poses)
+        sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, bf.noise_struct(*wl.noise), wl.lam, wl.eps)
+        scenes.append((band, sys_))
+    systems = [sy for _, sy in scenes]
+    sizes = [b.n for b, _ in scenes]
+    log(f"[batch] {len(scenes)} scenes, N total {sum(sizes)} (min {min(sizes)}, max {max(sizes)}) "
+        f"built in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    best, table = ctx.bf_autotune_batch(systems, K, 0, tol, precision=MIXED)
+    log(f"[batch] autotuned over {len(table)} schedules in {time.time() - t0:.1f}s: {best.as_dict()}")
+    mean_sched = bf.Context.schedule(best.rows_per_tile, best.blocks_per_cu, best.order, best.xcd_aware, 0)
+
+    def batched(prec, sched_probe):
+        def run():
+            _, r = ctx.bf_pcg_solve_batched(systems, tol, precision=prec, schedule=mean_sched)
+            _, pr = ctx.bf_diag_estimate_batched(systems, K, 0, tol, precision=prec, schedule=sched_probe)
+            return sum(x["col_iters"] for x in r) + sum(x["col_iters"] for x in pr)
+        return run
+
+    def per_scene_plain():
+        its = 0
+        for sy in systems:
+            _, r = ctx.bf_pcg_solve(sy, tol, precision=FP64)
+            its += r["iters"]
+            for k in range(K):
+                _, pr = ctx.bf_diag_estimate(sy, 1, 1000 + k, tol, precision=FP64)
+                its += pr["iters"]
+        return its
+
+    out = {"scenes": len(scenes), "band_voxels_total": int(sum(sizes)), "band_voxels_min": int(min(sizes)),
+           "band_voxels_max": int(max(sizes)), "probes": K, "tol": tol, "schedule": best.as_dict(),
+           "autotune_candidates": len(table)}
+    for name, fn, reps in (("plain_fp64_per_scene", per_scene_plain, 1),
+                           ("batched_fp64", batched(FP64, best), 3),
+                           ("batched_mixed", batched(MIXED, best), 3)):
+        its, ms = _timed(fn, reps)
+        out[name + "_ms"] = ms
+        out[name + "_column_iters"] = its
+        log(f"[batch] {name}: {ms:.1f} ms")
+    out["speedup_batched_mixed_vs_plain"] = out["plain_fp64_per_scene_ms"] / out["batched_mixed_ms"]
+    # mixed vs FP64 on the GPU, worst scene
+    m64, _ = ctx.bf_pcg_solve_batched(systems, 1e-10, precision=FP64, schedule=mean_sched)
+    s64, _ = ctx.bf_diag_estimate_batched(systems, K, 0, 1e-10, precision=FP64, schedule=best)
+    m32, _ = ctx.bf_pcg_solve_batched(systems, tol, precision=MIXED, schedule=mean_sched)
+    s32, _ = ctx.bf_diag_estimate_batched(systems, K, 0, tol, precision=MIXED, schedule=best)
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out["mixed_rel_err_vs_fp64_max"] = {"mean": max(rel(a, b) for a, b in zip(m32, m64)),
+                                        "variance": max(rel(a, b) for a, b in zip(s32, s64))}
+    for band, sy in scenes:
+        sy.free()
+        band.free()
     return out
 
 
@@ -249,12 +401,23 @@ def main():
     ap.add_argument("--workload", default="union256")
     ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
+                    help="solver precision of the timed step (the 256^3 configuration is FP64)")
+    ap.add_argument("--learned", action="store_true", help="start the timed solves from the learned network")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-scenes", type=int, default=32)
+    ap.add_argument("--batch-probes", type=int, default=64)
     ap.add_argument("--cpu-tsdf-sample", type=int, default=200000)
     ap.add_argument("--cpu-assembly-sample", type=int, default=40000)
     ap.add_argument("--cpu-probe-sample", type=int, default=2)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the narrow-band solve runs on a single MI355X "
@@ -263,15 +426,22 @@ def main():
 
     g = run_gpu(args)
     cmp = None if args.no_compare else time_to_tol(g, args)
+    batch = None if args.no_batch else batch_section(g, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
-    dom = g["dominant"]
-    roof = g["rooflines"].get(dom)
-    if roof is None and g["rooflines"]:
+    # The roofline is that of the longest-running kernel with a roofline
+    # claim.  The ray walk (nbv_rays) is irregular and latency-bound: it gets
+    # rays/s instead, and is named as the step's largest kernel when it is.
+    top = g["dominant"]
+    roof = None
+    if g["rooflines"]:
         dom = max(g["rooflines"], key=lambda k: g["kernels"][k]["share_of_step"])
-        roof = g["rooflines"][dom]
-    if roof is not None:
-        roof = dict(roof, kernel=dom, traffic=None)
+        roof = dict(g["rooflines"][dom], kernel=dom, traffic=measured_traffic(dom))
     wl = g["wl"]
+    nbv = g["kernels"].get("nbv_rays")
+    rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height
+    nbv_info = None if nbv is None else {
+        "rays_per_launch": rays, "avg_ms": nbv["avg_us"] * 1e-3, "rays_per_s": rays / (nbv["avg_us"] * 1e-6),
+        "share_of_step": nbv["share_of_step"], "bound": "latency (no roofline claim)"}
     line = {
         "metric": "band voxel-PCG-iters/s, probe-solves/s; learned+batched vs plain time-to-1e-6",
         "value": g["value"],
@@ -283,19 +453,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: union of 3 spheres, rounded box, torus; {wl.G}^3 grid, "
                                f"h={wl.h} m, band +-{round(wl.band / wl.h)} voxels, {wl.T} views "
-                               f"{wl.cam.width}x{wl.cam.height}; FP64 PCG tol {args.tol}, "
+                               f"{wl.cam.width}x{wl.cam.height}; {args.precision.upper()} PCG tol {args.tol}"
+                               f"{' from the learned start' if args.learned else ''}, "
                                f"{args.probes}-probe block PCG, NBV 512x160x120",
                    "band_voxels": g["info"]["N"], "pcg_iters": g["info"]["iters"],
                    "probe_iters": g["info"]["probe_iters"], "parallelism": "single GPU"},
         "probe_solves_per_s": args.probes / (g["ms_step"] * 1e-3),
         "roofline": roof,
+        "largest_kernel": {"name": top, "share_of_step": g["kernels"][top]["share_of_step"]} if top else None,
+        "nbv": nbv_info,
         "rooflines": g["rooflines"],
         "kernels": g["kernels"],
         "time_to_tol": cmp,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

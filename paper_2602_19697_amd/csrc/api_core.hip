@@ -79,7 +79,11 @@ hipEvent_t bf_event_get(bf_ctx* ctx) {
 void bf_timing_stop(bf_ctx* ctx, const char* name, hipEvent_t start) {
   hipEvent_t b = bf_event_get(ctx);
   (void)hipEventRecord(b, ctx->stream);
-  ctx->recs.push_back({name, start, b});
+  ctx->recs.push_back({name, start, b, 0});
+}
+
+void bf_timing_mark_idle(bf_ctx* ctx, size_t from, size_t to) {
+  for (size_t i = from; i < to && i < ctx->recs.size(); ++i) ctx->recs[i].idle = 1;
 }
 
 extern "C" {
@@ -98,13 +102,15 @@ bf_status bf_get_timings(bf_ctx* ctx, bf_kernel_time* out, int32_t cap, int32_t*
   for (auto& r : ctx->recs) {
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, r.a, r.b);
+    char name[sizeof(out[0].name)];
+    snprintf(name, sizeof(name), "%s%s", r.name, r.idle ? "_idle" : "");
     int32_t slot = -1;
     for (int32_t i = 0; i < n && i < cap; ++i)
-      if (strncmp(out[i].name, r.name, sizeof(out[i].name)) == 0) slot = i;
+      if (strncmp(out[i].name, name, sizeof(out[i].name)) == 0) slot = i;
     if (slot < 0 && n < cap) {
       slot = n++;
       memset(&out[slot], 0, sizeof(bf_kernel_time));
-      strncpy(out[slot].name, r.name, sizeof(out[slot].name) - 1);
+      strncpy(out[slot].name, name, sizeof(out[slot].name) - 1);
     }
     if (slot >= 0) {
       out[slot].launches += 1;
@@ -186,6 +192,9 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   bf_dev_free(ctx, band->dense_tsdf);
   bf_dev_free(ctx, band->dense_w);
   bf_dev_free(ctx, band->bricks);
+  bf_dev_free(ctx, band->brick_dist);
+  bf_dev_free(ctx, band->cell_mask);
+  bf_dev_free(ctx, band->cell_start);
   delete band;
   return BF_OK;
 }

@@ -205,6 +205,43 @@ __global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__
   atomicOr(&bits[bit >> 5], 1u << (bit & 31));
 }
 
+// Cell tables for the ray walker: occupancy mask and first band index of
+// every 4^3 cell that holds band voxels.
+__global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict__ keys, int64_t n, int ncell,
+                                                     unsigned long long* __restrict__ mask,
+                                                     int32_t* __restrict__ start) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const uint32_t ci = bf_compact3(key) >> 2, cj = bf_compact3(key >> 1) >> 2, ck = bf_compact3(key >> 2) >> 2;
+  const int64_t c = ((int64_t)ck * ncell + cj) * ncell + ci;
+  atomicOr(&mask[c], 1ull << (key & 63));
+  if (v == 0 || (keys[v - 1] >> 6) != (key >> 6)) start[c] = (int32_t)v;
+}
+
+// Chebyshev distance transform over the brick grid, one axis per pass:
+// out(x) = min over x' of max(|x - x'|, in(x')), with in = 0 on occupied bricks
+// and 255 elsewhere for the first pass.  axis 0 reads the bitmap.
+__global__ __launch_bounds__(256) void k_brick_dist(const uint32_t* __restrict__ bits, const uint8_t* __restrict__ in,
+                                                    uint8_t* __restrict__ out, int nb, int axis) {
+  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t total = (int64_t)nb * nb * nb;
+  if (id >= total) return;
+  const int x = (int)(id % nb), y = (int)((id / nb) % nb), z = (int)(id / ((int64_t)nb * nb));
+  const int pos = axis == 0 ? x : (axis == 1 ? y : z);
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nb : (int64_t)nb * nb);
+  const int64_t base = id - (int64_t)pos * stride;
+  int best = 255;
+  for (int t = 0; t < nb; ++t) {
+    const int64_t j = base + t * stride;
+    const int dv = axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)in[j];
+    const int dd = t > pos ? t - pos : pos - t;
+    const int m = dv > dd ? dv : dd;
+    if (m < best) best = m;
+  }
+  out[id] = (uint8_t)best;
+}
+
 }  // namespace
 
 extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
@@ -325,6 +362,26 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
       return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
     BF_LAUNCH(ctx, "brick_bits", k_brick_bits, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, shift, band->nbrick,
               band->bricks);
+    // brick distances (empty-space skipping) and 4^3 cell tables (voxel lookup) for the ray walker
+    const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
+    uint8_t* dtmp = nullptr;
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, nbr3)) return fail(s);
+    if (bf_status s = bf_ws(ctx, bf_ctx::WS_NBV_TMP, nbr3, (void**)&dtmp)) return fail(s);
+    const unsigned db = (unsigned)bf_cdiv(nbr3, 256);
+    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, (const uint8_t*)nullptr,
+              band->brick_dist, band->nbrick, 0);
+    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, band->brick_dist, dtmp,
+              band->nbrick, 1);
+    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, dtmp, band->brick_dist,
+              band->nbrick, 2);
+    band->ncell = std::max(1, band->P >> 2);
+    const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cell_mask, nc3 * 8)) return fail(s);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cell_start, nc3 * 4)) return fail(s);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(nc3, 256), 16384)), dim3(256), 0,
+                       ctx->stream, band->cell_mask, (uint64_t)nc3, 0ull);
+    BF_LAUNCH(ctx, "cell_tables", k_cell_tables, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->ncell,
+              (unsigned long long*)band->cell_mask, band->cell_start);
     if (bf_status s = bf_launch_check(ctx, "hash/neighbours")) return fail(s);
     if (hipMemcpyAsync(pin, scan_ws, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)

@@ -1,8 +1,8 @@
 // Hutchinson estimate of diag(Q^-1) (Sec. 3.7, eq. 12; Algorithm 1 step 6)
 // with all K probe solves run as one block CG.
 //
-// Layout: block vectors are row-major [N][KC] (KC = K rounded up to 16, 32 or
-// 64), so one band voxel's K values are contiguous: the stencil gathers of a
+// Layout: block vectors are row-major [N][KC] (KC = 1 for a single probe,
+// else K rounded up to 16, 32 or 64), so one band voxel's K values are contiguous: the stencil gathers of a
 // neighbour row are coalesced and the neighbour table and diagonal are read
 // once per row for all K columns.  Every column keeps its own FP64 alpha, beta
 // and stopping test (independent CGs sharing each matrix pass).  Probes z_k
@@ -17,7 +17,9 @@
 namespace {
 
 using namespace bt;
-constexpr int kRowsPerTile = 64;
+// rows per tile: 4 (one column) to 16 (64 columns) values per thread
+template <int KC>
+constexpr int kRowsPerTile = KC == 1 ? 1024 : 64;
 
 __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner) {
   state_init(st, K, tol, max_iter, inner);
@@ -34,9 +36,9 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   const int c = threadIdx.x % KC;
   double v1[1] = {0.0};
   if (st->active[c])
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
-      tile_A<V, KC>(c, (V)st->beta[c], nbr, diag, lam, zz, p_old, p_new, q, tile * kRowsPerTile,
-                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v1[0]);
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+      tile_A<V, KC>(c, (V)st->beta[c], nbr, diag, lam, zz, p_old, p_new, q, tile * kRowsPerTile<KC>,
+                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v1[0]);
   col_block_sum<KC, 1>(v1, lds);
   store_partials<KC, 1>(part, blockIdx.x, v1);
 }
@@ -64,9 +66,9 @@ __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __
   const int c = threadIdx.x % KC;
   double v2[2] = {0.0, 0.0};
   if (st->active[c])
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
-      tile_B<V, KC>(c, (V)st->alpha[c], dinv, p, q, x, r, zz, tile * kRowsPerTile,
-                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v2[0], v2[1]);
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+      tile_B<V, KC>(c, (V)st->alpha[c], dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
+                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v2[0], v2[1]);
   col_block_sum<KC, 2>(v2, lds);
   store_partials<KC, 2>(part, blockIdx.x, v2);
 }
@@ -89,8 +91,8 @@ __global__ __launch_bounds__(256) void k_bfold(const BState* __restrict__ st, in
   if (!force && (st->nactive == 0 || !st->any_check)) return;
   const int c = threadIdx.x % KC;
   if (!force && !(st->active[c] && st->check[c])) return;
-  for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
-    tile_fold<KC>(c, x64, cf, tile * kRowsPerTile, std::min<int64_t>(n, (tile + 1) * kRowsPerTile));
+  for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+    tile_fold<KC>(c, x64, cf, tile * kRowsPerTile<KC>, std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>));
 }
 
 // FP64 residual r = z - Q x for the checked columns (INIT: every active column).
@@ -109,9 +111,9 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   double v3[3] = {0.0, 0.0, 0.0};
   if (act)
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile < n; tile += gridDim.x)
-      tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile,
-                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile), v3);
+    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+      tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
+                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3);
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
@@ -148,7 +150,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                     double* s_out, bf_solve_report* rep) {
   const int64_t N = sys->n;
   const bool mixed = sizeof(V) == 4;
-  const int64_t ntiles = bf_cdiv(N, kRowsPerTile);
+  const int64_t ntiles = bf_cdiv(N, kRowsPerTile<KC>);
   const int nb = (int)std::min<int64_t>(ntiles, 4 * (int64_t)ctx->cu_count);
   const size_t st_bytes = (sizeof(BState) + 255) / 256 * 256;
   const size_t part_bytes = ((size_t)nb * 3 * KC * 8 + 255) / 256 * 256;
@@ -189,9 +191,11 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   int it = 0, next = 3;
   V* pa = p0;
   V* pb = p1;
+  std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
   for (;;) {
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
+      if (ctx->timing) iter_rec.push_back(ctx->recs.size());
       BF_LAUNCH(ctx, "block_A", (k_bA<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, zz, pa,
                 pb, q, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
@@ -209,6 +213,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     if (hs->nactive == 0 || it >= o->max_iter) break;
     next = it + std::max(it, 4);
   }
+  const size_t loop_rec_end = ctx->recs.size();
   if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
   BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, x64, o->seed, o->K,
             N, s_out);
@@ -235,6 +240,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     if (hs->bnorm2[k] > 0.0) maxres = std::max(maxres, sqrt(hs->rr_true[k] / hs->bnorm2[k]));
   }
   if (status == BF_OK && hs->nactive != 0) status = BF_ERR_NOT_CONVERGED;
+  if (ctx->timing && (size_t)maxit < iter_rec.size()) bf_timing_mark_idle(ctx, iter_rec[maxit], loop_rec_end);
   if (rep) {
     rep->iters = maxit;
     rep->status = status;
@@ -251,6 +257,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
 template <typename V>
 bf_status dispatch_k(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, const float* logvar, double* s,
                      bf_solve_report* rep) {
+  if (o->K == 1) return run_block<V, 1>(ctx, sys, o, logvar, s, rep);
   if (o->K <= 16) return run_block<V, 16>(ctx, sys, o, logvar, s, rep);
   if (o->K <= 32) return run_block<V, 32>(ctx, sys, o, logvar, s, rep);
   return run_block<V, 64>(ctx, sys, o, logvar, s, rep);

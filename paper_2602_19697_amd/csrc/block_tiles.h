@@ -3,7 +3,7 @@
 // multi-scene kernel: per-column solver state, the in-register Rademacher
 // probes, the per-tile work of each CG phase and the per-column decisions.
 //
-// Block vectors are row-major [N][KC] (KC = 16, 32 or 64 >= K).  A thread owns
+// Block vectors are row-major [N][KC] (KC = 1, 16, 32 or 64 >= K).  A thread owns
 // one column c = threadIdx.x % KC and rows rsub, rsub + 256/KC, ... of a tile,
 // so each row's KC values and each neighbour row's KC values are read as one
 // coalesced segment while the neighbour table and diagonal are read once per

@@ -3,9 +3,10 @@
 // Each candidate pose casts one ray per pixel of the ray camera.  A thread
 // walks its ray through the voxel grid (Amanatides-Woo, with the next
 // boundary on each axis computed directly from the voxel index so the walk is
-// reproducible), looks every voxel up in the band hash, and sums the
-// quantised variance of the band voxels it crosses up to and including the
-// first voxel whose posterior mean is <= 0.  Variances are quantised to int64
+// reproducible) and sums the quantised variance of the band voxels it crosses
+// up to and including the first voxel whose posterior mean is <= 0.  Band
+// membership is tested only in occupied bricks (a bitmap in LDS), through the
+// 4^3 cell masks; across empty bricks the walk jumps (see walk()).  Variances are quantised to int64
 // (q = rint(s / max s * 2^32)) before summation, so the per-candidate
 // utility is an exact integer independent of summation order: block sums
 // are combined with 64-bit integer atomics.
@@ -48,21 +49,43 @@ __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ s, 
 struct ray_k {
   bf_grid_k g;
   bf_cam_k cam;
-  int log2cap;
-  uint64_t hcap;
   int utility;
   double na, nc, nz0;  // sensor model for the variance-reduction utility
-  int brick_shift, nbrick;
+  int brick_shift, nbrick, ncell;
   int64_t tiles_per_cand, ntiles;
 };
 
 constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
+// Empty-space jumps start at bricks whose nearest occupied brick is at least
+// this many bricks away (Chebyshev); closer to the band the walk steps voxel by voxel.
+constexpr int kJumpMinDist = 2;
+
+// Time at which the ray crosses plane p of one axis (the plane between voxels
+// p - 1 and p).  Every step and every jump evaluates plane times with this one
+// expression, so a jump lands on exactly the state the voxel steps reach.
+__device__ __forceinline__ double plane_t(double org, double h, double o, double inv, int32_t p) {
+#pragma clang fp contract(off)
+  return ((org + (double)p * h) - o) * inv;
+}
 
 // Walk of one ray; returns the ray's integer utility.
+//
+// The voxel sequence is the Amanatides-Woo walk: each step crosses the
+// nearest next plane (lowest axis on ties), with plane times from plane_t.
+// Since every plane time depends only on the plane index, the walk is the
+// merge, ordered by (time, axis), of the three axes' plane sequences, and
+// "every crossing earlier than time c" is a prefix of it.  Inside a cube of
+// bricks known to hold no band voxel the walk jumps: c = the earliest time at
+// which a plane bounding the cube is crossed, and each axis advances by the
+// number of its planes with time < c (estimated from the continuous ray, then
+// corrected with plane_t).  The voxels skipped hold no band voxel, so the
+// visited band voxels, the utility and the stopping voxel are those of the
+// plain walk.
 __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t row, int32_t col,
-                        const uint64_t* __restrict__ hkeys, const int32_t* __restrict__ hvals,
-                        const double* __restrict__ mu, const double* __restrict__ s, const int64_t* __restrict__ q,
-                        double smax, const uint32_t* __restrict__ bricks) {
+                        const unsigned long long* __restrict__ cmask, const int32_t* __restrict__ cstart,
+                        const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
+                        const double* __restrict__ s, const int64_t* __restrict__ q, double smax,
+                        const uint32_t* __restrict__ bricks) {
 #pragma clang fp contract(off)
   const bf_grid_k& g = R.g;
   const double o[3] = {P[3], P[7], P[11]};
@@ -104,41 +127,84 @@ __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t ro
   }
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax)
-    tn[ax] = step[ax] == 0 ? INFINITY
-                           : ((org[ax] + (double)(idx[ax] + (step[ax] > 0 ? 1 : 0)) * g.h) - o[ax]) * inv[ax];
+    tn[ax] = step[ax] == 0 ? INFINITY : plane_t(org[ax], g.h, o[ax], inv[ax], idx[ax] + (step[ax] > 0 ? 1 : 0));
   int64_t score = 0;
+  const int bs = R.brick_shift, NB = R.nbrick, NC = R.ncell;
+  int32_t last_brick = -1, last_dist = 0;
+  // every iteration crosses at least one plane, and a ray crosses at most 3G
   const int64_t max_steps = 3 * (int64_t)g.G + 3;
   for (int64_t it = 0; it < max_steps; ++it) {
-    // only voxels of occupied bricks can be band voxels: look those up
-    const uint32_t bit = (((uint32_t)idx[2] >> R.brick_shift) * R.nbrick + ((uint32_t)idx[1] >> R.brick_shift)) *
-                             R.nbrick + ((uint32_t)idx[0] >> R.brick_shift);
-    const int32_t v = ((bricks[bit >> 5] >> (bit & 31)) & 1u)
-                          ? bf_hash_find(hkeys, hvals, R.log2cap, R.hcap, bf_morton(idx[0], idx[1], idx[2]))
-                          : -1;
-    if (v >= 0) {
-      if (R.utility == BF_UTILITY_SUM_VAR) {
-        score += q[v];
-      } else {
-        // expected variance reduction of one new observation at the voxel's depth
-        const double x = org[0] + ((double)idx[0] + 0.5) * g.h;
-        const double y = org[1] + ((double)idx[1] + 0.5) * g.h;
-        const double z = org[2] + ((double)idx[2] + 0.5) * g.h;
-        const double dx = x - P[3], dy = y - P[7], dz = z - P[11];
-        const double Z = (P[2] * dx + P[6] * dy) + P[10] * dz;
-        const double e = Z - R.nz0;
-        const double sd = R.na + R.nc * (e * e);
-        const double sv = s[v];
-        const double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
-        score += smax > 0.0 ? (int64_t)rint((term / smax) * kScale) : 0;
+    const int32_t bit = (int32_t)((((uint32_t)idx[2] >> bs) * NB + ((uint32_t)idx[1] >> bs)) * NB +
+                                  ((uint32_t)idx[0] >> bs));
+    if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
+      // occupied brick: is this voxel in the band?  (4^3 cell mask, rank by popcount)
+      const int64_t c = ((int64_t)(idx[2] >> 2) * NC + (idx[1] >> 2)) * NC + (idx[0] >> 2);
+      const uint32_t m = (idx[0] & 1) | ((idx[1] & 1) << 1) | ((idx[2] & 1) << 2) | ((idx[0] & 2) << 2) |
+                         ((idx[1] & 2) << 3) | ((idx[2] & 2) << 4);
+      const unsigned long long mk = cmask[c];
+      if ((mk >> m) & 1ull) {
+        const int32_t v = cstart[c] + __popcll(mk & ((1ull << m) - 1ull));
+        if (R.utility == BF_UTILITY_SUM_VAR) {
+          score += q[v];
+        } else {
+          // expected variance reduction of one new observation at the voxel's depth
+          const double x = org[0] + ((double)idx[0] + 0.5) * g.h;
+          const double y = org[1] + ((double)idx[1] + 0.5) * g.h;
+          const double z = org[2] + ((double)idx[2] + 0.5) * g.h;
+          const double dx = x - P[3], dy = y - P[7], dz = z - P[11];
+          const double Z = (P[2] * dx + P[6] * dy) + P[10] * dz;
+          const double e = Z - R.nz0;
+          const double sd = R.na + R.nc * (e * e);
+          const double sv = s[v];
+          const double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
+          score += smax > 0.0 ? (int64_t)rint((term / smax) * kScale) : 0;
+        }
+        if (mu[v] <= 0.0) break;
       }
-      if (mu[v] <= 0.0) break;
+    } else {
+      if (bit != last_brick) {
+        last_brick = bit;
+        last_dist = bdist[bit];
+      }
+      if (last_dist >= kJumpMinDist) {
+        // bricks within Chebyshev radius r of this one are empty: jump to the
+        // last voxel before the walk leaves that cube
+        const int r = last_dist - 1;
+        int32_t lo[3], hi[3];
+        double cut = INFINITY;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const int32_t bb = idx[ax] >> bs;
+          lo[ax] = max(0, (bb - r) << bs);
+          hi[ax] = min(g.G - 1, ((bb + r + 1) << bs) - 1);
+          if (step[ax] != 0) {
+            const double te = plane_t(org[ax], g.h, o[ax], inv[ax], step[ax] > 0 ? hi[ax] + 1 : lo[ax]);
+            cut = te < cut ? te : cut;
+          }
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          if (step[ax] == 0) continue;
+          const int32_t sg = step[ax];
+          const int32_t p0 = idx[ax] + (sg > 0 ? 1 : 0);
+          const int32_t nmax = sg > 0 ? hi[ax] + 1 - p0 : p0 - lo[ax];  // interior planes ahead
+          const double u = ((o[ax] + cut * d[ax]) - org[ax]) / g.h;
+          double ne = sg > 0 ? floor(u) - (double)p0 + 1.0 : (double)p0 - ceil(u) + 1.0;
+          ne = ne < 0.0 ? 0.0 : (ne > (double)nmax ? (double)nmax : ne);
+          int32_t n = (int32_t)ne;
+          while (n > 0 && plane_t(org[ax], g.h, o[ax], inv[ax], p0 + (n - 1) * sg) >= cut) --n;
+          while (n < nmax && plane_t(org[ax], g.h, o[ax], inv[ax], p0 + n * sg) < cut) ++n;
+          idx[ax] += n * sg;
+          tn[ax] = plane_t(org[ax], g.h, o[ax], inv[ax], p0 + n * sg);
+        }
+      }
     }
     int ax = 0;
     if (tn[1] < tn[ax]) ax = 1;
     if (tn[2] < tn[ax]) ax = 2;
     idx[ax] += step[ax];
     if (idx[ax] < 0 || idx[ax] >= g.G) break;
-    tn[ax] = ((org[ax] + (double)(idx[ax] + (step[ax] > 0 ? 1 : 0)) * g.h) - o[ax]) * inv[ax];
+    tn[ax] = plane_t(org[ax], g.h, o[ax], inv[ax], idx[ax] + (step[ax] > 0 ? 1 : 0));
   }
   return score;
 }
@@ -146,8 +212,9 @@ __device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t ro
 // Persistent grid over (candidate, ray tile) work items; one thread per ray.
 // Every workgroup stages the brick bitmap in LDS once.
 __global__ __launch_bounds__(256) void k_nbv_rays(ray_k R, const double* __restrict__ cands,
-                                                  const uint64_t* __restrict__ hkeys,
-                                                  const int32_t* __restrict__ hvals, const double* __restrict__ mu,
+                                                  const unsigned long long* __restrict__ cmask,
+                                                  const int32_t* __restrict__ cstart,
+                                                  const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
                                                   const double* __restrict__ s, const int64_t* __restrict__ q,
                                                   const double* __restrict__ smax_p,
                                                   const uint32_t* __restrict__ bricks_g,
@@ -165,7 +232,7 @@ __global__ __launch_bounds__(256) void k_nbv_rays(ray_k R, const double* __restr
     long long sc = 0;
     if (pix < npix) {
       const int32_t row = (int32_t)(pix / R.cam.W), col = (int32_t)(pix % R.cam.W);
-      sc = walk(R, cands + 12 * cand, row, col, hkeys, hvals, mu, s, q, smax, bricks);
+      sc = walk(R, cands + 12 * cand, row, col, cmask, cstart, bdist, mu, s, q, smax, bricks);
     }
     for (int off = 32; off > 0; off >>= 1) sc += __shfl_xor(sc, off, 64);
     __syncthreads();
@@ -241,13 +308,9 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     hipLaunchKernelGGL(k_max, dim3(nbm), dim3(kThreads), 0, ctx->stream, s_dev, N, (unsigned long long*)smax);
     hipLaunchKernelGGL(k_quantize, dim3((unsigned)bf_cdiv(N, kThreads)), dim3(kThreads), 0, ctx->stream, s_dev, N,
                        smax, q);
-    int l2 = 0;
-    while ((1ull << l2) < band->hcap) ++l2;
     ray_k R{};
     R.g = bf_grid_k{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
     R.cam = bf_cam_k{ray_cam->width, ray_cam->height, ray_cam->fx, ray_cam->fy, ray_cam->cx, ray_cam->cy};
-    R.log2cap = l2;
-    R.hcap = band->hcap;
     R.utility = utility;
     if (noise) {
       R.na = noise->a;
@@ -257,11 +320,13 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     const int64_t npix = (int64_t)ray_cam->width * ray_cam->height;
     R.brick_shift = band->brick_shift;
     R.nbrick = band->nbrick;
+    R.ncell = band->ncell;
     R.tiles_per_cand = bf_cdiv(npix, kThreads);
     R.ntiles = R.tiles_per_cand * n_cand;
     const unsigned grid = (unsigned)std::min<int64_t>(R.ntiles, 16 * (int64_t)ctx->cu_count);
-    BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev, band->hkeys,
-              band->hvals, mu_dev, s_dev, q, smax, band->bricks, (unsigned long long*)scores_dev);
+    BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev,
+              (const unsigned long long*)band->cell_mask, band->cell_start, band->brick_dist, mu_dev, s_dev, q, smax,
+              band->bricks, (unsigned long long*)scores_dev);
   }
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, ctx->stream, scores_dev, n_cand, dbest);
   BF_TRY(bf_launch_check(ctx, "nbv"));

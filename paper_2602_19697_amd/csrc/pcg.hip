@@ -320,9 +320,11 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   V* pa = p0;
   V* pb = p1;
   const V lamV = (V)sys->lambda;
+  std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
   for (;;) {
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
+      if (ctx->timing) iter_rec.push_back(ctx->recs.size());
       BF_LAUNCH(ctx, "pcg_A", k_pcg_A<V>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, z,
                          pa, pb, q, N, part);
       BF_LAUNCH(ctx, "pcg_scalars", k_pcg_alpha, dim3(1), dim3(256), 0, st, part, nb);
@@ -342,6 +344,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     if (hs->done || it >= o->max_iter) break;
     next = o->check_every > 0 ? it + o->check_every : it + std::max(it, 4);
   }
+  const size_t loop_rec_end = ctx->recs.size();
   if (mixed) BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
   BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
                      sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
@@ -353,6 +356,8 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (ctx->timing && hs->iters >= 0 && (size_t)hs->iters < iter_rec.size())
+    bf_timing_mark_idle(ctx, iter_rec[hs->iters], loop_rec_end);
   bf_status status = (bf_status)hs->status;
   if (status == BF_OK && !hs->done) status = BF_ERR_NOT_CONVERGED;
   if (hs->bnorm2 == 0.0) {  // Q x = 0 has the solution x = 0

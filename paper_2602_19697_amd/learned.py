@@ -192,7 +192,7 @@ def main():
         f, t = scene_pairs(ctx, wl, args.lam, seed=k)
         feats.append(f)
         tgts.append(t)
-        if k % 20 == 0:
+        if k % 10 == 0:
             print(f"[data] scene {k} {name} N={f.shape[0]} ({time.time() - t0:.0f}s)", file=sys.stderr, flush=True)
     feats = torch.cat(feats).contiguous()
     tgts = np.concatenate(tgts)

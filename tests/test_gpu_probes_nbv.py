@@ -23,7 +23,8 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("name,K,lam,tol", [("tiny", 8, 10.0, 1e-8), ("sphere64", 16, 10.0, 1e-8),
+@pytest.mark.parametrize("name,K,lam,tol", [("tiny", 1, 10.0, 1e-8), ("sphere64", 1, 1e5, 1e-8),
+                                            ("tiny", 8, 10.0, 1e-8), ("sphere64", 16, 10.0, 1e-8),
                                             ("sphere64", 16, 1e5, 1e-8), ("sphere64", 33, 1e5, 1e-8),
                                             ("sphere64", 64, 1e5, 1e-8)])
 def test_diag_estimate_fp64(ctx, name, K, lam, tol):
@@ -45,7 +46,7 @@ def test_diag_estimate_fp64(ctx, name, K, lam, tol):
     band.free()
 
 
-@pytest.mark.parametrize("lam,K", [(10.0, 16), (1e5, 64)])
+@pytest.mark.parametrize("lam,K", [(10.0, 16), (1e5, 64), (1e5, 1)])
 def test_diag_estimate_mixed(ctx, lam, K):
     import oracle as O
     import paper_2602_19697_amd as bf
@@ -79,6 +80,10 @@ def test_diag_estimate_warm_start(ctx):
     print(f"warm start: iters {rep0['iters']} -> {rep1['iters']}")
     assert rep1["used_warm_start"] == 1 and rep1["iters"] < rep0["iters"]
     assert gc.rel_l2(s1.cpu().numpy(), s_ref) <= 1e-6
+    # one column (its own instantiation) with the same start
+    s_ref1 = O.hutchinson(ref["nbr"], diag, lam, 1, 9, 1e-12)
+    s2, rep2 = ctx.bf_diag_estimate(sys_, 1, 9, 1e-8, logvar=logvar)
+    assert rep2["used_warm_start"] == 1 and gc.rel_l2(s2.cpu().numpy(), s_ref1) <= 1e-6
     sys_.free()
     band.free()
 
