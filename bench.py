@@ -117,9 +117,10 @@ def run_gpu(args):
     prec = bf.L.BF_PREC_FP64 if args.precision == "fp64" else bf.L.BF_PREC_MIXED
     params = None
     if args.learned:
-        if not os.path.exists(WEIGHTS):
-            raise SystemExit(f"--learned needs the trained weights at {WEIGHTS}")
-        params = torch.from_numpy(np.load(WEIGHTS)).to(dev)
+        path = _weights(wl.lam)
+        if path is None:
+            raise SystemExit(f"--learned: no trained warm start for lambda={wl.lam}")
+        params = torch.from_numpy(np.load(path)).to(dev)
 
     def step():
         band = ctx.bf_build_band(grid, wl.cam, depth, poses)
@@ -187,7 +188,13 @@ def run_gpu(args):
                 dominant=dominant)
 
 
-WEIGHTS = os.path.join(ROOT, "paper_2602_19697_amd", "weights", "warm_start_lam10.npy")
+def _weights(lam):
+    from paper_2602_19697_amd import learned
+    try:
+        path = learned.weights_path(lam)
+    except KeyError:
+        return None
+    return path if os.path.exists(path) else None
 
 
 def _timed(fn, reps=3):
@@ -232,8 +239,9 @@ def time_to_tol(g, args):
 
     variants = [("plain_fp64", plain), ("batched_fp64", block(FP64)), ("batched_mixed", block(MIXED))]
     params = None
-    if os.path.exists(WEIGHTS):
-        params = torch.from_numpy(np.load(WEIGHTS)).to(ctx.device)
+    path = _weights(wl.lam)
+    if path is not None:
+        params = torch.from_numpy(np.load(path)).to(ctx.device)
 
         def learned():
             f = ctx.bf_features(sys_)
@@ -393,6 +401,13 @@ def cpu_baseline(g, args):
             "extrapolated_step_s": t_step, "stage_s": t}
 
 
+def _scene_words(wl):
+    from collections import Counter
+    kinds = Counter(type(p).__name__ for p in getattr(wl.scene, "prims", []))
+    names = {"Sphere": "spheres", "RoundedBox": "rounded boxes", "Torus": "tori"}
+    return "union of " + ", ".join(f"{n} {names.get(k, k)}" for k, n in kinds.items())
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -455,7 +470,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: union of 3 spheres, rounded box, torus; {wl.G}^3 grid, "
+        "config": {"workload": f"{wl.name}: {_scene_words(wl)}; {wl.G}^3 grid, "
                                f"h={wl.h} m, band +-{round(wl.band / wl.h)} voxels, {wl.T} views "
                                f"{wl.cam.width}x{wl.cam.height}; {args.precision.upper()} PCG tol {args.tol}"
                                f"{' from the learned start' if args.learned else ''}, "

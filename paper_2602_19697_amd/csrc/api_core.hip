@@ -193,8 +193,7 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   bf_dev_free(ctx, band->dense_w);
   bf_dev_free(ctx, band->bricks);
   bf_dev_free(ctx, band->brick_dist);
-  bf_dev_free(ctx, band->cell_mask);
-  bf_dev_free(ctx, band->cell_start);
+  bf_dev_free(ctx, band->cells);
   delete band;
   return BF_OK;
 }

@@ -208,15 +208,14 @@ __global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__
 // Cell tables for the ray walker: occupancy mask and first band index of
 // every 4^3 cell that holds band voxels.
 __global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict__ keys, int64_t n, int ncell,
-                                                     unsigned long long* __restrict__ mask,
-                                                     int32_t* __restrict__ start) {
+                                                     bf_cell* __restrict__ cells) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
   const uint64_t key = keys[v];
   const uint32_t ci = bf_compact3(key) >> 2, cj = bf_compact3(key >> 1) >> 2, ck = bf_compact3(key >> 2) >> 2;
   const int64_t c = ((int64_t)ck * ncell + cj) * ncell + ci;
-  atomicOr(&mask[c], 1ull << (key & 63));
-  if (v == 0 || (keys[v - 1] >> 6) != (key >> 6)) start[c] = (int32_t)v;
+  atomicOr(&cells[c].mask, 1ull << (key & 63));
+  if (v == 0 || (keys[v - 1] >> 6) != (key >> 6)) cells[c].start = (int32_t)v;
 }
 
 // Chebyshev distance transform over the brick grid, one axis per pass:
@@ -376,12 +375,11 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               band->nbrick, 2);
     band->ncell = std::max(1, band->P >> 2);
     const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cell_mask, nc3 * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cell_start, nc3 * 4)) return fail(s);
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(nc3, 256), 16384)), dim3(256), 0,
-                       ctx->stream, band->cell_mask, (uint64_t)nc3, 0ull);
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cells, nc3 * sizeof(bf_cell))) return fail(s);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(2 * nc3, 256), 16384)), dim3(256), 0,
+                       ctx->stream, (uint64_t*)band->cells, (uint64_t)(2 * nc3), 0ull);
     BF_LAUNCH(ctx, "cell_tables", k_cell_tables, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->ncell,
-              (unsigned long long*)band->cell_mask, band->cell_start);
+              band->cells);
     if (bf_status s = bf_launch_check(ctx, "hash/neighbours")) return fail(s);
     if (hipMemcpyAsync(pin, scan_ws, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
         hipStreamSynchronize(ctx->stream) != hipSuccess)

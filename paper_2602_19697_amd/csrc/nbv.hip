@@ -37,19 +37,22 @@ __global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64
   }
 }
 
-__global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ s, int64_t n,
-                                                  const double* __restrict__ smax, int64_t* __restrict__ q) {
+// q = rint(s / max s * 2^32) >= 0, stored bitwise negated where mu <= 0.
+__global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ s, const double* __restrict__ mu,
+                                                  int64_t n, const double* __restrict__ smax,
+                                                  int64_t* __restrict__ qs) {
 #pragma clang fp contract(off)
   const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
   if (v >= n) return;
   const double m = *smax;
-  q[v] = m > 0.0 ? (int64_t)rint((s[v] / m) * kScale) : 0;
+  const int64_t q = m > 0.0 ? (int64_t)rint((s[v] / m) * kScale) : 0;
+  qs[v] = mu[v] <= 0.0 ? ~q : q;
 }
 
 struct ray_k {
   bf_grid_k g;
   bf_cam_k cam;
-  int utility;
+  double inv_h;        // 1/h, only for the jump estimate (corrected exactly after)
   double na, nc, nz0;  // sensor model for the variance-reduction utility
   int brick_shift, nbrick, ncell;
   int64_t tiles_per_cand, ntiles;
@@ -68,7 +71,8 @@ __device__ __forceinline__ double plane_t(double org, double h, double o, double
   return ((org + (double)p * h) - o) * inv;
 }
 
-// Walk of one ray; returns the ray's integer utility.
+// The walk of one ray, as a state advanced one iteration at a time so that a
+// lane whose ray has ended can start another while the rest of its wave walks.
 //
 // The voxel sequence is the Amanatides-Woo walk: each step crosses the
 // nearest next plane (lowest axis on ties), with plane times from plane_t.
@@ -81,168 +85,214 @@ __device__ __forceinline__ double plane_t(double org, double h, double o, double
 // corrected with plane_t).  The voxels skipped hold no band voxel, so the
 // visited band voxels, the utility and the stopping voxel are those of the
 // plain walk.
-__device__ int64_t walk(const ray_k& R, const double* __restrict__ P, int32_t row, int32_t col,
-                        const unsigned long long* __restrict__ cmask, const int32_t* __restrict__ cstart,
-                        const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
-                        const double* __restrict__ s, const int64_t* __restrict__ q, double smax,
-                        const uint32_t* __restrict__ bricks) {
+//
+// SUM_VAR reads qs[v]: the quantised variance, bitwise negated when the
+// voxel's posterior mean is <= 0 (the walk stops there), so one load serves
+// both.  VAR_REDUCTION reads mu and s.
+struct Ray {
+  double d[3], inv[3], tn[3];
+  int32_t idx[3], step[3];
+  int32_t last_brick, last_dist, iters;
+  int64_t score;
+};
+
+// Starts the ray through pixel (row, col) of the candidate camera at o with
+// rotation P; false when it misses the grid (utility 0).
+__device__ __forceinline__ bool ray_init(Ray& r, const ray_k& R, const double* __restrict__ P, const double (&o)[3],
+                                         int32_t row, int32_t col) {
 #pragma clang fp contract(off)
   const bf_grid_k& g = R.g;
-  const double o[3] = {P[3], P[7], P[11]};
   const double a = ((double)col - R.cam.cx) / R.cam.fx;
   const double b = ((double)row - R.cam.cy) / R.cam.fy;
-  double d[3];
-  d[0] = (P[0] * a + P[1] * b) + P[2];
-  d[1] = (P[4] * a + P[5] * b) + P[6];
-  d[2] = (P[8] * a + P[9] * b) + P[10];
+  r.d[0] = (P[0] * a + P[1] * b) + P[2];
+  r.d[1] = (P[4] * a + P[5] * b) + P[6];
+  r.d[2] = (P[8] * a + P[9] * b) + P[10];
   const double org[3] = {g.ox, g.oy, g.oz};
-  double inv[3];
   double tnear = 0.0, tfar = INFINITY;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     const double lo = org[ax];
     const double hi = org[ax] + (double)g.G * g.h;
-    if (d[ax] == 0.0) {
-      inv[ax] = 0.0;
-      if (o[ax] < lo || o[ax] > hi) return 0;
+    if (r.d[ax] == 0.0) {
+      r.inv[ax] = 0.0;
+      if (o[ax] < lo || o[ax] > hi) return false;
       continue;
     }
-    inv[ax] = 1.0 / d[ax];
-    const double t0 = (lo - o[ax]) * inv[ax];
-    const double t1 = (hi - o[ax]) * inv[ax];
+    r.inv[ax] = 1.0 / r.d[ax];
+    const double t0 = (lo - o[ax]) * r.inv[ax];
+    const double t1 = (hi - o[ax]) * r.inv[ax];
     const double tmin = t0 < t1 ? t0 : t1;
     const double tmax = t0 < t1 ? t1 : t0;
     if (tmin > tnear) tnear = tmin;
     if (tmax < tfar) tfar = tmax;
   }
-  if (!(tnear < tfar)) return 0;
-  int32_t idx[3], step[3];
-  double tn[3];
+  if (!(tnear < tfar)) return false;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
-    const double pa = o[ax] + tnear * d[ax];
+    const double pa = o[ax] + tnear * r.d[ax];
     const double f = floor((pa - org[ax]) / g.h);
-    idx[ax] = f < 0.0 ? 0 : (f > (double)(g.G - 1) ? g.G - 1 : (int32_t)f);
-    step[ax] = d[ax] > 0.0 ? 1 : (d[ax] < 0.0 ? -1 : 0);
+    r.idx[ax] = f < 0.0 ? 0 : (f > (double)(g.G - 1) ? g.G - 1 : (int32_t)f);
+    r.step[ax] = r.d[ax] > 0.0 ? 1 : (r.d[ax] < 0.0 ? -1 : 0);
+    r.tn[ax] = r.step[ax] == 0 ? INFINITY
+                               : plane_t(org[ax], g.h, o[ax], r.inv[ax], r.idx[ax] + (r.step[ax] > 0 ? 1 : 0));
   }
-#pragma unroll
-  for (int ax = 0; ax < 3; ++ax)
-    tn[ax] = step[ax] == 0 ? INFINITY : plane_t(org[ax], g.h, o[ax], inv[ax], idx[ax] + (step[ax] > 0 ? 1 : 0));
-  int64_t score = 0;
-  const int bs = R.brick_shift, NB = R.nbrick, NC = R.ncell;
-  int32_t last_brick = -1, last_dist = 0;
-  // every iteration crosses at least one plane, and a ray crosses at most 3G
-  const int64_t max_steps = 3 * (int64_t)g.G + 3;
-  for (int64_t it = 0; it < max_steps; ++it) {
-    const int32_t bit = (int32_t)((((uint32_t)idx[2] >> bs) * NB + ((uint32_t)idx[1] >> bs)) * NB +
-                                  ((uint32_t)idx[0] >> bs));
-    if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
-      // occupied brick: is this voxel in the band?  (4^3 cell mask, rank by popcount)
-      const int64_t c = ((int64_t)(idx[2] >> 2) * NC + (idx[1] >> 2)) * NC + (idx[0] >> 2);
-      const uint32_t m = (idx[0] & 1) | ((idx[1] & 1) << 1) | ((idx[2] & 1) << 2) | ((idx[0] & 2) << 2) |
-                         ((idx[1] & 2) << 3) | ((idx[2] & 2) << 4);
-      const unsigned long long mk = cmask[c];
-      if ((mk >> m) & 1ull) {
-        const int32_t v = cstart[c] + __popcll(mk & ((1ull << m) - 1ull));
-        if (R.utility == BF_UTILITY_SUM_VAR) {
-          score += q[v];
-        } else {
-          // expected variance reduction of one new observation at the voxel's depth
-          const double x = org[0] + ((double)idx[0] + 0.5) * g.h;
-          const double y = org[1] + ((double)idx[1] + 0.5) * g.h;
-          const double z = org[2] + ((double)idx[2] + 0.5) * g.h;
-          const double dx = x - P[3], dy = y - P[7], dz = z - P[11];
-          const double Z = (P[2] * dx + P[6] * dy) + P[10] * dz;
-          const double e = Z - R.nz0;
-          const double sd = R.na + R.nc * (e * e);
-          const double sv = s[v];
-          const double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
-          score += smax > 0.0 ? (int64_t)rint((term / smax) * kScale) : 0;
-        }
-        if (mu[v] <= 0.0) break;
-      }
-    } else {
-      if (bit != last_brick) {
-        last_brick = bit;
-        last_dist = bdist[bit];
-      }
-      if (last_dist >= kJumpMinDist) {
-        // bricks within Chebyshev radius r of this one are empty: jump to the
-        // last voxel before the walk leaves that cube
-        const int r = last_dist - 1;
-        int32_t lo[3], hi[3];
-        double cut = INFINITY;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const int32_t bb = idx[ax] >> bs;
-          lo[ax] = max(0, (bb - r) << bs);
-          hi[ax] = min(g.G - 1, ((bb + r + 1) << bs) - 1);
-          if (step[ax] != 0) {
-            const double te = plane_t(org[ax], g.h, o[ax], inv[ax], step[ax] > 0 ? hi[ax] + 1 : lo[ax]);
-            cut = te < cut ? te : cut;
-          }
-        }
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          if (step[ax] == 0) continue;
-          const int32_t sg = step[ax];
-          const int32_t p0 = idx[ax] + (sg > 0 ? 1 : 0);
-          const int32_t nmax = sg > 0 ? hi[ax] + 1 - p0 : p0 - lo[ax];  // interior planes ahead
-          const double u = ((o[ax] + cut * d[ax]) - org[ax]) / g.h;
-          double ne = sg > 0 ? floor(u) - (double)p0 + 1.0 : (double)p0 - ceil(u) + 1.0;
-          ne = ne < 0.0 ? 0.0 : (ne > (double)nmax ? (double)nmax : ne);
-          int32_t n = (int32_t)ne;
-          while (n > 0 && plane_t(org[ax], g.h, o[ax], inv[ax], p0 + (n - 1) * sg) >= cut) --n;
-          while (n < nmax && plane_t(org[ax], g.h, o[ax], inv[ax], p0 + n * sg) < cut) ++n;
-          idx[ax] += n * sg;
-          tn[ax] = plane_t(org[ax], g.h, o[ax], inv[ax], p0 + n * sg);
-        }
-      }
-    }
-    int ax = 0;
-    if (tn[1] < tn[ax]) ax = 1;
-    if (tn[2] < tn[ax]) ax = 2;
-    idx[ax] += step[ax];
-    if (idx[ax] < 0 || idx[ax] >= g.G) break;
-    tn[ax] = plane_t(org[ax], g.h, o[ax], inv[ax], idx[ax] + (step[ax] > 0 ? 1 : 0));
-  }
-  return score;
+  r.last_brick = -1;
+  r.last_dist = 0;
+  r.iters = 0;
+  r.score = 0;
+  return true;
 }
 
-// Persistent grid over (candidate, ray tile) work items; one thread per ray.
-// Every workgroup stages the brick bitmap in LDS once.
-__global__ __launch_bounds__(256) void k_nbv_rays(ray_k R, const double* __restrict__ cands,
-                                                  const unsigned long long* __restrict__ cmask,
-                                                  const int32_t* __restrict__ cstart,
-                                                  const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
-                                                  const double* __restrict__ s, const int64_t* __restrict__ q,
-                                                  const double* __restrict__ smax_p,
-                                                  const uint32_t* __restrict__ bricks_g,
-                                                  unsigned long long* __restrict__ scores) {
+// One iteration: test the current voxel (or jump across empty bricks), then
+// step.  Returns false when the ray has ended; r.score then holds its utility.
+template <int UTIL>
+__device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, const double* __restrict__ P,
+                                            const double (&o)[3], const bf_cell* __restrict__ cells,
+                                            const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
+                                            const double* __restrict__ s, const int64_t* __restrict__ qs,
+                                            double smax, const uint32_t* __restrict__ bricks) {
+#pragma clang fp contract(off)
+  const bf_grid_k& g = R.g;
+  const double org[3] = {g.ox, g.oy, g.oz};
+  const int bs = R.brick_shift, NB = R.nbrick, NC = R.ncell;
+  // every iteration crosses at least one plane, and a ray crosses at most 3G
+  if (++r.iters > 3 * g.G + 3) return false;
+  const int32_t bit = (int32_t)((((uint32_t)r.idx[2] >> bs) * NB + ((uint32_t)r.idx[1] >> bs)) * NB +
+                                ((uint32_t)r.idx[0] >> bs));
+  if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
+    // occupied brick: is this voxel in the band?  (4^3 cell mask, rank by popcount)
+    const int64_t c = ((int64_t)(r.idx[2] >> 2) * NC + (r.idx[1] >> 2)) * NC + (r.idx[0] >> 2);
+    const uint32_t m = (r.idx[0] & 1) | ((r.idx[1] & 1) << 1) | ((r.idx[2] & 1) << 2) | ((r.idx[0] & 2) << 2) |
+                       ((r.idx[1] & 2) << 3) | ((r.idx[2] & 2) << 4);
+    const bf_cell cl = cells[c];
+    if ((cl.mask >> m) & 1ull) {
+      const int32_t v = cl.start + __popcll(cl.mask & ((1ull << m) - 1ull));
+      if constexpr (UTIL == BF_UTILITY_SUM_VAR) {
+        const int64_t qv = qs[v];
+        if (qv < 0) {
+          r.score += ~qv;
+          return false;
+        }
+        r.score += qv;
+      } else {
+        // expected variance reduction of one new observation at the voxel's depth
+        const double x = org[0] + ((double)r.idx[0] + 0.5) * g.h;
+        const double y = org[1] + ((double)r.idx[1] + 0.5) * g.h;
+        const double z = org[2] + ((double)r.idx[2] + 0.5) * g.h;
+        const double dx = x - P[3], dy = y - P[7], dz = z - P[11];
+        const double Z = (P[2] * dx + P[6] * dy) + P[10] * dz;
+        const double e = Z - R.nz0;
+        const double sd = R.na + R.nc * (e * e);
+        const double sv = s[v];
+        const double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
+        r.score += smax > 0.0 ? (int64_t)rint((term / smax) * kScale) : 0;
+        if (mu[v] <= 0.0) return false;
+      }
+    }
+  } else {
+    if (bit != r.last_brick) {
+      r.last_brick = bit;
+      r.last_dist = bdist[bit];
+    }
+    if (r.last_dist >= kJumpMinDist) {
+      // bricks within Chebyshev radius rb of this one are empty: jump to the
+      // last voxel before the walk leaves that cube
+      const int rb = r.last_dist - 1;
+      int32_t lo[3], hi[3];
+      double cut = INFINITY;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const int32_t bb = r.idx[ax] >> bs;
+        lo[ax] = max(0, (bb - rb) << bs);
+        hi[ax] = min(g.G - 1, ((bb + rb + 1) << bs) - 1);
+        if (r.step[ax] != 0) {
+          const double te = plane_t(org[ax], g.h, o[ax], r.inv[ax], r.step[ax] > 0 ? hi[ax] + 1 : lo[ax]);
+          cut = te < cut ? te : cut;
+        }
+      }
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        if (r.step[ax] == 0) continue;
+        const int32_t sg = r.step[ax];
+        const int32_t p0 = r.idx[ax] + (sg > 0 ? 1 : 0);
+        const int32_t nmax = sg > 0 ? hi[ax] + 1 - p0 : p0 - lo[ax];  // interior planes ahead
+        const double u = ((o[ax] + cut * r.d[ax]) - org[ax]) * R.inv_h;
+        double ne = sg > 0 ? floor(u) - (double)p0 + 1.0 : (double)p0 - ceil(u) + 1.0;
+        ne = ne < 0.0 ? 0.0 : (ne > (double)nmax ? (double)nmax : ne);
+        int32_t n = (int32_t)ne;
+        while (n > 0 && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + (n - 1) * sg) >= cut) --n;
+        while (n < nmax && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg) < cut) ++n;
+        r.idx[ax] += n * sg;
+        r.tn[ax] = plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg);
+      }
+    }
+  }
+  int ax = 0;
+  if (r.tn[1] < r.tn[ax]) ax = 1;
+  if (r.tn[2] < r.tn[ax]) ax = 2;
+  r.idx[ax] += r.step[ax];
+  if (r.idx[ax] < 0 || r.idx[ax] >= g.G) return false;
+  r.tn[ax] = plane_t(org[ax], g.h, o[ax], r.inv[ax], r.idx[ax] + (r.step[ax] > 0 ? 1 : 0));
+  return true;
+}
+
+// Work queue over (candidate, chunk of kRaysPerTile rays) taken wave by wave;
+// every workgroup stages the brick bitmap in LDS once.  A lane walks the
+// chunk's rays lane, lane + 64, ...: when its ray ends it starts the next one,
+// in batches (once a quarter of the wave is idle, or all of it), so a wave
+// does not wait for its longest ray.
+constexpr int kRaysPerTile = 256;
+constexpr int kRefillBatch = 16;
+
+template <int UTIL>
+__global__ __launch_bounds__(256)
+void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __restrict__ cells,
+                const uint8_t* __restrict__ bdist, const double* __restrict__ mu, const double* __restrict__ s,
+                const int64_t* __restrict__ qs, const double* __restrict__ smax_p,
+                const uint32_t* __restrict__ bricks_g, unsigned int* __restrict__ queue,
+                unsigned long long* __restrict__ scores) {
   __shared__ uint32_t bricks[kMaxBrickWords];
-  __shared__ long long lds[kThreads / 64];
   const int words = (R.nbrick * R.nbrick * R.nbrick + 31) / 32;
   for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
   __syncthreads();
   const double smax = *smax_p;
   const int64_t npix = (int64_t)R.cam.W * R.cam.H;
-  for (int64_t tile = blockIdx.x; tile < R.ntiles; tile += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    unsigned int t = 0;
+    if (lane == 0) t = atomicAdd(queue, 1u);
+    // wave-uniform from here on: the pose and chunk live in scalar registers
+    const int64_t tile = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)__shfl(t, 0, 64));
+    if (tile >= R.ntiles) break;
     const int64_t cand = tile / R.tiles_per_cand;
-    const int64_t pix = (tile % R.tiles_per_cand) * kThreads + threadIdx.x;
-    long long sc = 0;
-    if (pix < npix) {
-      const int32_t row = (int32_t)(pix / R.cam.W), col = (int32_t)(pix % R.cam.W);
-      sc = walk(R, cands + 12 * cand, row, col, cmask, cstart, bdist, mu, s, q, smax, bricks);
+    const int64_t chunk = tile % R.tiles_per_cand;
+    const int64_t p_end = std::min<int64_t>(npix, (chunk + 1) * kRaysPerTile);
+    const double* P = cands + 12 * cand;
+    const double o[3] = {P[3], P[7], P[11]};
+    int64_t next = chunk * kRaysPerTile + lane;
+    long long acc = 0;
+    Ray r;
+    bool live = false;
+    for (;;) {
+      const bool want = !live && next < p_end;
+      const unsigned long long need = __ballot(want);
+      const unsigned long long busy = __ballot(live);
+      if (need == 0 && busy == 0) break;  // wave-uniform
+      if (need != 0 && (__popcll(need) >= kRefillBatch || busy == 0)) {
+        if (want) {
+          const int32_t row = (int32_t)(next / R.cam.W), col = (int32_t)(next % R.cam.W);
+          live = ray_init(r, R, P, o, row, col);
+          next += 64;
+        }
+        continue;
+      }
+      if (live && !ray_advance<UTIL>(r, R, P, o, cells, bdist, mu, s, qs, smax, bricks)) {
+        acc += r.score;
+        live = false;
+      }
     }
-    for (int off = 32; off > 0; off >>= 1) sc += __shfl_xor(sc, off, 64);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = sc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      long long t = 0;
-      for (int w = 0; w < kThreads / 64; ++w) t += lds[w];
-      atomicAdd(&scores[cand], (unsigned long long)t);  // two's complement: exact for signed sums
-    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) atomicAdd(&scores[cand], (unsigned long long)acc);  // two's complement: exact for signed sums
   }
 }
 
@@ -294,24 +344,25 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   BF_CHECK(ctx, cand_c2w_dev && scores_dev, "bf_nbv_score: NULL candidates or scores");
   BF_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t N = band->n;
-  // workspace: smax | best | q [N]
+  // workspace: smax | best | chunk counter | qs [N]
   const int nbm = (int)std::max<int64_t>(1, std::min<int64_t>(bf_cdiv(N, kThreads), 1024));
   char* ws = nullptr;
   BF_TRY(bf_ws(ctx, bf_ctx::WS_NBV, 256 + N * 8, (void**)&ws));
   double* smax = (double*)ws;
   int32_t* dbest = (int32_t*)(ws + 8);
+  unsigned int* queue = (unsigned int*)(ws + 12);
   int64_t* q = (int64_t*)(ws + 256);
   BF_HIP(ctx, hipMemsetAsync(ws, 0, 16, ctx->stream));
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, ctx->stream, scores_dev, n_cand);
   if (N > 0) {
     BF_CHECK(ctx, mu_dev && s_dev, "bf_nbv_score: NULL mu or s");
     hipLaunchKernelGGL(k_max, dim3(nbm), dim3(kThreads), 0, ctx->stream, s_dev, N, (unsigned long long*)smax);
-    hipLaunchKernelGGL(k_quantize, dim3((unsigned)bf_cdiv(N, kThreads)), dim3(kThreads), 0, ctx->stream, s_dev, N,
-                       smax, q);
+    hipLaunchKernelGGL(k_quantize, dim3((unsigned)bf_cdiv(N, kThreads)), dim3(kThreads), 0, ctx->stream, s_dev,
+                       mu_dev, N, smax, q);
     ray_k R{};
     R.g = bf_grid_k{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
     R.cam = bf_cam_k{ray_cam->width, ray_cam->height, ray_cam->fx, ray_cam->fy, ray_cam->cx, ray_cam->cy};
-    R.utility = utility;
+    R.inv_h = 1.0 / band->h;
     if (noise) {
       R.na = noise->a;
       R.nc = noise->c;
@@ -321,12 +372,21 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     R.brick_shift = band->brick_shift;
     R.nbrick = band->nbrick;
     R.ncell = band->ncell;
-    R.tiles_per_cand = bf_cdiv(npix, kThreads);
+    R.tiles_per_cand = bf_cdiv(npix, kRaysPerTile);
     R.ntiles = R.tiles_per_cand * n_cand;
-    const unsigned grid = (unsigned)std::min<int64_t>(R.ntiles, 16 * (int64_t)ctx->cu_count);
-    BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev,
-              (const unsigned long long*)band->cell_mask, band->cell_start, band->brick_dist, mu_dev, s_dev, q, smax,
-              band->bricks, (unsigned long long*)scores_dev);
+    BF_CHECK(ctx, R.ntiles < (1ll << 31), "bf_nbv_score: too many rays");
+    int per_cu = 0;
+    BF_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_nbv_rays<BF_UTILITY_SUM_VAR>,
+                                                             kThreads, 0));
+    const unsigned grid = (unsigned)std::min<int64_t>(R.ntiles, std::max(1, per_cu) * (int64_t)ctx->cu_count);
+    if (utility == BF_UTILITY_SUM_VAR)
+      BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays<BF_UTILITY_SUM_VAR>, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev,
+                band->cells, band->brick_dist, mu_dev, s_dev, q, smax, band->bricks, queue,
+                (unsigned long long*)scores_dev);
+    else
+      BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays<BF_UTILITY_VAR_REDUCTION>, dim3(grid), dim3(kThreads), 0, R,
+                cand_c2w_dev, band->cells, band->brick_dist, mu_dev, s_dev, q, smax, band->bricks, queue,
+                (unsigned long long*)scores_dev);
   }
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, ctx->stream, scores_dev, n_cand, dbest);
   BF_TRY(bf_launch_check(ctx, "nbv"));

@@ -26,6 +26,15 @@ from . import L, Context, grid_struct, noise_struct
 
 N_TRAIN = L.BF_MLP_TRAIN
 N_PARAMS = L.BF_MLP_PARAMS
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+_WEIGHT_NAMES = {10.0: "warm_start_lam10", 1e5: "warm_start_lam1e5"}
+
+
+def weights_path(lam: float, report: bool = False) -> str:
+    """The committed network (or its training report) for prior strength lam."""
+    if float(lam) not in _WEIGHT_NAMES:
+        raise KeyError(f"no trained warm start for lambda={lam}; trained: {sorted(_WEIGHT_NAMES)}")
+    return os.path.join(WEIGHTS_DIR, _WEIGHT_NAMES[float(lam)] + (".json" if report else ".npy"))
 _SHAPES = [(64, 12), (64,), (64, 64), (64,), (64, 64), (64,), (2, 64), (2,)]
 
 

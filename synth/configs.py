@@ -10,6 +10,10 @@ neither is available, so these seeded analytic scenes stand in for them.
                   4 mm voxels, +-4 voxel band, truncation 5 voxels, 40 hemisphere views
                   at 640x480 (fx=fy=525) on a 1.2 m hemisphere.
 * ``union512``  - the same generator on a 512^3 grid of 2 mm voxels, 120 views.
+* ``union512s`` - as union512 with 16 spheres, 6 rounded boxes and 6 tori (a larger band).
+* ``sphere512`` - the sphere64 scene on a 512^3 grid of 2 mm voxels (tests of the 512^3 walk).
+* ``union128``  - the union generator on a 128^3 grid of 8 mm voxels, 24 views at 320x240
+                  (training scenes of the warm start).
 * ``batchsphere`` - sphere64-type scenes whose voxel size is chosen so the band has a
                   seeded log-uniform target size (the uneven multi-scene batch).
 """
@@ -72,8 +76,8 @@ def sphere_workload(name, G, h, beta, trunc, cam, n_views, ring_radius, noise_se
 
 
 def union_workload(name, G, h, n_views, scene_seed, noise_seed, device="cpu",
-                   width=640, height=480, f=525.0, radius=1.2, beta=4, trunc=5, **kw) -> Workload:
-    scene = random_union(scene_seed)
+                   width=640, height=480, f=525.0, radius=1.2, beta=4, trunc=5, primitives=None, **kw) -> Workload:
+    scene = random_union(scene_seed, **(primitives or {}))
     cam = Camera.centred(width, height, f, f)
     poses = hemisphere_poses(n_views, radius)
     depth = add_depth_noise(render_depth(scene, cam, poses, device=device), noise_seed)
@@ -113,6 +117,9 @@ def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
     if name == "sphere64":
         return sphere_workload("sphere64", 64, 0.015, 3, 4, Camera.centred(160, 120, 150.0, 150.0),
                                8, 1.0, seed, device=device, probes=16, tol=1e-8)
+    if name == "sphere512":  # a 512^3 grid (8-voxel bricks) that the oracle can still walk whole
+        return sphere_workload("sphere512", 512, 0.002, 3, 4, Camera.centred(160, 120, 150.0, 150.0),
+                               8, 1.0, seed, device=device, probes=8, tol=1e-6)
     if name == "union128":
         return union_workload("union128", 128, 0.008, 24, seed, seed, device=device,
                               width=320, height=240, f=262.5, tol=1e-6, probes=16)
@@ -122,6 +129,9 @@ def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
     if name == "union512":
         return union_workload("union512", 512, 0.002, 120, seed, seed, device=device,
                               tol=1e-6, probes=32)
+    if name == "union512s":  # the 512^3 pass "sized" with more primitives, for a band of ~1e7 voxels
+        return union_workload("union512s", 512, 0.002, 120, seed, seed, device=device, tol=1e-6, probes=32,
+                              primitives=dict(n_spheres=16, n_boxes=6, n_tori=6))
     if name.startswith("batchsphere"):
         return batch_sphere(int(name[len("batchsphere"):]), device=device)
     if name.startswith("trainsphere"):
