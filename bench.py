@@ -87,7 +87,7 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True):
     if name == "block_A":    # nbr, diag; per column zz, p_old -> p_new, q
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
-        return N * (s + 8 * K * s), "B", "hbm"
+        return N * (s + 7 * K * s), "B", "hbm"
     if name == "tsdf_count":  # 35 FP64 operations per voxel and view + dense store
         return G ** 3 * T * 35, "flop", "alu"
     if name == "assemble":
@@ -208,17 +208,19 @@ def _timed(fn, reps=3):
     return r, 1e3 * (time.perf_counter() - t0) / reps
 
 
-def time_to_tol(g, args):
-    """Mean plus K-probe variance to relative residual 1e-6 on the bench scene:
-    plain FP64 (mean PCG + K sequential one-probe solves, all from zero)
-    against the block FP64 solve, the block mixed solve, and the learned start
-    (features + network, then mixed PCG from x0 and the mixed block solve from
-    the predicted log-variance)."""
+def time_to_tol(g, args, lam=None):
+    """Mean plus K-probe variance to relative residual 1e-6 on the bench scene
+    with prior strength lam: plain FP64 (mean PCG + K sequential one-probe
+    solves, all from zero) against the block FP64 solve, the block mixed solve,
+    and, where a network was trained for lam, the learned start (features +
+    network, then mixed PCG from x0 and the mixed block solve from the
+    predicted log-variance)."""
     import torch
     import paper_2602_19697_amd as bf
     ctx, wl = g["ctx"], g["wl"]
+    lam = wl.lam if lam is None else lam
     band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
-    sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], g["noise"], wl.lam, wl.eps)
+    sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], g["noise"], lam, wl.eps)
     K, tol = args.probes, 1e-6
     FP64, MIXED = bf.L.BF_PREC_FP64, bf.L.BF_PREC_MIXED
 
@@ -239,7 +241,7 @@ def time_to_tol(g, args):
 
     variants = [("plain_fp64", plain), ("batched_fp64", block(FP64)), ("batched_mixed", block(MIXED))]
     params = None
-    path = _weights(wl.lam)
+    path = _weights(lam)
     if path is not None:
         params = torch.from_numpy(np.load(path)).to(ctx.device)
 
@@ -250,7 +252,7 @@ def time_to_tol(g, args):
             _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED, logvar=lv)
             return [r["iters"], pr["col_iters"]]
         variants.append(("learned_batched_mixed", learned))
-    out = {"tol": tol, "probes": K}
+    out = {"lambda": lam, "tol": tol, "probes": K}
     for name, fn in variants:
         its, ms = _timed(fn)
         out[name + "_ms"] = ms
@@ -268,6 +270,70 @@ def time_to_tol(g, args):
     s32, _ = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED)
     out["mixed_rel_err_vs_fp64"] = {"mean": float(torch.linalg.norm(mu32 - mu64) / torch.linalg.norm(mu64)),
                                     "variance": float(torch.linalg.norm(s32 - s64) / torch.linalg.norm(s64))}
+    sys_.free()
+    band.free()
+    return out
+
+
+def stream_copy_gbs():
+    """Achieved device copy bandwidth (bytes read + written per second) of a
+    plain 1 GiB copy: the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * COPY_BYTES * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+
+def solver_section(g, args):
+    """HBM rooflines of the block-PCG kernels where the working set far exceeds
+    the 256 MB Infinity Cache: the 64-probe block solve (mixed and FP64) on the
+    512^3 union scene (about 2.3M band voxels: 0.58 GB per float block vector)
+    with a strong prior (lambda = 1e5, so that it takes tens of iterations)."""
+    import torch
+    import paper_2602_19697_amd as bf
+    from synth import make_workload
+    ctx, dev = g["ctx"], g["ctx"].device
+    wl = make_workload(args.solver_workload, device=dev)
+    depth = torch.from_numpy(np.ascontiguousarray(wl.depth)).to(dev)
+    poses = torch.from_numpy(np.ascontiguousarray(wl.poses)).to(dev)
+    band = ctx.bf_build_band(bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band), wl.cam, depth, poses)
+    lam, K, tol = 1e5, 64, 1e-6
+    sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, bf.noise_struct(*wl.noise), lam, wl.eps)
+    N = band.n
+    out = {"workload": wl.name, "band_voxels": N, "lambda": lam, "probes": K, "tol": tol}
+    for prec, name in ((bf.L.BF_PREC_MIXED, "mixed"), (bf.L.BF_PREC_FP64, "fp64")):
+        ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)  # warm-up (allocations)
+        torch.cuda.synchronize()
+        ctx.bf_get_timings()
+        ctx.bf_set_timing(True)
+        t0 = time.perf_counter()
+        _, rep = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.bf_set_timing(False)
+        tm = ctx.bf_get_timings()
+        res = {"iters": rep["iters"], "column_iters": rep["col_iters"], "wall_ms": wall * 1e3,
+               "voxel_column_iters_per_s": N * rep["col_iters"] / wall}
+        for kname in ("block_A", "block_B"):
+            launches, ms = tm.get(kname, (0, 0.0))
+            if launches == 0:
+                continue
+            amount, _, _ = algorithmic_work(kname, N, K, wl.T, wl.G, 0, fp64=(name == "fp64"))
+            gbs = amount / (ms * 1e-3 / launches) / 1e9
+            res[kname] = {"launches": launches, "avg_us": 1e3 * ms / launches,
+                          "algorithmic_bytes_per_launch": amount, "achieved_GBps": gbs,
+                          "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+        out[name] = res
+        log(f"[solver] {wl.name} N={N} {name}: {rep['iters']} iterations, {wall * 1e3:.1f} ms; "
+            + ", ".join(f"{k} {res[k]['achieved_GBps']:.0f} GB/s" for k in ("block_A", "block_B") if k in res))
     sys_.free()
     band.free()
     return out
@@ -422,6 +488,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-solver-roofline", action="store_true")
+    ap.add_argument("--solver-workload", default="union512")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
     ap.add_argument("--cpu-tsdf-sample", type=int, default=200000)
@@ -441,6 +509,11 @@ def main():
 
     g = run_gpu(args)
     cmp = None if args.no_compare else time_to_tol(g, args)
+    sweep = None
+    if not args.no_compare:
+        sweep = [time_to_tol(g, args, lam) for lam in (1e3, 1e5)]
+    solver = None if args.no_solver_roofline else solver_section(g, args)
+    copy_gbs = None if args.no_compare else stream_copy_gbs()
     batch = None if args.no_batch else batch_section(g, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
     # The roofline is that of the longest-running kernel with a roofline
@@ -484,6 +557,9 @@ def main():
         "rooflines": g["rooflines"],
         "kernels": g["kernels"],
         "time_to_tol": cmp,
+        "time_to_tol_lambda_sweep": sweep,
+        "block_solver_roofline": solver,
+        "stream_copy_GBps": copy_gbs,
         "batch": batch,
         "cpu_baseline": cpu,
     }

@@ -34,9 +34,10 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v1[1] = {0.0};
   if (st->active[c])
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       tile_A<V, KC>(c, (V)st->beta[c], nbr, diag, lam, zz, p_old, p_new, q, tile * kRowsPerTile<KC>,
                     std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v1[0]);
   col_block_sum<KC, 1>(v1, lds);
@@ -64,9 +65,10 @@ __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v2[2] = {0.0, 0.0};
   if (st->active[c])
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       tile_B<V, KC>(c, (V)st->alpha[c], dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
                     std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v2[0], v2[1]);
   col_block_sum<KC, 2>(v2, lds);
@@ -91,7 +93,8 @@ __global__ __launch_bounds__(256) void k_bfold(const BState* __restrict__ st, in
   if (!force && (st->nactive == 0 || !st->any_check)) return;
   const int c = threadIdx.x % KC;
   if (!force && !(st->active[c] && st->check[c])) return;
-  for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
     tile_fold<KC>(c, x64, cf, tile * kRowsPerTile<KC>, std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>));
 }
 
@@ -109,9 +112,10 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   const bool act = mode == MODE_REPORT ? c < st->K
                                        : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v3[3] = {0.0, 0.0, 0.0};
   if (act)
-    for (int64_t tile = blockIdx.x; tile * kRowsPerTile<KC> < n; tile += gridDim.x)
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
                         std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3);
   col_block_sum<KC, 3>(v3, lds);
@@ -151,7 +155,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const int64_t N = sys->n;
   const bool mixed = sizeof(V) == 4;
   const int64_t ntiles = bf_cdiv(N, kRowsPerTile<KC>);
-  const int nb = (int)std::min<int64_t>(ntiles, 4 * (int64_t)ctx->cu_count);
+  // a multiple of 8 workgroups so that each XCD walks a contiguous eighth of the tiles
+  const int nb = (int)bf_round8(std::min<int64_t>(ntiles, 4 * (int64_t)ctx->cu_count));
   const size_t st_bytes = (sizeof(BState) + 255) / 256 * 256;
   const size_t part_bytes = ((size_t)nb * 3 * KC * 8 + 255) / 256 * 256;
   const size_t vec = ((size_t)N * KC * sizeof(V) + 255) / 256 * 256;

@@ -101,27 +101,72 @@ __device__ __forceinline__ void col_partials_sum(const double* __restrict__ part
   }
 }
 
+// Tiles [start, end) with stride of this workgroup in a grid-strided loop
+// over ntiles: with a grid that is a multiple of 8, each XCD's workgroups
+// (b % 8 == x, dispatched round robin) walk one contiguous eighth of the tiles.
+struct TileWalk {
+  int64_t start, stride, end;
+  __device__ explicit TileWalk(int64_t ntiles) {
+    const int64_t g = gridDim.x, b = blockIdx.x;
+    if ((g & 7) == 0) {
+      const int64_t x = b & 7;
+      start = ntiles * x / 8 + (b >> 3);
+      stride = g >> 3;
+      end = ntiles * (x + 1) / 8;
+    } else {
+      start = b;
+      stride = g;
+      end = ntiles;
+    }
+  }
+};
+
 // ---------------------------------------------------------------- tile work
 // A: p = zz + beta p_old (neighbours on the fly), q = Q p; acc += p.q.
+// Each thread keeps kRowsInFlight rows' gathers in flight: the neighbour
+// indices of all of them are loaded first, and absent neighbours (-1) read the
+// row itself and add nothing, so every gather is an unconditional load that the
+// compiler can issue back to back.
+constexpr int kRowsInFlight = 4;
+
 template <typename V, int KC>
 __device__ __forceinline__ void tile_A(int c, V beta, const int32_t* __restrict__ nbr, const V* __restrict__ diag, V lam,
                                        const V* __restrict__ zz, const V* __restrict__ p_old, V* __restrict__ p_new,
                                        V* __restrict__ q, int64_t r0, int64_t r1, double& acc1) {
   constexpr int RS = kThreads / KC;
-  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
-    const int32_t* nb = nbr + v * 6;
-    V s = 0;
+  constexpr int U = kRowsInFlight;
+  for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
+    int64_t vr[U];
+    int32_t nb[U][6];
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const int32_t u = nb[t];
-      if (u >= 0) s += zz[(int64_t)u * KC + c] + beta * p_old[(int64_t)u * KC + c];
+    for (int j = 0; j < U; ++j) {
+      const int64_t v = v0 + j * RS;
+      vr[j] = v < r1 ? v : r0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
     }
-    const int64_t e = v * KC + c;
-    const V pv = zz[e] + beta * p_old[e];
-    const V qv = diag[v] * pv - lam * s;
-    p_new[e] = pv;
-    q[e] = qv;
-    acc1 += (double)pv * (double)qv;
+    V s[U], pv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      s[j] = 0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int64_t u = nb[j][t] >= 0 ? (int64_t)nb[j][t] : vr[j];
+        const V a = zz[u * KC + c] + beta * p_old[u * KC + c];
+        if (nb[j][t] >= 0) s[j] += a;
+      }
+      const int64_t e = vr[j] * KC + c;
+      pv[j] = zz[e] + beta * p_old[e];
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (v0 + j * RS >= r1) break;
+      const int64_t e = vr[j] * KC + c;
+      const V qv = diag[vr[j]] * pv[j] - lam * s[j];
+      p_new[e] = pv[j];
+      q[e] = qv;
+      acc1 += (double)pv[j] * (double)qv;
+    }
   }
 }
 
@@ -156,7 +201,8 @@ __device__ __forceinline__ void tile_fold(int c, double* __restrict__ x64, float
 }
 
 // FP64 residual r = z - Q x (INIT: x = 0 or the warm start exp(logvar) z / diag,
-// written to x64).  acc: r.r, r.zz (stored precision), z.z.
+// written to x64).  acc: r.r, r.zz (stored precision), z.z.  The gathers of
+// x64 are unconditional loads, kRowsInFlight rows at a time, as in tile_A.
 template <typename V, int KC>
 __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const int32_t* __restrict__ nbr,
                                            const double* __restrict__ diag, double lam,
@@ -164,43 +210,69 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
                                            const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
                                            int64_t r0, int64_t r1, double (&v3)[3]) {
   constexpr int RS = kThreads / KC;
-  for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
-    const int64_t e = v * KC + c;
-    const double zv = probe(cs, v);
-    double res = zv;
+  constexpr int U = kRowsInFlight;
+  for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
+    double res[U], zv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t v = v0 + j * RS < r1 ? v0 + j * RS : r0;
+      zv[j] = probe(cs, v);
+      res[j] = zv[j];
+    }
     if (mode == MODE_INIT) {
-      if (logvar) {
-        const int32_t* nb = nbr + v * 6;
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        if (v0 + j * RS >= r1) break;
+        const int64_t v = v0 + j * RS, e = v * KC + c;
+        if (logvar) {
+          const int32_t* nb = nbr + v * 6;
+          double acc = 0.0;
+#pragma unroll
+          for (int t = 0; t < 6; ++t) {
+            const int32_t u = nb[t];
+            if (u >= 0) acc += exp((double)logvar[u]) * probe(cs, u) / diag[u];
+          }
+          const double x0 = exp((double)logvar[v]) * zv[j] / diag[v];
+          x64[e] = x0;
+          res[j] = zv[j] - (diag[v] * x0 - lam * acc);
+        } else {
+          x64[e] = 0.0;
+        }
+      }
+    } else {
+      int64_t vr[U];
+      int32_t nb[U][6];
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
+      }
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
         double acc = 0.0;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-          const int32_t u = nb[t];
-          if (u >= 0) acc += exp((double)logvar[u]) * probe(cs, u) / diag[u];
+          const int64_t u = nb[j][t] >= 0 ? (int64_t)nb[j][t] : vr[j];
+          const double xu = x64[u * KC + c];
+          if (nb[j][t] >= 0) acc += xu;
         }
-        const double x0 = exp((double)logvar[v]) * zv / diag[v];
-        x64[e] = x0;
-        res = zv - (diag[v] * x0 - lam * acc);
-      } else {
-        x64[e] = 0.0;
+        res[j] = zv[j] - (diag[vr[j]] * x64[vr[j] * KC + c] - lam * acc);
       }
-    } else {
-      const int32_t* nb = nbr + v * 6;
-      double acc = 0.0;
-#pragma unroll
-      for (int t = 0; t < 6; ++t) {
-        const int32_t u = nb[t];
-        if (u >= 0) acc += x64[(int64_t)u * KC + c];
-      }
-      res = zv - (diag[v] * x64[e] - lam * acc);
     }
-    v3[0] += res * res;
-    v3[2] += zv * zv;
-    if (mode != MODE_REPORT) {
-      const V rv = (V)res;
-      const V zzv = rv * dinv[v];
-      r[e] = rv;
-      zz[e] = zzv;
-      v3[1] += (double)rv * (double)zzv;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (v0 + j * RS >= r1) break;
+      const int64_t v = v0 + j * RS, e = v * KC + c;
+      v3[0] += res[j] * res[j];
+      v3[2] += zv[j] * zv[j];
+      if (mode != MODE_REPORT) {
+        const V rv = (V)res[j];
+        const V zzv = rv * dinv[v];
+        r[e] = rv;
+        zz[e] = zzv;
+        v3[1] += (double)rv * (double)zzv;
+      }
     }
   }
 }

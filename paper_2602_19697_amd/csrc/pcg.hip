@@ -74,15 +74,16 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
   __shared__ double lds[16];
   if (st->done) return;
   const V beta = (V)st->beta;
-  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double pq = 0.0;
   if (v < n) {
     const int32_t* nb = nbr + v * 6;
     V s = 0;
 #pragma unroll
-    for (int t = 0; t < 6; ++t) {
-      const int32_t u = nb[t];
-      if (u >= 0) s += z[u] + beta * p_old[u];
+    for (int t = 0; t < 6; ++t) {  // unconditional loads: an absent neighbour reads the row itself
+      const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+      const V a = z[u] + beta * p_old[u];
+      if (nb[t] >= 0) s += a;
     }
     const V pv = z[v] + beta * p_old[v];
     const V qv = diag[v] * pv - lam * s;
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(256) void k_pcg_B(PcgState* __restrict__ st, const 
   __shared__ double lds[16];
   if (st->done) return;
   const V alpha = (V)st->alpha;
-  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double rz = 0.0, rr = 0.0;
   if (v < n) {
     x[v] = x[v] + alpha * p[v];
@@ -169,7 +170,7 @@ __global__ __launch_bounds__(256) void k_pcg_beta(PcgState* __restrict__ st, con
 __global__ __launch_bounds__(256) void k_fold(const PcgState* __restrict__ st, int force, double* __restrict__ x64,
                                               float* __restrict__ c, int64_t n) {
   if (!force && (st->done || !st->check)) return;
-  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   if (v < n) {
     x64[v] = x64[v] + (double)c[v];
     c[v] = 0.0f;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
                                                   double* __restrict__ part) {
   __shared__ double lds[16];
   if (mode == MODE_CHECK && (st->done || !st->check)) return;
-  const int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double rr = 0.0, rz = 0.0, bb = 0.0;
   if (v < n) {
     const double hv = rhs[v];
@@ -198,8 +199,9 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
       double s = 0.0;
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
-        const int32_t u = nb[t];
-        if (u >= 0) s += x[u];
+        const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+        const double xu = x[u];
+        if (nb[t] >= 0) s += xu;
       }
       res = hv - (diag[v] * x[v] - lam * s);
     }
@@ -273,7 +275,8 @@ template <typename V>
 bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, const double* rhs, double* x,
                   bf_solve_report* rep) {
   const int64_t N = sys->n;
-  const int nb = (int)bf_cdiv(N, kThreads);
+  // one workgroup per 256 rows, a multiple of 8 workgroups (XCD-contiguous row ranges)
+  const int nb = (int)bf_round8(bf_cdiv(N, kThreads));
   const bool mixed = sizeof(V) == 4;
   // workspace: state | partials [nb][3] | r z p0 p1 q (V) | c (float, mixed)
   const size_t st_bytes = 256;

@@ -95,9 +95,11 @@ def scene_pairs(ctx: Context, wl, lam: float, probes: int = 64, seed: int = 0):
     return feat, tgt
 
 
-def training_scenes(n_sphere: int = 100, n_union: int = 100):
-    """Names of the training scenes: seeded spheres and 128^3 unions."""
-    return [f"trainsphere{s}" for s in range(n_sphere)] + [("union128", 100 + s) for s in range(n_union)]
+def training_scenes(n_sphere: int = 100, n_union: int = 70, n_union256: int = 30):
+    """The training scenes: seeded spheres (voxel edge 12-20 mm), 128^3 unions
+    (8 mm) and 256^3 unions (4 mm), all with seeds disjoint from the held-out ones."""
+    return ([f"trainsphere{s}" for s in range(n_sphere)] + [("union128", 100 + s) for s in range(n_union)]
+            + [("union256", 100 + s) for s in range(n_union256)])
 
 
 def train(ctx: Context, feats, tgts_host, steps: int = 3000, batch: int = 16384, lr: float = 2e-3,
@@ -184,7 +186,8 @@ def main():
     ap = argparse.ArgumentParser(description="train the learned warm start on the GPU")
     ap.add_argument("--lam", type=float, default=10.0)
     ap.add_argument("--spheres", type=int, default=100)
-    ap.add_argument("--unions", type=int, default=100)
+    ap.add_argument("--unions", type=int, default=70)
+    ap.add_argument("--unions256", type=int, default=30)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=16384)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -195,17 +198,18 @@ def main():
     ctx = Context(dev)
     feats, tgts = [], []
     t0 = time.time()
-    for k, item in enumerate(training_scenes(args.spheres, args.unions)):
+    scenes = training_scenes(args.spheres, args.unions, args.unions256)
+    for k, item in enumerate(scenes):
         name, seed = (item, 0) if isinstance(item, str) else item
         wl = make_workload(name, device=dev, seed=seed)
         f, t = scene_pairs(ctx, wl, args.lam, seed=k)
         feats.append(f)
         tgts.append(t)
-        if k % 10 == 0:
+        if k % 10 == 0 or name == "union256":
             print(f"[data] scene {k} {name} N={f.shape[0]} ({time.time() - t0:.0f}s)", file=sys.stderr, flush=True)
     feats = torch.cat(feats).contiguous()
     tgts = np.concatenate(tgts)
-    print(f"[data] {feats.shape[0]} voxels from {len(training_scenes(args.spheres, args.unions))} scenes",
+    print(f"[data] {feats.shape[0]} voxels from {len(scenes)} scenes",
           file=sys.stderr, flush=True)
     params, hist = train(ctx, feats, tgts, steps=args.steps, batch=args.batch, lr=args.lr)
     np.save(args.out, params)
