@@ -48,12 +48,13 @@ COPY_BYTES = 1 << 30
 
 
 def copy_calibration():
-    """A plain device copy of COPY_BYTES (reads and writes that many bytes)."""
+    """A plain streaming kernel over COPY_BYTES: b = a * 1 reads and writes that
+    many bytes (torch's elementwise kernel)."""
     import torch
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
     for _ in range(3):
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
 

@@ -26,20 +26,81 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, d
 }
 
 // A: p = zz + beta p_old, q = Q p, per-column partial p.q.
+//
+// The tile's own rows of p are formed once and staged in LDS (32 KB: 64 to 512
+// rows, by column count and precision); neighbour rows inside the tile are
+// read from there, the others (Morton order keeps most neighbours within a few
+// hundred rows) from global memory as zz + beta p_old.  Every sum runs in the
+// same order as the plain tile, so the results are the same bits.
+template <typename V, int KC>
+constexpr int kStencilRows = KC == 1 ? 1024 : 32768 / (KC * (int)sizeof(V));
+
 template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                             const V* __restrict__ diag, V lam, const V* __restrict__ zz,
                                             const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
                                             int64_t n, double* __restrict__ part) {
+  constexpr int R = kStencilRows<V, KC>;
+  constexpr int RS = kThreads / KC;
   __shared__ double lds[4 * 3 * 64];
+  __shared__ V pt[KC == 1 ? 1 : R * KC];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
-  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  const TileWalk tw(bf_cdiv(n, R));
   double v1[1] = {0.0};
-  if (st->active[c])
-    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-      tile_A<V, KC>(c, (V)st->beta[c], nbr, diag, lam, zz, p_old, p_new, q, tile * kRowsPerTile<KC>,
-                    std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v1[0]);
+  const bool act = st->active[c] != 0;
+  const V beta = (V)st->beta[c];
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    if constexpr (KC == 1) {
+      if (act) tile_A<V, KC>(c, beta, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0]);
+    } else {
+      __syncthreads();  // the previous tile's readers are done
+      if (act)
+        for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+          const int64_t e = v * KC + c;
+          pt[(v - r0) * KC + c] = zz[e] + beta * p_old[e];
+        }
+      __syncthreads();
+      if (act) {
+        constexpr int U = kRowsInFlight;
+        for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
+          int64_t vr[U];
+          int32_t nb[U][6];
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
+          }
+          V sacc[U];
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            sacc[j] = 0;
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+              const int32_t u = nb[j][t];
+              if (u >= r0 && u < r1) {
+                sacc[j] += pt[(u - r0) * KC + c];
+              } else if (u >= 0) {
+                sacc[j] += zz[(int64_t)u * KC + c] + beta * p_old[(int64_t)u * KC + c];
+              }
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < U; ++j) {
+            if (v0 + j * RS >= r1) break;
+            const int64_t e = vr[j] * KC + c;
+            const V pv = pt[(vr[j] - r0) * KC + c];
+            const V qv = diag[vr[j]] * pv - lam * sacc[j];
+            p_new[e] = pv;
+            q[e] = qv;
+            v1[0] += (double)pv * (double)qv;
+          }
+        }
+      }
+    }
+  }
   col_block_sum<KC, 1>(v1, lds);
   store_partials<KC, 1>(part, blockIdx.x, v1);
 }

@@ -227,13 +227,24 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, const double
       }
     }
   }
+  // step across the nearest plane, lowest axis on ties; every array index is a
+  // compile-time constant so the ray state stays in registers
   int ax = 0;
-  if (r.tn[1] < r.tn[ax]) ax = 1;
-  if (r.tn[2] < r.tn[ax]) ax = 2;
-  r.idx[ax] += r.step[ax];
-  if (r.idx[ax] < 0 || r.idx[ax] >= g.G) return false;
-  r.tn[ax] = plane_t(org[ax], g.h, o[ax], r.inv[ax], r.idx[ax] + (r.step[ax] > 0 ? 1 : 0));
-  return true;
+  double tm = r.tn[0];
+  if (r.tn[1] < tm) {
+    ax = 1;
+    tm = r.tn[1];
+  }
+  if (r.tn[2] < tm) ax = 2;
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+    if (a == ax) {
+      r.idx[a] += r.step[a];
+      inside = r.idx[a] >= 0 && r.idx[a] < g.G;
+      r.tn[a] = plane_t(org[a], g.h, o[a], r.inv[a], r.idx[a] + (r.step[a] > 0 ? 1 : 0));
+    }
+  return inside;
 }
 
 // Work queue over (candidate, chunk of kRaysPerTile rays) taken wave by wave;
