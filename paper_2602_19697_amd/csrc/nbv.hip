@@ -13,6 +13,7 @@
 #include "bf_internal.h"
 
 #include <climits>
+#include <cstdlib>
 
 namespace {
 
@@ -53,15 +54,20 @@ struct ray_k {
   bf_grid_k g;
   bf_cam_k cam;
   double inv_h;        // 1/h, only for the jump estimate (corrected exactly after)
+  int jump_min;        // jump from empty bricks at least this far (Chebyshev, bricks) from the band
+  int jump_batch;      // ... once this many lanes of the wave want to jump (or a quarter of the live ones)
+  int refill_batch;    // idle lanes start new rays once this many are idle (or the whole wave)
   double na, nc, nz0;  // sensor model for the variance-reduction utility
   int brick_shift, nbrick, ncell;
   int64_t tiles_per_cand, ntiles;
 };
 
 constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
-// Empty-space jumps start at bricks whose nearest occupied brick is at least
-// this many bricks away (Chebyshev); closer to the band the walk steps voxel by voxel.
-constexpr int kJumpMinDist = 2;
+// Defaults of the walk's tuning knobs (see ray_k); BF_NBV_JUMP_MIN,
+// BF_NBV_JUMP_BATCH and BF_NBV_REFILL_BATCH override them.  None changes a result.
+constexpr int kJumpMinDist = 1;
+constexpr int kJumpBatch = 32;
+constexpr int kRefillBatch = 16;
 
 // Time at which the ray crosses plane p of one axis (the plane between voxels
 // p - 1 and p).  Every step and every jump evaluates plane times with this one
@@ -146,7 +152,7 @@ __device__ __forceinline__ bool ray_init(Ray& r, const ray_k& R, const double* _
 // One iteration: test the current voxel (or jump across empty bricks), then
 // step.  Returns false when the ray has ended; r.score then holds its utility.
 template <int UTIL>
-__device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, const double* __restrict__ P,
+__device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, const double* __restrict__ P,
                                             const double (&o)[3], const bf_cell* __restrict__ cells,
                                             const uint8_t* __restrict__ bdist, const double* __restrict__ mu,
                                             const double* __restrict__ s, const int64_t* __restrict__ qs,
@@ -194,7 +200,12 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, const double
       r.last_brick = bit;
       r.last_dist = bdist[bit];
     }
-    if (r.last_dist >= kJumpMinDist) {
+    // The jump costs as much as several voxel steps and the wave executes it for
+    // all lanes at once, so it runs only when enough lanes want it; the others
+    // (and these, meanwhile) take an ordinary voxel step, which is always exact.
+    const bool want = r.last_dist >= R.jump_min;
+    const int nwant = __popcll(__ballot(want));
+    if (want && (nwant >= R.jump_batch || 4 * nwant >= nlive)) {
       // bricks within Chebyshev radius rb of this one are empty: jump to the
       // last voxel before the walk leaves that cube
       const int rb = r.last_dist - 1;
@@ -253,7 +264,6 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, const double
 // in batches (once a quarter of the wave is idle, or all of it), so a wave
 // does not wait for its longest ray.
 constexpr int kRaysPerTile = 256;
-constexpr int kRefillBatch = 16;
 
 template <int UTIL>
 __global__ __launch_bounds__(256)
@@ -289,7 +299,7 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
       const unsigned long long need = __ballot(want);
       const unsigned long long busy = __ballot(live);
       if (need == 0 && busy == 0) break;  // wave-uniform
-      if (need != 0 && (__popcll(need) >= kRefillBatch || busy == 0)) {
+      if (need != 0 && (__popcll(need) >= R.refill_batch || busy == 0)) {
         if (want) {
           const int32_t row = (int32_t)(next / R.cam.W), col = (int32_t)(next % R.cam.W);
           live = ray_init(r, R, P, o, row, col);
@@ -297,7 +307,7 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
         }
         continue;
       }
-      if (live && !ray_advance<UTIL>(r, R, P, o, cells, bdist, mu, s, qs, smax, bricks)) {
+      if (live && !ray_advance<UTIL>(r, R, __popcll(busy), P, o, cells, bdist, mu, s, qs, smax, bricks)) {
         acc += r.score;
         live = false;
       }
@@ -339,6 +349,13 @@ __global__ __launch_bounds__(1024) void k_argmax(const int64_t* __restrict__ sc,
   if (threadIdx.x == 0) *best = bi[0];
 }
 
+int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* v = getenv(name);
+  if (!v) return dflt;
+  const int x = atoi(v);
+  return x < lo ? lo : (x > hi ? hi : x);
+}
+
 }  // namespace
 
 extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev, const double* s_dev,
@@ -374,6 +391,9 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     R.g = bf_grid_k{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
     R.cam = bf_cam_k{ray_cam->width, ray_cam->height, ray_cam->fx, ray_cam->fy, ray_cam->cx, ray_cam->cy};
     R.inv_h = 1.0 / band->h;
+    R.jump_min = env_int("BF_NBV_JUMP_MIN", kJumpMinDist, 1, 256);
+    R.jump_batch = env_int("BF_NBV_JUMP_BATCH", kJumpBatch, 1, 64);
+    R.refill_batch = env_int("BF_NBV_REFILL_BATCH", kRefillBatch, 1, 64);
     if (noise) {
       R.na = noise->a;
       R.nc = noise->c;
