@@ -233,6 +233,12 @@ bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
                        const bf_camera* ray_cam, int32_t utility, const bf_noise* noise,
                        int64_t* scores_dev, int32_t* best_host);
 
+/* Voxel visits of the plain Amanatides-Woo walk summed over every ray of the
+ * last bf_nbv_score call on ctx (voxels visited, plus voxels skipped by the
+ * exact empty-space jumps, which the plain walk would have visited): the
+ * "DDA steps" of that call.  Host only; valid after bf_nbv_score returned. */
+bf_status bf_nbv_walk_steps(bf_ctx* ctx, int64_t* steps);
+
 /* ---------------------------------------------------------------- batched solves */
 /* Many systems (scenes of uneven band size) solved together: the work list is
  * every system's row tiles in the schedule's order.  Persistent: one

@@ -86,6 +86,8 @@ def lib():
         L.orc_nbv_candidate.restype = C.c_int64
         L.orc_nbv_candidate.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _I64,
                                         _D]
+        L.orc_nbv_candidate_steps.restype = C.c_int64
+        L.orc_nbv_candidate_steps.argtypes = L.orc_nbv_candidate.argtypes
         L.orc_nbv_candidate_u.restype = C.c_int64
         L.orc_nbv_candidate_u.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D,
                                           _I64, C.POINTER(Utility), _D]
@@ -290,6 +292,17 @@ def nbv_scores(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
     return np.array([lib().orc_nbv_candidate(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
                                              np.ascontiguousarray(cands[c]))
                      for c in idx], dtype=np.int64)
+
+
+def nbv_walk_steps(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
+    """Voxels visited by the walks of each listed candidate's rays (as nbv_scores)."""
+    keys = _c(keys, np.uint64)
+    mu = _c(mu, np.float64)
+    q = _c(q, np.int64)
+    cands = _c(cands, np.float64).reshape(-1, 12)
+    idx = range(cands.shape[0]) if which is None else which
+    return np.array([lib().orc_nbv_candidate_steps(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
+                                                   _c(cands[i], np.float64)) for i in idx], dtype=np.int64)
 
 
 def nbv_scores_var_reduction(g: Grid, ray_cam: Cam, keys, mu, s, cands, noise=(0.0012, 0.0019, 0.4),

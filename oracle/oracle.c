@@ -531,6 +531,25 @@ int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* cam, const uint64_t*
   return orc_nbv_candidate_u(g, cam, keys, N, mu, q, NULL, P);
 }
 
+/* Voxels visited by the walks of every ray of one candidate (the same rays */
+/* and walk as orc_nbv_candidate; only the visit count is returned).         */
+int64_t orc_nbv_candidate_steps(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                                const double* mu, const int64_t* q, const double* P) {
+  int64_t steps = 0;
+  double o[3] = {P[3], P[7], P[11]};
+  for (int32_t row = 0; row < cam->height; ++row)
+    for (int32_t col = 0; col < cam->width; ++col) {
+      double a = ((double)col - cam->cx) / cam->fx;
+      double b = ((double)row - cam->cy) / cam->fy;
+      double d[3];
+      d[0] = (P[0] * a + P[1] * b) + P[2];
+      d[1] = (P[4] * a + P[5] * b) + P[6];
+      d[2] = (P[8] * a + P[9] * b) + P[10];
+      orc_nbv_ray_u(g, keys, N, mu, q, NULL, NULL, o, d, &steps);
+    }
+  return steps;
+}
+
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores) {
   int32_t best = 0;
   for (int32_t c = 1; c < n; ++c)

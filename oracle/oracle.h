@@ -96,6 +96,9 @@ int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const do
                     const int64_t* q, const double* o, const double* d, int64_t* steps_out);
 int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* ray_cam, const uint64_t* keys,
                           int64_t N, const double* mu, const int64_t* q, const double* c2w);
+/* Voxels visited by the walks of every ray of one candidate. */
+int64_t orc_nbv_candidate_steps(const orc_grid* g, const orc_cam* ray_cam, const uint64_t* keys, int64_t N,
+                                const double* mu, const int64_t* q, const double* P);
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores);
 void orc_features(int64_t N, int32_t T, double h, const double* tsdf, const int32_t* w,
                   const int32_t* nbr, const int32_t* deg, const double* Lambda, const double* acc,

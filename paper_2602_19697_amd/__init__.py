@@ -326,6 +326,11 @@ class Context:
         return s, rep.as_dict()
 
     # ---------------------------------------------------------- NBV
+    def bf_nbv_walk_steps(self) -> int:
+        v = C.c_int64()
+        self._check(self.lib.bf_nbv_walk_steps(self.handle, C.byref(v)))
+        return int(v.value)
+
     def bf_nbv_score(self, band: Band, mu, s, cands, ray_cam, utility=L.BF_UTILITY_SUM_VAR, noise=None):
         n = int(cands.shape[0])
         scores = torch.empty(n, dtype=torch.int64, device=self.device)

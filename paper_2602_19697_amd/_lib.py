@@ -115,6 +115,7 @@ SIGNATURES = {
                                    C.POINTER(bf_solve_report)]),
     "bf_nbv_score": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(bf_camera), C.c_int32,
                                C.POINTER(bf_noise), P, C.POINTER(C.c_int32)]),
+    "bf_nbv_walk_steps": (C.c_int, [P, C.POINTER(C.c_int64)]),
     "bf_diag_estimate_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_probe_opts), C.POINTER(bf_schedule),
                                            P, C.POINTER(bf_solve_report)]),
     "bf_pcg_solve_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_solve_opts), C.POINTER(bf_schedule), P,

@@ -99,6 +99,7 @@ struct Ray {
   double d[3], inv[3], tn[3];
   int32_t idx[3], step[3];
   int32_t last_brick, last_dist, iters;
+  int32_t steps;  // voxels the plain walk visits (visited here or jumped over)
   int64_t score;
 };
 
@@ -145,6 +146,7 @@ __device__ __forceinline__ bool ray_init(Ray& r, const ray_k& R, const double* _
   r.last_brick = -1;
   r.last_dist = 0;
   r.iters = 0;
+  r.steps = 0;
   r.score = 0;
   return true;
 }
@@ -163,6 +165,7 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
   const int bs = R.brick_shift, NB = R.nbrick, NC = R.ncell;
   // every iteration crosses at least one plane, and a ray crosses at most 3G
   if (++r.iters > 3 * g.G + 3) return false;
+  ++r.steps;
   const int32_t bit = (int32_t)((((uint32_t)r.idx[2] >> bs) * NB + ((uint32_t)r.idx[1] >> bs)) * NB +
                                 ((uint32_t)r.idx[0] >> bs));
   if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
@@ -234,6 +237,7 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
         while (n > 0 && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + (n - 1) * sg) >= cut) --n;
         while (n < nmax && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg) < cut) ++n;
         r.idx[ax] += n * sg;
+        r.steps += n;
         r.tn[ax] = plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg);
       }
     }
@@ -271,7 +275,7 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
                 const uint8_t* __restrict__ bdist, const double* __restrict__ mu, const double* __restrict__ s,
                 const int64_t* __restrict__ qs, const double* __restrict__ smax_p,
                 const uint32_t* __restrict__ bricks_g, unsigned int* __restrict__ queue,
-                unsigned long long* __restrict__ scores) {
+                unsigned long long* __restrict__ walk_steps, unsigned long long* __restrict__ scores) {
   __shared__ uint32_t bricks[kMaxBrickWords];
   const int words = (R.nbrick * R.nbrick * R.nbrick + 31) / 32;
   for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
@@ -292,6 +296,7 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
     const double o[3] = {P[3], P[7], P[11]};
     int64_t next = chunk * kRaysPerTile + lane;
     long long acc = 0;
+    unsigned long long nsteps = 0;
     Ray r;
     bool live = false;
     for (;;) {
@@ -309,11 +314,18 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
       }
       if (live && !ray_advance<UTIL>(r, R, __popcll(busy), P, o, cells, bdist, mu, s, qs, smax, bricks)) {
         acc += r.score;
+        nsteps += (unsigned long long)r.steps;
         live = false;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) atomicAdd(&scores[cand], (unsigned long long)acc);  // two's complement: exact for signed sums
+    for (int off = 32; off > 0; off >>= 1) {
+      acc += __shfl_xor(acc, off, 64);
+      nsteps += __shfl_xor(nsteps, off, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&scores[cand], (unsigned long long)acc);  // two's complement: exact for signed sums
+      atomicAdd(walk_steps, nsteps);
+    }
   }
 }
 
@@ -368,6 +380,7 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
            "bf_nbv_score: unknown utility or missing noise model");
   BF_CHECK(ctx, ray_cam->width > 0 && ray_cam->height > 0, "bf_nbv_score: bad ray camera");
   *best_host = -1;
+  ctx->nbv_walk_steps = 0;
   if (n_cand == 0) return BF_OK;
   BF_CHECK(ctx, cand_c2w_dev && scores_dev, "bf_nbv_score: NULL candidates or scores");
   BF_HIP(ctx, hipSetDevice(ctx->device));
@@ -379,8 +392,9 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   double* smax = (double*)ws;
   int32_t* dbest = (int32_t*)(ws + 8);
   unsigned int* queue = (unsigned int*)(ws + 12);
+  unsigned long long* walk_steps = (unsigned long long*)(ws + 16);
   int64_t* q = (int64_t*)(ws + 256);
-  BF_HIP(ctx, hipMemsetAsync(ws, 0, 16, ctx->stream));
+  BF_HIP(ctx, hipMemsetAsync(ws, 0, 24, ctx->stream));
   hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, ctx->stream, scores_dev, n_cand);
   if (N > 0) {
     BF_CHECK(ctx, mu_dev && s_dev, "bf_nbv_score: NULL mu or s");
@@ -413,18 +427,26 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     if (utility == BF_UTILITY_SUM_VAR)
       BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays<BF_UTILITY_SUM_VAR>, dim3(grid), dim3(kThreads), 0, R, cand_c2w_dev,
                 band->cells, band->brick_dist, mu_dev, s_dev, q, smax, band->bricks, queue,
-                (unsigned long long*)scores_dev);
+                walk_steps, (unsigned long long*)scores_dev);
     else
       BF_LAUNCH(ctx, "nbv_rays", k_nbv_rays<BF_UTILITY_VAR_REDUCTION>, dim3(grid), dim3(kThreads), 0, R,
                 cand_c2w_dev, band->cells, band->brick_dist, mu_dev, s_dev, q, smax, band->bricks, queue,
-                (unsigned long long*)scores_dev);
+                walk_steps, (unsigned long long*)scores_dev);
   }
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(1024), 0, ctx->stream, scores_dev, n_cand, dbest);
   BF_TRY(bf_launch_check(ctx, "nbv"));
   int32_t* pin = nullptr;
-  BF_TRY(bf_pinned(ctx, 8, (void**)&pin));
-  BF_HIP(ctx, hipMemcpyAsync(pin, dbest, 4, hipMemcpyDeviceToHost, ctx->stream));
+  BF_TRY(bf_pinned(ctx, 16, (void**)&pin));
+  BF_HIP(ctx, hipMemcpyAsync(pin, dbest, 16, hipMemcpyDeviceToHost, ctx->stream));
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
-  *best_host = *pin;
+  *best_host = pin[0];
+  ctx->nbv_walk_steps = *(const int64_t*)(pin + 2);
+  return BF_OK;
+}
+
+extern "C" bf_status bf_nbv_walk_steps(bf_ctx* ctx, int64_t* steps) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, steps, "bf_nbv_walk_steps: NULL argument");
+  *steps = ctx->nbv_walk_steps;
   return BF_OK;
 }

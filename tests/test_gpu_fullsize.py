@@ -80,3 +80,8 @@ def test_fullsize_nbv_sampled_bitexact(full):
     want = O.nbv_scores(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=sample)
     print(f"[union256] NBV best={best} sample={sample} scores={got[sample]}")
     assert np.array_equal(got[sample], want)
+    one = torch.from_numpy(np.ascontiguousarray(cands[best:best + 1])).to(gc.DEV)
+    ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV), one, wl.ray_cam)
+    steps = O.nbv_walk_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=[best])[0]
+    print(f"[union256] candidate {best}: walk steps {ctx.bf_nbv_walk_steps()} (oracle {steps})")
+    assert ctx.bf_nbv_walk_steps() == steps

@@ -86,6 +86,11 @@ def test_sphere512_nbv_sampled_bitexact(sphere512):
     want = O.nbv_scores(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=sample)
     print(f"[sphere512] NBV best={best} sample={sample} scores={got[sample]}", flush=True)
     assert np.array_equal(got[sample], want)
+    # visit counts of the 8-voxel-brick walk with jumps equal the plain walk's
+    one = torch.from_numpy(np.ascontiguousarray(cands[best:best + 1])).to(gc.DEV)
+    ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV), one, wl.ray_cam)
+    steps = O.nbv_walk_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=[best])[0]
+    assert ctx.bf_nbv_walk_steps() == steps
 
 
 # ---------------------------------------------------------------- union512

@@ -118,6 +118,27 @@ def test_nbv_bitexact_shared_inputs(ctx, name, ncand):
     band.free()
 
 
+@pytest.mark.parametrize("name", ["tiny", "sphere64"])
+def test_nbv_walk_steps_match_oracle(ctx, name):
+    """The walk with its empty-space jumps visits (or jumps over) exactly the
+    voxels of the oracle's plain walk: equal visit counts, candidate by candidate."""
+    import oracle as O
+    wl, ref, mu, s = _shared_nbv_inputs(name)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    cands = wl.candidates()
+    q = O.quantize_variance(s)
+    mu_d, s_d = torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV)
+    for c in (0, 7, 300):
+        one = torch.from_numpy(np.ascontiguousarray(cands[c:c + 1])).to(gc.DEV)
+        ctx.bf_nbv_score(band, mu_d, s_d, one, wl.ray_cam)
+        got = ctx.bf_nbv_walk_steps()
+        want = int(O.nbv_walk_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=[c])[0])
+        print(f"[{name}] candidate {c}: walk steps {got} (oracle {want})")
+        assert got == want > 0
+    sys_.free()
+    band.free()
+
+
 def test_nbv_var_reduction_bitexact(ctx):
     import oracle as O
     import paper_2602_19697_amd as bf

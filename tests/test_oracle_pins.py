@@ -380,6 +380,25 @@ def test_nbv_ray_stops_at_surface(orc):
         assert orc.nbv_ray(g, keys, mu, q, o, d)[0] == want
 
 
+def test_nbv_candidate_steps_sum_rays(orc):
+    """A candidate's visit count is the sum of its pixel rays' walks, each pinned
+    above against dense sampling; rays through pixel centres of the ray camera."""
+    G, h = 8, 0.125
+    g = orc.grid(G, h, (-0.5,) * 3, 0.5, 0.25)
+    keys = _full_band(orc, G)
+    mu = np.ones(len(keys))
+    q = np.ones(len(keys), dtype=np.int64)
+    cam = orc.cam(type("C", (), dict(width=6, height=5, fx=4.0, fy=4.0, cx=2.37, cy=1.91))())
+    # camera near (0, 0, -1.5) looking along +z (OpenCV axes), off the grid's symmetry planes
+    P = np.array([1.0, 0.0, 0.0, 0.013, 0.0, 1.0, 0.0, -0.021, 0.0, 0.0, 1.0, -1.5])
+    total = 0
+    for row in range(5):
+        for col in range(6):
+            d = np.array([(col - 2.37) / 4.0, (row - 1.91) / 4.0, 1.0])
+            total += len(_sample_voxels(g, P[[3, 7, 11]], d))
+    assert orc.nbv_walk_steps(g, cam, keys, mu, q, P[None, :])[0] == total > 0
+
+
 def test_nbv_ties_lowest_index(orc):
     assert orc.nbv_argmax(np.array([3, 7, 7, 1], dtype=np.int64)) == 1
     assert orc.nbv_argmax(np.array([5, 5], dtype=np.int64)) == 0
