@@ -133,7 +133,7 @@ def run_gpu(args):
         mu, rep = ctx.bf_pcg_solve(sys_, args.tol, precision=prec, x0=x0)
         s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
-        out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"],
+        out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
         sys_.free()
@@ -528,9 +528,11 @@ def main():
     wl = g["wl"]
     nbv = g["kernels"].get("nbv_rays")
     rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height
+    steps = g["info"]["walk_steps"]
     nbv_info = None if nbv is None else {
         "rays_per_launch": rays, "avg_ms": nbv["avg_us"] * 1e-3, "rays_per_s": rays / (nbv["avg_us"] * 1e-6),
-        "share_of_step": nbv["share_of_step"], "bound": "latency (no roofline claim)"}
+        "dda_steps_per_launch": steps, "dda_steps_per_s": steps / (nbv["avg_us"] * 1e-6),
+        "share_of_step": nbv["share_of_step"], "bound": "latency / instruction issue (no roofline claim)"}
     line = {
         "metric": "band voxel-PCG-iters/s, probe-solves/s; learned+batched vs plain time-to-1e-6",
         "value": g["value"],
