@@ -211,18 +211,26 @@ def _timed(fn, reps=3):
 
 def time_to_tol(g, args, lam=None):
     """Mean plus K-probe variance to relative residual 1e-6 on the bench scene
-    with prior strength lam: plain FP64 (mean PCG + K sequential one-probe
-    solves, all from zero) against the block FP64 solve, the block mixed solve,
-    and, where a network was trained for lam, the learned start (features +
-    network, then mixed PCG from x0 and the mixed block solve from the
-    predicted log-variance)."""
-    import torch
-    import paper_2602_19697_amd as bf
+    with prior strength lam (see compare_solvers)."""
     ctx, wl = g["ctx"], g["wl"]
     lam = wl.lam if lam is None else lam
     band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
     sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], g["noise"], lam, wl.eps)
-    K, tol = args.probes, 1e-6
+    out = compare_solvers(ctx, sys_, lam, args.probes)
+    sys_.free()
+    band.free()
+    return out
+
+
+def compare_solvers(ctx, sys_, lam, K, reps=3, plain_reps=None):
+    """Time to 1e-6 for the mean and the K-probe variance of one system: plain
+    FP64 (mean PCG + K sequential one-probe solves, all from zero) against the
+    block FP64 solve, the block mixed solve, and, where a network was trained
+    for lam, the learned start (features + network, then mixed PCG from x0 and
+    the mixed block solve from the predicted log-variance)."""
+    import torch
+    import paper_2602_19697_amd as bf
+    tol = 1e-6
     FP64, MIXED = bf.L.BF_PREC_FP64, bf.L.BF_PREC_MIXED
 
     def plain():
@@ -255,7 +263,7 @@ def time_to_tol(g, args, lam=None):
         variants.append(("learned_batched_mixed", learned))
     out = {"lambda": lam, "tol": tol, "probes": K}
     for name, fn in variants:
-        its, ms = _timed(fn)
+        its, ms = _timed(fn, plain_reps if (plain_reps and name == "plain_fp64") else reps)
         out[name + "_ms"] = ms
         out[name + "_iters"] = {"mean": its[0], "probe_columns": its[1]}
     out["speedup_batching"] = out["plain_fp64_ms"] / out["batched_fp64_ms"]
@@ -271,8 +279,6 @@ def time_to_tol(g, args, lam=None):
     s32, _ = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED)
     out["mixed_rel_err_vs_fp64"] = {"mean": float(torch.linalg.norm(mu32 - mu64) / torch.linalg.norm(mu64)),
                                     "variance": float(torch.linalg.norm(s32 - s64) / torch.linalg.norm(s64))}
-    sys_.free()
-    band.free()
     return out
 
 
@@ -335,6 +341,11 @@ def solver_section(g, args):
         out[name] = res
         log(f"[solver] {wl.name} N={N} {name}: {rep['iters']} iterations, {wall * 1e3:.1f} ms; "
             + ", ".join(f"{k} {res[k]['achieved_GBps']:.0f} GB/s" for k in ("block_A", "block_B") if k in res))
+    # time to tolerance on this large system with 32 probes (learned start trained at lambda = 1e5)
+    out["time_to_tol"] = compare_solvers(ctx, sys_, lam, 32, reps=2, plain_reps=1)
+    t = out["time_to_tol"]
+    log(f"[solver] time to 1e-6: plain {t['plain_fp64_ms']:.1f} ms, block fp64 {t['batched_fp64_ms']:.1f}, "
+        f"block mixed {t['batched_mixed_ms']:.1f}, learned {t.get('learned_batched_mixed_ms', float('nan')):.1f}")
     sys_.free()
     band.free()
     return out

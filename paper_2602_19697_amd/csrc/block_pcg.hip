@@ -12,6 +12,8 @@
 // folds/residuals and restarted float solves (mixed-precision iterative
 // refinement).  The per-tile work and the per-column decisions live in
 // block_tiles.h and are shared with the persistent multi-scene solver.
+#include <cstdlib>
+
 #include "block_tiles.h"
 
 namespace {
@@ -32,15 +34,15 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, d
 // read from there, the others (Morton order keeps most neighbours within a few
 // hundred rows) from global memory as zz + beta p_old.  Every sum runs in the
 // same order as the plain tile, so the results are the same bits.
-template <typename V, int KC>
-constexpr int kStencilRows = KC == 1 ? 1024 : 32768 / (KC * (int)sizeof(V));
+template <typename V, int KC, int LDSKB>
+constexpr int kStencilRows = KC == 1 ? 1024 : LDSKB * 1024 / (KC * (int)sizeof(V));
 
-template <typename V, int KC>
+template <typename V, int KC, int LDSKB>
 __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                             const V* __restrict__ diag, V lam, const V* __restrict__ zz,
                                             const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
                                             int64_t n, double* __restrict__ part) {
-  constexpr int R = kStencilRows<V, KC>;
+  constexpr int R = kStencilRows<V, KC, LDSKB>;
   constexpr int RS = kThreads / KC;
   __shared__ double lds[4 * 3 * 64];
   __shared__ V pt[KC == 1 ? 1 : R * KC];
@@ -254,6 +256,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
   BF_TRY(bf_pinned(ctx, sizeof(BState), (void**)&hs));
+  // LDS per workgroup for the stencil tile (KB): 32 measured best on the 256^3 and 512^3 bands
+  // (8: -12%, 16: -5%, 64: -34% at two workgroups per CU); BF_STENCIL_LDS_KB in {16, 32, 64} overrides
+  const char* skb = getenv("BF_STENCIL_LDS_KB");
+  const int stencil_kb = skb ? atoi(skb) : 32;
   int it = 0, next = 3;
   V* pa = p0;
   V* pb = p1;
@@ -262,8 +268,19 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
       if (ctx->timing) iter_rec.push_back(ctx->recs.size());
-      BF_LAUNCH(ctx, "block_A", (k_bA<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, zz, pa,
-                pb, q, N, part);
+      switch (stencil_kb) {
+        case 16:
+          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
+                    zz, pa, pb, q, N, part);
+          break;
+        case 64:
+          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 64>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
+                    zz, pa, pb, q, N, part);
+          break;
+        default:
+          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
+                    zz, pa, pb, q, N, part);
+      }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);

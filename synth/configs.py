@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import Optional
 
 import numpy as np
@@ -61,6 +62,21 @@ class Workload:
         return sphere_candidates(self.n_cand, self.cand_radius)
 
 
+def _cached_depth(name, seed, render):
+    """Rendered noisy depth, kept in $BF_SYNTH_CACHE (if set) as <name>_<seed>.npy
+    so that repeated runs (profilers) skip the ray casting."""
+    cache = os.environ.get("BF_SYNTH_CACHE")
+    if not cache:
+        return render()
+    path = os.path.join(cache, f"{name}_{seed}.npy")
+    if os.path.exists(path):
+        return np.load(path)
+    depth = render()
+    os.makedirs(cache, exist_ok=True)
+    np.save(path, depth)
+    return depth
+
+
 def _grid(G: int, h: float):
     o = -G * h / 2.0
     return (o, o, o)
@@ -70,7 +86,8 @@ def sphere_workload(name, G, h, beta, trunc, cam, n_views, ring_radius, noise_se
                     radius=0.30, device="cpu", **kw) -> Workload:
     scene = single_sphere(radius)
     poses = ring_poses(n_views, ring_radius)
-    depth = add_depth_noise(render_depth(scene, cam, poses, device=device), noise_seed)
+    depth = _cached_depth(name, noise_seed, lambda: add_depth_noise(
+        render_depth(scene, cam, poses, device=device), noise_seed))
     return Workload(name=name, G=G, h=h, origin=_grid(G, h), tau=trunc * h, band=beta * h,
                     cam=cam, poses=poses, depth=depth, scene=scene, **kw)
 
@@ -80,7 +97,8 @@ def union_workload(name, G, h, n_views, scene_seed, noise_seed, device="cpu",
     scene = random_union(scene_seed, **(primitives or {}))
     cam = Camera.centred(width, height, f, f)
     poses = hemisphere_poses(n_views, radius)
-    depth = add_depth_noise(render_depth(scene, cam, poses, device=device), noise_seed)
+    depth = _cached_depth(name, noise_seed, lambda: add_depth_noise(
+        render_depth(scene, cam, poses, device=device), noise_seed))
     return Workload(name=name, G=G, h=h, origin=_grid(G, h), tau=trunc * h, band=beta * h,
                     cam=cam, poses=poses, depth=depth, scene=scene, **kw)
 
