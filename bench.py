@@ -59,16 +59,16 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}), flush=True)
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counters, or None if
-    there are none for it or its source changed since they were taken."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counters, or None if there are none or its source changed since."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as f:
         rec = json.load(f)
     entry = rec.get("kernels", {}).get(kernel)
-    if entry is None:
+    if entry is None or entry.get("workload") != workload:
         return None
     with open(os.path.join(ROOT, entry["source"]), "rb") as f:
         if hashlib.sha256(f.read()).hexdigest() != entry["source_sha256"]:
@@ -78,7 +78,14 @@ def measured_traffic(kernel):
     return fetch + write
 
 
-def algorithmic_work(name, N, K, T, G, P, fp64=True):
+# FP64 operations per fused voxel-view of the coarse TSDF (projection, two
+# divisions, truncation, running sum) and per screened (4^3 cell, view) pair
+# (8 corner projections, bounds, pyramid lookup).
+TSDF_OPS_PER_VOXEL_VIEW = 35
+TSDF_OPS_PER_CELL_VIEW = 340
+
+
+def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None):
     """(amount, unit, bound) of one launch of a timed kernel."""
     s = 8 if fp64 else 4
     if name == "pcg_A":      # nbr, diag, z, p_old -> p_new, q
@@ -89,8 +96,10 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True):
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
         return N * (s + 7 * K * s), "B", "hbm"
-    if name == "tsdf_count":  # 35 FP64 operations per voxel and view + dense store
-        return G ** 3 * T * 35, "flop", "alu"
+    if name == "tsdf_count":  # fused voxel-views + screened cell-views
+        vv = G ** 3 * T if voxel_views is None else voxel_views
+        cells = -(-G // 4) ** 3
+        return vv * TSDF_OPS_PER_VOXEL_VIEW + cells * T * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
     if name == "assemble":
         return N * T * 45, "flop", "alu"
     return None
@@ -134,6 +143,7 @@ def run_gpu(args):
         s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
+                   tsdf_voxel_views=band.arrays()["tsdf_voxel_views"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
         sys_.free()
@@ -169,7 +179,8 @@ def run_gpu(args):
         P *= 2
     rooflines = {}
     for name, kt in kernels.items():
-        w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P)
+        w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
+                             voxel_views=info["tsdf_voxel_views"])
         if w is None:
             continue
         amount, unit, bound = w
@@ -535,7 +546,11 @@ def main():
     roof = None
     if g["rooflines"]:
         dom = max(g["rooflines"], key=lambda k: g["kernels"][k]["share_of_step"])
-        roof = dict(g["rooflines"][dom], kernel=dom, traffic=measured_traffic(dom))
+        roof = dict(g["rooflines"][dom], kernel=dom, traffic=measured_traffic(dom, g["wl"].name))
+        if dom == "tsdf_count":
+            full = g["wl"].G ** 3 * g["wl"].T
+            roof["fused_voxel_views"] = g["info"]["tsdf_voxel_views"]
+            roof["screened_fraction"] = 1.0 - g["info"]["tsdf_voxel_views"] / full
     wl = g["wl"]
     nbv = g["kernels"].get("nbv_rays")
     rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height

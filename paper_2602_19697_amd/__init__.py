@@ -113,7 +113,7 @@ class Band:
                "w": _view(a.w, (n,), torch.int32, dev),
                "nbr": _view(a.nbr, (n, 6), torch.int32, dev),
                "deg": _view(a.deg, (n,), torch.int32, dev),
-               "dense_side": int(a.dense_side)}
+               "dense_side": int(a.dense_side), "tsdf_voxel_views": int(a.tsdf_voxel_views)}
         P3 = int(a.dense_side) ** 3
         if a.dense_tsdf:
             out["dense_tsdf"] = _view(a.dense_tsdf, (P3,), torch.float64, dev)

@@ -176,6 +176,7 @@ bf_status bf_band_view(const bf_band* band, bf_band_arrays* out) {
   out->deg = band->deg;
   out->dense_tsdf = band->dense_tsdf;
   out->dense_w = band->dense_w;
+  out->tsdf_voxel_views = band->tsdf_voxel_views;
   return BF_OK;
 }
 

@@ -6,6 +6,16 @@
 // key order and a block-wise stream compaction emits the band already sorted.
 // Morton-local voxels also project to nearby pixels, which keeps the depth
 // gathers of a block inside a few cache lines.
+//
+// Screening: only voxels of the band need an exact TSDF.  Before fusing a
+// block, every 4^3 cell of it is tested against every view with a min/max
+// pyramid of the valid depths: if in each view every voxel of the cell either
+// sees free space further than the band half-width in front of the surface
+// (all its observations exceed the band, as the truncation does) or lies more
+// than tau behind it (occluded: skipped), no voxel of the cell can be in the
+// band, and the cell is not fused.  The band (keys, TSDF, weights) is the
+// same bit for bit; the dense grid then holds W = 0 for screened cells, so
+// screening is off when the dense grid is kept for inspection.
 #include "bf_internal.h"
 
 namespace {
@@ -25,20 +35,141 @@ __global__ __launch_bounds__(256) void k_validate_depth(const float* __restrict_
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// Min/max pyramid of the valid depths of every view: level l holds, per
+// 2^l x 2^l pixel block, the smallest and largest depth D > 0 (+inf / -1 when
+// the block has none).  Levels are packed per view at offsets off[l].
+constexpr int kMaxLevels = 16;
+struct Pyr {
+  int nl;
+  int32_t w[kMaxLevels], h[kMaxLevels];
+  int64_t off[kMaxLevels];
+  int64_t per_view;
+};
+
+__global__ __launch_bounds__(256) void k_pyr_base(const float* __restrict__ depth, int64_t npix_view, int T,
+                                                  Pyr P, float* __restrict__ dmin, float* __restrict__ dmax) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= npix_view * T) return;
+  const int64_t t = i / npix_view, p = i % npix_view;
+  const float d = depth[i];
+  dmin[t * P.per_view + p] = d > 0.0f ? d : INFINITY;
+  dmax[t * P.per_view + p] = d > 0.0f ? d : -1.0f;
+}
+
+__global__ __launch_bounds__(256) void k_pyr_level(int T, Pyr P, int l, float* __restrict__ dmin,
+                                                   float* __restrict__ dmax) {
+  const int64_t cells = (int64_t)P.w[l] * P.h[l];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= cells * T) return;
+  const int64_t t = i / cells, q = i % cells;
+  const int32_t x = (int32_t)(q % P.w[l]), y = (int32_t)(q / P.w[l]);
+  const int32_t pw = P.w[l - 1], ph = P.h[l - 1];
+  const int64_t base = t * P.per_view + P.off[l - 1];
+  float lo = INFINITY, hi = -1.0f;
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      const int32_t cx = 2 * x + dx, cy = 2 * y + dy;
+      if (cx < pw && cy < ph) {
+        lo = fminf(lo, dmin[base + (int64_t)cy * pw + cx]);
+        hi = fmaxf(hi, dmax[base + (int64_t)cy * pw + cx]);
+      }
+    }
+  dmin[t * P.per_view + P.off[l] + q] = lo;
+  dmax[t * P.per_view + P.off[l] + q] = hi;
+}
+
+// Can view t put a voxel of the 4^3 cell with lowest voxel (i0, j0, k0) into
+// the band?  False only when provably not (see the file comment); the bounds
+// use the cell's 8 corner voxel centres (the extremes of Z and of the
+// projected u, v over a box are at its corners) with generous margins.
+__device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
+                                     const float* __restrict__ dmin, const float* __restrict__ dmax,
+                                     const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0) {
+  double zlo = INFINITY, zhi = -INFINITY, ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+  bool behind = false;
+#pragma unroll
+  for (int corner = 0; corner < 8; ++corner) {
+    const double x = g.ox + ((double)(i0 + ((corner & 1) ? 3 : 0)) + 0.5) * g.h;
+    const double y = g.oy + ((double)(j0 + ((corner & 2) ? 3 : 0)) + 0.5) * g.h;
+    const double z = g.oz + ((double)(k0 + ((corner & 4) ? 3 : 0)) + 0.5) * g.h;
+    const double dx = x - Pose[3], dy = y - Pose[7], dz = z - Pose[11];
+    const double X = Pose[0] * dx + Pose[4] * dy + Pose[8] * dz;
+    const double Y = Pose[1] * dx + Pose[5] * dy + Pose[9] * dz;
+    const double Z = Pose[2] * dx + Pose[6] * dy + Pose[10] * dz;
+    zlo = fmin(zlo, Z);
+    zhi = fmax(zhi, Z);
+    if (Z <= 1e-6) {
+      behind = true;
+    } else {
+      const double u = c.fx * X / Z + c.cx, v = c.fy * Y / Z + c.cy;
+      ulo = fmin(ulo, u);
+      uhi = fmax(uhi, u);
+      vlo = fmin(vlo, v);
+      vhi = fmax(vhi, v);
+    }
+  }
+  if (zhi <= 0.0) return false;  // the whole cell is behind the camera: never observed
+  if (behind) return true;        // straddles the camera plane: no projection bound
+  // pixel (floor(u + 1/2)) range, widened by a thousandth of a pixel for rounding
+  const double c0f = floor(ulo + 0.5 - 1e-3), c1f = floor(uhi + 0.5 + 1e-3);
+  const double r0f = floor(vlo + 0.5 - 1e-3), r1f = floor(vhi + 0.5 + 1e-3);
+  if (c1f < 0.0 || r1f < 0.0 || c0f >= (double)c.W || r0f >= (double)c.H) return false;  // outside the image
+  const int32_t c0 = (int32_t)fmax(c0f, 0.0), c1 = (int32_t)fmin(c1f, (double)(c.W - 1));
+  const int32_t r0 = (int32_t)fmax(r0f, 0.0), r1 = (int32_t)fmin(r1f, (double)(c.H - 1));
+  int l = 0;
+  while (l < P.nl - 1 && (((c1 >> l) - (c0 >> l)) > 1 || ((r1 >> l) - (r0 >> l)) > 1)) ++l;
+  const int64_t base = (int64_t)t * P.per_view + P.off[l];
+  float lo = INFINITY, hi = -1.0f;
+  const int32_t xs[2] = {c0 >> l, c1 >> l}, ys[2] = {r0 >> l, r1 >> l};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int64_t q = base + (int64_t)ys[a] * P.w[l] + xs[b];
+      lo = fminf(lo, dmin[q]);
+      hi = fmaxf(hi, dmax[q]);
+    }
+  if (hi < 0.0f) return false;                                   // no valid depth under the cell
+  const double margin = 1e-9 + 1e-12 * (zhi > 0.0 ? zhi : 0.0);
+  if ((double)lo - zhi > g.band + margin) return false;          // free space beyond the band
+  if ((double)hi - zlo < -g.tau - margin) return false;          // occluded: every view skipped
+  return true;
+}
+
 // One block tile of Morton codes: fuse every view into the coarse TSDF of each
 // voxel (unit weights, truncation, occlusion test), store the dense grid and
 // count the band predicate |TSDF| <= band, W > 0.
+constexpr int kCells = kTile / 64;  // 4^3 cells per block tile
+
 __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
                                                     const float* __restrict__ depth,
                                                     const double* __restrict__ poses,
                                                     uint64_t total, double* __restrict__ dense_t,
                                                     int32_t* __restrict__ dense_w,
-                                                    uint32_t* __restrict__ counts) {
+                                                    uint32_t* __restrict__ counts, int screen, Pyr P,
+                                                    const float* __restrict__ dmin,
+                                                    const float* __restrict__ dmax,
+                                                    unsigned long long* __restrict__ evaluated) {
 #pragma clang fp contract(off)
   __shared__ uint32_t wave_cnt[kThreads / 64];
+  __shared__ int live[kCells];
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const int64_t plane = (int64_t)c.W * c.H;
-  uint32_t cnt = 0;
+  if (threadIdx.x < kCells) live[threadIdx.x] = screen ? 0 : 1;
+  __syncthreads();
+  if (screen) {
+    for (int e = threadIdx.x; e < kCells * T; e += kThreads) {
+      const int cell = e % kCells, t = e / kCells;
+      const uint64_t m0 = base + (uint64_t)cell * 64;
+      if (m0 >= total) continue;
+      const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
+                    k0 = (int32_t)bf_compact3(m0 >> 2);
+      if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
+      if (cell_view_may_matter(g, c, P, dmin, dmax, poses + 12 * t, t, i0, j0, k0)) atomicOr(&live[cell], 1);
+    }
+    __syncthreads();
+  }
+  uint32_t cnt = 0, fused = 0;
   for (int it = 0; it < kItems; ++it) {
     const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
     if (m >= total) break;
@@ -46,7 +177,8 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
                   k = (int32_t)bf_compact3(m >> 2);
     double tsdf = 0.0;
     int32_t W = 0;
-    if (i < g.G && j < g.G && k < g.G) {
+    if (i < g.G && j < g.G && k < g.G && live[(m - base) >> 6]) {
+      ++fused;
       double S = 0.0;
       for (int32_t t = 0; t < T; ++t) {
         double D, Z;
@@ -63,8 +195,14 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
     cnt += (W > 0 && fabs(tsdf) <= g.band) ? 1u : 0u;
   }
   // block count (integer: any order is exact)
-  for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
-  if ((threadIdx.x & 63) == 0) wave_cnt[threadIdx.x >> 6] = cnt;
+  for (int off = 32; off > 0; off >>= 1) {
+    cnt += __shfl_xor(cnt, off, 64);
+    fused += __shfl_xor(fused, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wave_cnt[threadIdx.x >> 6] = cnt;
+    if (fused) atomicAdd(evaluated, (unsigned long long)fused * (unsigned long long)T);
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t s = 0;
@@ -308,20 +446,54 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   }
   bf_grid_k gk{grid->G, grid->h, grid->origin[0], grid->origin[1], grid->origin[2], grid->tau, grid->band};
   bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+  // screening pyramid (off when the dense grid is kept, or when truncation does not exceed the band)
+  const int screen = (!(flags & BF_BAND_KEEP_DENSE) && grid->tau > grid->band && npix > 0) ? 1 : 0;
+  Pyr pyr{};
+  float* dmin = nullptr;
+  float* dmax = nullptr;
+  if (screen) {
+    int32_t w = cam->width, h = cam->height;
+    int64_t off = 0;
+    for (;;) {
+      if (pyr.nl >= kMaxLevels) return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth image too large"));
+      pyr.w[pyr.nl] = w;
+      pyr.h[pyr.nl] = h;
+      pyr.off[pyr.nl] = off;
+      off += (int64_t)w * h;
+      ++pyr.nl;
+      if (w == 1 && h == 1) break;
+      w = (w + 1) / 2;
+      h = (h + 1) / 2;
+    }
+    pyr.per_view = off;
+    void* pw = nullptr;
+    const size_t half = ((size_t)off * T * sizeof(float) + 255) / 256 * 256;
+    if (bf_status s = bf_ws(ctx, bf_ctx::WS_PYR, 2 * half, &pw)) return fail(s);
+    dmin = (float*)pw;
+    dmax = (float*)((char*)pw + half);
+    const int64_t npv = (int64_t)cam->width * cam->height;
+    BF_LAUNCH(ctx, "depth_pyramid", k_pyr_base, dim3((unsigned)bf_cdiv(npv * T, 256)), dim3(256), 0, depth_dev, npv,
+              T, pyr, dmin, dmax);
+    for (int l = 1; l < pyr.nl; ++l)
+      BF_LAUNCH(ctx, "depth_pyramid", k_pyr_level, dim3((unsigned)bf_cdiv((int64_t)pyr.w[l] * pyr.h[l] * T, 256)),
+                dim3(256), 0, T, pyr, l, dmin, dmax);
+  }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
-                     depth_dev, c2w_dev, total, dense_t, dense_w, counts);
+                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax,
+                     (unsigned long long*)((char*)scan_ws + 24));
   if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
   BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal);
   if (bf_status s = bf_launch_check(ctx, "k_scan_counts")) return fail(s);
 
   void* pin = nullptr;
   if (bf_status s = bf_pinned(ctx, 64, &pin)) return fail(s);
-  if (hipMemcpyAsync(pin, scan_ws, 24, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+  if (hipMemcpyAsync(pin, scan_ws, 32, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: count read-back failed"));
   if (((int*)pin)[0] & 1)
     return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth holds NaN, inf or negative values"));
   const uint64_t N = *(uint64_t*)((char*)pin + 16);
+  band->tsdf_voxel_views = *(const int64_t*)((char*)pin + 24);
   if (N >= (1ull << 31) - 1) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing", (unsigned long long)N));
   band->n = (int64_t)N;
 

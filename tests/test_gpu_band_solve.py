@@ -45,6 +45,29 @@ def test_band_bitexact(ctx, name):
     band.free()
 
 
+@pytest.mark.parametrize("name,seed", [("tiny", 0), ("sphere64", 0), ("union128", 3)])
+def test_band_screening_exact(ctx, name, seed):
+    """The screened coarse TSDF (cells that provably hold no band voxel are not
+    fused) yields the oracle's band bit for bit, and skips most of the work."""
+    wl = gc.workload(name, seed)
+    ref = gc.oracle_ref(name, seed)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    a = band.arrays()
+    full = wl.G ** 3 * wl.T
+    print(f"[{name}] screened: {a['tsdf_voxel_views']} of {full} voxel-views fused "
+          f"({100.0 * a['tsdf_voxel_views'] / full:.1f}%)", flush=True)
+    for key in ("keys", "tsdf", "w", "nbr", "deg"):
+        assert np.array_equal(a[key].cpu().numpy(), ref[key]), key
+    assert 0 < a["tsdf_voxel_views"] < full
+    sys_.free()
+    band.free()
+    # with the dense grid kept, nothing is screened
+    band2, sys2, _, _ = gc.gpu_system(ctx, wl, keep_dense=True)
+    assert band2.arrays()["tsdf_voxel_views"] == full
+    sys2.free()
+    band2.free()
+
+
 @pytest.mark.parametrize("name", ["tiny", "sphere64"])
 def test_assembly_bitexact(ctx, name):
     wl = gc.workload(name)
