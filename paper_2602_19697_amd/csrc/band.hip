@@ -337,6 +337,9 @@ __global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
   const uint64_t key = keys[v];
+  // a brick is a Morton range of 2^(3 shift) keys and the band is sorted, so
+  // only the first band voxel of each brick sets its bit
+  if (v > 0 && (keys[v - 1] >> (3 * shift)) == (key >> (3 * shift))) return;
   const uint32_t bi = bf_compact3(key) >> shift, bj = bf_compact3(key >> 1) >> shift,
                  bk = bf_compact3(key >> 2) >> shift;
   const uint32_t bit = (bk * nbrick + bj) * nbrick + bi;

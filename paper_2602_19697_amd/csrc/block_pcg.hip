@@ -199,11 +199,27 @@ __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mo
   if (threadIdx.x == 0) decide_R(st, c, mode, tot, nullptr);
 }
 
+// s_v = (1/K) sum_k z_k[v] u_k[v].  Lanes run along the columns of a row
+// (coalesced reads of the [N][KC] block), the products go through LDS, and
+// one thread per row sums them in ascending k, the order of hutch_row.
 template <int KC>
 __global__ __launch_bounds__(256) void k_hutch_final(const double* __restrict__ x64, uint64_t seed, int K,
                                                      int64_t n, double* __restrict__ s_out) {
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v < n) s_out[v] = hutch_row<KC>(x64, seed, K, v);
+  constexpr int RS = kThreads / KC;
+  __shared__ double prod[kThreads];
+  const int c = threadIdx.x % KC;
+  const uint64_t cs = splitmix_out(seed, (uint64_t)c);
+  for (int64_t r0 = blockIdx.x * (int64_t)RS; r0 < n; r0 += (int64_t)gridDim.x * RS) {
+    const int64_t v = r0 + threadIdx.x / KC;
+    prod[threadIdx.x] = (v < n && c < K) ? probe(cs, v) * x64[v * KC + c] : 0.0;
+    __syncthreads();
+    if (threadIdx.x < RS && r0 + threadIdx.x < n) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += prod[threadIdx.x * KC + k];
+      s_out[r0 + threadIdx.x] = acc / (double)K;
+    }
+    __syncthreads();
+  }
 }
 
 template <typename V>
@@ -298,13 +314,13 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   }
   const size_t loop_rec_end = ctx->recs.size();
   if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
-  BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, x64, o->seed, o->K,
-            N, s_out);
+  BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>,
+            dim3((unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 8 * (int64_t)ctx->cu_count)),
+            dim3(kThreads), 0, x64, o->seed, o->K, N, s_out);
   BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
-  // final FP64 residual of every probe column for the report
-  BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
-            sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
-  BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
+  // The report's residual of each column is the FP64 one of its last check:
+  // a column stops only after such a check (or at INIT, or on a breakdown),
+  // and its solution does not change afterwards, so no further pass is needed.
   BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   float ms = 0.0f;
