@@ -234,11 +234,19 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
         double ne = sg > 0 ? floor(u) - (double)p0 + 1.0 : (double)p0 - ceil(u) + 1.0;
         ne = ne < 0.0 ? 0.0 : (ne > (double)nmax ? (double)nmax : ne);
         int32_t n = (int32_t)ne;
-        while (n > 0 && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + (n - 1) * sg) >= cut) --n;
-        while (n < nmax && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg) < cut) ++n;
+        // n is right when the last plane taken is earlier than cut and the next
+        // one is not; the estimate almost always is, so test that first and
+        // walk plane by plane only otherwise
+        const double t_last = n > 0 ? plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + (n - 1) * sg) : -INFINITY;
+        double t_next = n < nmax ? plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg) : INFINITY;
+        if (!(t_last < cut && !(t_next < cut))) {
+          while (n > 0 && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + (n - 1) * sg) >= cut) --n;
+          while (n < nmax && plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg) < cut) ++n;
+          t_next = plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg);
+        }
         r.idx[ax] += n * sg;
         r.steps += n;
-        r.tn[ax] = plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg);
+        r.tn[ax] = n < nmax ? t_next : plane_t(org[ax], g.h, o[ax], r.inv[ax], p0 + n * sg);
       }
     }
   }
