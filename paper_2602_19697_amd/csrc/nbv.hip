@@ -315,7 +315,11 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
       if (need != 0 && (__popcll(need) >= R.refill_batch || busy == 0)) {
         if (want) {
           const int32_t row = (int32_t)(next / R.cam.W), col = (int32_t)(next % R.cam.W);
-          live = ray_init(r, R, P, o, row, col);
+          // re-read the pose here rather than keep its rotation in scalar
+          // registers across the whole walk loop (they would spill)
+          const double* Pi = P;
+          asm volatile("" : "+s"(Pi));
+          live = ray_init(r, R, Pi, o, row, col);
           next += 64;
         }
         continue;
