@@ -17,7 +17,7 @@ bf_status bf_fail(bf_ctx* ctx, bf_status st, const char* fmt, ...) {
 bf_status bf_dev_alloc(bf_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return BF_OK;
-  hipError_t e = hipMallocAsync(p, bytes, ctx->stream);
+  hipError_t e = hipMallocFromPoolAsync(p, bytes, ctx->mempool, ctx->stream);
   if (e != hipSuccess) {
     *p = nullptr;
     return bf_fail(ctx, BF_ERR_OOM, "device allocation of %zu bytes failed: %s", bytes,
@@ -76,10 +76,8 @@ hipEvent_t bf_event_get(bf_ctx* ctx) {
   return e;
 }
 
-void bf_timing_stop(bf_ctx* ctx, const char* name, hipEvent_t start) {
-  hipEvent_t b = bf_event_get(ctx);
-  (void)hipEventRecord(b, ctx->stream);
-  ctx->recs.push_back({name, start, b, 0});
+void bf_timing_add(bf_ctx* ctx, const char* name, hipEvent_t start, hipEvent_t stop) {
+  ctx->recs.push_back({name, start, stop, 0});
 }
 
 void bf_timing_mark_idle(bf_ctx* ctx, size_t from, size_t to) {
@@ -138,6 +136,19 @@ bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream) {
   ctx->stream = (hipStream_t)hip_stream;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
+  hipMemPoolProps pp;
+  memset(&pp, 0, sizeof(pp));
+  pp.allocType = hipMemAllocationTypePinned;
+  pp.handleTypes = hipMemHandleTypeNone;
+  pp.location.type = hipMemLocationTypeDevice;
+  pp.location.id = device;
+  uint64_t keep = UINT64_MAX;
+  if (hipMemPoolCreate(&ctx->mempool, &pp) != hipSuccess ||
+      hipMemPoolSetAttribute(ctx->mempool, hipMemPoolAttrReleaseThreshold, &keep) != hipSuccess) {
+    if (ctx->mempool) (void)hipMemPoolDestroy(ctx->mempool);
+    delete ctx;
+    return BF_ERR_HIP;
+  }
   *out = ctx;
   return BF_OK;
 }
@@ -153,6 +164,9 @@ bf_status bf_destroy(bf_ctx* ctx) {
   }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  // Allocations still held by bands or systems keep the pool alive until
+  // they are freed; everything else returns to the device here.
+  (void)hipMemPoolDestroy(ctx->mempool);
   delete ctx;
   return BF_OK;
 }

@@ -414,7 +414,11 @@ bf_status launch_persistent(bf_ctx* ctx, Batch& B, int max_iter, const bf_schedu
     }
     const hipError_t le =
         hipLaunchCooperativeKernel((const void*)k_batch<V, KC>, dim3(grid), dim3(256), args, 0, ctx->stream);
-    if (ctx->timing) bf_timing_stop(ctx, "batch_persistent", ta);
+    if (ctx->timing) {
+      hipEvent_t tb = bf_event_get(ctx);
+      (void)hipEventRecord(tb, ctx->stream);
+      bf_timing_add(ctx, "batch_persistent", ta, tb);
+    }
     if (le != hipSuccess) return bf_fail(ctx, BF_ERR_HIP, "cooperative launch failed: %s", hipGetErrorString(le));
     BF_HIP(ctx, hipMemcpyAsync(ctrl_host, B.ctrl, C_WORDS * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     return BF_OK;
