@@ -42,7 +42,7 @@ def log(msg):
 # HBM traffic of the roofline kernel, from two rocprofv3 --pmc runs of this
 # bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) scaled by what the same
 # counters read for a plain copy of known size (bench.py --copy-calibration).
-# The figures hold only for the kernel source they were taken from.
+# The figures hold only for the kernel sources they were taken from (hashes).
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 COPY_BYTES = 1 << 30
 
@@ -70,19 +70,23 @@ def measured_traffic(kernel, workload):
     entry = rec.get("kernels", {}).get(kernel)
     if entry is None or entry.get("workload") != workload:
         return None
-    with open(os.path.join(ROOT, entry["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != entry["source_sha256"]:
-            return None
+    for src, digest in entry["sources"].items():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
     fetch = entry["fetch_kib_per_dispatch"] * 1024 * rec["copy"]["fetch_factor"]
     write = entry["write_kib_per_dispatch"] * 1024 * rec["copy"]["write_factor"]
     return fetch + write
 
 
-# FP64 operations per fused voxel-view of the coarse TSDF (projection, two
-# divisions, truncation, running sum) and per screened (4^3 cell, view) pair
-# (8 corner projections, bounds, pyramid lookup).
+# Operations per fused voxel-view of the coarse TSDF (FP64 projection, two
+# divisions, truncation, running sum) and per screened (4^3 cell, view) pair:
+# one FP64 corner transform (27), cell edges and Z range (22), 36 FP64 corner
+# adds, 8 FP32 projections of 12 operations (96), pixel range and pyramid
+# bounds (31), final tests (5), counted arithmetic, min/max, compare and
+# convert operations alike.
 TSDF_OPS_PER_VOXEL_VIEW = 35
-TSDF_OPS_PER_CELL_VIEW = 340
+TSDF_OPS_PER_CELL_VIEW = 217
 
 
 def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None):
@@ -153,11 +157,14 @@ def run_gpu(args):
     for _ in range(args.warmup):
         info = step()
     torch.cuda.synchronize()
-    ctx.bf_set_timing(True)
-    torch.cuda.synchronize()
+    # per-kernel HIP events cost host time at every launch, so they run on the
+    # last timing_steps steps of the timed region only
+    timing_steps = max(1, min(args.timing_steps, args.steps))
     t_start = time.perf_counter()
     works = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        if i == args.steps - timing_steps:
+            ctx.bf_set_timing(True)
         info = step()
         works.append(info["work"])
     torch.cuda.synchronize()
@@ -173,7 +180,7 @@ def run_gpu(args):
     kernels = {}
     for name, (launches, ms) in sorted(timings.items(), key=lambda kv: -kv[1][1]):
         kernels[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
-                         "share_of_step": ms / args.steps / ms_step}
+                         "share_of_step": ms / timing_steps / ms_step}
     P = 1
     while P < wl.G:
         P *= 2
@@ -502,6 +509,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--timing-steps", type=int, default=2,
+                    help="per-kernel HIP event timing on the last this many timed steps")
     ap.add_argument("--workload", default="union256")
     ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-6)

@@ -174,7 +174,8 @@ const char* bf_version(void);
  * Morton order, builds the key -> index hash and the 6-neighbour table.
  * flags: BF_BAND_KEEP_DENSE keeps the dense grid in the band object.
  * Writes *out (new band) and *n_out (host; synchronises).  Errors:
- * INVALID_ARG for bad sizes or depth that is NaN, infinite or negative;
+ * INVALID_ARG for bad sizes (G outside [1, 2048], T outside [0, 65535]) or
+ * depth that is NaN, infinite or negative;
  * CAPACITY if the hash overflows; OOM; HIP. */
 bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
                         const float* depth_dev, const double* c2w_dev, uint32_t flags,

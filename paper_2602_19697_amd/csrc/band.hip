@@ -46,76 +46,134 @@ struct Pyr {
   int64_t per_view;
 };
 
-__global__ __launch_bounds__(256) void k_pyr_base(const float* __restrict__ depth, int64_t npix_view, int T,
-                                                  Pyr P, float* __restrict__ dmin, float* __restrict__ dmax) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= npix_view * T) return;
-  const int64_t t = i / npix_view, p = i % npix_view;
-  const float d = depth[i];
-  dmin[t * P.per_view + p] = d > 0.0f ? d : INFINITY;
-  dmax[t * P.per_view + p] = d > 0.0f ? d : -1.0f;
-}
-
-__global__ __launch_bounds__(256) void k_pyr_level(int T, Pyr P, int l, float* __restrict__ dmin,
-                                                   float* __restrict__ dmax) {
-  const int64_t cells = (int64_t)P.w[l] * P.h[l];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= cells * T) return;
-  const int64_t t = i / cells, q = i % cells;
-  const int32_t x = (int32_t)(q % P.w[l]), y = (int32_t)(q / P.w[l]);
-  const int32_t pw = P.w[l - 1], ph = P.h[l - 1];
-  const int64_t base = t * P.per_view + P.off[l - 1];
-  float lo = INFINITY, hi = -1.0f;
-  for (int dy = 0; dy < 2; ++dy)
-    for (int dx = 0; dx < 2; ++dx) {
-      const int32_t cx = 2 * x + dx, cy = 2 * y + dy;
-      if (cx < pw && cy < ph) {
-        lo = fminf(lo, dmin[base + (int64_t)cy * pw + cx]);
-        hi = fmaxf(hi, dmax[base + (int64_t)cy * pw + cx]);
+// Levels 0..kTileLevels of one 32x32 pixel tile of one view, built in LDS.
+// A level-l cell holds the extremes over its 2^l x 2^l base pixels inside the
+// image, so the tile-local reduction equals the level-by-level one.
+constexpr int kPyrTile = 32;
+constexpr int kTileLevels = 5;  // 32 >> 5 = 1
+__global__ __launch_bounds__(256) void k_pyr_tiles(const float* __restrict__ depth, int32_t W, int32_t H, Pyr P,
+                                                   float* __restrict__ dmin, float* __restrict__ dmax) {
+  __shared__ float lo[2][kPyrTile * kPyrTile], hi[2][kPyrTile * kPyrTile];
+  const int t = blockIdx.z;
+  const int32_t x0 = blockIdx.x * kPyrTile, y0 = blockIdx.y * kPyrTile;
+  const float* D = depth + (int64_t)t * W * H;
+  float* mn = dmin + (int64_t)t * P.per_view;
+  float* mx = dmax + (int64_t)t * P.per_view;
+  for (int e = threadIdx.x; e < kPyrTile * kPyrTile; e += blockDim.x) {
+    const int32_t x = x0 + (e % kPyrTile), y = y0 + (e / kPyrTile);
+    float a = INFINITY, b = -1.0f;
+    if (x < W && y < H) {
+      const float d = D[(int64_t)y * W + x];
+      if (d > 0.0f) a = b = d;
+      mn[(int64_t)y * W + x] = a;
+      mx[(int64_t)y * W + x] = b;
+    }
+    lo[0][e] = a;
+    hi[0][e] = b;
+  }
+  int cur = 0;
+  for (int l = 1; l <= kTileLevels && l < P.nl; ++l) {
+    __syncthreads();
+    const int side = kPyrTile >> l;
+    for (int e = threadIdx.x; e < side * side; e += blockDim.x) {
+      const int x = e % side, y = e / side;
+      float a = INFINITY, b = -1.0f;
+#pragma unroll
+      for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+          const int q = (2 * y + dy) * kPyrTile + 2 * x + dx;
+          a = fminf(a, lo[cur][q]);
+          b = fmaxf(b, hi[cur][q]);
+        }
+      lo[cur ^ 1][y * kPyrTile + x] = a;
+      hi[cur ^ 1][y * kPyrTile + x] = b;
+      const int32_t gx = (x0 >> l) + x, gy = (y0 >> l) + y;
+      if (gx < P.w[l] && gy < P.h[l]) {
+        mn[P.off[l] + (int64_t)gy * P.w[l] + gx] = a;
+        mx[P.off[l] + (int64_t)gy * P.w[l] + gx] = b;
       }
     }
-  dmin[t * P.per_view + P.off[l] + q] = lo;
-  dmax[t * P.per_view + P.off[l] + q] = hi;
+    cur ^= 1;
+  }
+}
+
+// The remaining levels of one view (one block per view), each from the one
+// below it in global memory.
+__global__ __launch_bounds__(1024) void k_pyr_top(Pyr P, float* __restrict__ dmin, float* __restrict__ dmax) {
+  const int t = blockIdx.x;
+  float* mn = dmin + (int64_t)t * P.per_view;
+  float* mx = dmax + (int64_t)t * P.per_view;
+  for (int l = kTileLevels + 1; l < P.nl; ++l) {
+    __threadfence_block();
+    __syncthreads();
+    const int32_t pw = P.w[l - 1], ph = P.h[l - 1];
+    const int64_t cells = (int64_t)P.w[l] * P.h[l];
+    for (int64_t q = threadIdx.x; q < cells; q += blockDim.x) {
+      const int32_t x = (int32_t)(q % P.w[l]), y = (int32_t)(q / P.w[l]);
+      float a = INFINITY, b = -1.0f;
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int32_t cx = 2 * x + dx, cy = 2 * y + dy;
+          if (cx < pw && cy < ph) {
+            a = fminf(a, mn[P.off[l - 1] + (int64_t)cy * pw + cx]);
+            b = fmaxf(b, mx[P.off[l - 1] + (int64_t)cy * pw + cx]);
+          }
+        }
+      mn[P.off[l] + q] = a;
+      mx[P.off[l] + q] = b;
+    }
+  }
 }
 
 // Can view t put a voxel of the 4^3 cell with lowest voxel (i0, j0, k0) into
-// the band?  False only when provably not (see the file comment); the bounds
-// use the cell's 8 corner voxel centres (the extremes of Z and of the
-// projected u, v over a box are at its corners) with generous margins.
+// the band?  False only when provably not (see the file comment).  The corner
+// centres are the lowest one plus sums of the three rotated cell edges (FP64);
+// the Z range over the cell follows from the edge signs, and the extremes of
+// the projected u, v over the box are at its 8 corners.  The test is a filter,
+// not part of the result, so the projection runs in FP32: its error is a few
+// 1e-7 of |u| (the coordinates stay FP64), which the twentieth-of-a-pixel
+// widening covers wherever an endpoint can fall near the image.
 __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
                                      const float* __restrict__ dmin, const float* __restrict__ dmax,
                                      const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0) {
-  double zlo = INFINITY, zhi = -INFINITY, ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
-  bool behind = false;
+  const double x = g.ox + ((double)i0 + 0.5) * g.h;
+  const double y = g.oy + ((double)j0 + 0.5) * g.h;
+  const double z = g.oz + ((double)k0 + 0.5) * g.h;
+  const double dx = x - Pose[3], dy = y - Pose[7], dz = z - Pose[11];
+  const double X0 = Pose[0] * dx + Pose[4] * dy + Pose[8] * dz;
+  const double Y0 = Pose[1] * dx + Pose[5] * dy + Pose[9] * dz;
+  const double Z0 = Pose[2] * dx + Pose[6] * dy + Pose[10] * dz;
+  const double e = 3.0 * g.h;  // lowest to highest voxel centre of the cell along one axis
+  const double ax = e * Pose[0], ay = e * Pose[1], az = e * Pose[2];  // per grid-x edge
+  const double bx = e * Pose[4], by = e * Pose[5], bz = e * Pose[6];  // per grid-y edge
+  const double qx = e * Pose[8], qy = e * Pose[9], qz = e * Pose[10];  // per grid-z edge
+  const double zlo = Z0 + fmin(az, 0.0) + fmin(bz, 0.0) + fmin(qz, 0.0);
+  const double zhi = Z0 + fmax(az, 0.0) + fmax(bz, 0.0) + fmax(qz, 0.0);
+  const double zmargin = 1e-9 + 1e-12 * fabs(zhi);
+  if (zhi < -zmargin) return false;  // the whole cell is behind the camera: never observed
+  if (zlo <= 1e-6) return true;      // straddles the camera plane: no projection bound
+  const float fx = (float)c.fx, fy = (float)c.fy;
+  float ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
 #pragma unroll
   for (int corner = 0; corner < 8; ++corner) {
-    const double x = g.ox + ((double)(i0 + ((corner & 1) ? 3 : 0)) + 0.5) * g.h;
-    const double y = g.oy + ((double)(j0 + ((corner & 2) ? 3 : 0)) + 0.5) * g.h;
-    const double z = g.oz + ((double)(k0 + ((corner & 4) ? 3 : 0)) + 0.5) * g.h;
-    const double dx = x - Pose[3], dy = y - Pose[7], dz = z - Pose[11];
-    const double X = Pose[0] * dx + Pose[4] * dy + Pose[8] * dz;
-    const double Y = Pose[1] * dx + Pose[5] * dy + Pose[9] * dz;
-    const double Z = Pose[2] * dx + Pose[6] * dy + Pose[10] * dz;
-    zlo = fmin(zlo, Z);
-    zhi = fmax(zhi, Z);
-    if (Z <= 1e-6) {
-      behind = true;
-    } else {
-      const double u = c.fx * X / Z + c.cx, v = c.fy * Y / Z + c.cy;
-      ulo = fmin(ulo, u);
-      uhi = fmax(uhi, u);
-      vlo = fmin(vlo, v);
-      vhi = fmax(vhi, v);
-    }
+    const double X = X0 + ((corner & 1) ? ax : 0.0) + ((corner & 2) ? bx : 0.0) + ((corner & 4) ? qx : 0.0);
+    const double Y = Y0 + ((corner & 1) ? ay : 0.0) + ((corner & 2) ? by : 0.0) + ((corner & 4) ? qy : 0.0);
+    const double Z = Z0 + ((corner & 1) ? az : 0.0) + ((corner & 2) ? bz : 0.0) + ((corner & 4) ? qz : 0.0);
+    const float rz = __builtin_amdgcn_rcpf((float)Z);  // v_rcp_f32, within 1 ulp
+    const float u = (fx * (float)X) * rz, v = (fy * (float)Y) * rz;
+    ulo = fminf(ulo, u);
+    uhi = fmaxf(uhi, u);
+    vlo = fminf(vlo, v);
+    vhi = fmaxf(vhi, v);
   }
-  if (zhi <= 0.0) return false;  // the whole cell is behind the camera: never observed
-  if (behind) return true;        // straddles the camera plane: no projection bound
-  // pixel (floor(u + 1/2)) range, widened by a thousandth of a pixel for rounding
-  const double c0f = floor(ulo + 0.5 - 1e-3), c1f = floor(uhi + 0.5 + 1e-3);
-  const double r0f = floor(vlo + 0.5 - 1e-3), r1f = floor(vhi + 0.5 + 1e-3);
-  if (c1f < 0.0 || r1f < 0.0 || c0f >= (double)c.W || r0f >= (double)c.H) return false;  // outside the image
-  const int32_t c0 = (int32_t)fmax(c0f, 0.0), c1 = (int32_t)fmin(c1f, (double)(c.W - 1));
-  const int32_t r0 = (int32_t)fmax(r0f, 0.0), r1 = (int32_t)fmin(r1f, (double)(c.H - 1));
+  // pixel (floor(u + cx + 1/2)) range, widened by a twentieth of a pixel
+  const float hcx = (float)c.cx + 0.5f, hcy = (float)c.cy + 0.5f;
+  const float c0f = floorf(ulo + hcx - 0.05f), c1f = floorf(uhi + hcx + 0.05f);
+  const float r0f = floorf(vlo + hcy - 0.05f), r1f = floorf(vhi + hcy + 0.05f);
+  if (c1f < 0.0f || r1f < 0.0f || c0f >= (float)c.W || r0f >= (float)c.H) return false;  // outside the image
+  const int32_t c0 = (int32_t)fmaxf(c0f, 0.0f), c1 = (int32_t)fminf(c1f, (float)(c.W - 1));
+  const int32_t r0 = (int32_t)fmaxf(r0f, 0.0f), r1 = (int32_t)fminf(r1f, (float)(c.H - 1));
   int l = 0;
   while (l < P.nl - 1 && (((c1 >> l) - (c0 >> l)) > 1 || ((r1 >> l) - (r0 >> l)) > 1)) ++l;
   const int64_t base = (int64_t)t * P.per_view + P.off[l];
@@ -130,9 +188,8 @@ __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, cons
       hi = fmaxf(hi, dmax[q]);
     }
   if (hi < 0.0f) return false;                                   // no valid depth under the cell
-  const double margin = 1e-9 + 1e-12 * (zhi > 0.0 ? zhi : 0.0);
-  if ((double)lo - zhi > g.band + margin) return false;          // free space beyond the band
-  if ((double)hi - zlo < -g.tau - margin) return false;          // occluded: every view skipped
+  if ((double)lo - zhi > g.band + zmargin) return false;         // free space beyond the band
+  if ((double)hi - zlo < -g.tau - zmargin) return false;         // occluded: every view skipped
   return true;
 }
 
@@ -394,7 +451,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   BF_CHECK(ctx, grid->G >= 1 && grid->G <= 2048, "bf_build_band: G=%d outside [1, 2048]", grid->G);
   BF_CHECK(ctx, grid->h > 0.0 && grid->tau >= 0.0 && grid->band >= 0.0,
            "bf_build_band: h must be > 0, tau and band >= 0");
-  BF_CHECK(ctx, T >= 0, "bf_build_band: T < 0");
+  BF_CHECK(ctx, T >= 0 && T <= 65535, "bf_build_band: T=%d outside [0, 65535]", T);
   BF_CHECK(ctx, T == 0 || (cam->width > 0 && cam->height > 0 && depth_dev && c2w_dev),
            "bf_build_band: bad camera size or NULL depth/poses");
   BF_HIP(ctx, hipSetDevice(ctx->device));
@@ -474,12 +531,11 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     if (bf_status s = bf_ws(ctx, bf_ctx::WS_PYR, 2 * half, &pw)) return fail(s);
     dmin = (float*)pw;
     dmax = (float*)((char*)pw + half);
-    const int64_t npv = (int64_t)cam->width * cam->height;
-    BF_LAUNCH(ctx, "depth_pyramid", k_pyr_base, dim3((unsigned)bf_cdiv(npv * T, 256)), dim3(256), 0, depth_dev, npv,
-              T, pyr, dmin, dmax);
-    for (int l = 1; l < pyr.nl; ++l)
-      BF_LAUNCH(ctx, "depth_pyramid", k_pyr_level, dim3((unsigned)bf_cdiv((int64_t)pyr.w[l] * pyr.h[l] * T, 256)),
-                dim3(256), 0, T, pyr, l, dmin, dmax);
+    BF_LAUNCH(ctx, "depth_pyramid", k_pyr_tiles,
+              dim3((unsigned)bf_cdiv(cam->width, kPyrTile), (unsigned)bf_cdiv(cam->height, kPyrTile), (unsigned)T),
+              dim3(256), 0, depth_dev, cam->width, cam->height, pyr, dmin, dmax);
+    if (pyr.nl > kTileLevels + 1)
+      BF_LAUNCH(ctx, "depth_pyramid", k_pyr_top, dim3((unsigned)T), dim3(1024), 0, pyr, dmin, dmax);
   }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
                      depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax,

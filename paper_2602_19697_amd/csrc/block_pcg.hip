@@ -58,14 +58,33 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
       if (act) tile_A<V, KC>(c, beta, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0]);
     } else {
       __syncthreads();  // the previous tile's readers are done
-      if (act)
-        for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
-          const int64_t e = v * KC + c;
-          pt[(v - r0) * KC + c] = zz[e] + beta * p_old[e];
+      if (act) {
+        // every load of a batch of rows is issued before the first LDS store
+        constexpr int SJ = R / RS, SB = SJ < 8 ? SJ : 8;
+        static_assert(SJ % SB == 0, "staging batches must tile the rows of a thread");
+        for (int j0 = 0; j0 < SJ; j0 += SB) {
+          V za[SB], pa[SB];
+#pragma unroll
+          for (int j = 0; j < SB; ++j) {
+            const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
+            if (v < r1) {
+              za[j] = zz[v * KC + c];
+              pa[j] = p_old[v * KC + c];
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < SB; ++j) {
+            const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
+            if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * pa[j];
+          }
         }
+      }
       __syncthreads();
       if (act) {
-        constexpr int U = kRowsInFlight;
+        // the gathers of neighbours outside the tile are all issued before the
+        // sums use them; an absent neighbour adds +0.0, which leaves the sum
+        // unchanged (it starts at +0.0, so it is never -0.0)
+        constexpr int U = 2;
         for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
           int64_t vr[U];
           int32_t nb[U][6];
@@ -75,6 +94,19 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
 #pragma unroll
             for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
           }
+          V gz[U][6], gp[U][6];
+#pragma unroll
+          for (int j = 0; j < U; ++j)
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+              const int32_t u = nb[j][t];
+              gz[j][t] = 0;
+              gp[j][t] = 0;
+              if (u >= 0 && !(u >= r0 && u < r1)) {
+                gz[j][t] = zz[(int64_t)u * KC + c];
+                gp[j][t] = p_old[(int64_t)u * KC + c];
+              }
+            }
           V sacc[U];
 #pragma unroll
           for (int j = 0; j < U; ++j) {
@@ -82,11 +114,10 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
 #pragma unroll
             for (int t = 0; t < 6; ++t) {
               const int32_t u = nb[j][t];
-              if (u >= r0 && u < r1) {
-                sacc[j] += pt[(u - r0) * KC + c];
-              } else if (u >= 0) {
-                sacc[j] += zz[(int64_t)u * KC + c] + beta * p_old[(int64_t)u * KC + c];
-              }
+              const bool in = u >= r0 && u < r1;
+              const V lv = pt[(in ? u - r0 : 0) * KC + c];
+              const V gv = gz[j][t] + beta * gp[j][t];
+              sacc[j] += in ? lv : (u >= 0 ? gv : (V)0);
             }
           }
 #pragma unroll
