@@ -95,6 +95,21 @@ def lib():
         L.orc_nbv_argmax.argtypes = [C.c_int32, _I64]
         L.orc_features.argtypes = [C.c_int64, C.c_int32, C.c_double, _D, _I32, _I32, _I32, _D, _D,
                                    _D]
+        L.orc_tri_slot.restype = C.c_int32
+        L.orc_tri_slot.argtypes = [C.c_int32] * 3
+        L.orc_tri_sample_list.restype = C.c_int64
+        L.orc_tri_sample_list.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, C.POINTER(Noise),
+                                          C.c_int32, _U64, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_tri_assemble.restype = C.c_int64
+        L.orc_tri_assemble.argtypes = [C.POINTER(Grid), C.POINTER(Cam), C.c_int32, _F, _D, C.POINTER(Noise),
+                                       C.c_int32, _U64, C.c_int64, _I32, _D, C.c_double, C.c_double,
+                                       C.c_double, _D, _D, _D, _D, _D, _I32, C.POINTER(C.c_int64)]
+        L.orc_apply_Q27.argtypes = [C.c_int64, _D, _D, _I32, _D, _D]
+        L.orc_pcg27.argtypes = [C.c_int64, _D, _D, _I32, _D, C.c_void_p, C.c_double, C.c_int32, _D,
+                                C.POINTER(Report)]
+        L.orc_hutchinson27.argtypes = [C.c_int64, _D, _D, _I32, C.c_int32, C.c_uint64, C.c_double, C.c_int32,
+                                       _D, C.c_void_p]
         _lib = L
     return _lib
 
@@ -264,6 +279,94 @@ def hutchinson(nbr, diag, lam, K, seed, tol, max_iter=10000, with_iters=False):
     its = np.zeros(max(K, 1), dtype=np.int32)
     lib().orc_hutchinson(N, _c(nbr, np.int32), diag, float(lam), int(K), C.c_uint64(int(seed)),
                          float(tol), int(max_iter), s, its.ctypes.data)
+    if with_iters:
+        return s[:N], its[:K]
+    return s[:N]
+
+
+def _noise(noise, sigma2_pose=None, sigma2_model=0.0):
+    nz = Noise()
+    nz.a, nz.c, nz.z0 = (float(v) for v in noise)
+    nz.sigma2_model = float(sigma2_model)
+    keep = None
+    if sigma2_pose is not None:
+        keep = _c(sigma2_pose, np.float64)
+        nz.sigma2_pose = keep.ctypes.data_as(C.POINTER(C.c_double))
+    return nz, keep
+
+
+def tri_slot(dx, dy, dz) -> int:
+    return int(lib().orc_tri_slot(dx, dy, dz))
+
+
+def tri_samples(g: Grid, cm: Cam, depth, c2w, keys, S, noise=(0.0012, 0.0019, 0.4), sigma2_pose=None,
+                sigma2_model=0.0):
+    """Kept trilinear samples in (cell, id) order: base[n][3], a[n][8], y[n], w[n] and
+    (t, row, col, s)[n][4]."""
+    depth = _c(depth, np.float32)
+    keys = _c(keys, np.uint64)
+    c2w = _c(c2w, np.float64)
+    nz, keep = _noise(noise, sigma2_pose, sigma2_model)
+    L = lib()
+    n = L.orc_tri_sample_list(C.byref(g), C.byref(cm), depth.shape[0], depth, c2w, C.byref(nz), int(S), keys,
+                              keys.shape[0], 0, None, None, None, None, None)
+    base = np.zeros((max(n, 1), 3), dtype=np.int32)
+    a = np.zeros((max(n, 1), 8), dtype=np.float64)
+    y = np.zeros(max(n, 1), dtype=np.float64)
+    w = np.zeros(max(n, 1), dtype=np.float64)
+    tcrs = np.zeros((max(n, 1), 4), dtype=np.int32)
+    L.orc_tri_sample_list(C.byref(g), C.byref(cm), depth.shape[0], depth, c2w, C.byref(nz), int(S), keys,
+                          keys.shape[0], n, base.ctypes.data, a.ctypes.data, y.ctypes.data, w.ctypes.data,
+                          tcrs.ctypes.data)
+    return base[:n], a[:n], y[:n], w[:n], tcrs[:n]
+
+
+def tri_assemble(g: Grid, cm: Cam, depth, c2w, keys, deg, tsdf, S, lam, eps, lam_b=0.0,
+                 noise=(0.0012, 0.0019, 0.4), sigma2_pose=None, sigma2_model=0.0):
+    """Trilinear system: dict of Lambda, b, rhs, diag [N], off, nb26 [N][26], samples, cells."""
+    depth = _c(depth, np.float32)
+    keys = _c(keys, np.uint64)
+    N = keys.shape[0]
+    nz, keep = _noise(noise, sigma2_pose, sigma2_model)
+    M = max(N, 1)
+    out = {k: np.zeros(M, dtype=np.float64) for k in ("Lambda", "b", "rhs", "diag")}
+    off = np.zeros((M, 26), dtype=np.float64)
+    nb26 = np.full((M, 26), -1, dtype=np.int32)
+    ncell = C.c_int64(0)
+    n = lib().orc_tri_assemble(C.byref(g), C.byref(cm), depth.shape[0], depth, _c(c2w, np.float64),
+                               C.byref(nz), int(S), keys, N, _c(deg, np.int32), _c(tsdf, np.float64),
+                               float(lam), float(eps), float(lam_b), out["Lambda"], out["b"], out["rhs"],
+                               out["diag"], off, nb26, C.byref(ncell))
+    res = {k: v[:N] for k, v in out.items()}
+    res.update(off=off[:N], nb26=nb26[:N], samples=int(n), cells=int(ncell.value))
+    return res
+
+
+def apply_Q27(diag, off, nb26, p):
+    p = _c(p, np.float64)
+    q = np.zeros(max(p.shape[0], 1), dtype=np.float64)
+    lib().orc_apply_Q27(p.shape[0], _c(diag, np.float64), _c(off, np.float64), _c(nb26, np.int32), p, q)
+    return q[:p.shape[0]]
+
+
+def pcg27(diag, off, nb26, rhs, tol, max_iter=10000, x0=None):
+    rhs = _c(rhs, np.float64)
+    N = rhs.shape[0]
+    x = np.zeros(max(N, 1), dtype=np.float64)
+    rep = Report()
+    x0a = _c(x0, np.float64) if x0 is not None else None
+    lib().orc_pcg27(N, _c(diag, np.float64), _c(off, np.float64), _c(nb26, np.int32), rhs,
+                    x0a.ctypes.data if x0a is not None else None, float(tol), int(max_iter), x, C.byref(rep))
+    return x[:N], {"iters": rep.iters, "status": rep.status, "rel_res": rep.rel_res}
+
+
+def hutchinson27(diag, off, nb26, K, seed, tol, max_iter=10000, with_iters=False):
+    diag = _c(diag, np.float64)
+    N = diag.shape[0]
+    s = np.zeros(max(N, 1), dtype=np.float64)
+    its = np.zeros(max(K, 1), dtype=np.int32)
+    lib().orc_hutchinson27(N, diag, _c(off, np.float64), _c(nb26, np.int32), int(K), C.c_uint64(int(seed)),
+                           float(tol), int(max_iter), s, its.ctypes.data)
     if with_iters:
         return s[:N], its[:K]
     return s[:N]

@@ -104,4 +104,25 @@ void orc_features(int64_t N, int32_t T, double h, const double* tsdf, const int3
                   const int32_t* nbr, const int32_t* deg, const double* Lambda, const double* acc,
                   double* feat);
 
+
+/* Trilinear observation rows (trilinear.c; Sec. 3.2, eqs. 2-5, 7, 10-12). */
+int32_t orc_tri_slot(int32_t dx, int32_t dy, int32_t dz);
+int orc_tri_sample(const orc_grid* g, const orc_cam* cam, const float* depth_t, const double* P,
+                   const orc_noise* nz, double sigma2_pose_t, int32_t row, int32_t col, int32_t s,
+                   int32_t* base, double* a, double* y, double* wv);
+int64_t orc_tri_sample_list(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
+                            const double* c2w, const orc_noise* nz, int32_t S, const uint64_t* keys, int64_t N,
+                            int64_t cap, int32_t* base, double* a, double* y, double* wv, int32_t* tcrs);
+int64_t orc_tri_assemble(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
+                         const double* c2w, const orc_noise* nz, int32_t S, const uint64_t* keys, int64_t N,
+                         const int32_t* deg, const double* tsdf, double lam, double eps, double lam_b,
+                         double* Lambda, double* b, double* rhs, double* diag, double* off, int32_t* nb26,
+                         int64_t* ncells_out);
+void orc_apply_Q27(int64_t N, const double* diag, const double* off, const int32_t* nb26, const double* p,
+                   double* q);
+void orc_pcg27(int64_t N, const double* diag, const double* off, const int32_t* nb26, const double* rhs,
+               const double* x0, double tol, int32_t max_iter, double* x, orc_report* rep);
+void orc_hutchinson27(int64_t N, const double* diag, const double* off, const int32_t* nb26, int32_t K,
+                      uint64_t seed, double tol, int32_t max_iter, double* s_out, int32_t* iters_out);
+
 #endif
