@@ -369,6 +369,72 @@ def solver_section(g, args):
     return out
 
 
+def trilinear_section(g, args):
+    """Trilinear pixel-centric rows (eq. 4) on the step's workload: assembly
+    time, mean solves (FP64 and mixed) and an 8-probe mixed variance to 1e-6,
+    and the HBM rate of the 27-point product pass (pcg_A).  Algorithmic bytes
+    per row of that pass: nb26 (104 B) and the couplings (26 s), diag, p_old
+    and z of the row in, p and q out (5 s), neighbour rows as cache hits."""
+    import torch
+    import paper_2602_19697_amd as bf
+    ctx, wl = g["ctx"], g["wl"]
+    S = int(round(wl.tau / wl.h))
+    noise = bf.noise_struct(*wl.noise)
+    band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
+    N = band.n
+
+    def assemble():
+        return ctx.bf_assemble_trilinear(band, wl.cam, g["depth"], g["poses"], noise, wl.lam, wl.eps, wl.lam_b,
+                                         samples_per_side=S)
+    assemble().free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        sys_ = assemble()
+        sys_.free()
+    torch.cuda.synchronize()
+    asm_ms = 1e3 * (time.perf_counter() - t0) / 3
+    sys_ = assemble()
+    arr = sys_.arrays()
+    out = {"workload": wl.name, "band_voxels": N, "samples_per_side": S, "samples": arr["n_samples"],
+           "cells": arr["n_cells"], "assemble_ms": asm_ms, "tol": 1e-6}
+    for prec, name in ((bf.L.BF_PREC_FP64, "fp64"), (bf.L.BF_PREC_MIXED, "mixed")):
+        ctx.bf_pcg_solve(sys_, 1e-6, precision=prec)
+        torch.cuda.synchronize()
+        ctx.bf_get_timings()
+        ctx.bf_set_timing(True)
+        t0 = time.perf_counter()
+        _, rep = ctx.bf_pcg_solve(sys_, 1e-6, precision=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.bf_set_timing(False)
+        tm = ctx.bf_get_timings()
+        s = 8 if name == "fp64" else 4
+        launches, ms = tm.get("pcg_A", (0, 0.0))
+        res = {"iters": rep["iters"], "refinements": rep["refinements"], "wall_ms": wall * 1e3,
+               "voxel_pcg_iters_per_s": N * rep["iters"] / wall}
+        if launches:
+            amount = N * (104 + 26 * s + 5 * s)
+            gbs = amount / (ms * 1e-3 / launches) / 1e9
+            res["pcg_A"] = {"launches": launches, "avg_us": 1e3 * ms / launches,
+                            "algorithmic_bytes_per_launch": amount, "achieved_GBps": gbs,
+                            "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+        out[name] = res
+    _, rep = ctx.bf_diag_estimate(sys_, 8, 0, 1e-6, precision=bf.L.BF_PREC_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = ctx.bf_diag_estimate(sys_, 8, 0, 1e-6, precision=bf.L.BF_PREC_MIXED)
+    torch.cuda.synchronize()
+    out["variance_mixed_K8"] = {"iters": rep["iters"], "column_iters": rep["col_iters"],
+                                "wall_ms": 1e3 * (time.perf_counter() - t0)}
+    log(f"[trilinear] {wl.name}: {arr['n_samples']} samples in {arr['n_cells']} cells, assembly {asm_ms:.1f} ms; "
+        f"mean fp64 {out['fp64']['iters']} it {out['fp64']['wall_ms']:.1f} ms, mixed {out['mixed']['iters']} it "
+        f"{out['mixed']['wall_ms']:.1f} ms; 8-probe variance {rep['iters']} it {out['variance_mixed_K8']['wall_ms']:.1f} ms")
+    sys_.free()
+    band.free()
+    return out
+
+
 def batch_section(g, args):
     """Many scenes of uneven size: args.batch_scenes sphere scenes whose band
     sizes are log-uniform in [2e4, 8e5], mean + 64-probe variance, to 1e-6.
@@ -521,6 +587,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-solver-roofline", action="store_true")
+    ap.add_argument("--no-trilinear", action="store_true")
     ap.add_argument("--solver-workload", default="union512")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
@@ -547,6 +614,7 @@ def main():
     solver = None if args.no_solver_roofline else solver_section(g, args)
     copy_gbs = None if args.no_compare else stream_copy_gbs()
     batch = None if args.no_batch else batch_section(g, args)
+    trilinear = None if args.no_trilinear else trilinear_section(g, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
     # The roofline is that of the longest-running kernel with a roofline
     # claim.  The ray walk (nbv_rays) is irregular and latency-bound: it gets
@@ -599,6 +667,7 @@ def main():
         "block_solver_roofline": solver,
         "stream_copy_GBps": copy_gbs,
         "batch": batch,
+        "trilinear": trilinear,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

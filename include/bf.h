@@ -43,7 +43,7 @@ typedef enum bf_status {
   BF_OK = 0,
   BF_ERR_INVALID_ARG = 1,    /* bad size, NULL pointer, NaN/negative depth, ... */
   BF_ERR_OOM = 2,            /* device allocation failed */
-  BF_ERR_CAPACITY = 3,       /* hash table could not place every band voxel */
+  BF_ERR_CAPACITY = 3,       /* band too large for 32-bit band indices */
   BF_ERR_BREAKDOWN = 4,      /* CG met p.Qp <= 0 or a non-finite scalar */
   BF_ERR_NOT_CONVERGED = 5,  /* max_iter reached; result and report are written */
   BF_ERR_HIP = 6             /* a HIP runtime call failed */
@@ -89,6 +89,7 @@ typedef struct bf_prior {
 enum { BF_PREC_FP64 = 0, BF_PREC_MIXED = 1 };
 enum { BF_BAND_KEEP_DENSE = 1 };
 enum { BF_UTILITY_SUM_VAR = 0, BF_UTILITY_VAR_REDUCTION = 1 };
+enum { BF_SYSTEM_VOXEL = 0, BF_SYSTEM_TRILINEAR = 1 };
 
 /* CG stopping rule: ||rhs - Q x|| <= tol ||rhs|| with the residual recomputed
  * in FP64 before stopping.  precision: BF_PREC_FP64 runs every vector
@@ -147,7 +148,12 @@ typedef struct bf_system_arrays {
   const double* rhs;       /* [N] h = A^T W y + b0 (anchor term included) */
   const double* diag;      /* [N] diagonal of Q */
   const float* diag32;     /* [N] diag rounded to float */
-  const double* acc;       /* [N][5] n_obs, sum y, sum y^2, sum sigma, min sigma */
+  const double* acc;       /* [N][5] n_obs, sum y, sum y^2, sum sigma, min sigma (voxel rows only) */
+  int32_t kind;            /* BF_SYSTEM_VOXEL or BF_SYSTEM_TRILINEAR */
+  const double* off;       /* [N][26] trilinear couplings Q_vu (see bf_assemble_trilinear), or NULL */
+  const int32_t* nb26;     /* [N][26] band index of each coupling's voxel or -1, or NULL */
+  int64_t n_samples;       /* trilinear samples kept */
+  int64_t n_cells;         /* 2x2x2 cells holding at least one kept sample */
 } bf_system_arrays;
 
 /* ---------------------------------------------------------------- context */
@@ -171,12 +177,13 @@ const char* bf_version(void);
  * whole grid (unit weight per view; a view counts when the projective distance
  * D - Z of the nearest pixel is >= -tau, and contributes min(D - Z, tau)),
  * then activates B = { v : W(v) > 0 and |TSDF(v)| <= band } in ascending
- * Morton order, builds the key -> index hash and the 6-neighbour table.
+ * Morton order, builds the key -> index map (direct 4^3-block records) and the
+ * 6-neighbour table.
  * flags: BF_BAND_KEEP_DENSE keeps the dense grid in the band object.
  * Writes *out (new band) and *n_out (host; synchronises).  Errors:
  * INVALID_ARG for bad sizes (G outside [1, 2048], T outside [0, 65535]) or
  * depth that is NaN, infinite or negative;
- * CAPACITY if the hash overflows; OOM; HIP. */
+ * CAPACITY if the band exceeds 2^31 - 1 voxels; OOM; HIP. */
 bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_camera* cam, int32_t T,
                         const float* depth_dev, const double* c2w_dev, uint32_t flags,
                         bf_band** out, int64_t* n_out);
@@ -194,6 +201,32 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band);
 bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, int32_t T,
                       const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
                       const bf_prior* prior, bf_system** out);
+
+/* Sec. 3.2, eqs. (2)-(5), (7), (10)-(11): trilinear pixel-centric observation
+ * rows (eq. 4, up to 8 non-zeros).  Every valid pixel (row, col) of view t
+ * gives 2S+1 samples (S = samples_per_side, 0..15) along its camera ray at
+ * camera depths z = D + s h, s = -S..S (eq. 2); y = clamp(D - z, -tau, tau)
+ * (eq. 3, normal = viewing axis); the row holds the trilinear weights of the
+ * sample point on the 8 surrounding voxel centres, and the sample is kept only
+ * when all 8 are band voxels; weight 1/sigma^2 as in bf_assemble (eq. 5).
+ * Q = A^T W A + lambda L + eps I (+ lambda_b on the boundary) is stored as
+ * diag(Q) and 26 couplings per row: slot order of the offsets d in
+ * {-1,0,1}^3 \ {0} by (dx+1) + 3(dy+1) + 9(dz+1) ascending, centre removed;
+ * face slots include -lambda; absent voxels have nb26 = -1 and coupling 0.
+ * FP64 results are reproducible bit for bit: samples are summed per 2x2x2
+ * cell (the cube whose lowest voxel is the sample's floor corner) in
+ * ascending sample id ((t H + row) W + col)(2S+1) + (s + S), and each voxel
+ * sums its 8 cells in the order of its corner index q = dx + 2dy + 4dz inside
+ * the cell.  The system works with bf_apply_Q, bf_pcg_solve and
+ * bf_diag_estimate (without a log-variance start); bf_features, the warm
+ * start and the batched solves reject it.  n_samples_out (host, may be NULL)
+ * receives the kept sample count.  Synchronises.  Errors: INVALID_ARG (bad
+ * sizes, S outside [0, 15], more samples than a 64-bit sort key holds), OOM,
+ * HIP. */
+bf_status bf_assemble_trilinear(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, int32_t T,
+                                const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                                const bf_prior* prior, int32_t samples_per_side, bf_system** out,
+                                int64_t* n_samples_out);
 bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out);
 bf_status bf_system_free(bf_ctx* ctx, bf_system* sys);
 

@@ -137,12 +137,18 @@ class System:
         a = L.bf_system_arrays()
         self.ctx._check(self.ctx.lib.bf_system_view(self.handle, C.byref(a)))
         dev, n = self.ctx.device, int(a.n)
-        return {"Lambda": _view(a.Lambda, (n,), torch.float64, dev),
-                "b": _view(a.b, (n,), torch.float64, dev),
-                "rhs": _view(a.rhs, (n,), torch.float64, dev),
-                "diag": _view(a.diag, (n,), torch.float64, dev),
-                "diag32": _view(a.diag32, (n,), torch.float32, dev),
-                "acc": _view(a.acc, (n, 5), torch.float64, dev)}
+        out = {"Lambda": _view(a.Lambda, (n,), torch.float64, dev),
+               "b": _view(a.b, (n,), torch.float64, dev),
+               "rhs": _view(a.rhs, (n,), torch.float64, dev),
+               "diag": _view(a.diag, (n,), torch.float64, dev),
+               "diag32": _view(a.diag32, (n,), torch.float32, dev),
+               "kind": int(a.kind), "n_samples": int(a.n_samples), "n_cells": int(a.n_cells)}
+        if a.kind == L.BF_SYSTEM_VOXEL:
+            out["acc"] = _view(a.acc, (n, 5), torch.float64, dev)
+        else:
+            out["off"] = _view(a.off, (n, 26), torch.float64, dev)
+            out["nb26"] = _view(a.nb26, (n, 26), torch.int32, dev)
+        return out
 
     def free(self):
         if self.handle:
@@ -216,6 +222,18 @@ class Context:
         self._check(self.lib.bf_assemble(self.handle, band.handle, C.byref(camera_struct(cam)),
                                          int(depth.shape[0]), _ptr(depth), _ptr(poses), C.byref(noise),
                                          C.byref(pr), C.byref(h)))
+        return System(self, h, band.n, band)
+
+    def bf_assemble_trilinear(self, band: Band, cam, depth, poses, noise: L.bf_noise, lam, eps, lam_b=0.0,
+                              samples_per_side=4) -> System:
+        """Trilinear pixel-centric rows (eq. 4): 2S+1 samples per pixel, 27-point Q."""
+        pr = L.bf_prior()
+        pr.lam, pr.eps, pr.lambda_b = float(lam), float(eps), float(lam_b)
+        h = C.c_void_p()
+        ns = C.c_int64()
+        self._check(self.lib.bf_assemble_trilinear(self.handle, band.handle, C.byref(camera_struct(cam)),
+                                                   int(depth.shape[0]), _ptr(depth), _ptr(poses), C.byref(noise),
+                                                   C.byref(pr), int(samples_per_side), C.byref(h), C.byref(ns)))
         return System(self, h, band.n, band)
 
     def bf_apply_Q(self, sys: System, p):

@@ -22,6 +22,8 @@ BF_PREC_MIXED = 1
 BF_BAND_KEEP_DENSE = 1
 BF_UTILITY_SUM_VAR = 0
 BF_UTILITY_VAR_REDUCTION = 1
+BF_SYSTEM_VOXEL = 0
+BF_SYSTEM_TRILINEAR = 1
 BF_ORDER_SCENE_MAJOR = 0
 BF_ORDER_INTERLEAVED = 1
 BF_ORDER_LARGEST_FIRST = 2
@@ -83,7 +85,8 @@ class bf_band_arrays(C.Structure):
 
 class bf_system_arrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("Lambda", C.c_void_p), ("b", C.c_void_p), ("rhs", C.c_void_p),
-                ("diag", C.c_void_p), ("diag32", C.c_void_p), ("acc", C.c_void_p)]
+                ("diag", C.c_void_p), ("diag32", C.c_void_p), ("acc", C.c_void_p), ("kind", C.c_int32),
+                ("off", C.c_void_p), ("nb26", C.c_void_p), ("n_samples", C.c_int64), ("n_cells", C.c_int64)]
 
 
 class bf_kernel_time(C.Structure):
@@ -106,6 +109,8 @@ SIGNATURES = {
     "bf_band_free": (C.c_int, [P, P]),
     "bf_assemble": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise),
                               C.POINTER(bf_prior), PP]),
+    "bf_assemble_trilinear": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise),
+                                        C.POINTER(bf_prior), C.c_int32, PP, C.POINTER(C.c_int64)]),
     "bf_system_view": (C.c_int, [P, C.POINTER(bf_system_arrays)]),
     "bf_system_free": (C.c_int, [P, P]),
     "bf_apply_Q": (C.c_int, [P, P, P, P]),

@@ -202,8 +202,6 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   bf_dev_free(ctx, band->w);
   bf_dev_free(ctx, band->nbr);
   bf_dev_free(ctx, band->deg);
-  bf_dev_free(ctx, band->hkeys);
-  bf_dev_free(ctx, band->hvals);
   bf_dev_free(ctx, band->dense_tsdf);
   bf_dev_free(ctx, band->dense_w);
   bf_dev_free(ctx, band->bricks);
@@ -222,6 +220,11 @@ bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out) {
   out->diag = sys->diag;
   out->diag32 = sys->diag32;
   out->acc = sys->acc;
+  out->kind = sys->kind;
+  out->off = sys->off;
+  out->nb26 = sys->nb26;
+  out->n_samples = sys->n_samples;
+  out->n_cells = sys->n_cells;
   return BF_OK;
 }
 
@@ -236,6 +239,9 @@ bf_status bf_system_free(bf_ctx* ctx, bf_system* sys) {
   bf_dev_free(ctx, sys->diag32);
   bf_dev_free(ctx, sys->dinv32);
   bf_dev_free(ctx, sys->acc);
+  bf_dev_free(ctx, sys->off);
+  bf_dev_free(ctx, sys->off32);
+  bf_dev_free(ctx, sys->nb26);
   delete sys;
   return BF_OK;
 }

@@ -94,6 +94,21 @@ __global__ __launch_bounds__(256) void k_apply_Q(const int32_t* __restrict__ nbr
   q[v] = diag[v] * p[v] - lam * s;
 }
 
+// q = Q p for a trilinear system: diag p plus the 26 couplings in slot order.
+__global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ nb26, const double* __restrict__ off,
+                                                   const double* __restrict__ diag, const double* __restrict__ p,
+                                                   double* __restrict__ q, int64_t n) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  double s = 0.0;
+#pragma unroll
+  for (int t = 0; t < 26; ++t) {
+    const int32_t u = nb26[v * 26 + t];
+    if (u >= 0) s += off[v * 26 + t] * p[u];
+  }
+  q[v] = diag[v] * p[v] + s;
+}
+
 // Features of the learned warm start, lengths in units of h (see bf_features).
 __global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h,
                                                   const double* __restrict__ tsdf,
@@ -185,6 +200,11 @@ extern "C" bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double*
   BF_CHECK(ctx, sys, "bf_apply_Q: NULL system");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, p_dev && q_dev && p_dev != q_dev, "bf_apply_Q: bad vectors");
+  if (sys->kind == BF_SYSTEM_TRILINEAR) {
+    hipLaunchKernelGGL(k_apply_Q27, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, ctx->stream, sys->nb26,
+                       sys->off, sys->diag, p_dev, q_dev, sys->n);
+    return bf_launch_check(ctx, "k_apply_Q27");
+  }
   hipLaunchKernelGGL(k_apply_Q, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, ctx->stream,
                      sys->band->nbr, sys->diag, sys->lambda, p_dev, q_dev, sys->n);
   return bf_launch_check(ctx, "k_apply_Q");
@@ -193,6 +213,7 @@ extern "C" bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double*
 extern "C" bf_status bf_features(bf_ctx* ctx, const bf_system* sys, float* feat_dev) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   BF_CHECK(ctx, sys, "bf_features: NULL system");
+  BF_CHECK(ctx, sys->kind == BF_SYSTEM_VOXEL, "bf_features: the features need voxel-centric rows");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, feat_dev && sys->T > 0, "bf_features: NULL output or system without views");
   const bf_band* band = sys->band;

@@ -1,5 +1,6 @@
 // Coarse TSDF bootstrap, narrow-band activation in Morton order, key->index
-// hash and 6-neighbour table (Sec. 3.3-3.4, eq. 1; Algorithm 1 steps 1-2).
+// block records and 6-neighbour table (Sec. 3.3-3.4, eq. 1; Algorithm 1
+// steps 1-2).
 //
 // Layout: the dense coarse TSDF lives on a P^3 cube (P = next power of two
 // >= G) indexed by Morton code m, so walking m = 0..P^3-1 visits voxels in
@@ -343,33 +344,11 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t* __restrict__ p, uint
     p[i] = v;
 }
 
-__global__ __launch_bounds__(256) void k_hash_insert(const uint64_t* __restrict__ keys, int64_t n,
-                                                     uint64_t* __restrict__ hkeys,
-                                                     int32_t* __restrict__ hvals, int log2cap,
-                                                     uint64_t max_probe, int* __restrict__ flag) {
-  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const uint64_t key = keys[v];
-  const uint64_t mask = (1ull << log2cap) - 1ull;
-  uint64_t slot = bf_hash_slot(key, log2cap);
-  for (uint64_t p = 0; p < max_probe; ++p) {
-    const unsigned long long prev =
-        atomicCAS((unsigned long long*)&hkeys[slot], (unsigned long long)kBfEmptyKey,
-                  (unsigned long long)key);
-    if (prev == kBfEmptyKey || prev == key) {
-      hvals[slot] = (int32_t)v;
-      return;
-    }
-    slot = (slot + 1) & mask;
-  }
-  atomicOr(flag, 2);
-}
-
-__global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__ keys, int64_t n,
-                                                    int32_t G, const uint64_t* __restrict__ hkeys,
-                                                    const int32_t* __restrict__ hvals, int log2cap,
-                                                    uint64_t max_probe, int32_t* __restrict__ nbr,
-                                                    int32_t* __restrict__ deg) {
+// 6-neighbour table: each neighbour's band index through the 4^3 cell records
+// (the same key -> index map the ray walker uses).
+__global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__ keys, int64_t n, int32_t G,
+                                                    const bf_cell* __restrict__ cells, int32_t ncell,
+                                                    int32_t* __restrict__ nbr, int32_t* __restrict__ deg) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
   const uint64_t key = keys[v];
@@ -380,9 +359,7 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__
   for (int s = 0; s < 6; ++s) {
     int32_t q[3] = {c[0], c[1], c[2]};
     q[s >> 1] += (s & 1) ? 1 : -1;
-    int32_t idx = -1;
-    if (q[s >> 1] >= 0 && q[s >> 1] < G)
-      idx = bf_hash_find(hkeys, hvals, log2cap, max_probe, bf_morton(q[0], q[1], q[2]));
+    const int32_t idx = bf_band_index(cells, ncell, G, q[0], q[1], q[2]);
     nbr[v * 6 + s] = idx;
     d += idx >= 0;
   }
@@ -403,8 +380,9 @@ __global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__
   atomicOr(&bits[bit >> 5], 1u << (bit & 31));
 }
 
-// Cell tables for the ray walker: occupancy mask and first band index of
-// every 4^3 cell that holds band voxels.
+// Cell records (the key -> band index map of the neighbour table and the ray
+// walker): occupancy mask and first band index of every 4^3 cell, addressed
+// directly by the cell's coordinates, so a lookup never collides or probes.
 __global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict__ keys, int64_t n, int ncell,
                                                      bf_cell* __restrict__ cells) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -475,7 +453,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     return st;
   };
 
-  // flags[0]: depth invalid, flags[1]: hash overflow; then the band count
+  // flags[0]: depth invalid; then the band count
   void* scan_ws = nullptr;
   const size_t scan_bytes = 64 + nblocks * (sizeof(uint32_t) + sizeof(uint64_t)) + 64;
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
@@ -566,20 +544,17 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
                        grid->band, dense_t, dense_w, offsets, band->keys, band->tsdf, band->w);
     if (bf_status s = bf_launch_check(ctx, "k_band_scatter")) return fail(s);
 
-    int log2cap = 6;
-    while ((1ull << log2cap) < 2 * N) ++log2cap;
-    band->hcap = 1ull << log2cap;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->hkeys, band->hcap * sizeof(uint64_t))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->hvals, band->hcap * sizeof(int32_t))) return fail(s);
-    const int fb = (int)std::min<uint64_t>((band->hcap + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_fill_u64, dim3(fb), dim3(256), 0, ctx->stream, band->hkeys, band->hcap, kBfEmptyKey);
     const unsigned nb = (unsigned)bf_cdiv((int64_t)N, 256);
-    const uint64_t max_probe = getenv("BF_DEBUG_HASH_PROBES") ? strtoull(getenv("BF_DEBUG_HASH_PROBES"), nullptr, 10)
-                                                               : band->hcap;
-    BF_LAUNCH(ctx, "hash_insert", k_hash_insert, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->hkeys,
-                       band->hvals, log2cap, max_probe, dflags);
-    BF_LAUNCH(ctx, "neighbours", k_neighbours, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, grid->G,
-                       band->hkeys, band->hvals, log2cap, band->hcap, band->nbr, band->deg);
+    // 4^3 cell records (key -> band index) for the neighbour table and the ray walker
+    band->ncell = std::max(1, band->P >> 2);
+    const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cells, nc3 * sizeof(bf_cell))) return fail(s);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(2 * nc3, 256), 16384)), dim3(256), 0,
+                       ctx->stream, (uint64_t*)band->cells, (uint64_t)(2 * nc3), 0ull);
+    BF_LAUNCH(ctx, "cell_tables", k_cell_tables, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->ncell,
+              band->cells);
+    BF_LAUNCH(ctx, "neighbours", k_neighbours, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, grid->G, band->cells,
+              band->ncell, band->nbr, band->deg);
     // brick occupancy bitmap for the ray walker: brick edge 2^shift with at
     // most 64 bricks per axis
     int shift = 2;
@@ -592,7 +567,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
       return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
     BF_LAUNCH(ctx, "brick_bits", k_brick_bits, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, shift, band->nbrick,
               band->bricks);
-    // brick distances (empty-space skipping) and 4^3 cell tables (voxel lookup) for the ray walker
+    // brick distances (empty-space skipping) for the ray walker
     const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
     uint8_t* dtmp = nullptr;
     if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, nbr3)) return fail(s);
@@ -604,18 +579,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               band->nbrick, 1);
     BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, dtmp, band->brick_dist,
               band->nbrick, 2);
-    band->ncell = std::max(1, band->P >> 2);
-    const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cells, nc3 * sizeof(bf_cell))) return fail(s);
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(2 * nc3, 256), 16384)), dim3(256), 0,
-                       ctx->stream, (uint64_t*)band->cells, (uint64_t)(2 * nc3), 0ull);
-    BF_LAUNCH(ctx, "cell_tables", k_cell_tables, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->ncell,
-              band->cells);
-    if (bf_status s = bf_launch_check(ctx, "hash/neighbours")) return fail(s);
-    if (hipMemcpyAsync(pin, scan_ws, 8, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess)
-      return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: flag read-back failed"));
-    if (((int*)pin)[0] & 2) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: hash table overflow"));
+    if (bf_status s = bf_launch_check(ctx, "neighbours/bricks/cells")) return fail(s);
   }
   *out = band;
   *n_out = band->n;

@@ -647,6 +647,7 @@ bf_status check_batch(bf_ctx* ctx, const bf_system* const* systems, int32_t n_sy
   BF_CHECK(ctx, systems && out && n_sys >= 1, "batched solve: bad system list");
   for (int s = 0; s < n_sys; ++s) {
     BF_CHECK(ctx, systems[s] && systems[s]->n > 0, "batched solve: system %d is NULL or empty", s);
+    BF_CHECK(ctx, systems[s]->kind == BF_SYSTEM_VOXEL, "batched solve: system %d has trilinear rows", s);
     BF_CHECK(ctx, out[s], "batched solve: NULL output for system %d", s);
   }
   BF_CHECK(ctx, sched->rows_per_tile >= 16 && sched->rows_per_tile <= 4096, "batched solve: rows_per_tile %d",

@@ -216,6 +216,98 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
 
+// Trilinear systems: A and the FP64 residual with the 26 stored couplings per
+// row (ascending slot), rows of a tile spread over the workgroup as in tile_B.
+// An absent voxel reads the row itself and adds nothing.
+template <typename V, int KC>
+__global__ __launch_bounds__(256) void k_bA27(BState* __restrict__ st, const int32_t* __restrict__ nb26,
+                                              const V* __restrict__ off, const V* __restrict__ diag,
+                                              const V* __restrict__ zz, const V* __restrict__ p_old,
+                                              V* __restrict__ p_new, V* __restrict__ q, int64_t n,
+                                              double* __restrict__ part) {
+  __shared__ double lds[4 * 3 * 64];
+  if (st->nactive == 0) return;
+  constexpr int RS = kThreads / KC;
+  const int c = threadIdx.x % KC;
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  double v1[1] = {0.0};
+  const V beta = (V)st->beta[c];
+  if (st->active[c])
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+      const int64_t r1 = std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>);
+      for (int64_t v = tile * kRowsPerTile<KC> + threadIdx.x / KC; v < r1; v += RS) {
+        const int32_t* nb = nb26 + v * 26;
+        const V* o = off + v * 26;
+        V s = 0;
+#pragma unroll
+        for (int t = 0; t < 26; ++t) {
+          const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+          const V a = zz[u * KC + c] + beta * p_old[u * KC + c];
+          if (nb[t] >= 0) s += o[t] * a;
+        }
+        const int64_t e = v * KC + c;
+        const V pv = zz[e] + beta * p_old[e];
+        const V qv = diag[v] * pv + s;
+        p_new[e] = pv;
+        q[e] = qv;
+        v1[0] += (double)pv * (double)qv;
+      }
+    }
+  col_block_sum<KC, 1>(v1, lds);
+  store_partials<KC, 1>(part, blockIdx.x, v1);
+}
+
+template <typename V, int KC>
+__global__ __launch_bounds__(256) void k_bresid27(BState* __restrict__ st, int mode, const int32_t* __restrict__ nb26,
+                                                  const double* __restrict__ off, const double* __restrict__ diag,
+                                                  uint64_t seed, double* __restrict__ x64,
+                                                  const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
+                                                  int64_t n, double* __restrict__ part) {
+  __shared__ double lds[4 * 3 * 64];
+  if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
+  constexpr int RS = kThreads / KC;
+  const int c = threadIdx.x % KC;
+  const bool act = mode == MODE_REPORT ? c < st->K
+                                       : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
+  const uint64_t cs = splitmix_out(seed, (uint64_t)c);
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  double v3[3] = {0.0, 0.0, 0.0};
+  if (act)
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+      const int64_t r1 = std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>);
+      for (int64_t v = tile * kRowsPerTile<KC> + threadIdx.x / KC; v < r1; v += RS) {
+        const int64_t e = v * KC + c;
+        const double zv = probe(cs, v);
+        double res = zv;
+        if (mode == MODE_INIT) {
+          x64[e] = 0.0;
+        } else {
+          const int32_t* nb = nb26 + v * 26;
+          const double* o = off + v * 26;
+          double s = 0.0;
+#pragma unroll
+          for (int t = 0; t < 26; ++t) {
+            const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+            const double xu = x64[u * KC + c];
+            if (nb[t] >= 0) s += o[t] * xu;
+          }
+          res = zv - (diag[v] * x64[e] + s);
+        }
+        v3[0] += res * res;
+        v3[2] += zv * zv;
+        if (mode != MODE_REPORT) {
+          const V rv = (V)res;
+          const V zzv = rv * dinv[v];
+          r[e] = rv;
+          zz[e] = zzv;
+          v3[1] += (double)rv * (double)zzv;
+        }
+      }
+    }
+  col_block_sum<KC, 3>(v3, lds);
+  store_partials<KC, 3>(part, blockIdx.x, v3);
+}
+
 // Per-column decisions after an FP64 residual (one workgroup per column).
 template <int KC>
 __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mode, const double* __restrict__ part,
@@ -297,8 +389,14 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                      mixed ? 1e-6 : 0.0);
   hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
-  BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->band->nbr,
-            sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
+  const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
+  const V* offV = mixed ? (const V*)sys->off32 : (const V*)sys->off;
+  if (tri)
+    BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->nb26,
+              sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
+  else
+    BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
+              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
@@ -315,7 +413,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
       if (ctx->timing) iter_rec.push_back(ctx->recs.size());
-      switch (stencil_kb) {
+      if (tri) {
+        BF_LAUNCH(ctx, "block_A", (k_bA27<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->nb26, offV, diagV, zz, pa,
+                  pb, q, N, part);
+      } else switch (stencil_kb) {
         case 16:
           BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
                     zz, pa, pb, q, N, part);
@@ -332,8 +433,12 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
-      BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
-                sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+      if (tri)
+        BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
+                  sys->nb26, sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
+      else
+        BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
+                  sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       std::swap(pa, pb);
     }
@@ -404,6 +509,8 @@ extern "C" bf_status bf_diag_estimate(bf_ctx* ctx, const bf_system* sys, const b
   BF_CHECK(ctx, opts->precision == BF_PREC_FP64 || opts->precision == BF_PREC_MIXED,
            "bf_diag_estimate: unknown precision %d", opts->precision);
   if (rep) *rep = bf_solve_report{};
+  BF_CHECK(ctx, !(sys->kind == BF_SYSTEM_TRILINEAR && logvar_dev),
+           "bf_diag_estimate: no log-variance start for trilinear systems");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, s_dev, "bf_diag_estimate: NULL output");
   BF_HIP(ctx, hipSetDevice(ctx->device));

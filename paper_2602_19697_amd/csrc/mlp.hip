@@ -462,6 +462,7 @@ extern "C" bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const floa
                                    const float* feat_dev, double* x0_dev, float* logvar_dev) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   BF_CHECK(ctx, sys && params_dev && feat_dev, "bf_warm_start: NULL argument");
+  BF_CHECK(ctx, sys->kind == BF_SYSTEM_VOXEL, "bf_warm_start: the network was trained on voxel-centric rows");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, x0_dev || logvar_dev, "bf_warm_start: no output requested");
   BF_HIP(ctx, hipSetDevice(ctx->device));

@@ -95,6 +95,39 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
   if (threadIdx.x == 0) part[blockIdx.x] = pq;
 }
 
+// A for a trilinear system: q = diag p + sum over the 26 stored couplings
+// (ascending slot) of off * p_u, with p = z + beta p_old formed on the fly.
+template <typename V>
+__global__ __launch_bounds__(256) void k_pcg_A27(PcgState* __restrict__ st, const int32_t* __restrict__ nb26,
+                                                 const V* __restrict__ off, const V* __restrict__ diag,
+                                                 const V* __restrict__ z, const V* __restrict__ p_old,
+                                                 V* __restrict__ p_new, V* __restrict__ q, int64_t n,
+                                                 double* __restrict__ part) {
+  __shared__ double lds[16];
+  if (st->done) return;
+  const V beta = (V)st->beta;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  double pq = 0.0;
+  if (v < n) {
+    const int32_t* nb = nb26 + v * 26;
+    const V* o = off + v * 26;
+    V s = 0;
+#pragma unroll
+    for (int t = 0; t < 26; ++t) {  // unconditional loads: an absent voxel reads the row itself
+      const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+      const V a = z[u] + beta * p_old[u];
+      if (nb[t] >= 0) s += o[t] * a;
+    }
+    const V pv = z[v] + beta * p_old[v];
+    const V qv = diag[v] * pv + s;
+    p_new[v] = pv;
+    q[v] = qv;
+    pq = (double)pv * (double)qv;
+  }
+  pq = bf_block_sum(pq, lds);
+  if (threadIdx.x == 0) part[blockIdx.x] = pq;
+}
+
 // alpha = rho / p.q from A's block partials (one workgroup, fixed order).
 __global__ __launch_bounds__(256) void k_pcg_alpha(PcgState* __restrict__ st, const double* __restrict__ part,
                                                    int nb) {
@@ -225,6 +258,53 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
   }
 }
 
+// True FP64 residual of a trilinear system (modes as in k_residual).
+template <typename V>
+__global__ __launch_bounds__(256) void k_residual27(PcgState* __restrict__ st, int mode,
+                                                    const int32_t* __restrict__ nb26, const double* __restrict__ off,
+                                                    const double* __restrict__ diag, const double* __restrict__ rhs,
+                                                    const double* __restrict__ x, const V* __restrict__ dinv,
+                                                    V* __restrict__ r, V* __restrict__ z, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double lds[16];
+  if (mode == MODE_CHECK && (st->done || !st->check)) return;
+  const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
+  double rr = 0.0, rz = 0.0, bb = 0.0;
+  if (v < n) {
+    const double hv = rhs[v];
+    double res = hv;
+    if (x) {
+      const int32_t* nb = nb26 + v * 26;
+      const double* o = off + v * 26;
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 26; ++t) {
+        const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+        const double xu = x[u];
+        if (nb[t] >= 0) s += o[t] * xu;
+      }
+      res = hv - (diag[v] * x[v] + s);
+    }
+    rr = res * res;
+    bb = hv * hv;
+    if (mode != MODE_REPORT) {
+      const V rv = (V)res;
+      const V zv = rv * dinv[v];
+      r[v] = rv;
+      z[v] = zv;
+      rz = (double)rv * (double)zv;
+    }
+  }
+  rr = bf_block_sum(rr, lds);
+  rz = bf_block_sum(rz, lds);
+  bb = bf_block_sum(bb, lds);
+  if (threadIdx.x == 0) {
+    part[3 * blockIdx.x] = rr;
+    part[3 * blockIdx.x + 1] = rz;
+    part[3 * blockIdx.x + 2] = bb;
+  }
+}
+
 // Decisions after an FP64 residual: stop, or continue / restart from it.
 __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__ st, int mode,
                                                           const double* __restrict__ part, int nb) {
@@ -310,9 +390,18 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   if (!o->use_x0) hipLaunchKernelGGL(k_fill<double>, dim3(fb), dim3(256), 0, ctx->stream, x, N, 0.0);
   hipLaunchKernelGGL(k_fill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N, (V)0);
   if (mixed) hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, ctx->stream, c, N, 0.0f);
-  BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
-                     sys->band->nbr, sys->diag, sys->lambda, rhs, o->use_x0 ? (const double*)x : nullptr, dinvV,
-                     r, z, N, part);
+  const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
+  const V* offV = mixed ? (const V*)sys->off32 : (const V*)sys->off;
+  // FP64 true residual r = rhs - Q x (x == nullptr: x = 0)
+  auto residual = [&](int mode, const double* xr) {
+    if (tri)
+      BF_LAUNCH(ctx, "pcg_residual", k_residual27<V>, dim3(nb), dim3(kThreads), 0, st, mode, sys->nb26, sys->off,
+                sys->diag, rhs, xr, dinvV, r, z, N, part);
+    else
+      BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, mode, sys->band->nbr,
+                sys->diag, sys->lambda, rhs, xr, dinvV, r, z, N, part);
+  };
+  residual((int)MODE_INIT, o->use_x0 ? (const double*)x : nullptr);
   BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "pcg init"));
 
@@ -328,16 +417,19 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
       if (ctx->timing) iter_rec.push_back(ctx->recs.size());
-      BF_LAUNCH(ctx, "pcg_A", k_pcg_A<V>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, z,
-                         pa, pb, q, N, part);
+      if (tri)
+        BF_LAUNCH(ctx, "pcg_A", k_pcg_A27<V>, dim3(nb), dim3(kThreads), 0, st, sys->nb26, offV, diagV, z, pa, pb, q,
+                  N, part);
+      else
+        BF_LAUNCH(ctx, "pcg_A", k_pcg_A<V>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV, z, pa, pb,
+                  q, N, part);
       BF_LAUNCH(ctx, "pcg_scalars", k_pcg_alpha, dim3(1), dim3(256), 0, st, part, nb);
       BF_LAUNCH(ctx, "pcg_B", k_pcg_B<V>, dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, z, N,
                          part);
       BF_LAUNCH(ctx, "pcg_scalars", k_pcg_beta, dim3(1), dim3(256), 0, st, part, nb);
       if (mixed)
         BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 0, x, c, N);
-      BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
-                         sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+      residual((int)MODE_CHECK, (const double*)x);
       BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       std::swap(pa, pb);
     }
@@ -349,8 +441,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   }
   const size_t loop_rec_end = ctx->recs.size();
   if (mixed) BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
-  BF_LAUNCH(ctx, "pcg_residual", k_residual<V>, dim3(nb), dim3(kThreads), 0, st, (int)MODE_REPORT,
-                     sys->band->nbr, sys->diag, sys->lambda, rhs, (const double*)x, dinvV, r, z, N, part);
+  residual((int)MODE_REPORT, (const double*)x);
   BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
   BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
   BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
