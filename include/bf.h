@@ -150,8 +150,8 @@ typedef struct bf_system_arrays {
   const float* diag32;     /* [N] diag rounded to float */
   const double* acc;       /* [N][5] n_obs, sum y, sum y^2, sum sigma, min sigma (voxel rows only) */
   int32_t kind;            /* BF_SYSTEM_VOXEL or BF_SYSTEM_TRILINEAR */
-  const double* off;       /* [N][26] trilinear couplings Q_vu (see bf_assemble_trilinear), or NULL */
-  const int32_t* nb26;     /* [N][26] band index of each coupling's voxel or -1, or NULL */
+  const double* off;       /* [26][N] trilinear couplings Q_vu, slot-major (see bf_assemble_trilinear), or NULL */
+  const int32_t* nb26;     /* [26][N] band index of each coupling's voxel or -1, slot-major, or NULL */
   int64_t n_samples;       /* trilinear samples kept */
   int64_t n_cells;         /* 2x2x2 cells holding at least one kept sample */
 } bf_system_arrays;
@@ -210,7 +210,8 @@ bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, in
  * sample point on the 8 surrounding voxel centres, and the sample is kept only
  * when all 8 are band voxels; weight 1/sigma^2 as in bf_assemble (eq. 5).
  * Q = A^T W A + lambda L + eps I (+ lambda_b on the boundary) is stored as
- * diag(Q) and 26 couplings per row: slot order of the offsets d in
+ * diag(Q) and 26 couplings per row, stored slot-major ([26][N], so the
+ * rows of a wave read them coalesced): slot order of the offsets d in
  * {-1,0,1}^3 \ {0} by (dx+1) + 3(dy+1) + 9(dz+1) ascending, centre removed;
  * face slots include -lambda; absent voxels have nb26 = -1 and coupling 0.
  * FP64 results are reproducible bit for bit: samples are summed per 2x2x2

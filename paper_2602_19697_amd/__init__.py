@@ -146,8 +146,9 @@ class System:
         if a.kind == L.BF_SYSTEM_VOXEL:
             out["acc"] = _view(a.acc, (n, 5), torch.float64, dev)
         else:
-            out["off"] = _view(a.off, (n, 26), torch.float64, dev)
-            out["nb26"] = _view(a.nb26, (n, 26), torch.int32, dev)
+            # stored slot-major [26][N]; shown as [N][26] (a transposed view)
+            out["off"] = _view(a.off, (26, n), torch.float64, dev).t()
+            out["nb26"] = _view(a.nb26, (26, n), torch.int32, dev).t()
         return out
 
     def free(self):

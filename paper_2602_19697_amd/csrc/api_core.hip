@@ -14,6 +14,13 @@ bf_status bf_fail(bf_ctx* ctx, bf_status st, const char* fmt, ...) {
   return st;
 }
 
+int bf_mixed_restart() {
+  const char* v = getenv("BF_MIXED_RESTART");
+  if (!v) return 0;
+  const int x = atoi(v);
+  return x < 0 ? 0 : x;
+}
+
 bf_status bf_dev_alloc(bf_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return BF_OK;

@@ -94,7 +94,8 @@ __global__ __launch_bounds__(256) void k_apply_Q(const int32_t* __restrict__ nbr
   q[v] = diag[v] * p[v] - lam * s;
 }
 
-// q = Q p for a trilinear system: diag p plus the 26 couplings in slot order.
+// q = Q p for a trilinear system: diag p plus the 26 couplings (slot-major
+// [26][N]) in slot order.
 __global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ nb26, const double* __restrict__ off,
                                                    const double* __restrict__ diag, const double* __restrict__ p,
                                                    double* __restrict__ q, int64_t n) {
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ n
   double s = 0.0;
 #pragma unroll
   for (int t = 0; t < 26; ++t) {
-    const int32_t u = nb26[v * 26 + t];
-    if (u >= 0) s += off[v * 26 + t] * p[u];
+    const int32_t u = nb26[t * n + v];
+    if (u >= 0) s += off[t * n + v] * p[u];
   }
   q[v] = diag[v] * p[v] + s;
 }

@@ -386,8 +386,9 @@ __global__ __launch_bounds__(256) void kp_decide(Batch B, int which, int mode) {
   }
 }
 
-__global__ void k_batch_state_init(BState* st, int S, int K, double tol, int32_t max_iter, double inner) {
-  for (int s = blockIdx.x; s < S; s += gridDim.x) bt::state_init(st + s, K, tol, max_iter, inner);
+__global__ void k_batch_state_init(BState* st, int S, int K, double tol, int32_t max_iter, double inner,
+                                   int32_t replace_every) {
+  for (int s = blockIdx.x; s < S; s += gridDim.x) bt::state_init(st + s, K, tol, max_iter, inner, replace_every);
 }
 
 template <typename V>
@@ -558,7 +559,7 @@ bf_status run_batch(bf_ctx* ctx, const bf_system* const* systems, int S, int K, 
   BF_HIP(ctx, hipMemcpyAsync(dtstart, tstart.data(), S * 8, hipMemcpyHostToDevice, ctx->stream));
   BF_HIP(ctx, hipMemcpyAsync(ctrl, hinit, sizeof(hinit), hipMemcpyHostToDevice, ctx->stream));
   hipLaunchKernelGGL(k_batch_state_init, dim3(std::min(S, 1024)), dim3(64), 0, ctx->stream, dst, S, K, tol, max_iter,
-                     mixed ? 1e-6 : 0.0);
+                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
   for (int s = 0; s < S; ++s) {
     const int64_t nn = hsc[s].n * KC;
     const int fb = (int)std::min<int64_t>(bf_cdiv(nn, 256), 4096);

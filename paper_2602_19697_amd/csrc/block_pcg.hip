@@ -23,8 +23,8 @@ using namespace bt;
 template <int KC>
 constexpr int kRowsPerTile = KC == 1 ? 1024 : 64;
 
-__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner) {
-  state_init(st, K, tol, max_iter, inner);
+__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner, int32_t replace_every) {
+  state_init(st, K, tol, max_iter, inner, replace_every);
 }
 
 // A: p = zz + beta p_old, q = Q p, per-column partial p.q.
@@ -216,43 +216,69 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
 
+// Couplings and neighbour indices of rows [r0, r1) of one tile, staged in LDS
+// as [26][R] from the slot-major arrays (each slot's rows are contiguous, so
+// the loads are coalesced); all K column threads of a row then share them.
+template <typename W, int R>
+__device__ __forceinline__ void stage27(const W* __restrict__ off, const int32_t* __restrict__ nb26, int64_t n,
+                                        int64_t r0, int64_t r1, W* __restrict__ soff, int32_t* __restrict__ snb) {
+  for (int e = threadIdx.x; e < 26 * R; e += kThreads) {
+    const int t = e / R;
+    const int64_t v = r0 + (e % R);
+    const bool in = v < r1;
+    soff[e] = in ? off[t * n + v] : (W)0;
+    snb[e] = in ? nb26[t * n + v] : -1;
+  }
+}
+
 // Trilinear systems: A and the FP64 residual with the 26 stored couplings per
-// row (ascending slot), rows of a tile spread over the workgroup as in tile_B.
-// An absent voxel reads the row itself and adds nothing.
+// row (ascending slot; slot-major [26][N], staged per tile in LDS for K > 1),
+// rows of a tile spread over the workgroup as in tile_B.  An absent voxel
+// reads the row itself and adds nothing.
 template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bA27(BState* __restrict__ st, const int32_t* __restrict__ nb26,
                                               const V* __restrict__ off, const V* __restrict__ diag,
                                               const V* __restrict__ zz, const V* __restrict__ p_old,
                                               V* __restrict__ p_new, V* __restrict__ q, int64_t n,
                                               double* __restrict__ part) {
-  __shared__ double lds[4 * 3 * 64];
-  if (st->nactive == 0) return;
+  constexpr int R = kRowsPerTile<KC>;
   constexpr int RS = kThreads / KC;
+  constexpr bool kStage = KC > 1;
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ V soff[kStage ? 26 * R : 1];
+  __shared__ int32_t snb[kStage ? 26 * R : 1];
+  if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
-  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  const TileWalk tw(bf_cdiv(n, R));
   double v1[1] = {0.0};
   const V beta = (V)st->beta[c];
-  if (st->active[c])
-    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
-      const int64_t r1 = std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>);
-      for (int64_t v = tile * kRowsPerTile<KC> + threadIdx.x / KC; v < r1; v += RS) {
-        const int32_t* nb = nb26 + v * 26;
-        const V* o = off + v * 26;
-        V s = 0;
-#pragma unroll
-        for (int t = 0; t < 26; ++t) {
-          const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
-          const V a = zz[u * KC + c] + beta * p_old[u * KC + c];
-          if (nb[t] >= 0) s += o[t] * a;
-        }
-        const int64_t e = v * KC + c;
-        const V pv = zz[e] + beta * p_old[e];
-        const V qv = diag[v] * pv + s;
-        p_new[e] = pv;
-        q[e] = qv;
-        v1[0] += (double)pv * (double)qv;
-      }
+  const bool act = st->active[c] != 0;
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    if constexpr (kStage) {
+      __syncthreads();  // the previous tile's readers are done
+      stage27<V, R>(off, nb26, n, r0, r1, soff, snb);
+      __syncthreads();
     }
+    if (!act) continue;
+    for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+      V s = 0;
+#pragma unroll
+      for (int t = 0; t < 26; ++t) {
+        const int32_t nbt = kStage ? snb[t * R + (v - r0)] : nb26[t * n + v];
+        const V o = kStage ? soff[t * R + (v - r0)] : off[t * n + v];
+        const int64_t u = nbt >= 0 ? (int64_t)nbt : v;
+        const V a = zz[u * KC + c] + beta * p_old[u * KC + c];
+        if (nbt >= 0) s += o * a;
+      }
+      const int64_t e = v * KC + c;
+      const V pv = zz[e] + beta * p_old[e];
+      const V qv = diag[v] * pv + s;
+      p_new[e] = pv;
+      q[e] = qv;
+      v1[0] += (double)pv * (double)qv;
+    }
+  }
   col_block_sum<KC, 1>(v1, lds);
   store_partials<KC, 1>(part, blockIdx.x, v1);
 }
@@ -263,47 +289,58 @@ __global__ __launch_bounds__(256) void k_bresid27(BState* __restrict__ st, int m
                                                   uint64_t seed, double* __restrict__ x64,
                                                   const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
                                                   int64_t n, double* __restrict__ part) {
-  __shared__ double lds[4 * 3 * 64];
-  if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
+  constexpr int R = kRowsPerTile<KC>;
   constexpr int RS = kThreads / KC;
+  constexpr bool kStage = KC > 1;
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ double soff[kStage ? 26 * R : 1];
+  __shared__ int32_t snb[kStage ? 26 * R : 1];
+  if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
   const int c = threadIdx.x % KC;
   const bool act = mode == MODE_REPORT ? c < st->K
                                        : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
-  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  const TileWalk tw(bf_cdiv(n, R));
   double v3[3] = {0.0, 0.0, 0.0};
-  if (act)
-    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
-      const int64_t r1 = std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>);
-      for (int64_t v = tile * kRowsPerTile<KC> + threadIdx.x / KC; v < r1; v += RS) {
-        const int64_t e = v * KC + c;
-        const double zv = probe(cs, v);
-        double res = zv;
-        if (mode == MODE_INIT) {
-          x64[e] = 0.0;
-        } else {
-          const int32_t* nb = nb26 + v * 26;
-          const double* o = off + v * 26;
-          double s = 0.0;
-#pragma unroll
-          for (int t = 0; t < 26; ++t) {
-            const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
-            const double xu = x64[u * KC + c];
-            if (nb[t] >= 0) s += o[t] * xu;
-          }
-          res = zv - (diag[v] * x64[e] + s);
-        }
-        v3[0] += res * res;
-        v3[2] += zv * zv;
-        if (mode != MODE_REPORT) {
-          const V rv = (V)res;
-          const V zzv = rv * dinv[v];
-          r[e] = rv;
-          zz[e] = zzv;
-          v3[1] += (double)rv * (double)zzv;
-        }
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    if constexpr (kStage) {
+      if (mode != MODE_INIT) {  // uniform across the workgroup
+        __syncthreads();
+        stage27<double, R>(off, nb26, n, r0, r1, soff, snb);
+        __syncthreads();
       }
     }
+    if (!act) continue;
+    for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+      const int64_t e = v * KC + c;
+      const double zv = probe(cs, v);
+      double res = zv;
+      if (mode == MODE_INIT) {
+        x64[e] = 0.0;
+      } else {
+        double s = 0.0;
+#pragma unroll
+        for (int t = 0; t < 26; ++t) {
+          const int32_t nbt = kStage ? snb[t * R + (v - r0)] : nb26[t * n + v];
+          const double o = kStage ? soff[t * R + (v - r0)] : off[t * n + v];
+          const int64_t u = nbt >= 0 ? (int64_t)nbt : v;
+          const double xu = x64[u * KC + c];
+          if (nbt >= 0) s += o * xu;
+        }
+        res = zv - (diag[v] * x64[e] + s);
+      }
+      v3[0] += res * res;
+      v3[2] += zv * zv;
+      if (mode != MODE_REPORT) {
+        const V rv = (V)res;
+        const V zzv = rv * dinv[v];
+        r[e] = rv;
+        zz[e] = zzv;
+        v3[1] += (double)rv * (double)zzv;
+      }
+    }
+  }
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
@@ -386,7 +423,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   BF_HIP(ctx, hipEventCreate(&e1));
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
-                     mixed ? 1e-6 : 0.0);
+                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
   hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;

@@ -39,7 +39,8 @@ __device__ __forceinline__ double probe(uint64_t col_seed, int64_t i) {
   return (splitmix_out(col_seed, (uint64_t)i) >> 63) ? -1.0 : 1.0;
 }
 
-__device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_t max_iter, double inner) {
+__device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_t max_iter, double inner,
+                                           int32_t replace_every) {
   const int c = threadIdx.x;
   if (c < kMaxK) {
     st->rho[c] = st->alpha[c] = st->beta[c] = st->rr_true[c] = st->bnorm2[c] = st->rr_ref[c] = 0.0;
@@ -52,7 +53,7 @@ __device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_
     st->nactive = K;
     st->any_check = 0;
     st->max_iter = max_iter;
-    st->replace_every = 0;
+    st->replace_every = replace_every;
     st->K = K;
     st->refinements = 0;
   }

@@ -96,7 +96,8 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
 }
 
 // A for a trilinear system: q = diag p + sum over the 26 stored couplings
-// (ascending slot) of off * p_u, with p = z + beta p_old formed on the fly.
+// (ascending slot; slot-major [26][N]) of off * p_u, with p = z + beta p_old
+// formed on the fly.
 template <typename V>
 __global__ __launch_bounds__(256) void k_pcg_A27(PcgState* __restrict__ st, const int32_t* __restrict__ nb26,
                                                  const V* __restrict__ off, const V* __restrict__ diag,
@@ -109,14 +110,13 @@ __global__ __launch_bounds__(256) void k_pcg_A27(PcgState* __restrict__ st, cons
   const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double pq = 0.0;
   if (v < n) {
-    const int32_t* nb = nb26 + v * 26;
-    const V* o = off + v * 26;
     V s = 0;
 #pragma unroll
     for (int t = 0; t < 26; ++t) {  // unconditional loads: an absent voxel reads the row itself
-      const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+      const int32_t nbt = nb26[t * n + v];
+      const int64_t u = nbt >= 0 ? (int64_t)nbt : v;
       const V a = z[u] + beta * p_old[u];
-      if (nb[t] >= 0) s += o[t] * a;
+      if (nbt >= 0) s += off[t * n + v] * a;
     }
     const V pv = z[v] + beta * p_old[v];
     const V qv = diag[v] * pv + s;
@@ -274,14 +274,13 @@ __global__ __launch_bounds__(256) void k_residual27(PcgState* __restrict__ st, i
     const double hv = rhs[v];
     double res = hv;
     if (x) {
-      const int32_t* nb = nb26 + v * 26;
-      const double* o = off + v * 26;
       double s = 0.0;
 #pragma unroll
       for (int t = 0; t < 26; ++t) {
-        const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
+        const int32_t nbt = nb26[t * n + v];
+        const int64_t u = nbt >= 0 ? (int64_t)nbt : v;
         const double xu = x[u];
-        if (nb[t] >= 0) s += o[t] * xu;
+        if (nbt >= 0) s += off[t * n + v] * xu;
       }
       res = hv - (diag[v] * x[v] + s);
     }
@@ -376,8 +375,9 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   const V* diagV = mixed ? (const V*)sys->diag32 : (const V*)sys->diag;
   const V* dinvV = mixed ? (const V*)sys->dinv32 : (const V*)sys->dinv;
   V* xin = mixed ? (V*)c : (V*)x;
-  const int replace_every = 0;
-  // Mixed: each inner float solve reduces its residual 1e6-fold before an FP64 check.
+  const int replace_every = mixed ? bf_mixed_restart() : 0;
+  // Mixed: each inner float solve reduces its residual 1e6-fold (or runs
+  // replace_every iterations) before an FP64 check.
   const double inner = mixed ? 1e-6 : 0.0;
   const int fb = std::min(nb, 4096);
 

@@ -247,9 +247,6 @@ __global__ __launch_bounds__(256) void k_tri_gather(tri_k K, const uint64_t* __r
     }
     B = B + cellG[c * 8 + q];
   }
-  int32_t* nbv = nb26 + v * 26;
-  double* ov = off + v * 26;
-  float* ov32 = off32 + v * 26;
 #pragma unroll
   for (int dz = -1; dz <= 1; ++dz)
 #pragma unroll
@@ -262,9 +259,9 @@ __global__ __launch_bounds__(256) void k_tri_gather(tri_k K, const uint64_t* __r
         double o = cpl[slot];
         if ((dx != 0) + (dy != 0) + (dz != 0) == 1 && u >= 0) o = o - lam;
         o = u >= 0 ? o : 0.0;
-        nbv[slot] = u;
-        ov[slot] = o;
-        ov32[slot] = (float)o;
+        nb26[slot * n + v] = u;  // slot-major [26][N]: coalesced across the rows of a wave
+        off[slot * n + v] = o;
+        off32[slot * n + v] = (float)o;
       }
   const int32_t dg = deg[v];
   double dq = L + lam * (double)dg;
