@@ -110,6 +110,11 @@ def lib():
                                 C.POINTER(Report)]
         L.orc_hutchinson27.argtypes = [C.c_int64, _D, _D, _I32, C.c_int32, C.c_uint64, C.c_double, C.c_int32,
                                        _D, C.c_void_p]
+        L.orc_surf_dir.restype = C.c_int32
+        L.orc_surf_dir.argtypes = [C.c_int32] * 3
+        L.orc_extract_surface.argtypes = [C.POINTER(Grid), _U64, C.c_int64, _D, C.c_double, C.c_int64, C.c_int64,
+                                          C.c_void_p, C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.orc_nn_dist2.argtypes = [_D, C.c_int64, _D, C.c_int64, _D]
         _lib = L
     return _lib
 
@@ -370,6 +375,50 @@ def hutchinson27(diag, off, nb26, K, seed, tol, max_iter=10000, with_iters=False
     if with_iters:
         return s[:N], its[:K]
     return s[:N]
+
+
+def extract_surface(g: Grid, keys, mu, iso=0.0):
+    """Marching-tetrahedra mesh of mu = iso over the band: verts[nv][3], tris[nt][3]."""
+    keys = _c(keys, np.uint64)
+    mu = _c(mu, np.float64)
+    N = keys.shape[0]
+    L = lib()
+    nv, nt = C.c_int64(), C.c_int64()
+    L.orc_extract_surface(C.byref(g), keys, N, mu, float(iso), 0, 0, None, None, C.byref(nv), C.byref(nt))
+    verts = np.zeros((max(nv.value, 1), 3), dtype=np.float64)
+    tris = np.zeros((max(nt.value, 1), 3), dtype=np.int32)
+    L.orc_extract_surface(C.byref(g), keys, N, mu, float(iso), nv.value, nt.value, verts.ctypes.data,
+                          tris.ctypes.data, C.byref(nv), C.byref(nt))
+    return verts[:nv.value], tris[:nt.value]
+
+
+def nn_dist2(a, b):
+    """Squared distance from each point of a[n][3] to its nearest point of b[m][3]."""
+    a = _c(a, np.float64)
+    b = _c(b, np.float64)
+    d = np.zeros(max(a.shape[0], 1), dtype=np.float64)
+    lib().orc_nn_dist2(a, a.shape[0], b, b.shape[0], d)
+    return d[:a.shape[0]]
+
+
+def surface_metrics(pred, gt, thresholds):
+    """Eq. (14) and the paper's accuracy, completeness and F-scores from the
+    nearest-point distances: CD = mean_p d(p,G)^2 + mean_g d(g,P)^2, accuracy =
+    mean_p d(p,G), completeness = mean_g d(g,P), precision/recall = fraction
+    within each threshold, F = 2 P R / (P + R).  Sums in ascending index."""
+    dp = nn_dist2(pred, gt)
+    dg = nn_dist2(gt, pred)
+    sp, sg = np.sqrt(dp), np.sqrt(dg)
+    acc = {"chamfer": float(np.sum(dp) / len(dp) + np.sum(dg) / len(dg)),
+           "accuracy": float(np.sum(sp) / len(sp)), "completeness": float(np.sum(sg) / len(sg)),
+           "precision": [], "recall": [], "fscore": []}
+    for t in thresholds:
+        pr = float(np.count_nonzero(sp < t) / len(sp))
+        rc = float(np.count_nonzero(sg < t) / len(sg))
+        acc["precision"].append(pr)
+        acc["recall"].append(rc)
+        acc["fscore"].append(2 * pr * rc / (pr + rc) if pr + rc > 0 else 0.0)
+    return acc, dp, dg
 
 
 def quantize_variance(s):

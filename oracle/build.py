@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(verbose: bool = False) -> str:
     cmd = ["gcc", "-std=c99", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
            "-shared", "-Wall", "-Wextra", "-o", LIB + ".tmp", os.path.join(HERE, "oracle.c"),
-           os.path.join(HERE, "trilinear.c"), "-lm"]
+           os.path.join(HERE, "trilinear.c"), os.path.join(HERE, "surface.c"), "-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

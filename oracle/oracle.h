@@ -125,4 +125,10 @@ void orc_pcg27(int64_t N, const double* diag, const double* off, const int32_t* 
 void orc_hutchinson27(int64_t N, const double* diag, const double* off, const int32_t* nb26, int32_t K,
                       uint64_t seed, double tol, int32_t max_iter, double* s_out, int32_t* iters_out);
 
+/* Surface extraction and geometry-metric distances (surface.c; Alg. 1 step 7, eq. 14). */
+int32_t orc_surf_dir(int32_t dx, int32_t dy, int32_t dz);
+void orc_extract_surface(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu, double iso,
+                         int64_t cap_v, int64_t cap_t, double* verts, int32_t* tris, int64_t* nv, int64_t* nt);
+void orc_nn_dist2(const double* a, int64_t na, const double* b, int64_t nb, double* d_out);
+
 #endif
