@@ -437,6 +437,71 @@ def trilinear_section(g, args):
     return out
 
 
+NN_OPS_PER_PAIR = 9  # 3 differences, 3 products, 2 sums, 1 minimum (FP64)
+
+
+def surface_section(g, args):
+    """Algorithm 1 step 7 and the geometry metrics of Sec. 4.2 on the step's
+    workload: marching-tetrahedra meshes of the coarse TSDF and of the mean of
+    the voxel-centric system (without and with the boundary anchor) and of the
+    trilinear system, each against 200k points of the analytic surface (F at
+    5, 10, 20 mm).  Timings of extraction and of the all-pairs nearest-point
+    kernel (ALU bound: 9 FP64 operations per pair)."""
+    import torch
+    import paper_2602_19697_amd as bf
+    from synth import surface_points
+    ctx, wl = g["ctx"], g["wl"]
+    thr = (0.005, 0.01, 0.02)
+    gt = torch.from_numpy(surface_points(wl.scene, 200000, 0)).to(ctx.device)
+    noise = bf.noise_struct(*wl.noise)
+    band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
+    fields = {"tsdf": band.arrays()["tsdf"]}
+    for label, lam_b in (("mean", 0.0), ("mean_anchored", 10.0)):
+        sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], noise, wl.lam, wl.eps, lam_b)
+        fields[label], _ = ctx.bf_pcg_solve(sys_, 1e-8, precision=bf.L.BF_PREC_FP64)
+        sys_.free()
+    S = int(round(wl.tau / wl.h))
+    sys_ = ctx.bf_assemble_trilinear(band, wl.cam, g["depth"], g["poses"], noise, wl.lam, wl.eps,
+                                     samples_per_side=S)
+    fields["mean_trilinear"], _ = ctx.bf_pcg_solve(sys_, 1e-8, precision=bf.L.BF_PREC_FP64)
+    sys_.free()
+    out = {"gt_points": int(gt.shape[0]), "thresholds_m": list(thr), "meshes": {}}
+    for label, field in fields.items():
+        mesh = ctx.bf_extract_surface(band, field)
+        v = mesh.arrays()["verts"]
+        m = ctx.bf_surface_metrics(v, gt, thr)
+        out["meshes"][label] = {"vertices": mesh.n_vert, "triangles": mesh.n_tri,
+                                **{k: m[k] for k in ("chamfer", "accuracy", "completeness", "precision", "recall",
+                                                     "fscore")}}
+        mesh.free()
+    # timings on the plain mean's mesh
+    mesh_ms = _timed(lambda: ctx.bf_extract_surface(band, fields["mean"]).free(), reps=5)[1]
+    mesh = ctx.bf_extract_surface(band, fields["mean"])
+    v = mesh.arrays()["verts"]
+    torch.cuda.synchronize()
+    ctx.bf_get_timings()
+    ctx.bf_set_timing(True)
+    _, met_ms = _timed(lambda: ctx.bf_surface_metrics(v, gt, thr), reps=2)
+    ctx.bf_set_timing(False)
+    tm = ctx.bf_get_timings()
+    launches, ms = tm.get("nn_dist2", (0, 0.0))
+    pairs = 2 * mesh.n_vert * int(gt.shape[0])  # both directions
+    out["extract_ms"] = mesh_ms
+    out["metrics_ms"] = met_ms
+    if launches:
+        ach = pairs * NN_OPS_PER_PAIR / (ms * 1e-3 / launches * 2) / 1e12  # two launches per metrics call
+        out["nn_dist2"] = {"launches": launches, "avg_us": 1e3 * ms / launches, "pairs_per_call": pairs,
+                           "achieved_TOPs": ach, "peak_TOPs": FP64_ALU_PEAK_TOPS,
+                           "frac": ach / FP64_ALU_PEAK_TOPS}
+    mesh.free()
+    band.free()
+    mm = out["meshes"]
+    log("[surface] " + "; ".join(f"{k}: CD {mm[k]['chamfer']:.2e} acc {1e3 * mm[k]['accuracy']:.2f} mm "
+                                 f"comp {1e3 * mm[k]['completeness']:.2f} mm F@20 {mm[k]['fscore'][2]:.3f}"
+                                 for k in mm) + f"; extract {mesh_ms:.2f} ms, metrics {met_ms:.1f} ms")
+    return out
+
+
 def batch_section(g, args):
     """Many scenes of uneven size: args.batch_scenes sphere scenes whose band
     sizes are log-uniform in [2e4, 8e5], mean + 64-probe variance, to 1e-6.
@@ -590,6 +655,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-solver-roofline", action="store_true")
     ap.add_argument("--no-trilinear", action="store_true")
+    ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--solver-workload", default="union512")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
@@ -617,6 +683,7 @@ def main():
     copy_gbs = None if args.no_compare else stream_copy_gbs()
     batch = None if args.no_batch else batch_section(g, args)
     trilinear = None if args.no_trilinear else trilinear_section(g, args)
+    surface = None if args.no_surface else surface_section(g, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
     # The roofline is that of the longest-running kernel with a roofline
     # claim.  The ray walk (nbv_rays) is irregular and latency-bound: it gets
@@ -670,6 +737,7 @@ def main():
         "stream_copy_GBps": copy_gbs,
         "batch": batch,
         "trilinear": trilinear,
+        "surface": surface,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

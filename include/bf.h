@@ -234,6 +234,53 @@ bf_status bf_system_free(bf_ctx* ctx, bf_system* sys);
 /* q_dev = Q p_dev for device vectors of N doubles (eq. 10). */
 bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double* p_dev, double* q_dev);
 
+/* ---------------------------------------------------------------- surface */
+
+typedef struct bf_mesh bf_mesh;
+
+typedef struct bf_mesh_arrays {
+  int64_t n_vert, n_tri;
+  const double* verts;     /* [n_vert][3] world positions (m) */
+  const int32_t* tris;     /* [n_tri][3] vertex indices, normal (b-a)x(c-a) towards mu > iso */
+} bf_mesh_arrays;
+
+/* Algorithm 1 step 7: the iso-surface mu = iso of a field over the band
+ * (mu_dev [N], e.g. the posterior mean) by marching tetrahedra, the
+ * tetrahedral form of marching cubes.  A voxel is inside when mu < iso.  Each
+ * cube of 8 band voxel centres is split into the 6 tetrahedra of the
+ * Freudenthal split along its main diagonal (the split matches across cubes,
+ * so the mesh is watertight inside the band).  Vertices lie on grid edges
+ * from a band voxel v along one of the 7 directions {0,1}^3 \ 0 (x, y, z, xy,
+ * xz, yz, xyz) to a band voxel with the other inside state, at
+ * x_v + t (x_u - x_v), t = (mu_v - iso) / (mu_v - mu_u); they are numbered by
+ * band index, then direction; triangles by cube (band index of its lowest
+ * voxel), tetrahedron (axis orders 012, 021, 102, 120, 201, 210), position.
+ * Writes *out (a new mesh; free with bf_mesh_free on this context) and the
+ * host counts (may be NULL).  Synchronises.  Errors: INVALID_ARG, CAPACITY
+ * (2^31 vertices or more), OOM, HIP. */
+bf_status bf_extract_surface(bf_ctx* ctx, const bf_band* band, const double* mu_dev, double iso,
+                             bf_mesh** out, int64_t* n_vert, int64_t* n_tri);
+bf_status bf_mesh_view(const bf_mesh* mesh, bf_mesh_arrays* out);
+bf_status bf_mesh_free(bf_ctx* ctx, bf_mesh* mesh);
+
+/* Geometry metrics of Sec. 4.2 between predicted points P and ground-truth
+ * points G (both [n][3] device arrays, m): with d(x, S) the distance to the
+ * nearest point of S (exact, by brute force over all pairs),
+ * chamfer = mean_P d(p,G)^2 + mean_G d(g,P)^2 (eq. 14), accuracy =
+ * mean_P d(p,G), completeness = mean_G d(g,P), and per threshold thr[t]
+ * (n_thr <= 8): precision = fraction of P with d < thr, recall = fraction of
+ * G with d < thr, F = 2 P R / (P + R).  d_pred_dev [n_pred] and d_gt_dev
+ * [n_gt] (may be NULL) receive the squared distances.  Synchronises. */
+typedef struct bf_metrics {
+  int64_t n_pred, n_gt;
+  double chamfer, accuracy, completeness;
+  int32_t n_thr;
+  double thr[8], precision[8], recall[8], fscore[8];
+} bf_metrics;
+bf_status bf_surface_metrics(bf_ctx* ctx, const double* pred_dev, int64_t n_pred, const double* gt_dev,
+                             int64_t n_gt, int32_t n_thr, const double* thr_host, bf_metrics* out,
+                             double* d_pred_dev, double* d_gt_dev);
+
 /* ---------------------------------------------------------------- solves */
 
 /* Sec. 3.6, eq. (11), Algorithm 1 step 5: Jacobi-preconditioned CG for

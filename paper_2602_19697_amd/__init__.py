@@ -99,6 +99,26 @@ def noise_struct(a=0.0012, c=0.0019, z0=0.4, sigma2_pose=None, sigma2_model=0.0)
 
 
 @dataclasses.dataclass
+class Mesh:
+    ctx: "Context"
+    handle: C.c_void_p
+    n_vert: int
+    n_tri: int
+
+    def arrays(self) -> dict:
+        a = L.bf_mesh_arrays()
+        self.ctx._check(self.ctx.lib.bf_mesh_view(self.handle, C.byref(a)))
+        dev = self.ctx.device
+        return {"verts": _view(a.verts, (int(a.n_vert), 3), torch.float64, dev),
+                "tris": _view(a.tris, (int(a.n_tri), 3), torch.int32, dev)}
+
+    def free(self):
+        if self.handle:
+            self.ctx.lib.bf_mesh_free(self.ctx.handle, self.handle)
+            self.handle = None
+
+
+@dataclasses.dataclass
 class Band:
     ctx: "Context"
     handle: C.c_void_p
@@ -236,6 +256,32 @@ class Context:
                                                    int(depth.shape[0]), _ptr(depth), _ptr(poses), C.byref(noise),
                                                    C.byref(pr), int(samples_per_side), C.byref(h), C.byref(ns)))
         return System(self, h, band.n, band)
+
+    # ---------------------------------------------------------- surface
+    def bf_extract_surface(self, band: Band, mu, iso=0.0) -> Mesh:
+        """Marching-tetrahedra iso-surface mu = iso over the band (Algorithm 1 step 7)."""
+        h = C.c_void_p()
+        nv, nt = C.c_int64(), C.c_int64()
+        self._check(self.lib.bf_extract_surface(self.handle, band.handle, _ptr(mu), float(iso), C.byref(h),
+                                                C.byref(nv), C.byref(nt)))
+        return Mesh(self, h, int(nv.value), int(nt.value))
+
+    def bf_surface_metrics(self, pred, gt, thresholds=(), with_distances=False):
+        """Chamfer (eq. 14), accuracy, completeness and F-scores between point sets."""
+        thr = (C.c_double * max(len(thresholds), 1))(*[float(t) for t in thresholds])
+        m = L.bf_metrics()
+        dp = torch.empty(pred.shape[0], dtype=torch.float64, device=self.device) if with_distances else None
+        dg = torch.empty(gt.shape[0], dtype=torch.float64, device=self.device) if with_distances else None
+        self._check(self.lib.bf_surface_metrics(self.handle, _ptr(pred), int(pred.shape[0]), _ptr(gt),
+                                                int(gt.shape[0]), len(thresholds), thr, C.byref(m), _ptr(dp),
+                                                _ptr(dg)))
+        k = int(m.n_thr)
+        out = {"chamfer": m.chamfer, "accuracy": m.accuracy, "completeness": m.completeness,
+               "thresholds": list(m.thr[:k]), "precision": list(m.precision[:k]), "recall": list(m.recall[:k]),
+               "fscore": list(m.fscore[:k])}
+        if with_distances:
+            out["d_pred"], out["d_gt"] = dp, dg
+        return out
 
     def bf_apply_Q(self, sys: System, p):
         q = torch.empty_like(p)

@@ -89,6 +89,16 @@ class bf_system_arrays(C.Structure):
                 ("off", C.c_void_p), ("nb26", C.c_void_p), ("n_samples", C.c_int64), ("n_cells", C.c_int64)]
 
 
+class bf_mesh_arrays(C.Structure):
+    _fields_ = [("n_vert", C.c_int64), ("n_tri", C.c_int64), ("verts", C.c_void_p), ("tris", C.c_void_p)]
+
+
+class bf_metrics(C.Structure):
+    _fields_ = [("n_pred", C.c_int64), ("n_gt", C.c_int64), ("chamfer", C.c_double), ("accuracy", C.c_double),
+                ("completeness", C.c_double), ("n_thr", C.c_int32), ("thr", C.c_double * 8),
+                ("precision", C.c_double * 8), ("recall", C.c_double * 8), ("fscore", C.c_double * 8)]
+
+
 class bf_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -112,6 +122,11 @@ SIGNATURES = {
     "bf_assemble_trilinear": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise),
                                         C.POINTER(bf_prior), C.c_int32, PP, C.POINTER(C.c_int64)]),
     "bf_system_view": (C.c_int, [P, C.POINTER(bf_system_arrays)]),
+    "bf_extract_surface": (C.c_int, [P, P, P, C.c_double, PP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "bf_mesh_view": (C.c_int, [P, C.POINTER(bf_mesh_arrays)]),
+    "bf_mesh_free": (C.c_int, [P, P]),
+    "bf_surface_metrics": (C.c_int, [P, P, C.c_int64, P, C.c_int64, C.c_int32, C.POINTER(C.c_double),
+                                     C.POINTER(bf_metrics), P, P]),
     "bf_system_free": (C.c_int, [P, P]),
     "bf_apply_Q": (C.c_int, [P, P, P, P]),
     "bf_features": (C.c_int, [P, P, P]),

@@ -7,11 +7,12 @@ candidate poses.  Everything it returns is plain numpy (or torch on a chosen
 device for the depth renderer) and is handed unchanged to both sides.
 """
 from .cameras import look_at, ring_poses, hemisphere_poses, sphere_candidates, Camera
-from .scenes import Sphere, RoundedBox, Torus, Scene, single_sphere, random_union
+from .scenes import Sphere, RoundedBox, Torus, Scene, single_sphere, random_union, surface_points
 from .render import render_depth, add_depth_noise, sigma_depth
 from .configs import Workload, make_workload, WORKLOADS
 
 __all__ = [
+    "surface_points",
     "look_at", "ring_poses", "hemisphere_poses", "sphere_candidates", "Camera",
     "Sphere", "RoundedBox", "Torus", "Scene", "single_sphere", "random_union",
     "render_depth", "add_depth_noise", "sigma_depth",

@@ -127,3 +127,35 @@ def random_union(seed: int, n_spheres: int = 3, n_boxes: int = 1, n_tori: int = 
         tor.centre = centre_for(tor.bound())
         prims.append(tor)
     return Scene(prims)
+
+
+def surface_points(scene: Scene, n: int, seed: int, shell: float = 0.01, device="cpu") -> np.ndarray:
+    """n seeded points on the scene's surface (the zero set of its SDF), the
+    ground truth of the geometry metrics.
+
+    Candidates are uniform in the scene's bounding cube and kept inside the
+    shell |sdf| < shell, so they are spread about evenly by area; each is
+    moved by Newton steps p <- p - f(p) grad f / |grad f|^2 (for the exact
+    SDFs here one step lands on the nearest surface point of the active
+    primitive) and kept when |f| <= 1e-9 afterwards, which drops points that
+    landed inside another primitive of the union.
+    """
+    rng = np.random.default_rng((0x5F3, int(seed)))
+    bound = scene.bound()
+    out, have = [], 0
+    while have < n:
+        cand = rng.uniform(-bound, bound, size=(max(4 * n, 65536), 3))
+        with torch.no_grad():
+            f = scene.sdf(torch.as_tensor(cand, dtype=torch.float64, device=device)).cpu().numpy()
+        p = torch.as_tensor(cand[np.abs(f) < shell], dtype=torch.float64, device=device)
+        for _ in range(3):
+            p = p.detach().requires_grad_(True)
+            f = scene.sdf(p)
+            (g,) = torch.autograd.grad(f.sum(), p)
+            p = p - (f / (g * g).sum(dim=-1).clamp(min=1e-30)).unsqueeze(-1) * g
+        with torch.no_grad():
+            ok = scene.sdf(p).abs() <= 1e-9
+        pts = p.detach()[ok].cpu().numpy()
+        out.append(pts)
+        have += len(pts)
+    return np.ascontiguousarray(np.concatenate(out)[:n])
