@@ -60,6 +60,7 @@ struct ray_k {
   double na, nc, nz0;  // sensor model for the variance-reduction utility
   int brick_shift, nbrick, ncell;
   int64_t tiles_per_cand, ntiles;
+  int32_t tiles_x;     // 16x16-pixel tiles per image row
 };
 
 constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
@@ -270,11 +271,14 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
   return inside;
 }
 
-// Work queue over (candidate, chunk of kRaysPerTile rays) taken wave by wave;
-// every workgroup stages the brick bitmap in LDS once.  A lane walks the
-// chunk's rays lane, lane + 64, ...: when its ray ends it starts the next one,
-// in batches (once a quarter of the wave is idle, or all of it), so a wave
-// does not wait for its longest ray.
+// Work queue over (candidate, 16x16-pixel tile) taken wave by wave; every
+// workgroup stages the brick bitmap in LDS once.  A tile's 256 rays are four
+// 8x8 pixel blocks, taken block by block, so the 64 rays a wave walks at a
+// time are neighbours in both image directions (similar paths: fewer
+// divergent branches, shared cache lines).  A lane walks rays lane,
+// lane + 64, ...: when its ray ends it starts the next one, in batches (once
+// a quarter of the wave is idle, or all of it), so a wave does not wait for
+// its longest ray.
 constexpr int kRaysPerTile = 256;
 
 template <int UTIL>
@@ -289,7 +293,6 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
   for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
   __syncthreads();
   const double smax = *smax_p;
-  const int64_t npix = (int64_t)R.cam.W * R.cam.H;
   const int lane = threadIdx.x & 63;
   for (;;) {
     unsigned int t = 0;
@@ -298,28 +301,29 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
     const int64_t tile = (int64_t)(unsigned int)__builtin_amdgcn_readfirstlane((int)__shfl(t, 0, 64));
     if (tile >= R.ntiles) break;
     const int64_t cand = tile / R.tiles_per_cand;
-    const int64_t chunk = tile % R.tiles_per_cand;
-    const int64_t p_end = std::min<int64_t>(npix, (chunk + 1) * kRaysPerTile);
+    const int32_t tb = (int32_t)(tile % R.tiles_per_cand);
+    const int32_t ty = tb / R.tiles_x, tx = tb % R.tiles_x;
     const double* P = cands + 12 * cand;
     const double o[3] = {P[3], P[7], P[11]};
-    int64_t next = chunk * kRaysPerTile + lane;
+    int32_t next = lane;  // ray of the tile: 8x8 block next / 64, position next % 64 in it
     long long acc = 0;
     unsigned long long nsteps = 0;
     Ray r;
     bool live = false;
     for (;;) {
-      const bool want = !live && next < p_end;
+      const bool want = !live && next < kRaysPerTile;
       const unsigned long long need = __ballot(want);
       const unsigned long long busy = __ballot(live);
       if (need == 0 && busy == 0) break;  // wave-uniform
       if (need != 0 && (__popcll(need) >= R.refill_batch || busy == 0)) {
         if (want) {
-          const int32_t row = (int32_t)(next / R.cam.W), col = (int32_t)(next % R.cam.W);
+          const int32_t blk = next >> 6, l = next & 63;
+          const int32_t row = ty * 16 + (blk >> 1) * 8 + (l >> 3), col = tx * 16 + (blk & 1) * 8 + (l & 7);
           // re-read the pose here rather than keep its rotation in scalar
           // registers across the whole walk loop (they would spill)
           const double* Pi = P;
           asm volatile("" : "+s"(Pi));
-          live = ray_init(r, R, Pi, o, row, col);
+          live = row < R.cam.H && col < R.cam.W && ray_init(r, R, Pi, o, row, col);
           next += 64;
         }
         continue;
@@ -425,11 +429,11 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
       R.nc = noise->c;
       R.nz0 = noise->z0;
     }
-    const int64_t npix = (int64_t)ray_cam->width * ray_cam->height;
     R.brick_shift = band->brick_shift;
     R.nbrick = band->nbrick;
     R.ncell = band->ncell;
-    R.tiles_per_cand = bf_cdiv(npix, kRaysPerTile);
+    R.tiles_x = (int32_t)bf_cdiv(ray_cam->width, 16);
+    R.tiles_per_cand = (int64_t)R.tiles_x * bf_cdiv(ray_cam->height, 16);
     R.ntiles = R.tiles_per_cand * n_cand;
     BF_CHECK(ctx, R.ntiles < (1ll << 31), "bf_nbv_score: too many rays");
     int per_cu = 0;
