@@ -272,14 +272,13 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
 }
 
 // Work queue over (candidate, 16x16-pixel tile) taken wave by wave; every
-// workgroup stages the brick bitmap in LDS once.  A tile's 256 rays are four
-// 8x8 pixel blocks, taken block by block, so the 64 rays a wave walks at a
-// time are neighbours in both image directions (similar paths: fewer
-// divergent branches, shared cache lines).  A lane walks rays lane,
-// lane + 64, ...: when its ray ends it starts the next one, in batches (once
-// a quarter of the wave is idle, or all of it), so a wave does not wait for
-// its longest ray.
-constexpr int kRaysPerTile = 256;
+// workgroup stages the brick bitmap in LDS once.  A tile's rays are up to four
+// 8x8 pixel blocks (fewer on the image's right and bottom edges), handed out
+// block by block, so the 64 rays a wave walks at a time are neighbours in both
+// image directions (similar paths: fewer divergent branches, shared cache
+// lines).  Rays go to lanes on demand: once enough lanes are idle (refill_batch,
+// or the whole wave), they take the tile's next unwalked rays in lane order, so
+// no lane is tied to a fixed share of long rays while the others wait.
 
 template <int UTIL>
 __global__ __launch_bounds__(256)
@@ -305,27 +304,34 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
     const int32_t ty = tb / R.tiles_x, tx = tb % R.tiles_x;
     const double* P = cands + 12 * cand;
     const double o[3] = {P[3], P[7], P[11]};
-    int32_t next = lane;  // ray of the tile: 8x8 block next / 64, position next % 64 in it
+    const int32_t bxn = min(2, (R.cam.W - tx * 16 + 7) >> 3);  // 8x8 blocks of the tile in the image
+    const int32_t byn = min(2, (R.cam.H - ty * 16 + 7) >> 3);
+    const int32_t nrays = 64 * bxn * byn;
+    int32_t base = 0;  // rays of the tile handed out so far (wave-uniform)
     long long acc = 0;
     unsigned long long nsteps = 0;
     Ray r;
     bool live = false;
     for (;;) {
-      const bool want = !live && next < kRaysPerTile;
+      const bool want = !live && base < nrays;
       const unsigned long long need = __ballot(want);
       const unsigned long long busy = __ballot(live);
       if (need == 0 && busy == 0) break;  // wave-uniform
       if (need != 0 && (__popcll(need) >= R.refill_batch || busy == 0)) {
         if (want) {
-          const int32_t blk = next >> 6, l = next & 63;
-          const int32_t row = ty * 16 + (blk >> 1) * 8 + (l >> 3), col = tx * 16 + (blk & 1) * 8 + (l & 7);
+          // ray of the tile: 8x8 block ray / 64, position ray % 64 in it
+          const int32_t ray = base + (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+          const int32_t blk = ray >> 6, l = ray & 63;
+          const int32_t bx = bxn == 2 ? (blk & 1) : 0, by = bxn == 2 ? (blk >> 1) : blk;
+          const int32_t row = ty * 16 + by * 8 + (l >> 3), col = tx * 16 + bx * 8 + (l & 7);
           // re-read the pose here rather than keep its rotation in scalar
           // registers across the whole walk loop (they would spill)
           const double* Pi = P;
           asm volatile("" : "+s"(Pi));
-          live = row < R.cam.H && col < R.cam.W && ray_init(r, R, Pi, o, row, col);
-          next += 64;
+          live = ray < nrays && row < R.cam.H && col < R.cam.W && ray_init(r, R, Pi, o, row, col);
         }
+        base += __popcll(need);
         continue;
       }
       if (live && !ray_advance<UTIL>(r, R, __popcll(busy), P, o, cells, bdist, mu, s, qs, smax, bricks)) {
