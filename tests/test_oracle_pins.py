@@ -428,3 +428,100 @@ def test_features_planar_wall(orc):
     assert np.all(f[:, 9] == 0.0) and np.all(f[:, 10] == 0.0)
     assert np.allclose(f[:, 4], bt / h)  # one view: mean y = TSDF
     assert np.all(f[:, 5] == 0.0)
+
+
+def _rot(ax, ay, az):
+    cx, sx, cy, sy, cz, sz = math.cos(ax), math.sin(ax), math.cos(ay), math.sin(ay), math.cos(az), math.sin(az)
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    return Rz @ Ry @ Rx
+
+
+def _look_at_centre(R0, dist, jitter):
+    """Camera-to-world pose (3x4, row-major) at dist from the origin whose optical
+    axis (third column of R) points at the grid centre, before a small rotation."""
+    R = R0
+    o = -dist * R[:, 2] + jitter
+    return np.concatenate([R, o[:, None]], axis=1).reshape(-1)
+
+
+def _crossed_voxels(g, o, d):
+    """Voxels the ray o + t d (t >= 0) passes through, in order: every time the ray
+    crosses a grid plane is computed, the times are sorted, and each segment between
+    consecutive crossings lies in the voxel holding its midpoint."""
+    G, h, org = g.G, g.h, np.array(g.origin[:])
+    ts = [0.0]
+    for ax in range(3):
+        if d[ax] != 0.0:
+            ts.extend(((org[ax] + np.arange(G + 1) * h - o[ax]) / d[ax]).tolist())
+    ts = np.unique(np.array([t for t in ts if t >= 0.0]))
+    out = []
+    for t0, t1 in zip(ts[:-1], ts[1:]):
+        idx = np.floor((o + 0.5 * (t0 + t1) * d - org) / h).astype(int)
+        if np.all(idx >= 0) and np.all(idx < G):
+            out.append(tuple(int(i) for i in idx))
+    return out
+
+
+def _vr_setup(orc, seed):
+    G, h = 8, 0.125
+    g = orc.grid(G, h, (-0.5,) * 3, 0.5, 0.25)
+    keys = _full_band(orc, G)
+    rng = np.random.default_rng(seed)
+    # variances with at most 20 significant bits, so s * s is exact and (s * s) / s == s
+    s = rng.integers(1, 1 << 20, size=len(keys)).astype(np.float64) / 1024.0
+    mu = np.ones(len(keys))
+    for n, k in enumerate(keys):
+        c = orc.morton_decode(int(k))
+        if sum((x - 3.5) ** 2 for x in c) < 5.0:
+            mu[n] = -1.0
+    cam = orc.cam(type("C", (), dict(width=5, height=4, fx=3.0, fy=3.0, cx=1.93, cy=1.41))())
+    poses = np.stack([_look_at_centre(_rot(*rng.uniform(-0.6, 0.6, 3)), 1.6, rng.uniform(-0.05, 0.05, 3))
+                      for _ in range(4)])
+    return g, keys, s, mu, cam, poses
+
+
+def test_nbv_var_reduction_noiseless_equals_summed_variance(orc):
+    """With a noiseless sensor (sigma = 0) one more observation removes all of a
+    voxel's variance: s^2 / (s + 0) = s, so the expected-variance-reduction utility
+    equals the summed-variance utility (pinned above by dense ray sampling)."""
+    g, keys, s, mu, cam, poses = _vr_setup(orc, 21)
+    q = orc.quantize_variance(s)
+    want = orc.nbv_scores(g, cam, keys, mu, q, poses)
+    got = orc.nbv_scores_var_reduction(g, cam, keys, mu, s, poses, noise=(0.0, 0.0, 0.4))
+    assert np.all(want > 0)
+    assert np.array_equal(got, want)
+
+
+def test_nbv_var_reduction_depth_from_geometry(orc):
+    """Depth-dependent sensor noise sigma(Z) = a + c (Z - z0)^2: the expected
+    reduction at a voxel is s^2 / (s + sigma^2) with Z the voxel centre's depth
+    along the candidate's optical axis (the rotation's third column), summed over
+    the voxels each pixel ray crosses (from its sorted plane crossings) up to the
+    first voxel with mu <= 0.  Each voxel's term may round differently by 1."""
+    g, keys, s, mu, cam, poses = _vr_setup(orc, 22)
+    a, c, z0 = 0.3, 2.0, 0.9
+    smax = s.max()
+    pos = {orc.morton_decode(int(k)): n for n, k in enumerate(keys)}
+    got = orc.nbv_scores_var_reduction(g, cam, keys, mu, s, poses, noise=(a, c, z0))
+    for ci, P in enumerate(poses):
+        M = P.reshape(3, 4)
+        R, o = M[:, :3], M[:, 3]
+        want, nvox = 0, 0
+        for row in range(cam.height):
+            for col in range(cam.width):
+                d = R @ np.array([(col - cam.cx) / cam.fx, (row - cam.cy) / cam.fy, 1.0])
+                for vx in _crossed_voxels(g, o, d):
+                    n = pos[vx]
+                    centre = np.array(g.origin[:]) + (np.array(vx) + 0.5) * g.h
+                    Z = float(R[:, 2] @ (centre - o))
+                    sig = a + c * (Z - z0) ** 2
+                    want += int(np.rint(s[n] ** 2 / (s[n] + sig ** 2) / smax * 2.0 ** 32))
+                    nvox += 1
+                    if mu[n] <= 0:
+                        break
+        assert nvox > 20
+        assert abs(int(got[ci]) - want) <= nvox, (ci, got[ci], want)
+    # the noise model matters: a noiseless sensor gives strictly larger utilities
+    assert np.all(orc.nbv_scores_var_reduction(g, cam, keys, mu, s, poses, noise=(0.0, 0.0, z0)) > got)
