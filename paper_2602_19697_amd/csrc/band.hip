@@ -394,24 +394,39 @@ __global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict_
   if (v == 0 || (keys[v - 1] >> 6) != (key >> 6)) cells[c].start = (int32_t)v;
 }
 
-// Chebyshev distance transform over the brick grid, one axis per pass:
-// out(x) = min over x' of max(|x - x'|, in(x')), with in = 0 on occupied bricks
-// and 255 elsewhere for the first pass.  axis 0 reads the bitmap.
-__global__ __launch_bounds__(256) void k_brick_dist(const uint32_t* __restrict__ bits, const uint8_t* __restrict__ in,
-                                                    uint8_t* __restrict__ out, int nb, int axis) {
+// Forward-octant Chebyshev distances over the brick grid (empty-space skipping
+// for the ray walker).  Octant o has bit a set when the ray moves towards lower
+// coordinates on axis a.  For brick b, dist_o(b) = min over occupied bricks b'
+// ahead of b in that octant (b'_a - b_a of the octant's sign, or 0, on every
+// axis) of max_a |b'_a - b_a|, capped at 255 (also: no such brick).  So the
+// box from b to b + (dist - 1) bricks along the octant holds no occupied brick.
+// The min of max separates into one pass per axis,
+//   out(x) = min over t >= 0 of max(t, in(x + sign t)),
+// each pass doubling the variants (bit a of a variant = sign on axis a): 2 after
+// the x pass (which reads the bitmap, in = 0 on occupied bricks, else 255), 4
+// after y, 8 after z.  Variant v's grid is at offset v nb^3.
+__global__ __launch_bounds__(256) void k_brick_oct(const uint32_t* __restrict__ bits, const uint8_t* __restrict__ in,
+                                                   uint8_t* __restrict__ out, int nb, int axis) {
+  const int64_t nb3 = (int64_t)nb * nb * nb;
   const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t total = (int64_t)nb * nb * nb;
-  if (id >= total) return;
-  const int x = (int)(id % nb), y = (int)((id / nb) % nb), z = (int)(id / ((int64_t)nb * nb));
+  if (id >= (nb3 << (axis + 1))) return;
+  const int vout = (int)(id / nb3);
+  const int64_t e = id - vout * nb3;
+  const int vin = vout & ((1 << axis) - 1);
+  const int dir = ((vout >> axis) & 1) ? -1 : 1;
+  const int x = (int)(e % nb), y = (int)((e / nb) % nb), z = (int)(e / ((int64_t)nb * nb));
   const int pos = axis == 0 ? x : (axis == 1 ? y : z);
   const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nb : (int64_t)nb * nb);
-  const int64_t base = id - (int64_t)pos * stride;
+  const int64_t base = e - (int64_t)pos * stride;
+  const uint8_t* src = axis == 0 ? nullptr : in + vin * nb3;
   int best = 255;
-  for (int t = 0; t < nb; ++t) {
-    const int64_t j = base + t * stride;
-    const int dv = axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)in[j];
-    const int dd = t > pos ? t - pos : pos - t;
-    const int m = dv > dd ? dv : dd;
+  // max(t, .) >= t: nothing at t >= best can improve on best
+  for (int t = 0; t < best; ++t) {
+    const int q = pos + dir * t;
+    if (q < 0 || q >= nb) break;
+    const int64_t j = base + (int64_t)q * stride;
+    const int dv = axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)src[j];
+    const int m = dv > t ? dv : t;
     if (m < best) best = m;
   }
   out[id] = (uint8_t)best;
@@ -567,18 +582,17 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
       return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
     BF_LAUNCH(ctx, "brick_bits", k_brick_bits, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, shift, band->nbrick,
               band->bricks);
-    // brick distances (empty-space skipping) for the ray walker
+    // forward-octant brick distances (empty-space skipping) for the ray walker
     const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
-    uint8_t* dtmp = nullptr;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, nbr3)) return fail(s);
-    if (bf_status s = bf_ws(ctx, bf_ctx::WS_NBV_TMP, nbr3, (void**)&dtmp)) return fail(s);
-    const unsigned db = (unsigned)bf_cdiv(nbr3, 256);
-    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, (const uint8_t*)nullptr,
-              band->brick_dist, band->nbrick, 0);
-    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, band->brick_dist, dtmp,
-              band->nbrick, 1);
-    BF_LAUNCH(ctx, "brick_dist", k_brick_dist, dim3(db), dim3(256), 0, band->bricks, dtmp, band->brick_dist,
-              band->nbrick, 2);
+    uint8_t* dtmp = nullptr;  // 2 nbr3 after the x pass, then 4 nbr3 after y
+    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, 8 * nbr3)) return fail(s);
+    if (bf_status s = bf_ws(ctx, bf_ctx::WS_NBV_TMP, 6 * nbr3, (void**)&dtmp)) return fail(s);
+    for (int axis = 0; axis < 3; ++axis) {
+      const uint8_t* in = axis == 0 ? nullptr : (axis == 1 ? dtmp : dtmp + 2 * nbr3);
+      uint8_t* o = axis == 0 ? dtmp : (axis == 1 ? dtmp + 2 * nbr3 : band->brick_dist);
+      BF_LAUNCH(ctx, "brick_dist", k_brick_oct, dim3((unsigned)bf_cdiv(nbr3 << (axis + 1), 256)), dim3(256), 0,
+                band->bricks, in, o, band->nbrick, axis);
+    }
     if (bf_status s = bf_launch_check(ctx, "neighbours/bricks/cells")) return fail(s);
   }
   *out = band;

@@ -6,7 +6,7 @@
 // reproducible) and sums the quantised variance of the band voxels it crosses
 // up to and including the first voxel whose posterior mean is <= 0.  Band
 // membership is tested only in occupied bricks (a bitmap in LDS), through the
-// 4^3 cell masks; across empty bricks the walk jumps (see walk()).  Variances are quantised to int64
+// 4^3 cell masks; across empty bricks the walk jumps (see Ray).  Variances are quantised to int64
 // (q = rint(s / max s * 2^32)) before summation, so the per-candidate
 // utility is an exact integer independent of summation order: block sums
 // are combined with 64-bit integer atomics.
@@ -59,6 +59,7 @@ struct ray_k {
   int refill_batch;    // idle lanes start new rays once this many are idle (or the whole wave)
   double na, nc, nz0;  // sensor model for the variance-reduction utility
   int brick_shift, nbrick, ncell;
+  int32_t nbrick3;     // bricks in the grid: offset between octants of the distance table
   int64_t tiles_per_cand, ntiles;
   int32_t tiles_x;     // 16x16-pixel tiles per image row
 };
@@ -68,7 +69,7 @@ constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
 // BF_NBV_JUMP_BATCH and BF_NBV_REFILL_BATCH override them.  None changes a result.
 constexpr int kJumpMinDist = 1;
 constexpr int kJumpBatch = 32;
-constexpr int kRefillBatch = 16;
+constexpr int kRefillBatch = 24;
 
 // Time at which the ray crosses plane p of one axis (the plane between voxels
 // p - 1 and p).  Every step and every jump evaluates plane times with this one
@@ -85,13 +86,15 @@ __device__ __forceinline__ double plane_t(double org, double h, double o, double
 // nearest next plane (lowest axis on ties), with plane times from plane_t.
 // Since every plane time depends only on the plane index, the walk is the
 // merge, ordered by (time, axis), of the three axes' plane sequences, and
-// "every crossing earlier than time c" is a prefix of it.  Inside a cube of
-// bricks known to hold no band voxel the walk jumps: c = the earliest time at
-// which a plane bounding the cube is crossed, and each axis advances by the
-// number of its planes with time < c (estimated from the continuous ray, then
-// corrected with plane_t).  The voxels skipped hold no band voxel, so the
-// visited band voxels, the utility and the stopping voxel are those of the
-// plain walk.
+// "every crossing earlier than time c" is a prefix of it.  In an empty brick
+// the walk jumps across the box of bricks ahead of the ray that the brick's
+// forward-octant distance (for the octant of the ray's direction) proves empty:
+// from the current brick to dist - 1 bricks further along each axis the ray
+// moves on.  c = the earliest time at which the ray crosses a far face of that
+// box, and each axis advances by the number of its planes with time < c
+// (estimated from the continuous ray, then corrected with plane_t).  The
+// voxels skipped hold no band voxel, so the visited band voxels, the utility
+// and the stopping voxel are those of the plain walk.
 //
 // SUM_VAR reads qs[v]: the quantised variance, bitwise negated when the
 // voxel's posterior mean is <= 0 (the walk stops there), so one load serves
@@ -202,7 +205,8 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
   } else {
     if (bit != r.last_brick) {
       r.last_brick = bit;
-      r.last_dist = bdist[bit];
+      const int32_t oct = (r.step[0] < 0 ? 1 : 0) | (r.step[1] < 0 ? 2 : 0) | (r.step[2] < 0 ? 4 : 0);
+      r.last_dist = bdist[oct * R.nbrick3 + bit];
     }
     // The jump costs as much as several voxel steps and the wave executes it for
     // all lanes at once, so it runs only when enough lanes want it; the others
@@ -210,16 +214,16 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
     const bool want = r.last_dist >= R.jump_min;
     const int nwant = __popcll(__ballot(want));
     if (want && (nwant >= R.jump_batch || 4 * nwant >= nlive)) {
-      // bricks within Chebyshev radius rb of this one are empty: jump to the
-      // last voxel before the walk leaves that cube
+      // the bricks from this one to rb further along the ray's octant are
+      // empty: jump to the last voxel before the walk leaves that box
       const int rb = r.last_dist - 1;
       int32_t lo[3], hi[3];
       double cut = INFINITY;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         const int32_t bb = r.idx[ax] >> bs;
-        lo[ax] = max(0, (bb - rb) << bs);
-        hi[ax] = min(g.G - 1, ((bb + rb + 1) << bs) - 1);
+        lo[ax] = r.step[ax] < 0 ? max(0, (bb - rb) << bs) : bb << bs;
+        hi[ax] = r.step[ax] < 0 ? ((bb + 1) << bs) - 1 : min(g.G - 1, ((bb + rb + 1) << bs) - 1);
         if (r.step[ax] != 0) {
           const double te = plane_t(org[ax], g.h, o[ax], r.inv[ax], r.step[ax] > 0 ? hi[ax] + 1 : lo[ax]);
           cut = te < cut ? te : cut;
@@ -437,6 +441,7 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
     }
     R.brick_shift = band->brick_shift;
     R.nbrick = band->nbrick;
+    R.nbrick3 = band->nbrick * band->nbrick * band->nbrick;
     R.ncell = band->ncell;
     R.tiles_x = (int32_t)bf_cdiv(ray_cam->width, 16);
     R.tiles_per_cand = (int64_t)R.tiles_x * bf_cdiv(ray_cam->height, 16);
