@@ -406,28 +406,38 @@ __global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict_
 // the x pass (which reads the bitmap, in = 0 on occupied bricks, else 255), 4
 // after y, 8 after z.  Variant v's grid is at offset v nb^3.
 __global__ __launch_bounds__(256) void k_brick_oct(const uint32_t* __restrict__ bits, const uint8_t* __restrict__ in,
-                                                   uint8_t* __restrict__ out, int nb, int axis) {
-  const int64_t nb3 = (int64_t)nb * nb * nb;
-  const int64_t id = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (id >= (nb3 << (axis + 1))) return;
-  const int vout = (int)(id / nb3);
-  const int64_t e = id - vout * nb3;
+                                                   uint8_t* __restrict__ out, int lnb, int axis) {
+  // nb = 2^lnb <= 64 bricks per axis: every index fits 32 bits and splits by shifts
+  const int nb = 1 << lnb;
+  const int32_t id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (1 << (3 * lnb + axis + 1))) return;
+  const int vout = id >> (3 * lnb);
+  const int32_t e = id & ((1 << (3 * lnb)) - 1);
   const int vin = vout & ((1 << axis) - 1);
   const int dir = ((vout >> axis) & 1) ? -1 : 1;
-  const int x = (int)(e % nb), y = (int)((e / nb) % nb), z = (int)(e / ((int64_t)nb * nb));
-  const int pos = axis == 0 ? x : (axis == 1 ? y : z);
-  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? nb : (int64_t)nb * nb);
-  const int64_t base = e - (int64_t)pos * stride;
-  const uint8_t* src = axis == 0 ? nullptr : in + vin * nb3;
+  const int pos = (e >> (axis * lnb)) & (nb - 1);
+  const int32_t stride = 1 << (axis * lnb);
+  const int32_t base = e - pos * stride;
+  const uint8_t* src = axis == 0 ? nullptr : in + (vin << (3 * lnb));
+  // Candidates are taken 8 at a time so their loads are in flight together.
+  // Taking more than needed changes nothing: max(t, .) >= t >= best once
+  // t >= best, and positions outside the grid count as 255.
+  const int tend = dir > 0 ? nb - pos : pos + 1;  // positions along the line from pos on
   int best = 255;
-  // max(t, .) >= t: nothing at t >= best can improve on best
-  for (int t = 0; t < best; ++t) {
-    const int q = pos + dir * t;
-    if (q < 0 || q >= nb) break;
-    const int64_t j = base + (int64_t)q * stride;
-    const int dv = axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)src[j];
-    const int m = dv > t ? dv : t;
-    if (m < best) best = m;
+  for (int t0 = 0; t0 < best && t0 < tend; t0 += 8) {
+    int dv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int t = t0 + u;
+      const int q = min(max(pos + dir * t, 0), nb - 1);  // in the grid even where unused
+      const int32_t j = base + q * stride;
+      dv[u] = t >= tend ? 255 : (axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)src[j]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int m = dv[u] > t0 + u ? dv[u] : t0 + u;
+      best = m < best ? m : best;
+    }
   }
   out[id] = (uint8_t)best;
 }
@@ -587,11 +597,13 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     uint8_t* dtmp = nullptr;  // 2 nbr3 after the x pass, then 4 nbr3 after y
     if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, 8 * nbr3)) return fail(s);
     if (bf_status s = bf_ws(ctx, bf_ctx::WS_NBV_TMP, 6 * nbr3, (void**)&dtmp)) return fail(s);
+    int lnb = 0;  // nbrick is a power of two, at most 64
+    while ((1 << lnb) < band->nbrick) ++lnb;
     for (int axis = 0; axis < 3; ++axis) {
       const uint8_t* in = axis == 0 ? nullptr : (axis == 1 ? dtmp : dtmp + 2 * nbr3);
       uint8_t* o = axis == 0 ? dtmp : (axis == 1 ? dtmp + 2 * nbr3 : band->brick_dist);
       BF_LAUNCH(ctx, "brick_dist", k_brick_oct, dim3((unsigned)bf_cdiv(nbr3 << (axis + 1), 256)), dim3(256), 0,
-                band->bricks, in, o, band->nbrick, axis);
+                band->bricks, in, o, lnb, axis);
     }
     if (bf_status s = bf_launch_check(ctx, "neighbours/bricks/cells")) return fail(s);
   }
