@@ -201,10 +201,12 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
                                                 V* __restrict__ r, V* __restrict__ zz, int64_t n,
                                                 double* __restrict__ part) {
   __shared__ double lds[4 * 3 * 64];
-  if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
+  if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
+  if (mode == MODE_CHECK && st->pending == 0) return;
   const int c = threadIdx.x % KC;
   const bool act = mode == MODE_REPORT ? c < st->K
-                                       : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
+                                       : (st->active[c] != 0 &&
+                                          (mode == MODE_INIT || st->check[c] == (mode == MODE_VERIFY ? 2 : 1)));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v3[3] = {0.0, 0.0, 0.0};
@@ -295,10 +297,12 @@ __global__ __launch_bounds__(256) void k_bresid27(BState* __restrict__ st, int m
   __shared__ double lds[4 * 3 * 64];
   __shared__ double soff[kStage ? 26 * R : 1];
   __shared__ int32_t snb[kStage ? 26 * R : 1];
-  if (mode == MODE_CHECK && (st->nactive == 0 || !st->any_check)) return;
+  if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
+  if (mode == MODE_CHECK && st->pending == 0) return;
   const int c = threadIdx.x % KC;
   const bool act = mode == MODE_REPORT ? c < st->K
-                                       : (st->active[c] != 0 && (mode == MODE_INIT || st->check[c] != 0));
+                                       : (st->active[c] != 0 &&
+                                          (mode == MODE_INIT || st->check[c] == (mode == MODE_VERIFY ? 2 : 1)));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   const TileWalk tw(bf_cdiv(n, R));
   double v3[3] = {0.0, 0.0, 0.0};
@@ -332,7 +336,10 @@ __global__ __launch_bounds__(256) void k_bresid27(BState* __restrict__ st, int m
       }
       v3[0] += res * res;
       v3[2] += zv * zv;
-      if (mode != MODE_REPORT) {
+      if (mode == MODE_VERIFY) {
+        const V rv = (V)res;
+        v3[1] += (double)rv * (double)(rv * dinv[v]);
+      } else if (mode != MODE_REPORT) {
         const V rv = (V)res;
         const V zzv = rv * dinv[v];
         r[e] = rv;
@@ -351,12 +358,18 @@ __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mo
                                                  int nb) {
   __shared__ double lds[16];
   const int c = blockIdx.x;
-  if (mode == MODE_CHECK && !(st->active[c] && st->check[c])) return;
+  if (mode == MODE_CHECK && !(st->active[c] && st->check[c] == 1)) return;
+  if (mode == MODE_VERIFY && !(st->active[c] && st->check[c] == 2)) return;
   if (mode == MODE_REPORT && c >= st->K) return;
   if (mode == MODE_INIT && !st->active[c]) return;
   double tot[3];
   col_partials_sum<KC, 3>(part, nb, c, tot, lds);
-  if (threadIdx.x == 0) decide_R(st, c, mode, tot, nullptr);
+  if (threadIdx.x == 0) {
+    if (mode == MODE_VERIFY)
+      decide_V(st, c, tot, nullptr);
+    else
+      decide_R(st, c, mode, tot, nullptr);
+  }
 }
 
 // s_v = (1/K) sum_k z_k[v] u_k[v].  Lanes run along the columns of a row
@@ -470,13 +483,18 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
-      if (tri)
-        BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
-                  sys->nb26, sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
-      else
-        BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_CHECK,
-                  sys->band->nbr, sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
-      BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
+      // columns the recurrence calls converged: FP64 residual norms without
+      // stores; then the stored FP64 residual of the columns to go on from it
+      for (const int mode : {(int)MODE_VERIFY, (int)MODE_CHECK}) {
+        const char* kname = mode == MODE_VERIFY ? "block_verify" : "block_residual";
+        if (tri)
+          BF_LAUNCH(ctx, kname, (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->nb26, sys->off,
+                    sys->diag, o->seed, x64, dinvV, r, zz, N, part);
+        else
+          BF_LAUNCH(ctx, kname, (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->band->nbr,
+                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+        BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, mode, part, nb);
+      }
       std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "block pcg iteration"));

@@ -17,14 +17,18 @@ namespace bt {
 constexpr int kThreads = 256;
 constexpr int kMaxK = 64;
 
-enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
+// VERIFY: residual norms of the columns whose recurrence residual met the
+// tolerance (check == 2), with no stores; CHECK: the residual, stored, of the
+// columns to continue or restart from it (check == 1).
+enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2, MODE_VERIFY = 3 };
 
 struct BState {
   double rho[kMaxK], alpha[kMaxK], beta[kMaxK], tol2b[kMaxK], rr_true[kMaxK], bnorm2[kMaxK], rr_ref[kMaxK];
   double inner2;
   int32_t active[kMaxK], check[kMaxK], last[kMaxK], iters[kMaxK], status[kMaxK];
   int32_t nactive, any_check, max_iter, replace_every, K, refinements;
-  int32_t pad_[2];
+  int32_t pending;  // columns with check == 1 (a stored residual is due)
+  int32_t pad_;
 };
 
 // SplitMix64 output n (0-based) of the generator started at `start`.
@@ -56,6 +60,7 @@ __device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_
     st->replace_every = replace_every;
     st->K = K;
     st->refinements = 0;
+    st->pending = 0;
   }
 }
 
@@ -267,7 +272,10 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
       const int64_t v = v0 + j * RS, e = v * KC + c;
       v3[0] += res[j] * res[j];
       v3[2] += zv[j] * zv[j];
-      if (mode != MODE_REPORT) {
+      if (mode == MODE_VERIFY) {
+        const V rv = (V)res[j];
+        v3[1] += (double)rv * (double)(rv * dinv[v]);
+      } else if (mode != MODE_REPORT) {
         const V rv = (V)res[j];
         const V zzv = rv * dinv[v];
         r[e] = rv;
@@ -301,13 +309,31 @@ __device__ __forceinline__ void decide_B(BState* st, int c, double rz, double rr
   if (!isfinite(rz) || !isfinite(rr)) {
     deactivate(st, c, BF_ERR_BREAKDOWN, nactive_all);
   } else if (rr <= fmax(st->tol2b[c], st->inner2 * st->rr_ref[c]) || at_max || periodic) {
-    st->check[c] = 1;
+    // 2: the recurrence says converged, so a store-free FP64 residual decides
+    // first; 1: the column continues or restarts from a stored FP64 residual
+    st->check[c] = rr <= st->tol2b[c] ? 2 : 1;
+    if (st->check[c] == 1) atomicAdd(&st->pending, 1);
     st->last[c] = at_max ? 1 : 0;
     atomicOr(&st->any_check, 1);
     if (any_all) atomicOr(any_all, 1);
   } else {
     st->beta[c] = rz / st->rho[c];
     st->rho[c] = rz;
+  }
+}
+
+// After a VERIFY pass: a column whose FP64 residual meets the tolerance stops
+// (as it would after a CHECK); any other one is handed to the CHECK pass,
+// which recomputes the same residual and stores it.
+__device__ __forceinline__ void decide_V(BState* st, int c, const double (&tot)[3], int* nactive_all) {
+  st->rr_true[c] = tot[0];
+  if (isfinite(tot[0]) && isfinite(tot[1]) && tot[0] <= st->tol2b[c]) {
+    atomicAdd(&st->refinements, 1);
+    deactivate(st, c, 0, nactive_all);
+    st->check[c] = 0;
+  } else {
+    st->check[c] = 1;
+    atomicAdd(&st->pending, 1);
   }
 }
 
@@ -343,6 +369,7 @@ __device__ __forceinline__ void decide_R(BState* st, int c, int mode, const doub
       st->rho[c] = tot[1];
       st->rr_ref[c] = tot[0];
     }
+    if (st->check[c] == 1) atomicSub(&st->pending, 1);
     st->check[c] = 0;
   }
 }
