@@ -147,7 +147,7 @@ def run_gpu(args):
         s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
-                   tsdf_voxel_views=band.arrays()["tsdf_voxel_views"],
+                   tsdf_voxel_views=band.info()["tsdf_voxel_views"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
         sys_.free()

@@ -124,6 +124,12 @@ class Band:
     handle: C.c_void_p
     n: int
 
+    def info(self) -> dict:
+        """The band's scalar fields only (no tensor views)."""
+        a = L.bf_band_arrays()
+        self.ctx._check(self.ctx.lib.bf_band_view(self.handle, C.byref(a)))
+        return {"n": int(a.n), "dense_side": int(a.dense_side), "tsdf_voxel_views": int(a.tsdf_voxel_views)}
+
     def arrays(self) -> dict:
         a = L.bf_band_arrays()
         self.ctx._check(self.ctx.lib.bf_band_view(self.handle, C.byref(a)))

@@ -456,6 +456,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const char* skb = getenv("BF_STENCIL_LDS_KB");
   const int stencil_kb = skb ? atoi(skb) : 32;
   int it = 0, next = 3;
+  size_t fin_rec = 0;  // timing record of the last queued estimate pass (FP64)
+  const unsigned hutch_grid = (unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 8 * (int64_t)ctx->cu_count);
   V* pa = p0;
   V* pb = p1;
   std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
@@ -498,22 +500,32 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "block pcg iteration"));
+    // FP64: the estimate is formed behind every batch, so the poll that finds
+    // every column done has it already; it reads the solutions only, and a
+    // later batch's pass overwrites it.
+    if (!mixed) {
+      fin_rec = ctx->recs.size();
+      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, x64, o->seed, o->K,
+                N, s_out);
+      BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    }
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (hs->nactive == 0 || it >= o->max_iter) break;
     next = it + std::max(it, 4);
   }
-  const size_t loop_rec_end = ctx->recs.size();
-  if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
-  BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>,
-            dim3((unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 8 * (int64_t)ctx->cu_count)),
-            dim3(kThreads), 0, x64, o->seed, o->K, N, s_out);
-  BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+  const size_t loop_rec_end = mixed ? ctx->recs.size() : fin_rec;
   // The report's residual of each column is the FP64 one of its last check:
   // a column stops only after such a check (or at INIT, or on a breakdown),
   // and its solution does not change afterwards, so no further pass is needed.
-  BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
-  BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  if (mixed) {
+    BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
+    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, x64, o->seed, o->K, N,
+              s_out);
+    BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
+    BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);

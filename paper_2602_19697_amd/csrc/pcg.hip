@@ -413,6 +413,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   V* pb = p1;
   const V lamV = (V)sys->lambda;
   std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
+  size_t fin_rec = 0;  // timing record of the last queued report pass (FP64)
   for (;;) {
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
@@ -434,18 +435,30 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
       std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "pcg iteration"));
+    // FP64: the report's residual is queued behind every batch, so the poll
+    // that finds the solve done has it already.  It reads x and sets only the
+    // reported residual, which every later check overwrites, so a batch that
+    // is not the last one loses nothing but the pass.
+    if (!mixed) {
+      fin_rec = ctx->recs.size();
+      residual((int)MODE_REPORT, (const double*)x);
+      BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
+      BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    }
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (hs->done || it >= o->max_iter) break;
     next = o->check_every > 0 ? it + o->check_every : it + std::max(it, 4);
   }
-  const size_t loop_rec_end = ctx->recs.size();
-  if (mixed) BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
-  residual((int)MODE_REPORT, (const double*)x);
-  BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
-  BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
-  BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
-  BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  const size_t loop_rec_end = mixed ? ctx->recs.size() : fin_rec;
+  if (mixed) {
+    BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
+    residual((int)MODE_REPORT, (const double*)x);
+    BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
+    BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
+    BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
