@@ -270,31 +270,47 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
 }
 
 // Exclusive scan of the per-block counts in one block of 1024 threads; writes
-// offsets[nb] and the total to *n_total.
+// offsets[nb] and the total to *n_total.  Each thread sums a contiguous chunk
+// (loads unrolled so several are in flight), the 1024 chunk sums are scanned
+// with wave shuffles and one pass over the 16 wave totals, and each thread
+// then writes its chunk's offsets.  Integer sums: any order is exact.
 __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ counts, int64_t nb,
                                                       uint64_t* __restrict__ offsets,
                                                       uint64_t* __restrict__ n_total) {
-  __shared__ uint64_t part[1024];
+  __shared__ uint64_t wsum[16];
   const int64_t chunk = bf_cdiv(nb, 1024);
   const int64_t lo = threadIdx.x * chunk;
   const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
   uint64_t s = 0;
+#pragma unroll 8
   for (int64_t b = lo; b < hi; ++b) s += counts[b];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 chunk sums
-  for (int off = 1; off < 1024; off <<= 1) {
-    uint64_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
+  // inclusive scan of the chunk sums: within each wave, then across waves
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint64_t inc = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t v = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += v;
   }
-  uint64_t run = threadIdx.x > 0 ? part[threadIdx.x - 1] : 0;
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    uint64_t w = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      const uint64_t v = __shfl_up(w, off, 64);
+      if (lane >= off) w += v;
+    }
+    if (lane < 16) wsum[lane] = w;  // inclusive totals through wave `lane`
+  }
+  __syncthreads();
+  uint64_t run = (wid > 0 ? wsum[wid - 1] : 0) + inc - s;  // exclusive offset of this chunk
+#pragma unroll 8
   for (int64_t b = lo; b < hi; ++b) {
     offsets[b] = run;
     run += counts[b];
   }
-  if (threadIdx.x == 1023) *n_total = part[1023];
+  if (threadIdx.x == 1023) *n_total = wsum[15];
 }
 
 // Scatter of the band voxels of one block tile in Morton order.
@@ -383,15 +399,38 @@ __global__ __launch_bounds__(256) void k_brick_bits(const uint64_t* __restrict__
 // Cell records (the key -> band index map of the neighbour table and the ray
 // walker): occupancy mask and first band index of every 4^3 cell, addressed
 // directly by the cell's coordinates, so a lookup never collides or probes.
+// A cell is a range of 64 Morton codes and the band is sorted, so a cell's
+// voxels are consecutive: each wave ORs its runs of one cell with a segmented
+// shuffle scan, and the run's last lane writes the mask (an atomic OR where
+// the run may continue in the neighbouring wave, a plain store otherwise).
 __global__ __launch_bounds__(256) void k_cell_tables(const uint64_t* __restrict__ keys, int64_t n, int ncell,
                                                      bf_cell* __restrict__ cells) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const uint64_t key = keys[v];
-  const uint32_t ci = bf_compact3(key) >> 2, cj = bf_compact3(key >> 1) >> 2, ck = bf_compact3(key >> 2) >> 2;
-  const int64_t c = ((int64_t)ck * ncell + cj) * ncell + ci;
-  atomicOr(&cells[c].mask, 1ull << (key & 63));
-  if (v == 0 || (keys[v - 1] >> 6) != (key >> 6)) cells[c].start = (int32_t)v;
+  const int lane = threadIdx.x & 63;
+  const bool valid = v < n;
+  const uint64_t key = valid ? keys[v] : ~0ull;
+  const uint64_t ck = key >> 6;  // cell of the key (lanes past n share an impossible one)
+  uint64_t m = valid ? 1ull << (key & 63) : 0ull;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t om = __shfl_up(m, off, 64);
+    const uint64_t oc = __shfl_up(ck, off, 64);
+    if (lane >= off && oc == ck) m |= om;  // sorted keys: lanes in between are in the same cell
+  }
+  const uint64_t next_ck = __shfl_down(ck, 1, 64);
+  const uint64_t first_ck = __shfl(ck, 0, 64);
+  const bool last = lane == 63 || next_ck != ck;
+  if (!valid) return;
+  const uint32_t ci = bf_compact3(key) >> 2, cj = bf_compact3(key >> 1) >> 2, ck3 = bf_compact3(key >> 2) >> 2;
+  const int64_t c = ((int64_t)ck3 * ncell + cj) * ncell + ci;
+  if (last) {
+    const bool edge = lane == 63 || first_ck == ck;  // the run may go on in the next or previous wave
+    if (edge)
+      atomicOr(&cells[c].mask, m);
+    else
+      cells[c].mask = m;
+  }
+  if (v == 0 || (keys[v - 1] >> 6) != ck) cells[c].start = (int32_t)v;
 }
 
 // Forward-octant Chebyshev distances over the brick grid (empty-space skipping
