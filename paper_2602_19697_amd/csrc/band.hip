@@ -38,7 +38,9 @@ __global__ __launch_bounds__(256) void k_validate_depth(const float* __restrict_
 
 // Min/max pyramid of the valid depths of every view: level l holds, per
 // 2^l x 2^l pixel block, the smallest and largest depth D > 0 (+inf / -1 when
-// the block has none).  Levels are packed per view at offsets off[l].
+// the block has none).  Levels are packed per view at offsets off[l].  Level
+// 0 is the depth map itself under that rule, so it is read from there and its
+// slots stay unwritten.
 constexpr int kMaxLevels = 16;
 struct Pyr {
   int nl;
@@ -52,26 +54,30 @@ struct Pyr {
 // image, so the tile-local reduction equals the level-by-level one.
 constexpr int kPyrTile = 32;
 constexpr int kTileLevels = 5;  // 32 >> 5 = 1
+// The kernel reads every pixel once, so it also flags invalid depth (NaN,
+// inf or negative) as k_validate_depth does.
 __global__ __launch_bounds__(256) void k_pyr_tiles(const float* __restrict__ depth, int32_t W, int32_t H, Pyr P,
-                                                   float* __restrict__ dmin, float* __restrict__ dmax) {
+                                                   float* __restrict__ dmin, float* __restrict__ dmax,
+                                                   int* __restrict__ flag) {
   __shared__ float lo[2][kPyrTile * kPyrTile], hi[2][kPyrTile * kPyrTile];
   const int t = blockIdx.z;
   const int32_t x0 = blockIdx.x * kPyrTile, y0 = blockIdx.y * kPyrTile;
   const float* D = depth + (int64_t)t * W * H;
   float* mn = dmin + (int64_t)t * P.per_view;
   float* mx = dmax + (int64_t)t * P.per_view;
+  int bad = 0;
   for (int e = threadIdx.x; e < kPyrTile * kPyrTile; e += blockDim.x) {
     const int32_t x = x0 + (e % kPyrTile), y = y0 + (e / kPyrTile);
     float a = INFINITY, b = -1.0f;
     if (x < W && y < H) {
       const float d = D[(int64_t)y * W + x];
+      if (!(d >= 0.0f) || d == INFINITY) bad = 1;
       if (d > 0.0f) a = b = d;
-      mn[(int64_t)y * W + x] = a;
-      mx[(int64_t)y * W + x] = b;
     }
     lo[0][e] = a;
     hi[0][e] = b;
   }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
   int cur = 0;
   for (int l = 1; l <= kTileLevels && l < P.nl; ++l) {
     __syncthreads();
@@ -136,6 +142,7 @@ __global__ __launch_bounds__(1024) void k_pyr_top(Pyr P, float* __restrict__ dmi
 // 1e-7 of |u| (the coordinates stay FP64), which the twentieth-of-a-pixel
 // widening covers wherever an endpoint can fall near the image.
 __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
+                                     const float* __restrict__ depth_t,
                                      const float* __restrict__ dmin, const float* __restrict__ dmax,
                                      const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0) {
   const double x = g.ox + ((double)i0 + 0.5) * g.h;
@@ -177,16 +184,23 @@ __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, cons
   const int32_t r0 = (int32_t)fmaxf(r0f, 0.0f), r1 = (int32_t)fminf(r1f, (float)(c.H - 1));
   int l = 0;
   while (l < P.nl - 1 && (((c1 >> l) - (c0 >> l)) > 1 || ((r1 >> l) - (r0 >> l)) > 1)) ++l;
+  // level 0 is the depth map (invalid: +inf / -1); the sources are chosen per
+  // lane so that every lane runs the same loads
+  const bool l0 = l == 0;
   const int64_t base = (int64_t)t * P.per_view + P.off[l];
+  const float* smin = l0 ? depth_t : dmin + base;
+  const float* smax = l0 ? depth_t : dmax + base;
+  const int64_t pitch = l0 ? c.W : P.w[l];
   float lo = INFINITY, hi = -1.0f;
   const int32_t xs[2] = {c0 >> l, c1 >> l}, ys[2] = {r0 >> l, r1 >> l};
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      const int64_t q = base + (int64_t)ys[a] * P.w[l] + xs[b];
-      lo = fminf(lo, dmin[q]);
-      hi = fmaxf(hi, dmax[q]);
+      const int64_t q = (int64_t)ys[a] * pitch + xs[b];
+      const float vmin = smin[q], vmax = smax[q];
+      lo = fminf(lo, (l0 && !(vmin > 0.0f)) ? INFINITY : vmin);
+      hi = fmaxf(hi, (l0 && !(vmax > 0.0f)) ? -1.0f : vmax);
     }
   if (hi < 0.0f) return false;                                   // no valid depth under the cell
   if ((double)lo - zhi > g.band + zmargin) return false;         // free space beyond the band
@@ -223,7 +237,8 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
       const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
                     k0 = (int32_t)bf_compact3(m0 >> 2);
       if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
-      if (cell_view_may_matter(g, c, P, dmin, dmax, poses + 12 * t, t, i0, j0, k0)) atomicOr(&live[cell], 1);
+      if (cell_view_may_matter(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0))
+        atomicOr(&live[cell], 1);
     }
     __syncthreads();
   }
@@ -541,15 +556,15 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   }
 
   const int64_t npix = (int64_t)T * cam->width * cam->height;
-  if (npix > 0) {
-    const int vb = (int)std::min<int64_t>(bf_cdiv(npix, 256), 8192);
-    BF_LAUNCH(ctx, "validate_depth", k_validate_depth, dim3(vb), dim3(256), 0, depth_dev, npix, dflags);
-    if (bf_status s = bf_launch_check(ctx, "k_validate_depth")) return fail(s);
-  }
   bf_grid_k gk{grid->G, grid->h, grid->origin[0], grid->origin[1], grid->origin[2], grid->tau, grid->band};
   bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
   // screening pyramid (off when the dense grid is kept, or when truncation does not exceed the band)
   const int screen = (!(flags & BF_BAND_KEEP_DENSE) && grid->tau > grid->band && npix > 0) ? 1 : 0;
+  if (npix > 0 && !screen) {  // with screening the pyramid kernel validates the depth
+    const int vb = (int)std::min<int64_t>(bf_cdiv(npix, 256), 8192);
+    BF_LAUNCH(ctx, "validate_depth", k_validate_depth, dim3(vb), dim3(256), 0, depth_dev, npix, dflags);
+    if (bf_status s = bf_launch_check(ctx, "k_validate_depth")) return fail(s);
+  }
   Pyr pyr{};
   float* dmin = nullptr;
   float* dmax = nullptr;
@@ -575,7 +590,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     dmax = (float*)((char*)pw + half);
     BF_LAUNCH(ctx, "depth_pyramid", k_pyr_tiles,
               dim3((unsigned)bf_cdiv(cam->width, kPyrTile), (unsigned)bf_cdiv(cam->height, kPyrTile), (unsigned)T),
-              dim3(256), 0, depth_dev, cam->width, cam->height, pyr, dmin, dmax);
+              dim3(256), 0, depth_dev, cam->width, cam->height, pyr, dmin, dmax, dflags);
     if (pyr.nl > kTileLevels + 1)
       BF_LAUNCH(ctx, "depth_pyramid", k_pyr_top, dim3((unsigned)T), dim3(1024), 0, pyr, dmin, dmax);
   }
