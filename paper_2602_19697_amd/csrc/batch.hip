@@ -179,7 +179,7 @@ __device__ void item_A(const Batch& B, int64_t w, int it, double* lds) {
   V* pb = (V*)((it & 1) ? d.p0 : d.p1);
   double v1[1] = {0.0};
   if (st->active[c])
-    tile_A<V, KC>(c, (V)st->beta[c], d.nbr, (const V*)d.diagV, (V)d.lam, (const V*)d.zz, pa, pb, (V*)d.q, r0, r1,
+    tile_A<V, KC>(c, (V)st->beta[c], false, d.nbr, (const V*)d.diagV, (V)d.lam, (const V*)d.zz, pa, pb, (V*)d.q, r0, r1,
                   v1[0]);
   col_block_sum<KC, 1>(v1, lds);
   store_partials<KC, 1>(d.part, slot, v1);

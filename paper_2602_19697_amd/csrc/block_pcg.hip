@@ -52,10 +52,13 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   double v1[1] = {0.0};
   const bool act = st->active[c] != 0;
   const V beta = (V)st->beta[c];
+  // a column's first direction is z (beta = 0): p_old is not read, as if it
+  // held zeros (z + 0 * 0, the same value), so it needs no clearing
+  const bool first = st->iters[c] == 0;
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
     if constexpr (KC == 1) {
-      if (act) tile_A<V, KC>(c, beta, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0]);
+      if (act) tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0]);
     } else {
       __syncthreads();  // the previous tile's readers are done
       if (act) {
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
             const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
             if (v < r1) {
               za[j] = zz[v * KC + c];
-              pa[j] = p_old[v * KC + c];
+              pa[j] = first ? (V)0 : p_old[v * KC + c];
             }
           }
 #pragma unroll
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
               gp[j][t] = 0;
               if (u >= 0 && !(u >= r0 && u < r1)) {
                 gz[j][t] = zz[(int64_t)u * KC + c];
-                gp[j][t] = p_old[(int64_t)u * KC + c];
+                gp[j][t] = first ? (V)0 : p_old[(int64_t)u * KC + c];
               }
             }
           V sacc[U];
@@ -437,9 +440,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
                      mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
-  hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
-  if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
+  // the 27-point A reads the first p_old (all zeros); the 7-point one does not
+  if (tri) hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
+  if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   const V* offV = mixed ? (const V*)sys->off32 : (const V*)sys->off;
   if (tri)
     BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->nb26,

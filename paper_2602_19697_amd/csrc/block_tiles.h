@@ -136,9 +136,10 @@ struct TileWalk {
 constexpr int kRowsInFlight = 4;
 
 template <typename V, int KC>
-__device__ __forceinline__ void tile_A(int c, V beta, const int32_t* __restrict__ nbr, const V* __restrict__ diag, V lam,
-                                       const V* __restrict__ zz, const V* __restrict__ p_old, V* __restrict__ p_new,
-                                       V* __restrict__ q, int64_t r0, int64_t r1, double& acc1) {
+__device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t* __restrict__ nbr,
+                                       const V* __restrict__ diag, V lam, const V* __restrict__ zz,
+                                       const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
+                                       int64_t r0, int64_t r1, double& acc1) {
   constexpr int RS = kThreads / KC;
   constexpr int U = kRowsInFlight;
   for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
@@ -158,11 +159,11 @@ __device__ __forceinline__ void tile_A(int c, V beta, const int32_t* __restrict_
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int64_t u = nb[j][t] >= 0 ? (int64_t)nb[j][t] : vr[j];
-        const V a = zz[u * KC + c] + beta * p_old[u * KC + c];
+        const V a = zz[u * KC + c] + beta * (first ? (V)0 : p_old[u * KC + c]);
         if (nb[j][t] >= 0) s[j] += a;
       }
       const int64_t e = vr[j] * KC + c;
-      pv[j] = zz[e] + beta * p_old[e];
+      pv[j] = zz[e] + beta * (first ? (V)0 : p_old[e]);
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
