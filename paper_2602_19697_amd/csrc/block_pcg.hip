@@ -158,15 +158,16 @@ template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __restrict__ dinv,
                                             const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
                                             V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                            double* __restrict__ part) {
+                                            double* __restrict__ part, int zero_start) {
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v2[2] = {0.0, 0.0};
+  const bool first = zero_start && st->iters[c] == 0;  // x is still its (unwritten) zero start
   if (st->active[c])
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-      tile_B<V, KC>(c, (V)st->alpha[c], dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
+      tile_B<V, KC>(c, (V)st->alpha[c], first, dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
                     std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v2[0], v2[1]);
   col_block_sum<KC, 2>(v2, lds);
   store_partials<KC, 2>(part, blockIdx.x, v2);
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
                                                 const float* __restrict__ logvar, uint64_t seed,
                                                 double* __restrict__ x64, const V* __restrict__ dinv,
                                                 V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                                double* __restrict__ part) {
+                                                double* __restrict__ part, int write_x0) {
   __shared__ double lds[4 * 3 * 64];
   if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
   if (mode == MODE_CHECK && st->pending == 0) return;
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   if (act)
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
-                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3);
+                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, write_x0 != 0);
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
@@ -379,15 +380,19 @@ __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mo
 // (coalesced reads of the [N][KC] block), the products go through LDS, and
 // one thread per row sums them in ascending k, the order of hutch_row.
 template <int KC>
-__global__ __launch_bounds__(256) void k_hutch_final(const double* __restrict__ x64, uint64_t seed, int K,
+// zero_start: a column that never iterated still has its zero start, which
+// was not written.
+__global__ __launch_bounds__(256) void k_hutch_final(const BState* __restrict__ st, int zero_start,
+                                                     const double* __restrict__ x64, uint64_t seed, int K,
                                                      int64_t n, double* __restrict__ s_out) {
   constexpr int RS = kThreads / KC;
   __shared__ double prod[kThreads];
   const int c = threadIdx.x % KC;
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
+  const bool zero = c < K && zero_start && st->iters[c] == 0;
   for (int64_t r0 = blockIdx.x * (int64_t)RS; r0 < n; r0 += (int64_t)gridDim.x * RS) {
     const int64_t v = r0 + threadIdx.x / KC;
-    prod[threadIdx.x] = (v < n && c < K) ? probe(cs, v) * x64[v * KC + c] : 0.0;
+    prod[threadIdx.x] = (v < n && c < K) ? probe(cs, v) * (zero ? 0.0 : x64[v * KC + c]) : 0.0;
     __syncthreads();
     if (threadIdx.x < RS && r0 + threadIdx.x < n) {
       double acc = 0.0;
@@ -441,6 +446,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
                      mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
   const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
+  // FP64 from x = 0: the zero start is not written; the first B pass takes x
+  // as 0 and the estimate takes a column that never iterated as 0.  (Mixed
+  // precision folds its float corrections into x64, which must hold zeros.)
+  const int zero_start = (!mixed && !logvar) ? 1 : 0;
   // the 27-point A reads the first p_old (all zeros); the 7-point one does not
   if (tri) hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
@@ -450,7 +459,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
               sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
   else
     BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
-              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part);
+              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part, zero_start ? 0 : 1);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
@@ -486,7 +495,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                     zz, pa, pb, q, N, part);
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
-      BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part);
+      BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part,
+                zero_start);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
       // columns the recurrence calls converged: FP64 residual norms without
@@ -498,7 +508,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                     sys->diag, o->seed, x64, dinvV, r, zz, N, part);
         else
           BF_LAUNCH(ctx, kname, (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->band->nbr,
-                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part);
+                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part, 1);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, mode, part, nb);
       }
       std::swap(pa, pb);
@@ -509,7 +519,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     // later batch's pass overwrites it.
     if (!mixed) {
       fin_rec = ctx->recs.size();
-      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, x64, o->seed, o->K,
+      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64, o->seed, o->K,
                 N, s_out);
       BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
@@ -524,7 +534,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // and its solution does not change afterwards, so no further pass is needed.
   if (mixed) {
     BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
-    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, x64, o->seed, o->K, N,
+    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64, o->seed, o->K, N,
               s_out);
     BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
