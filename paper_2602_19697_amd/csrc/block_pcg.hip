@@ -158,16 +158,19 @@ template <typename V, int KC>
 __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __restrict__ dinv,
                                             const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
                                             V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                            double* __restrict__ part, int zero_start) {
+                                            double* __restrict__ part, int zero_start, uint64_t seed,
+                                            int gen_start) {
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v2[2] = {0.0, 0.0};
   const bool first = zero_start && st->iters[c] == 0;  // x is still its (unwritten) zero start
+  const bool gen = gen_start && st->iters[c] == 0;     // r is still the (unstored) probe z
+  const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   if (st->active[c])
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-      tile_B<V, KC>(c, (V)st->alpha[c], first, dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
+      tile_B<V, KC>(c, (V)st->alpha[c], first, gen, cs, dinv, p, q, x, r, zz, tile * kRowsPerTile<KC>,
                     std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v2[0], v2[1]);
   col_block_sum<KC, 2>(v2, lds);
   store_partials<KC, 2>(part, blockIdx.x, v2);
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
                                                 const float* __restrict__ logvar, uint64_t seed,
                                                 double* __restrict__ x64, const V* __restrict__ dinv,
                                                 V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                                double* __restrict__ part, int write_x0) {
+                                                double* __restrict__ part, int write_x0, int store_r) {
   __shared__ double lds[4 * 3 * 64];
   if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
   if (mode == MODE_CHECK && st->pending == 0) return;
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   if (act)
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
-                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, write_x0 != 0);
+                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, write_x0 != 0, store_r != 0);
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
@@ -450,6 +453,9 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // as 0 and the estimate takes a column that never iterated as 0.  (Mixed
   // precision folds its float corrections into x64, which must hold zeros.)
   const int zero_start = (!mixed && !logvar) ? 1 : 0;
+  // ... and the initial residual r = z is not stored either: the first B pass
+  // regenerates it from the probe (the 7-point system's initial pass)
+  const int gen_start = (zero_start && sys->kind != BF_SYSTEM_TRILINEAR) ? 1 : 0;
   // the 27-point A reads the first p_old (all zeros); the 7-point one does not
   if (tri) hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
@@ -459,7 +465,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
               sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
   else
     BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
-              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part, zero_start ? 0 : 1);
+              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part,
+              zero_start ? 0 : 1, gen_start ? 0 : 1);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
@@ -496,7 +503,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part,
-                zero_start);
+                zero_start, o->seed, gen_start);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
       // columns the recurrence calls converged: FP64 residual norms without
@@ -508,7 +515,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                     sys->diag, o->seed, x64, dinvV, r, zz, N, part);
         else
           BF_LAUNCH(ctx, kname, (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->band->nbr,
-                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part, 1);
+                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part, 1, 1);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, mode, part, nb);
       }
       std::swap(pa, pb);

@@ -180,15 +180,17 @@ __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t*
 // B: x += alpha p, r -= alpha q, zz = r / diag; acc += r.zz, r.r.
 template <typename V, int KC>
 // first: x still holds its zero start, taken as the literal 0 (not read).
-__device__ __forceinline__ void tile_B(int c, V alpha, bool first, const V* __restrict__ dinv,
-                                       const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
-                                       V* __restrict__ r, V* __restrict__ zz, int64_t r0, int64_t r1, double& rz,
-                                       double& rr) {
+// gen: r still holds the probe z (not stored), regenerated from the column's
+// generator cs.
+__device__ __forceinline__ void tile_B(int c, V alpha, bool first, bool gen, uint64_t cs,
+                                       const V* __restrict__ dinv, const V* __restrict__ p, const V* __restrict__ q,
+                                       V* __restrict__ x, V* __restrict__ r, V* __restrict__ zz, int64_t r0,
+                                       int64_t r1, double& rz, double& rr) {
   constexpr int RS = kThreads / KC;
   for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
     const int64_t e = v * KC + c;
     x[e] = (first ? (V)0 : x[e]) + alpha * p[e];
-    const V rv = r[e] - alpha * q[e];
+    const V rv = (gen ? (V)probe(cs, v) : r[e]) - alpha * q[e];
     const V zv = rv * dinv[v];
     r[e] = rv;
     zz[e] = zv;
@@ -217,7 +219,7 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
                                            const double* __restrict__ diag, double lam,
                                            const float* __restrict__ logvar, double* __restrict__ x64,
                                            const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                           int64_t r0, int64_t r1, double (&v3)[3], bool write_x0 = true) {
+                                           int64_t r0, int64_t r1, double (&v3)[3], bool write_x0 = true, bool store_r = true) {
   constexpr int RS = kThreads / KC;
   constexpr int U = kRowsInFlight;
   for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
@@ -281,7 +283,7 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
       } else if (mode != MODE_REPORT) {
         const V rv = (V)res[j];
         const V zzv = rv * dinv[v];
-        r[e] = rv;
+        if (store_r || mode != MODE_INIT) r[e] = rv;
         zz[e] = zzv;
         v3[1] += (double)rv * (double)zzv;
       }
