@@ -174,7 +174,9 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
                                 ((uint32_t)r.idx[0] >> bs));
   if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
     // occupied brick: is this voxel in the band?  (4^3 cell mask, rank by popcount)
-    const int64_t c = ((int64_t)(r.idx[2] >> 2) * NC + (r.idx[1] >> 2)) * NC + (r.idx[0] >> 2);
+    // at most 512^3 cells (G <= 2048): the index fits 32 bits
+    const uint32_t c = (((uint32_t)r.idx[2] >> 2) * (uint32_t)NC + ((uint32_t)r.idx[1] >> 2)) * (uint32_t)NC +
+                       ((uint32_t)r.idx[0] >> 2);
     const uint32_t m = (r.idx[0] & 1) | ((r.idx[1] & 1) << 1) | ((r.idx[2] & 1) << 2) | ((r.idx[0] & 2) << 2) |
                        ((r.idx[1] & 2) << 3) | ((r.idx[2] & 2) << 4);
     const bf_cell cl = cells[c];
