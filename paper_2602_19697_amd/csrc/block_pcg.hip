@@ -37,7 +37,7 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, d
 template <typename V, int KC, int LDSKB>
 constexpr int kStencilRows = KC == 1 ? 1024 : LDSKB * 1024 / (KC * (int)sizeof(V));
 
-template <typename V, int KC, int LDSKB>
+template <typename V, int KC, int LDSKB, bool FIRST>
 __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                             const V* __restrict__ diag, V lam, const V* __restrict__ zz,
                                             const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
@@ -52,9 +52,11 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   double v1[1] = {0.0};
   const bool act = st->active[c] != 0;
   const V beta = (V)st->beta[c];
-  // a column's first direction is z (beta = 0): p_old is not read, as if it
-  // held zeros (z + 0 * 0, the same value), so it needs no clearing
-  const bool first = st->iters[c] == 0;
+  // FIRST (the first iteration's launch; every active column starts there):
+  // the direction is z (beta = 0) and p_old is not read, as if it held zeros
+  // (z + 0 * 0, the same value), so it needs no clearing.  A separate
+  // instantiation, so the later launches carry no switch around their loads.
+  constexpr bool first = FIRST;
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
     if constexpr (KC == 1) {
@@ -154,19 +156,20 @@ __global__ __launch_bounds__(256) void k_bscal_A(BState* __restrict__ st, const 
 }
 
 // B: x += alpha p, r -= alpha q, zz = r / diag, per-column partials r.zz, r.r.
-template <typename V, int KC>
+template <typename V, int KC, bool ZX, bool GR>
 __global__ __launch_bounds__(256) void k_bB(BState* __restrict__ st, const V* __restrict__ dinv,
                                             const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
                                             V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                            double* __restrict__ part, int zero_start, uint64_t seed,
-                                            int gen_start) {
+                                            double* __restrict__ part, uint64_t seed) {
   __shared__ double lds[4 * 3 * 64];
   if (st->nactive == 0) return;
   const int c = threadIdx.x % KC;
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v2[2] = {0.0, 0.0};
-  const bool first = zero_start && st->iters[c] == 0;  // x is still its (unwritten) zero start
-  const bool gen = gen_start && st->iters[c] == 0;     // r is still the (unstored) probe z
+  // first launch only (every active column starts there), as instantiations of
+  // their own: ZX, x is still its (unwritten) zero start; GR, r is still the
+  // (unstored) probe z
+  constexpr bool first = ZX, gen = GR;
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   if (st->active[c])
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
@@ -490,20 +493,39 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                   pb, q, N, part);
       } else switch (stencil_kb) {
         case 16:
-          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
-                    zz, pa, pb, q, N, part);
+          if (it == 0)
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
+          else
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
           break;
         case 64:
-          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 64>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
-                    zz, pa, pb, q, N, part);
+          if (it == 0)
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 64, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
+          else
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 64, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
           break;
         default:
-          BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, diagV, lamV,
-                    zz, pa, pb, q, N, part);
+          if (it == 0)
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
+          else
+            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                      diagV, lamV, zz, pa, pb, q, N, part);
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
-      BF_LAUNCH(ctx, "block_B", (k_bB<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz, N, part,
-                zero_start, o->seed, gen_start);
+      if (it == 0 && gen_start)
+        BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, true, true>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r,
+                  zz, N, part, o->seed);
+      else if (it == 0 && zero_start)
+        BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r,
+                  zz, N, part, o->seed);
+      else
+        BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, false, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin,
+                  r, zz, N, part, o->seed);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
       // columns the recurrence calls converged: FP64 residual norms without
