@@ -610,7 +610,9 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth holds NaN, inf or negative values"));
   const uint64_t N = *(uint64_t*)((char*)pin + 16);
   band->tsdf_voxel_views = *(const int64_t*)((char*)pin + 24);
-  if (N >= (1ull << 31) - 1) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing", (unsigned long long)N));
+  if (N >= (1ull << 31) - 1)
+    return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing",
+                        (unsigned long long)N));
   band->n = (int64_t)N;
 
   if (N > 0) {

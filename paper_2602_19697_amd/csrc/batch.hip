@@ -196,7 +196,8 @@ __device__ void item_B(const Batch& B, int64_t w, int it, double* lds) {
   V* xin = sizeof(V) == 4 ? (V*)d.cf : (V*)d.x64;
   double v2[2] = {0.0, 0.0};
   if (st->active[c])
-    tile_B<V, KC>(c, (V)st->alpha[c], false, false, 0ull, (const V*)d.dinvV, pb, (const V*)d.q, xin, (V*)d.r, (V*)d.zz, r0, r1, v2[0],
+    tile_B<V, KC>(c, (V)st->alpha[c], false, false, 0ull, (const V*)d.dinvV, pb, (const V*)d.q, xin, (V*)d.r,
+                  (V*)d.zz, r0, r1, v2[0],
                   v2[1]);
   col_block_sum<KC, 2>(v2, lds);
   store_partials<KC, 2>(d.part, slot, v2);

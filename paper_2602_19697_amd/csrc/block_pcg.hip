@@ -520,11 +520,11 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (it == 0 && gen_start)
-        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, true>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r,
-                  zz, N, part, o->seed);
+        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, true>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
+                  xin, r, zz, N, part, o->seed);
       else if (it == 0 && zero_start)
-        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r,
-                  zz, N, part, o->seed);
+        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
+                  xin, r, zz, N, part, o->seed);
       else
         BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, false, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin,
                   r, zz, N, part, o->seed);
@@ -550,8 +550,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     // later batch's pass overwrites it.
     if (!mixed) {
       fin_rec = ctx->recs.size();
-      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64, o->seed, o->K,
-                N, s_out);
+      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64,
+                o->seed, o->K, N, s_out);
       BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
@@ -565,7 +565,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // and its solution does not change afterwards, so no further pass is needed.
   if (mixed) {
     BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
-    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64, o->seed, o->K, N,
+    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64,
+              o->seed, o->K, N,
               s_out);
     BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));

@@ -219,7 +219,8 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
                                            const double* __restrict__ diag, double lam,
                                            const float* __restrict__ logvar, double* __restrict__ x64,
                                            const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                           int64_t r0, int64_t r1, double (&v3)[3], bool write_x0 = true, bool store_r = true) {
+                                           int64_t r0, int64_t r1, double (&v3)[3], bool write_x0 = true,
+                                           bool store_r = true) {
   constexpr int RS = kThreads / KC;
   constexpr int U = kRowsInFlight;
   for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
