@@ -640,8 +640,10 @@ def _scene_words(wl):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    # 20 timed steps (under 0.1 s): the 2 with per-kernel event timing, which
+    # costs host time at every launch, then weigh 10% of the average
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--timing-steps", type=int, default=2,
                     help="per-kernel HIP event timing on the last this many timed steps")
     ap.add_argument("--workload", default="union256")
