@@ -573,16 +573,16 @@ bf_status run_batch(bf_ctx* ctx, const bf_system* const* systems, int S, int K, 
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   Batch B{dsc, S, dorder, dtstart, Sched{rows, sched->xcd_aware ? 1 : 0, T}, ctrl};
 
-  hipEvent_t e0, e1;
-  BF_HIP(ctx, hipEventCreate(&e0));
-  BF_HIP(ctx, hipEventCreate(&e1));
+  // solve-time events from the context's pool (no create / destroy per call)
+  hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
+  if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   bf_status ls = sched->persistent ? launch_persistent<V, KC>(ctx, B, max_iter, sched, hc)
                                    : launch_phased<V, KC>(ctx, B, S, T, max_iter, sched, hc);
   if (ls != BF_OK) {
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    ctx->pool.push_back(e0);
+    ctx->pool.push_back(e1);
     return ls;
   }
   BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
@@ -591,8 +591,8 @@ bf_status run_batch(bf_ctx* ctx, const bf_system* const* systems, int S, int K, 
   BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  ctx->pool.push_back(e0);
+  ctx->pool.push_back(e1);
   if (seconds) *seconds = ms * 1e-3;
   if (sched->persistent && hc[C_ABORT])
     return bf_fail(ctx, BF_ERR_HIP, "persistent batch: a grid barrier timed out (workgroups not co-resident)");

@@ -445,9 +445,9 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const V lamV = (V)sys->lambda;
   const int fb = (int)std::min<int64_t>(bf_cdiv(N * KC, 256), 8192);
 
-  hipEvent_t e0, e1;
-  BF_HIP(ctx, hipEventCreate(&e0));
-  BF_HIP(ctx, hipEventCreate(&e1));
+  // solve-time events from the context's pool (no create / destroy per call)
+  hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
+  if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
                      mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
@@ -574,8 +574,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  ctx->pool.push_back(e0);
+  ctx->pool.push_back(e1);
   bf_status status = BF_OK;
   int maxit = 0;
   int64_t sumit = 0;

@@ -381,9 +381,9 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   const double inner = mixed ? 1e-6 : 0.0;
   const int fb = std::min(nb, 4096);
 
-  hipEvent_t e0, e1;
-  BF_HIP(ctx, hipEventCreate(&e0));
-  BF_HIP(ctx, hipEventCreate(&e1));
+  // solve-time events from the context's pool (no create / destroy per call)
+  hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
+  if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, ctx->stream, st, o->tol, o->max_iter, replace_every,
                      inner);
@@ -461,8 +461,8 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  ctx->pool.push_back(e0);
+  ctx->pool.push_back(e1);
   if (ctx->timing && hs->iters >= 0 && (size_t)hs->iters < iter_rec.size())
     bf_timing_mark_idle(ctx, iter_rec[hs->iters], loop_rec_end);
   bf_status status = (bf_status)hs->status;
