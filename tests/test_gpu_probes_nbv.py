@@ -170,3 +170,30 @@ def test_nbv_ties_and_facing_away(ctx):
     assert sc[0] == 0 and sc[3] == 0 and sc[1] == sc[2] > 0 and best == 1
     sys_.free()
     band.free()
+
+
+@pytest.mark.parametrize("W,H", [(23, 17), (9, 5), (8, 24), (1, 1), (31, 40)])
+def test_nbv_odd_ray_cameras(ctx, W, H):
+    """Ray cameras whose sides are not multiples of the 8-pixel blocks or 16-pixel
+    tiles the walk hands out: the partial blocks on the right and bottom edges score
+    exactly as the oracle does, and visit the same voxels."""
+    import oracle as O
+    from synth import Camera
+    wl, ref, mu, s = _shared_nbv_inputs("tiny")
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    rc = Camera.centred(W, H, 150.0 * W / 160.0, 150.0 * W / 160.0)
+    cands = wl.candidates()[:16]
+    q = O.quantize_variance(s)
+    mu_d, s_d = torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV)
+    scores, best = ctx.bf_nbv_score(band, mu_d, s_d, torch.from_numpy(np.ascontiguousarray(cands)).to(gc.DEV), rc)
+    want = O.nbv_scores(ref["grid"], O.cam(rc), ref["keys"], mu, q, cands)
+    got = scores.cpu().numpy()
+    print(f"[{W}x{H}] scores {got[:4]} best={best}")
+    assert np.array_equal(got, want)
+    assert best == O.nbv_argmax(want)
+    one = torch.from_numpy(np.ascontiguousarray(cands[3:4])).to(gc.DEV)
+    ctx.bf_nbv_score(band, mu_d, s_d, one, rc)
+    steps = ctx.bf_nbv_walk_steps()
+    assert steps == int(O.nbv_walk_steps(ref["grid"], O.cam(rc), ref["keys"], mu, q, cands, which=[3])[0])
+    sys_.free()
+    band.free()
