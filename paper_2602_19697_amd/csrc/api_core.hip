@@ -33,6 +33,20 @@ bf_status bf_dev_alloc(bf_ctx* ctx, void** p, size_t bytes) {
   return BF_OK;
 }
 
+bf_status bf_dev_alloc_parts(bf_ctx* ctx, void** block, std::initializer_list<bf_part> parts) {
+  size_t total = 0;
+  for (const bf_part& q : parts) total += (q.bytes + 255) / 256 * 256;
+  char* base = nullptr;
+  BF_TRY(bf_dev_alloc(ctx, (void**)&base, total));
+  *block = base;
+  size_t off = 0;
+  for (const bf_part& q : parts) {
+    *q.p = q.bytes ? base + off : nullptr;
+    off += (q.bytes + 255) / 256 * 256;
+  }
+  return BF_OK;
+}
+
 void bf_dev_free(bf_ctx* ctx, void* p) {
   if (p) (void)hipFreeAsync(p, ctx->stream);
 }
@@ -204,16 +218,9 @@ bf_status bf_band_view(const bf_band* band, bf_band_arrays* out) {
 bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   if (!band) return BF_OK;
-  bf_dev_free(ctx, band->keys);
-  bf_dev_free(ctx, band->tsdf);
-  bf_dev_free(ctx, band->w);
-  bf_dev_free(ctx, band->nbr);
-  bf_dev_free(ctx, band->deg);
+  bf_dev_free(ctx, band->block);
   bf_dev_free(ctx, band->dense_tsdf);
   bf_dev_free(ctx, band->dense_w);
-  bf_dev_free(ctx, band->bricks);
-  bf_dev_free(ctx, band->brick_dist);
-  bf_dev_free(ctx, band->cells);
   delete band;
   return BF_OK;
 }
@@ -238,17 +245,7 @@ bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out) {
 bf_status bf_system_free(bf_ctx* ctx, bf_system* sys) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   if (!sys) return BF_OK;
-  bf_dev_free(ctx, sys->Lambda);
-  bf_dev_free(ctx, sys->b);
-  bf_dev_free(ctx, sys->rhs);
-  bf_dev_free(ctx, sys->diag);
-  bf_dev_free(ctx, sys->dinv);
-  bf_dev_free(ctx, sys->diag32);
-  bf_dev_free(ctx, sys->dinv32);
-  bf_dev_free(ctx, sys->acc);
-  bf_dev_free(ctx, sys->off);
-  bf_dev_free(ctx, sys->off32);
-  bf_dev_free(ctx, sys->nb26);
+  bf_dev_free(ctx, sys->block);
   delete sys;
   return BF_OK;
 }

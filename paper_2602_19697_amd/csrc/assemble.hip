@@ -175,14 +175,12 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
     return st;
   };
   if (N > 0) {
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->Lambda, N * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->b, N * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->rhs, N * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag, N * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv, N * 8)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag32, N * 4)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv32, N * 4)) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->acc, N * 40)) return fail(s);
+    if (bf_status s = bf_dev_alloc_parts(ctx, &sys->block,
+                                         {{(void**)&sys->Lambda, (size_t)N * 8}, {(void**)&sys->b, (size_t)N * 8},
+                                          {(void**)&sys->rhs, (size_t)N * 8}, {(void**)&sys->diag, (size_t)N * 8},
+                                          {(void**)&sys->dinv, (size_t)N * 8}, {(void**)&sys->diag32, (size_t)N * 4},
+                                          {(void**)&sys->dinv32, (size_t)N * 4}, {(void**)&sys->acc, (size_t)N * 40}}))
+      return fail(s);
     bf_grid_k gk{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
     bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
     noise_k nz{noise->a, noise->c, noise->z0, noise->sigma2_model, noise->sigma2_pose_dev};

@@ -133,15 +133,22 @@ __global__ __launch_bounds__(1024) void k_pyr_top(Pyr P, float* __restrict__ dmi
   }
 }
 
-// Can view t put a voxel of the 4^3 cell with lowest voxel (i0, j0, k0) into
-// the band?  False only when provably not (see the file comment).  The corner
+// What can view t do to the voxels of the 4^3 cell with lowest voxel
+// (i0, j0, k0)?  kViewNone: provably nothing (behind the camera, outside the
+// image, no valid depth under the cell, or occluded), so no voxel of the cell
+// takes an observation from it; kViewFar: each voxel it observes sees free
+// space further than the band in front of the surface, so it adds to the TSDF
+// but cannot bring a voxel into the band; kViewMay: anything else (see the
+// file comment).  The corner
 // centres are the lowest one plus sums of the three rotated cell edges (FP64);
 // the Z range over the cell follows from the edge signs, and the extremes of
 // the projected u, v over the box are at its 8 corners.  The test is a filter,
 // not part of the result, so the projection runs in FP32: its error is a few
 // 1e-7 of |u| (the coordinates stay FP64), which the twentieth-of-a-pixel
 // widening covers wherever an endpoint can fall near the image.
-__device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
+constexpr int kViewNone = 0, kViewFar = 1, kViewMay = 2;
+
+__device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
                                      const float* __restrict__ depth_t,
                                      const float* __restrict__ dmin, const float* __restrict__ dmax,
                                      const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0) {
@@ -159,8 +166,8 @@ __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, cons
   const double zlo = Z0 + fmin(az, 0.0) + fmin(bz, 0.0) + fmin(qz, 0.0);
   const double zhi = Z0 + fmax(az, 0.0) + fmax(bz, 0.0) + fmax(qz, 0.0);
   const double zmargin = 1e-9 + 1e-12 * fabs(zhi);
-  if (zhi < -zmargin) return false;  // the whole cell is behind the camera: never observed
-  if (zlo <= 1e-6) return true;      // straddles the camera plane: no projection bound
+  if (zhi < -zmargin) return kViewNone;  // the whole cell is behind the camera: never observed
+  if (zlo <= 1e-6) return kViewMay;      // straddles the camera plane: no projection bound
   const float fx = (float)c.fx, fy = (float)c.fy;
   float ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
 #pragma unroll
@@ -179,7 +186,7 @@ __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, cons
   const float hcx = (float)c.cx + 0.5f, hcy = (float)c.cy + 0.5f;
   const float c0f = floorf(ulo + hcx - 0.05f), c1f = floorf(uhi + hcx + 0.05f);
   const float r0f = floorf(vlo + hcy - 0.05f), r1f = floorf(vhi + hcy + 0.05f);
-  if (c1f < 0.0f || r1f < 0.0f || c0f >= (float)c.W || r0f >= (float)c.H) return false;  // outside the image
+  if (c1f < 0.0f || r1f < 0.0f || c0f >= (float)c.W || r0f >= (float)c.H) return kViewNone;  // outside the image
   const int32_t c0 = (int32_t)fmaxf(c0f, 0.0f), c1 = (int32_t)fminf(c1f, (float)(c.W - 1));
   const int32_t r0 = (int32_t)fmaxf(r0f, 0.0f), r1 = (int32_t)fminf(r1f, (float)(c.H - 1));
   int l = 0;
@@ -202,16 +209,22 @@ __device__ bool cell_view_may_matter(const bf_grid_k& g, const bf_cam_k& c, cons
       lo = fminf(lo, (l0 && !(vmin > 0.0f)) ? INFINITY : vmin);
       hi = fmaxf(hi, (l0 && !(vmax > 0.0f)) ? -1.0f : vmax);
     }
-  if (hi < 0.0f) return false;                                   // no valid depth under the cell
-  if ((double)lo - zhi > g.band + zmargin) return false;         // free space beyond the band
-  if ((double)hi - zlo < -g.tau - zmargin) return false;         // occluded: every view skipped
-  return true;
+  if (hi < 0.0f) return kViewNone;                               // no valid depth under the cell
+  if ((double)hi - zlo < -g.tau - zmargin) return kViewNone;     // occluded: skipped by every voxel
+  if ((double)lo - zhi > g.band + zmargin) return kViewFar;      // free space beyond the band
+  return kViewMay;
 }
 
 // One block tile of Morton codes: fuse every view into the coarse TSDF of each
 // voxel (unit weights, truncation, occlusion test), store the dense grid and
-// count the band predicate |TSDF| <= band, W > 0.
-constexpr int kCells = kTile / 64;  // 4^3 cells per block tile
+// count the band predicate |TSDF| <= band, W > 0.  With screening, a cell is
+// fused only if some view may bring one of its voxels into the band, and then
+// only over the views that can observe it at all: a view of class kViewNone
+// adds nothing to any voxel of the cell, so leaving it out keeps every sum
+// (taken in view order) bit for bit.  Per-view masks cover the first
+// 32 * kMaskWords views; later views are always fused.
+constexpr int kCells = kTile / 64;  // 4^3 cells per block tile; one wave fuses one cell
+constexpr int kMaskWords = 8;
 
 __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
                                                     const float* __restrict__ depth,
@@ -225,9 +238,11 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
 #pragma clang fp contract(off)
   __shared__ uint32_t wave_cnt[kThreads / 64];
   __shared__ int live[kCells];
+  __shared__ uint32_t vmask[kCells][kMaskWords];
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const int64_t plane = (int64_t)c.W * c.H;
   if (threadIdx.x < kCells) live[threadIdx.x] = screen ? 0 : 1;
+  if (threadIdx.x < kCells * kMaskWords) vmask[threadIdx.x / kMaskWords][threadIdx.x % kMaskWords] = screen ? 0u : ~0u;
   __syncthreads();
   if (screen) {
     for (int e = threadIdx.x; e < kCells * T; e += kThreads) {
@@ -237,29 +252,39 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
       const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
                     k0 = (int32_t)bf_compact3(m0 >> 2);
       if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
-      if (cell_view_may_matter(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0))
-        atomicOr(&live[cell], 1);
+      const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0);
+      if (cls != kViewNone && t < 32 * kMaskWords) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
+      if (cls == kViewMay) atomicOr(&live[cell], 1);
     }
     __syncthreads();
   }
   uint32_t cnt = 0, fused = 0;
+  const int nwords = (T + 31) >> 5;
   for (int it = 0; it < kItems; ++it) {
     const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
     if (m >= total) break;
     const int32_t i = (int32_t)bf_compact3(m), j = (int32_t)bf_compact3(m >> 1),
                   k = (int32_t)bf_compact3(m >> 2);
+    const int cell = (int)((m - base) >> 6);  // the same for every lane of the wave
     double tsdf = 0.0;
     int32_t W = 0;
-    if (i < g.G && j < g.G && k < g.G && live[(m - base) >> 6]) {
-      ++fused;
+    if (i < g.G && j < g.G && k < g.G && live[cell]) {
       double S = 0.0;
-      for (int32_t t = 0; t < T; ++t) {
-        double D, Z;
-        if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
-        const double d = D - Z;
-        if (d < -g.tau) continue;
-        S = S + (d < g.tau ? d : g.tau);
-        W = W + 1;
+      for (int w = 0; w < nwords; ++w) {
+        uint32_t bits = w < kMaskWords ? vmask[cell][w] : ~0u;
+        bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)bits);
+        if (w == nwords - 1 && (T & 31)) bits &= (1u << (T & 31)) - 1u;
+        fused += (uint32_t)__popc(bits);
+        while (bits) {
+          const int32_t t = 32 * w + __builtin_ctz(bits);
+          bits &= bits - 1u;
+          double D, Z;
+          if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
+          const double d = D - Z;
+          if (d < -g.tau) continue;
+          S = S + (d < g.tau ? d : g.tau);
+          W = W + 1;
+        }
       }
       if (W > 0) tsdf = S / (double)W;
     }
@@ -274,7 +299,7 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
   }
   if ((threadIdx.x & 63) == 0) {
     wave_cnt[threadIdx.x >> 6] = cnt;
-    if (fused) atomicAdd(evaluated, (unsigned long long)fused * (unsigned long long)T);
+    if (fused) atomicAdd(evaluated, (unsigned long long)fused);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -540,8 +565,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
   uint32_t* counts = (uint32_t*)((char*)scan_ws + 64);
   uint64_t* offsets = (uint64_t*)((char*)scan_ws + 64 + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64);
-  if (hipMemsetAsync(scan_ws, 0, 64, ctx->stream) != hipSuccess)
-    return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, ctx->stream, (uint64_t*)scan_ws, (uint64_t)8, 0ull);
 
   double* dense_t = nullptr;
   int32_t* dense_w = nullptr;
@@ -616,42 +640,41 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   band->n = (int64_t)N;
 
   if (N > 0) {
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->keys, N * sizeof(uint64_t))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->tsdf, N * sizeof(double))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->w, N * sizeof(int32_t))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->nbr, N * 6 * sizeof(int32_t))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->deg, N * sizeof(int32_t))) return fail(s);
+    // 4^3 cell records (key -> band index) for the neighbour table and the
+    // ray walker; brick occupancy bitmap for the ray walker (brick edge
+    // 2^shift, at most 64 bricks per axis) and its forward-octant distances
+    band->ncell = std::max(1, band->P >> 2);
+    const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
+    int shift = 2;
+    while ((band->P >> shift) > 64) ++shift;
+    band->brick_shift = shift;
+    band->nbrick = std::max(1, band->P >> shift);
+    const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
+    const size_t words = ((size_t)nbr3 + 31) / 32;
+    if (bf_status s = bf_dev_alloc_parts(
+            ctx, &band->block,
+            {{(void**)&band->keys, N * sizeof(uint64_t)}, {(void**)&band->tsdf, N * sizeof(double)},
+             {(void**)&band->w, N * sizeof(int32_t)}, {(void**)&band->nbr, N * 6 * sizeof(int32_t)},
+             {(void**)&band->deg, N * sizeof(int32_t)}, {(void**)&band->cells, (size_t)nc3 * sizeof(bf_cell)},
+             {(void**)&band->bricks, words * 4}, {(void**)&band->brick_dist, (size_t)(8 * nbr3)}}))
+      return fail(s);
     BF_LAUNCH(ctx, "band_scatter", k_band_scatter, dim3((unsigned)nblocks), dim3(kThreads), 0, total,
                        grid->band, dense_t, dense_w, offsets, band->keys, band->tsdf, band->w);
     if (bf_status s = bf_launch_check(ctx, "k_band_scatter")) return fail(s);
 
     const unsigned nb = (unsigned)bf_cdiv((int64_t)N, 256);
-    // 4^3 cell records (key -> band index) for the neighbour table and the ray walker
-    band->ncell = std::max(1, band->P >> 2);
-    const int64_t nc3 = (int64_t)band->ncell * band->ncell * band->ncell;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->cells, nc3 * sizeof(bf_cell))) return fail(s);
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<int64_t>(bf_cdiv(2 * nc3, 256), 16384)), dim3(256), 0,
-                       ctx->stream, (uint64_t*)band->cells, (uint64_t)(2 * nc3), 0ull);
+    // clear the cell records and the brick bitmap, which follows them in the block
+    const uint64_t nclear = (uint64_t)(((char*)band->bricks + words * 4 - (char*)band->cells + 7) / 8);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)std::min<uint64_t>(bf_cdiv((int64_t)nclear, 256), 16384)),
+                       dim3(256), 0, ctx->stream, (uint64_t*)band->cells, nclear, 0ull);
     BF_LAUNCH(ctx, "cell_tables", k_cell_tables, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, band->ncell,
               band->cells);
     BF_LAUNCH(ctx, "neighbours", k_neighbours, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, grid->G, band->cells,
               band->ncell, band->nbr, band->deg);
-    // brick occupancy bitmap for the ray walker: brick edge 2^shift with at
-    // most 64 bricks per axis
-    int shift = 2;
-    while ((band->P >> shift) > 64) ++shift;
-    band->brick_shift = shift;
-    band->nbrick = std::max(1, band->P >> shift);
-    const size_t words = ((size_t)band->nbrick * band->nbrick * band->nbrick + 31) / 32;
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->bricks, words * 4)) return fail(s);
-    if (hipMemsetAsync(band->bricks, 0, words * 4, ctx->stream) != hipSuccess)
-      return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: memset"));
     BF_LAUNCH(ctx, "brick_bits", k_brick_bits, dim3(nb), dim3(256), 0, band->keys, (int64_t)N, shift, band->nbrick,
               band->bricks);
     // forward-octant brick distances (empty-space skipping) for the ray walker
-    const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
     uint8_t* dtmp = nullptr;  // 2 nbr3 after the x pass, then 4 nbr3 after y
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->brick_dist, 8 * nbr3)) return fail(s);
     if (bf_status s = bf_ws(ctx, bf_ctx::WS_NBV_TMP, 6 * nbr3, (void**)&dtmp)) return fail(s);
     int lnb = 0;  // nbrick is a power of two, at most 64
     while ((1 << lnb) < band->nbrick) ++lnb;

@@ -357,7 +357,10 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
   }
 }
 
-__global__ void k_zero_i64(int64_t* p, int n) {
+// Clears the scores and the walk's three workspace words (maximum variance,
+// best index and hand-out counter, visit count).
+__global__ void k_zero_i64(int64_t* p, int n, uint64_t* ws3) {
+  if (threadIdx.x < 3) ws3[threadIdx.x] = 0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
@@ -422,8 +425,7 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   unsigned int* queue = (unsigned int*)(ws + 12);
   unsigned long long* walk_steps = (unsigned long long*)(ws + 16);
   int64_t* q = (int64_t*)(ws + 256);
-  BF_HIP(ctx, hipMemsetAsync(ws, 0, 24, ctx->stream));
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, ctx->stream, scores_dev, n_cand);
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(256), 0, ctx->stream, scores_dev, n_cand, (uint64_t*)ws);
   if (N > 0) {
     BF_CHECK(ctx, mu_dev && s_dev, "bf_nbv_score: NULL mu or s");
     hipLaunchKernelGGL(k_max, dim3(nbm), dim3(kThreads), 0, ctx->stream, s_dev, N, (unsigned long long*)smax);

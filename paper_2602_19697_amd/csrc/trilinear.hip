@@ -339,16 +339,14 @@ extern "C" bf_status bf_assemble_trilinear(bf_ctx* ctx, const bf_band* band, con
     *out = sys;
     return BF_OK;
   }
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->Lambda, N * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->b, N * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->rhs, N * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag, N * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv, N * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->diag32, N * 4)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->dinv32, N * 4)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->off, N * 26 * 8)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->off32, N * 26 * 4)) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&sys->nb26, N * 26 * 4)) return fail(s);
+  if (bf_status s = bf_dev_alloc_parts(ctx, &sys->block,
+                                       {{(void**)&sys->Lambda, (size_t)N * 8}, {(void**)&sys->b, (size_t)N * 8},
+                                        {(void**)&sys->rhs, (size_t)N * 8}, {(void**)&sys->diag, (size_t)N * 8},
+                                        {(void**)&sys->dinv, (size_t)N * 8}, {(void**)&sys->diag32, (size_t)N * 4},
+                                        {(void**)&sys->dinv32, (size_t)N * 4}, {(void**)&sys->off, (size_t)N * 26 * 8},
+                                        {(void**)&sys->off32, (size_t)N * 26 * 4},
+                                        {(void**)&sys->nb26, (size_t)N * 26 * 4}}))
+    return fail(s);
 
   tri_k K{};
   K.g = bf_grid_k{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
