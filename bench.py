@@ -80,16 +80,16 @@ def measured_traffic(kernel, workload):
 
 
 # Operations per fused voxel-view of the coarse TSDF (FP64 projection, two
-# divisions, truncation, running sum) and per screened (4^3 cell, view) pair:
-# one FP64 corner transform (27), cell edges and Z range (22), 36 FP64 corner
-# adds, 8 FP32 projections of 12 operations (96), pixel range and pyramid
-# bounds (31), final tests (5), counted arithmetic, min/max, compare and
-# convert operations alike.
+# divisions, truncation, running sum) and per screening test of a (box, view)
+# pair, the box being a block tile or a 4^3 cell: one FP64 corner transform
+# (27), box edges and Z range (22), 36 FP64 corner adds, 8 FP32 projections of
+# 12 operations (96), pixel range and pyramid bounds (31), final tests (5),
+# counted arithmetic, min/max, compare and convert operations alike.
 TSDF_OPS_PER_VOXEL_VIEW = 35
 TSDF_OPS_PER_CELL_VIEW = 217
 
 
-def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None):
+def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None):
     """(amount, unit, bound) of one launch of a timed kernel."""
     s = 8 if fp64 else 4
     if name == "pcg_A":      # nbr, diag, z, p_old -> p_new, q
@@ -100,10 +100,10 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None):
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
         return N * (s + 7 * K * s), "B", "hbm"
-    if name == "tsdf_count":  # fused voxel-views + screened cell-views
+    if name == "tsdf_count":  # fused voxel-views + screening tests (counted by the kernel)
         vv = G ** 3 * T if voxel_views is None else voxel_views
-        cells = -(-G // 4) ** 3
-        return vv * TSDF_OPS_PER_VOXEL_VIEW + cells * T * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
+        tests = -(-G // 4) ** 3 * T if box_tests is None else box_tests
+        return vv * TSDF_OPS_PER_VOXEL_VIEW + tests * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
     if name == "assemble":
         return N * T * 45, "flop", "alu"
     return None
@@ -147,7 +147,7 @@ def run_gpu(args):
         s, prep = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
-                   tsdf_voxel_views=band.info()["tsdf_voxel_views"],
+                   tsdf_voxel_views=band.info()["tsdf_voxel_views"], tsdf_box_tests=band.info()["tsdf_box_tests"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
         sys_.free()
@@ -187,7 +187,7 @@ def run_gpu(args):
     rooflines = {}
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
-                             voxel_views=info["tsdf_voxel_views"])
+                             voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"])
         if w is None:
             continue
         amount, unit, bound = w
@@ -699,6 +699,7 @@ def main():
             full = g["wl"].G ** 3 * g["wl"].T
             roof["fused_voxel_views"] = g["info"]["tsdf_voxel_views"]
             roof["screened_fraction"] = 1.0 - g["info"]["tsdf_voxel_views"] / full
+            roof["screening_tests"] = g["info"]["tsdf_box_tests"]
     wl = g["wl"]
     nbv = g["kernels"].get("nbv_rays")
     rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height

@@ -139,6 +139,7 @@ typedef struct bf_band_arrays {
   const int32_t* dense_w;     /* [P^3] Morton-ordered dense weights, or NULL */
   int64_t tsdf_voxel_views;   /* voxel x view projections the coarse TSDF evaluated; 4^3 cells that
                                  provably hold no band voxel are skipped (not with BF_BAND_KEEP_DENSE) */
+  int64_t tsdf_box_tests;     /* (block tile or 4^3 cell, view) screening tests made for that skipping */
 } bf_band_arrays;
 
 typedef struct bf_system_arrays {

@@ -80,7 +80,8 @@ class bf_schedule(C.Structure):
 class bf_band_arrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("dense_side", C.c_int32), ("keys", C.c_void_p),
                 ("tsdf", C.c_void_p), ("w", C.c_void_p), ("nbr", C.c_void_p), ("deg", C.c_void_p),
-                ("dense_tsdf", C.c_void_p), ("dense_w", C.c_void_p), ("tsdf_voxel_views", C.c_int64)]
+                ("dense_tsdf", C.c_void_p), ("dense_w", C.c_void_p), ("tsdf_voxel_views", C.c_int64),
+                ("tsdf_box_tests", C.c_int64)]
 
 
 class bf_system_arrays(C.Structure):

@@ -133,8 +133,8 @@ __global__ __launch_bounds__(1024) void k_pyr_top(Pyr P, float* __restrict__ dmi
   }
 }
 
-// What can view t do to the voxels of the 4^3 cell with lowest voxel
-// (i0, j0, k0)?  kViewNone: provably nothing (behind the camera, outside the
+// What can view t do to the voxels of the box of voxel centres from
+// (i0, j0, k0) to (i0, j0, k0) + (ni, nj, nk) - 1 (a 4^3 cell or a block tile)?  kViewNone: provably nothing (behind the camera, outside the
 // image, no valid depth under the cell, or occluded), so no voxel of the cell
 // takes an observation from it; kViewFar: each voxel it observes sees free
 // space further than the band in front of the surface, so it adds to the TSDF
@@ -151,7 +151,8 @@ constexpr int kViewNone = 0, kViewFar = 1, kViewMay = 2;
 __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr& P,
                                      const float* __restrict__ depth_t,
                                      const float* __restrict__ dmin, const float* __restrict__ dmax,
-                                     const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0) {
+                                     const double* __restrict__ Pose, int t, int32_t i0, int32_t j0, int32_t k0,
+                                     int32_t ni, int32_t nj, int32_t nk) {
   const double x = g.ox + ((double)i0 + 0.5) * g.h;
   const double y = g.oy + ((double)j0 + 0.5) * g.h;
   const double z = g.oz + ((double)k0 + 0.5) * g.h;
@@ -159,10 +160,11 @@ __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr&
   const double X0 = Pose[0] * dx + Pose[4] * dy + Pose[8] * dz;
   const double Y0 = Pose[1] * dx + Pose[5] * dy + Pose[9] * dz;
   const double Z0 = Pose[2] * dx + Pose[6] * dy + Pose[10] * dz;
-  const double e = 3.0 * g.h;  // lowest to highest voxel centre of the cell along one axis
-  const double ax = e * Pose[0], ay = e * Pose[1], az = e * Pose[2];  // per grid-x edge
-  const double bx = e * Pose[4], by = e * Pose[5], bz = e * Pose[6];  // per grid-y edge
-  const double qx = e * Pose[8], qy = e * Pose[9], qz = e * Pose[10];  // per grid-z edge
+  // lowest to highest voxel centre of the box along each axis
+  const double ex = (ni - 1) * g.h, ey = (nj - 1) * g.h, ez = (nk - 1) * g.h;
+  const double ax = ex * Pose[0], ay = ex * Pose[1], az = ex * Pose[2];  // per grid-x edge
+  const double bx = ey * Pose[4], by = ey * Pose[5], bz = ey * Pose[6];  // per grid-y edge
+  const double qx = ez * Pose[8], qy = ez * Pose[9], qz = ez * Pose[10];  // per grid-z edge
   const double zlo = Z0 + fmin(az, 0.0) + fmin(bz, 0.0) + fmin(qz, 0.0);
   const double zhi = Z0 + fmax(az, 0.0) + fmax(bz, 0.0) + fmax(qz, 0.0);
   const double zmargin = 1e-9 + 1e-12 * fabs(zhi);
@@ -223,8 +225,51 @@ __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr&
 // adds nothing to any voxel of the cell, so leaving it out keeps every sum
 // (taken in view order) bit for bit.  Per-view masks cover the first
 // 32 * kMaskWords views; later views are always fused.
+//
+// The screen is two-level: k_tile_screen first tests each block tile (a
+// 16 x 8 x 8 voxel box) against each of the first kTileViews views.  What
+// holds for the tile holds for each of its cells, so a tile-level kViewNone
+// needs no cell tests and a tile-level kViewFar marks the view as
+// contributing for every cell (a cell the view does not in fact observe gets
+// no observation from it in the fused loop); only the kViewMay views, and
+// views past kTileViews, are tested cell by cell here.
 constexpr int kCells = kTile / 64;  // 4^3 cells per block tile; one wave fuses one cell
 constexpr int kMaskWords = 8;
+constexpr int kTileViews = 32 * kMaskWords;
+constexpr int kTileI = 16, kTileJ = 8, kTileK = 8;  // Morton tile of kTile codes (x takes the low bit)
+static_assert(kTileI * kTileJ * kTileK == kTile, "block tile box");
+
+// One wave per (block tile, 64 views): the tile's kViewFar and kViewMay view
+// masks, tmask[tile][0 | 1][word], from the ballots of the lanes' tests.
+__global__ __launch_bounds__(256) void k_tile_screen(bf_grid_k g, bf_cam_k c, int32_t T, int64_t ntiles,
+                                                     const float* __restrict__ depth,
+                                                     const double* __restrict__ poses, Pyr P,
+                                                     const float* __restrict__ dmin,
+                                                     const float* __restrict__ dmax, uint32_t* __restrict__ tmask) {
+#pragma clang fp contract(off)
+  const int32_t tv = min(T, kTileViews);
+  const int nchunk = (tv + 63) >> 6;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= ntiles * nchunk) return;  // whole waves: ntiles * nchunk waves exactly
+  const int64_t tile = wave / nchunk;
+  const int chunk = (int)(wave % nchunk);
+  const uint64_t base = (uint64_t)tile * kTile;
+  const int32_t ti = (int32_t)bf_compact3(base), tj = (int32_t)bf_compact3(base >> 1),
+                tk = (int32_t)bf_compact3(base >> 2);
+  const int t = chunk * 64 + lane;
+  int cls = kViewNone;
+  const bool test = t < tv && ti < g.G && tj < g.G && tk < g.G;  // else no voxel of the tile exists
+  if (test)
+    cls = cell_view_class(g, c, P, depth + t * ((int64_t)c.W * c.H), dmin, dmax, poses + 12 * t, t, ti, tj, tk,
+                          kTileI, kTileJ, kTileK);
+  const uint64_t far = __ballot(cls == kViewFar), may = __ballot(cls == kViewMay);
+  uint32_t* tm = tmask + tile * (2 * kMaskWords);
+  if (lane < 2) {
+    tm[2 * chunk + lane] = (uint32_t)(far >> (32 * lane));
+    tm[kMaskWords + 2 * chunk + lane] = (uint32_t)(may >> (32 * lane));
+  }
+}
 
 __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
                                                     const float* __restrict__ depth,
@@ -234,26 +279,61 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
                                                     uint32_t* __restrict__ counts, int screen, Pyr P,
                                                     const float* __restrict__ dmin,
                                                     const float* __restrict__ dmax,
-                                                    unsigned long long* __restrict__ evaluated) {
+                                                    const uint32_t* __restrict__ tmask,
+                                                    uint2* __restrict__ work) {
 #pragma clang fp contract(off)
-  __shared__ uint32_t wave_cnt[kThreads / 64];
+  __shared__ uint32_t wave_cnt[kThreads / 64], wave_fused[kThreads / 64], wave_tests[kThreads / 64];
   __shared__ int live[kCells];
   __shared__ uint32_t vmask[kCells][kMaskWords];
+  __shared__ uint32_t may_w[kMaskWords];
+  __shared__ int may_pre[kMaskWords + 1];
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const int64_t plane = (int64_t)c.W * c.H;
+  const int32_t tv = min(T, kTileViews);  // views the tile screen tested
+  const int tvw = (tv + 31) >> 5;
+  const uint32_t* tm = tmask + (int64_t)blockIdx.x * (2 * kMaskWords);
+  // every cell starts with the tile's kViewFar views marked
   if (threadIdx.x < kCells) live[threadIdx.x] = screen ? 0 : 1;
-  if (threadIdx.x < kCells * kMaskWords) vmask[threadIdx.x / kMaskWords][threadIdx.x % kMaskWords] = screen ? 0u : ~0u;
+  if (threadIdx.x < kCells * kMaskWords) {
+    const int w = threadIdx.x % kMaskWords;
+    vmask[threadIdx.x / kMaskWords][w] = screen ? (w < tvw ? tm[w] : 0u) : ~0u;
+  }
+  if (screen && threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < kMaskWords; ++w) {
+      const uint32_t mw = w < tvw ? tm[kMaskWords + w] : 0u;
+      may_w[w] = mw;
+      may_pre[w] = acc;
+      acc += __popc(mw);
+    }
+    may_pre[kMaskWords] = acc;
+  }
   __syncthreads();
+  uint32_t tests = 0;
   if (screen) {
-    for (int e = threadIdx.x; e < kCells * T; e += kThreads) {
-      const int cell = e % kCells, t = e / kCells;
+    // cell tests: the tile's kViewMay views in view order, then every view past kTileViews
+    const int nm_tile = may_pre[kMaskWords];
+    const int nm = nm_tile + (T - tv);
+    for (int e = threadIdx.x; e < kCells * nm; e += kThreads) {
+      const int cell = e % kCells, r = e / kCells;
+      int t;
+      if (r < nm_tile) {  // the r-th set bit of the kViewMay mask
+        int w = 0;
+        while (may_pre[w + 1] <= r) ++w;
+        uint32_t x = may_w[w];
+        for (int q = r - may_pre[w]; q > 0; --q) x &= x - 1u;
+        t = 32 * w + __builtin_ctz(x);
+      } else {
+        t = tv + (r - nm_tile);
+      }
       const uint64_t m0 = base + (uint64_t)cell * 64;
       if (m0 >= total) continue;
       const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
                     k0 = (int32_t)bf_compact3(m0 >> 2);
       if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
-      const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0);
-      if (cls != kViewNone && t < 32 * kMaskWords) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
+      ++tests;
+      const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0, 4, 4, 4);
+      if (cls != kViewNone && t < kTileViews) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
       if (cls == kViewMay) atomicOr(&live[cell], 1);
     }
     __syncthreads();
@@ -292,20 +372,28 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
     dense_w[m] = W;
     cnt += (W > 0 && fabs(tsdf) <= g.band) ? 1u : 0u;
   }
-  // block count (integer: any order is exact)
+  // block counts (integer: any order is exact); the work counts are summed
+  // by the scan, as one atomic per wave on a single address serialises in L2
   for (int off = 32; off > 0; off >>= 1) {
     cnt += __shfl_xor(cnt, off, 64);
     fused += __shfl_xor(fused, off, 64);
+    tests += __shfl_xor(tests, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     wave_cnt[threadIdx.x >> 6] = cnt;
-    if (fused) atomicAdd(evaluated, (unsigned long long)fused);
+    wave_fused[threadIdx.x >> 6] = fused;
+    wave_tests[threadIdx.x >> 6] = tests;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t s = 0;
-    for (int w = 0; w < kThreads / 64; ++w) s += wave_cnt[w];
+    uint32_t s = 0, f = 0, n = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      s += wave_cnt[w];
+      f += wave_fused[w];
+      n += wave_tests[w];
+    }
     counts[blockIdx.x] = s;
+    work[blockIdx.x] = make_uint2(f, n);
   }
 }
 
@@ -313,17 +401,30 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
 // offsets[nb] and the total to *n_total.  Each thread sums a contiguous chunk
 // (loads unrolled so several are in flight), the 1024 chunk sums are scanned
 // with wave shuffles and one pass over the 16 wave totals, and each thread
-// then writes its chunk's offsets.  Integer sums: any order is exact.
+// then writes its chunk's offsets.  The per-block work counts (fused
+// voxel-views, cell tests) are summed into work_total[0..1] alongside.
+// Integer sums: any order is exact.
 __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ counts, int64_t nb,
                                                       uint64_t* __restrict__ offsets,
-                                                      uint64_t* __restrict__ n_total) {
-  __shared__ uint64_t wsum[16];
+                                                      uint64_t* __restrict__ n_total,
+                                                      const uint2* __restrict__ work,
+                                                      unsigned long long* __restrict__ work_total) {
+  __shared__ uint64_t wsum[16], wf[16], wt[16];
   const int64_t chunk = bf_cdiv(nb, 1024);
   const int64_t lo = threadIdx.x * chunk;
   const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
-  uint64_t s = 0;
+  uint64_t s = 0, sf = 0, st = 0;
 #pragma unroll 8
-  for (int64_t b = lo; b < hi; ++b) s += counts[b];
+  for (int64_t b = lo; b < hi; ++b) {
+    s += counts[b];
+    const uint2 wk = work[b];
+    sf += wk.x;
+    st += wk.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    sf += __shfl_xor(sf, off, 64);
+    st += __shfl_xor(st, off, 64);
+  }
   // inclusive scan of the chunk sums: within each wave, then across waves
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint64_t inc = s;
@@ -333,7 +434,20 @@ __global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict
     if (lane >= off) inc += v;
   }
   if (lane == 63) wsum[wid] = inc;
+  if (lane == 0) {
+    wf[wid] = sf;
+    wt[wid] = st;
+  }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t a = 0, c = 0;
+    for (int w = 0; w < 16; ++w) {
+      a += wf[w];
+      c += wt[w];
+    }
+    work_total[0] = a;
+    work_total[1] = c;
+  }
   if (wid == 0) {
     uint64_t w = lane < 16 ? wsum[lane] : 0;
 #pragma unroll
@@ -559,12 +673,19 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
 
   // flags[0]: depth invalid; then the band count
   void* scan_ws = nullptr;
-  const size_t scan_bytes = 64 + nblocks * (sizeof(uint32_t) + sizeof(uint64_t)) + 64;
+  // layout: flags and counters (64 B) | counts [nblocks] | offsets [nblocks + 1] | work counts
+  // [nblocks] | tile view masks
+  const size_t off_counts = 64, off_offsets = off_counts + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64;
+  const size_t off_work = (off_offsets + (nblocks + 1) * sizeof(uint64_t) + 255) / 256 * 256;
+  const size_t off_tmask = (off_work + nblocks * sizeof(uint2) + 255) / 256 * 256;
+  const size_t scan_bytes = off_tmask + nblocks * (2 * kMaskWords * sizeof(uint32_t));
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
   int* dflags = (int*)scan_ws;
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
-  uint32_t* counts = (uint32_t*)((char*)scan_ws + 64);
-  uint64_t* offsets = (uint64_t*)((char*)scan_ws + 64 + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64);
+  uint32_t* counts = (uint32_t*)((char*)scan_ws + off_counts);
+  uint64_t* offsets = (uint64_t*)((char*)scan_ws + off_offsets);
+  uint2* work = (uint2*)((char*)scan_ws + off_work);
+  uint32_t* tmask = (uint32_t*)((char*)scan_ws + off_tmask);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, ctx->stream, (uint64_t*)scan_ws, (uint64_t)8, 0ull);
 
   double* dense_t = nullptr;
@@ -617,23 +738,32 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               dim3(256), 0, depth_dev, cam->width, cam->height, pyr, dmin, dmax, dflags);
     if (pyr.nl > kTileLevels + 1)
       BF_LAUNCH(ctx, "depth_pyramid", k_pyr_top, dim3((unsigned)T), dim3(1024), 0, pyr, dmin, dmax);
+    // one wave per (block tile, 64 of the first kTileViews views)
+    const int64_t waves = (int64_t)nblocks * ((std::min<int32_t>(T, kTileViews) + 63) / 64);
+    BF_LAUNCH(ctx, "tile_screen", k_tile_screen, dim3((unsigned)bf_cdiv(waves, 4)), dim3(256), 0, gk, ck, T,
+              (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, tmask);
   }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
-                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax,
-                     (unsigned long long*)((char*)scan_ws + 24));
+                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax, tmask, work);
   if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
-  BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal);
+  BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal, work,
+            (unsigned long long*)((char*)scan_ws + 24));
   if (bf_status s = bf_launch_check(ctx, "k_scan_counts")) return fail(s);
 
   void* pin = nullptr;
   if (bf_status s = bf_pinned(ctx, 64, &pin)) return fail(s);
-  if (hipMemcpyAsync(pin, scan_ws, 32, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+  if (hipMemcpyAsync(pin, scan_ws, 40, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: count read-back failed"));
   if (((int*)pin)[0] & 1)
     return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth holds NaN, inf or negative values"));
   const uint64_t N = *(uint64_t*)((char*)pin + 16);
   band->tsdf_voxel_views = *(const int64_t*)((char*)pin + 24);
+  // cell tests, plus one tile test per (block tile holding a grid voxel, screened view)
+  band->tsdf_box_tests = *(const int64_t*)((char*)pin + 32);
+  if (screen)
+    band->tsdf_box_tests += bf_cdiv(grid->G, kTileI) * bf_cdiv(grid->G, kTileJ) * bf_cdiv(grid->G, kTileK) *
+                            (int64_t)std::min<int32_t>(T, kTileViews);
   if (N >= (1ull << 31) - 1)
     return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing",
                         (unsigned long long)N));

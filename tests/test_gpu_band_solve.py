@@ -54,16 +54,21 @@ def test_band_screening_exact(ctx, name, seed):
     band, sys_, _, _ = gc.gpu_system(ctx, wl)
     a = band.arrays()
     full = wl.G ** 3 * wl.T
+    cell_views = (-(-wl.G // 4)) ** 3 * wl.T
     print(f"[{name}] screened: {a['tsdf_voxel_views']} of {full} voxel-views fused "
-          f"({100.0 * a['tsdf_voxel_views'] / full:.1f}%)", flush=True)
+          f"({100.0 * a['tsdf_voxel_views'] / full:.1f}%); {a['tsdf_box_tests']} screening tests "
+          f"for {cell_views} cell-views", flush=True)
     for key in ("keys", "tsdf", "w", "nbr", "deg"):
         assert np.array_equal(a[key].cpu().numpy(), ref[key]), key
     assert 0 < a["tsdf_voxel_views"] < full
+    # the tile-level tests spare most cell tests
+    assert 0 < a["tsdf_box_tests"] < cell_views
     sys_.free()
     band.free()
     # with the dense grid kept, nothing is screened
     band2, sys2, _, _ = gc.gpu_system(ctx, wl, keep_dense=True)
     assert band2.arrays()["tsdf_voxel_views"] == full
+    assert band2.arrays()["tsdf_box_tests"] == 0
     sys2.free()
     band2.free()
 
