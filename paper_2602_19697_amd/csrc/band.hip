@@ -10,13 +10,14 @@
 //
 // Screening: only voxels of the band need an exact TSDF.  Before fusing a
 // block, every 4^3 cell of it is tested against every view with a min/max
-// pyramid of the valid depths: if in each view every voxel of the cell either
-// sees free space further than the band half-width in front of the surface
-// (all its observations exceed the band, as the truncation does) or lies more
-// than tau behind it (occluded: skipped), no voxel of the cell can be in the
-// band, and the cell is not fused.  The band (keys, TSDF, weights) is the
-// same bit for bit; the dense grid then holds W = 0 for screened cells, so
-// screening is off when the dense grid is kept for inspection.
+// pyramid of the valid depths (block tiles first, then cells; see
+// k_tsdf_count): if in each view every voxel of the cell either sees free
+// space further than the band half-width in front of the surface (all its
+// observations exceed the band, as the truncation does) or lies more than tau
+// behind it (occluded: skipped), no voxel of the cell can be in the band, and
+// the cell is not fused, nor are its dense values stored or read back by the
+// scatter.  The band (keys, TSDF, weights) is the same bit for bit; screening
+// is off when the dense grid is kept for inspection.
 #include "bf_internal.h"
 
 namespace {
@@ -236,6 +237,7 @@ __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr&
 constexpr int kCells = kTile / 64;  // 4^3 cells per block tile; one wave fuses one cell
 constexpr int kMaskWords = 8;
 constexpr int kTileViews = 32 * kMaskWords;
+constexpr int kViewBatch = 4;  // views whose depth loads the fused loop has in flight together
 constexpr int kTileI = 16, kTileJ = 8, kTileK = 8;  // Morton tile of kTile codes (x takes the low bit)
 static_assert(kTileI * kTileJ * kTileK == kTile, "block tile box");
 
@@ -280,7 +282,7 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
                                                     const float* __restrict__ dmin,
                                                     const float* __restrict__ dmax,
                                                     const uint32_t* __restrict__ tmask,
-                                                    uint2* __restrict__ work) {
+                                                    uint2* __restrict__ work, uint32_t* __restrict__ cellmask) {
 #pragma clang fp contract(off)
   __shared__ uint32_t wave_cnt[kThreads / 64], wave_fused[kThreads / 64], wave_tests[kThreads / 64];
   __shared__ int live[kCells];
@@ -346,9 +348,12 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
     const int32_t i = (int32_t)bf_compact3(m), j = (int32_t)bf_compact3(m >> 1),
                   k = (int32_t)bf_compact3(m >> 2);
     const int cell = (int)((m - base) >> 6);  // the same for every lane of the wave
+    // a screened cell holds no band voxel: its dense values are never read
+    // (the scatter skips it by cellmask), so they are not stored either
+    if (!live[cell]) continue;
     double tsdf = 0.0;
     int32_t W = 0;
-    if (i < g.G && j < g.G && k < g.G && live[cell]) {
+    if (i < g.G && j < g.G && k < g.G) {
       double S = 0.0;
       for (int w = 0; w < nwords; ++w) {
         uint32_t bits = w < kMaskWords ? vmask[cell][w] : ~0u;
@@ -356,14 +361,33 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
         if (w == nwords - 1 && (T & 31)) bits &= (1u << (T & 31)) - 1u;
         fused += (uint32_t)__popc(bits);
         while (bits) {
-          const int32_t t = 32 * w + __builtin_ctz(bits);
-          bits &= bits - 1u;
-          double D, Z;
-          if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
-          const double d = D - Z;
-          if (d < -g.tau) continue;
-          S = S + (d < g.tau ? d : g.tau);
-          W = W + 1;
+          // up to kViewBatch views at a time: project, issue every depth
+          // load, then add in view order (the sum's order is unchanged)
+          int32_t tq[kViewBatch];
+          int64_t px[kViewBatch];
+          double Zq[kViewBatch];
+          float Dq[kViewBatch];
+#pragma unroll
+          for (int q = 0; q < kViewBatch; ++q) {
+            tq[q] = bits ? 32 * w + __builtin_ctz(bits) : -1;
+            bits &= bits - 1u;  // 0 stays 0
+          }
+#pragma unroll
+          for (int q = 0; q < kViewBatch; ++q) {
+            Zq[q] = 0.0;
+            px[q] = tq[q] >= 0 ? bf_project(g, c, poses + 12 * tq[q], i, j, k, Zq[q]) : -1;
+          }
+#pragma unroll
+          for (int q = 0; q < kViewBatch; ++q) Dq[q] = px[q] >= 0 ? depth[tq[q] * plane + px[q]] : 0.0f;
+#pragma unroll
+          for (int q = 0; q < kViewBatch; ++q) {
+            const double D = (double)Dq[q];
+            if (px[q] < 0 || !(D > 0.0)) continue;
+            const double d = D - Zq[q];
+            if (d < -g.tau) continue;
+            S = S + (d < g.tau ? d : g.tau);
+            W = W + 1;
+          }
         }
       }
       if (W > 0) tsdf = S / (double)W;
@@ -394,6 +418,9 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
     }
     counts[blockIdx.x] = s;
     work[blockIdx.x] = make_uint2(f, n);
+    uint32_t lm = 0;
+    for (int q = 0; q < kCells; ++q) lm |= live[q] ? 1u << q : 0u;
+    cellmask[blockIdx.x] = lm;
   }
 }
 
@@ -472,18 +499,22 @@ __global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double ban
                                                       const double* __restrict__ dense_t,
                                                       const int32_t* __restrict__ dense_w,
                                                       const uint64_t* __restrict__ offsets,
+                                                      const uint32_t* __restrict__ counts,
+                                                      const uint32_t* __restrict__ cellmask,
                                                       uint64_t* __restrict__ keys,
                                                       double* __restrict__ tsdf,
                                                       int32_t* __restrict__ w) {
   __shared__ uint32_t wave_cnt[kThreads / 64];
+  if (counts[blockIdx.x] == 0) return;  // the whole block: no band voxel in the tile
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  const uint32_t lm = cellmask[blockIdx.x];  // cells whose dense values were stored
   uint64_t out = offsets[blockIdx.x];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int it = 0; it < kItems; ++it) {
     const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
     double t = 0.0;
     int32_t W = 0;
-    if (m < total) {
+    if (m < total && ((lm >> (it * (kThreads / 64) + wid)) & 1u)) {
       t = dense_t[m];
       W = dense_w[m];
     }
@@ -674,11 +705,12 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   // flags[0]: depth invalid; then the band count
   void* scan_ws = nullptr;
   // layout: flags and counters (64 B) | counts [nblocks] | offsets [nblocks + 1] | work counts
-  // [nblocks] | tile view masks
+  // [nblocks] | tile view masks [nblocks][2][kMaskWords] | live-cell masks [nblocks]
   const size_t off_counts = 64, off_offsets = off_counts + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64;
   const size_t off_work = (off_offsets + (nblocks + 1) * sizeof(uint64_t) + 255) / 256 * 256;
   const size_t off_tmask = (off_work + nblocks * sizeof(uint2) + 255) / 256 * 256;
-  const size_t scan_bytes = off_tmask + nblocks * (2 * kMaskWords * sizeof(uint32_t));
+  const size_t off_cmask = off_tmask + nblocks * (2 * kMaskWords * sizeof(uint32_t));
+  const size_t scan_bytes = off_cmask + nblocks * sizeof(uint32_t);
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
   int* dflags = (int*)scan_ws;
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
@@ -686,6 +718,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   uint64_t* offsets = (uint64_t*)((char*)scan_ws + off_offsets);
   uint2* work = (uint2*)((char*)scan_ws + off_work);
   uint32_t* tmask = (uint32_t*)((char*)scan_ws + off_tmask);
+  uint32_t* cellmask = (uint32_t*)((char*)scan_ws + off_cmask);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, ctx->stream, (uint64_t*)scan_ws, (uint64_t)8, 0ull);
 
   double* dense_t = nullptr;
@@ -744,7 +777,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, tmask);
   }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
-                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax, tmask, work);
+                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax, tmask, work,
+                     cellmask);
   if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
   BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal, work,
             (unsigned long long*)((char*)scan_ws + 24));
@@ -789,7 +823,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
              {(void**)&band->bricks, words * 4}, {(void**)&band->brick_dist, (size_t)(8 * nbr3)}}))
       return fail(s);
     BF_LAUNCH(ctx, "band_scatter", k_band_scatter, dim3((unsigned)nblocks), dim3(kThreads), 0, total,
-                       grid->band, dense_t, dense_w, offsets, band->keys, band->tsdf, band->w);
+                       grid->band, dense_t, dense_w, offsets, counts, cellmask, band->keys, band->tsdf, band->w);
     if (bf_status s = bf_launch_check(ctx, "k_band_scatter")) return fail(s);
 
     const unsigned nb = (unsigned)bf_cdiv((int64_t)N, 256);
