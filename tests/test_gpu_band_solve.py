@@ -199,3 +199,34 @@ def test_empty_band(ctx):
     assert x.numel() == 0 and rep["iters"] == 0
     sys_.free()
     band.free()
+
+
+def test_band_many_views_exact(ctx):
+    """264 views: the block-tile screen keeps per-view masks for the first 256 views
+    only; the views past them are tested cell by cell and always fused.  Band, TSDF,
+    weights, neighbours and the assembled Lambda and b match the oracle bit for bit."""
+    import oracle as O
+    from synth.configs import union_workload
+    wl = union_workload("union64_264v", 64, 0.016, 264, 1, 1, width=48, height=36, f=39.375)
+    assert wl.T > 256
+    g, cm = O.grid_of(wl), O.cam(wl.cam)
+    td, wd = O.tsdf_dense(g, cm, wl.depth, wl.poses)
+    keys, bt, bw = O.band(g, td, wd)
+    nbr, deg = O.neighbours(wl.G, keys)
+    Lam, b = O.assemble(g, cm, wl.depth, wl.poses, keys, noise=wl.noise)[:2]
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    a = band.arrays()
+    cells = (-(-wl.G // 4)) ** 3
+    print(f"[{wl.T} views] band {a['keys'].shape[0]} voxels, {a['tsdf_voxel_views']} voxel-views fused, "
+          f"{a['tsdf_box_tests']} screening tests", flush=True)
+    assert len(keys) > 0
+    for key, want in (("keys", keys), ("tsdf", bt), ("w", bw), ("nbr", nbr), ("deg", deg)):
+        assert np.array_equal(a[key].cpu().numpy(), want), key
+    s = sys_.arrays()
+    assert np.array_equal(s["Lambda"].cpu().numpy(), Lam)
+    assert np.array_equal(s["b"].cpu().numpy(), b)
+    # every cell is tested against each view past the masked ones
+    assert a["tsdf_box_tests"] >= cells * (wl.T - 256)
+    assert 0 < a["tsdf_voxel_views"] < wl.G ** 3 * wl.T
+    sys_.free()
+    band.free()
