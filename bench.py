@@ -100,10 +100,16 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
         return N * (s + 7 * K * s), "B", "hbm"
-    if name == "tsdf_count":  # fused voxel-views + screening tests (counted by the kernel)
+    # screening: one tile test per (16x8x8 block tile, view of the first 256);
+    # the rest of the counted tests are cell tests
+    tile_tests = (-(-G // 16)) * (-(-G // 8)) ** 2 * min(T, 256)
+    if name == "tsdf_count":  # fused voxel-views (counted by the kernel)
         vv = G ** 3 * T if voxel_views is None else voxel_views
-        tests = -(-G // 4) ** 3 * T if box_tests is None else box_tests
-        return vv * TSDF_OPS_PER_VOXEL_VIEW + tests * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
+        return vv * TSDF_OPS_PER_VOXEL_VIEW, "flop", "alu"
+    if name == "tile_screen":
+        return tile_tests * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
+    if name == "cell_screen" and box_tests is not None:
+        return (box_tests - tile_tests) * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
     if name == "assemble":
         return N * T * 45, "flop", "alu"
     return None

@@ -233,7 +233,7 @@ __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr&
 // needs no cell tests and a tile-level kViewFar marks the view as
 // contributing for every cell (a cell the view does not in fact observe gets
 // no observation from it in the fused loop); only the kViewMay views, and
-// views past kTileViews, are tested cell by cell here.
+// views past kTileViews, are tested cell by cell (k_cell_screen).
 constexpr int kCells = kTile / 64;  // 4^3 cells per block tile; one wave fuses one cell
 constexpr int kMaskWords = 8;
 constexpr int kTileViews = 32 * kMaskWords;
@@ -273,34 +273,36 @@ __global__ __launch_bounds__(256) void k_tile_screen(bf_grid_k g, bf_cam_k c, in
   }
 }
 
-__global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
-                                                    const float* __restrict__ depth,
-                                                    const double* __restrict__ poses,
-                                                    uint64_t total, double* __restrict__ dense_t,
-                                                    int32_t* __restrict__ dense_w,
-                                                    uint32_t* __restrict__ counts, int screen, Pyr P,
-                                                    const float* __restrict__ dmin,
-                                                    const float* __restrict__ dmax,
-                                                    const uint32_t* __restrict__ tmask,
-                                                    uint2* __restrict__ work, uint32_t* __restrict__ cellmask) {
+// Cell tests of one block tile: each cell starts with the tile's kViewFar
+// views marked, then is tested against the tile's kViewMay views (in view
+// order) and every view past kTileViews.  Writes the tile's live-cell bits
+// and, for its live cells only (the only ones read), the view masks
+// cmask[tile][cell][word]; the test count goes to the high word of work[tile].
+__global__ __launch_bounds__(256) void k_cell_screen(bf_grid_k g, bf_cam_k c, int32_t T,
+                                                     const float* __restrict__ depth,
+                                                     const double* __restrict__ poses, uint64_t total, Pyr P,
+                                                     const float* __restrict__ dmin,
+                                                     const float* __restrict__ dmax,
+                                                     const uint32_t* __restrict__ tmask,
+                                                     uint32_t* __restrict__ cmask, uint32_t* __restrict__ live_bits,
+                                                     uint2* __restrict__ work) {
 #pragma clang fp contract(off)
-  __shared__ uint32_t wave_cnt[kThreads / 64], wave_fused[kThreads / 64], wave_tests[kThreads / 64];
   __shared__ int live[kCells];
   __shared__ uint32_t vmask[kCells][kMaskWords];
   __shared__ uint32_t may_w[kMaskWords];
   __shared__ int may_pre[kMaskWords + 1];
+  __shared__ uint32_t wave_tests[kThreads / 64];
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const int64_t plane = (int64_t)c.W * c.H;
   const int32_t tv = min(T, kTileViews);  // views the tile screen tested
   const int tvw = (tv + 31) >> 5;
   const uint32_t* tm = tmask + (int64_t)blockIdx.x * (2 * kMaskWords);
-  // every cell starts with the tile's kViewFar views marked
-  if (threadIdx.x < kCells) live[threadIdx.x] = screen ? 0 : 1;
+  if (threadIdx.x < kCells) live[threadIdx.x] = 0;
   if (threadIdx.x < kCells * kMaskWords) {
     const int w = threadIdx.x % kMaskWords;
-    vmask[threadIdx.x / kMaskWords][w] = screen ? (w < tvw ? tm[w] : 0u) : ~0u;
+    vmask[threadIdx.x / kMaskWords][w] = w < tvw ? tm[w] : 0u;
   }
-  if (screen && threadIdx.x == 0) {
+  if (threadIdx.x == 0) {
     int acc = 0;
     for (int w = 0; w < kMaskWords; ++w) {
       const uint32_t mw = w < tvw ? tm[kMaskWords + w] : 0u;
@@ -312,34 +314,70 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
   }
   __syncthreads();
   uint32_t tests = 0;
-  if (screen) {
-    // cell tests: the tile's kViewMay views in view order, then every view past kTileViews
-    const int nm_tile = may_pre[kMaskWords];
-    const int nm = nm_tile + (T - tv);
-    for (int e = threadIdx.x; e < kCells * nm; e += kThreads) {
-      const int cell = e % kCells, r = e / kCells;
-      int t;
-      if (r < nm_tile) {  // the r-th set bit of the kViewMay mask
-        int w = 0;
-        while (may_pre[w + 1] <= r) ++w;
-        uint32_t x = may_w[w];
-        for (int q = r - may_pre[w]; q > 0; --q) x &= x - 1u;
-        t = 32 * w + __builtin_ctz(x);
-      } else {
-        t = tv + (r - nm_tile);
-      }
-      const uint64_t m0 = base + (uint64_t)cell * 64;
-      if (m0 >= total) continue;
-      const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
-                    k0 = (int32_t)bf_compact3(m0 >> 2);
-      if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
-      ++tests;
-      const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0, 4, 4, 4);
-      if (cls != kViewNone && t < kTileViews) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
-      if (cls == kViewMay) atomicOr(&live[cell], 1);
+  const int nm_tile = may_pre[kMaskWords];
+  const int nm = nm_tile + (T - tv);
+  for (int e = threadIdx.x; e < kCells * nm; e += kThreads) {
+    const int cell = e % kCells, r = e / kCells;
+    int t;
+    if (r < nm_tile) {  // the r-th set bit of the kViewMay mask
+      int w = 0;
+      while (may_pre[w + 1] <= r) ++w;
+      uint32_t x = may_w[w];
+      for (int q = r - may_pre[w]; q > 0; --q) x &= x - 1u;
+      t = 32 * w + __builtin_ctz(x);
+    } else {
+      t = tv + (r - nm_tile);
     }
-    __syncthreads();
+    const uint64_t m0 = base + (uint64_t)cell * 64;
+    if (m0 >= total) continue;
+    const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
+                  k0 = (int32_t)bf_compact3(m0 >> 2);
+    if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
+    ++tests;
+    const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0, 4, 4, 4);
+    if (cls != kViewNone && t < kTileViews) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
+    if (cls == kViewMay) atomicOr(&live[cell], 1);
   }
+  for (int off = 32; off > 0; off >>= 1) tests += __shfl_xor(tests, off, 64);
+  if ((threadIdx.x & 63) == 0) wave_tests[threadIdx.x >> 6] = tests;
+  __syncthreads();
+  if (threadIdx.x < kCells * kMaskWords && live[threadIdx.x / kMaskWords])
+    cmask[(int64_t)blockIdx.x * (kCells * kMaskWords) + threadIdx.x] =
+        vmask[threadIdx.x / kMaskWords][threadIdx.x % kMaskWords];
+  if (threadIdx.x == 0) {
+    uint32_t lm = 0, n = 0;
+    for (int q = 0; q < kCells; ++q) lm |= live[q] ? 1u << q : 0u;
+    for (int w = 0; w < kThreads / 64; ++w) n += wave_tests[w];
+    live_bits[blockIdx.x] = lm;
+    reinterpret_cast<uint32_t*>(work)[2 * blockIdx.x + 1] = n;
+  }
+}
+
+// Fusion of one block tile over the views the cell masks keep (all views
+// without screening); see the comment above kCells.
+__global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int32_t T,
+                                                    const float* __restrict__ depth,
+                                                    const double* __restrict__ poses,
+                                                    uint64_t total, double* __restrict__ dense_t,
+                                                    int32_t* __restrict__ dense_w,
+                                                    uint32_t* __restrict__ counts, int screen,
+                                                    const uint32_t* __restrict__ cmask,
+                                                    const uint32_t* __restrict__ live_bits,
+                                                    uint2* __restrict__ work, uint32_t* __restrict__ cellmask) {
+#pragma clang fp contract(off)
+  __shared__ uint32_t wave_cnt[kThreads / 64], wave_fused[kThreads / 64];
+  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  const int64_t plane = (int64_t)c.W * c.H;
+  const uint32_t lm = screen ? live_bits[blockIdx.x] : (1u << kCells) - 1u;
+  if (lm == 0) {  // no live cell: nothing fused, stored or counted
+    if (threadIdx.x == 0) {
+      counts[blockIdx.x] = 0;
+      reinterpret_cast<uint32_t*>(work)[2 * blockIdx.x] = 0;
+      cellmask[blockIdx.x] = 0;
+    }
+    return;
+  }
+  const uint32_t* cm = cmask + (int64_t)blockIdx.x * (kCells * kMaskWords);
   uint32_t cnt = 0, fused = 0;
   const int nwords = (T + 31) >> 5;
   for (int it = 0; it < kItems; ++it) {
@@ -350,13 +388,13 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
     const int cell = (int)((m - base) >> 6);  // the same for every lane of the wave
     // a screened cell holds no band voxel: its dense values are never read
     // (the scatter skips it by cellmask), so they are not stored either
-    if (!live[cell]) continue;
+    if (!((lm >> cell) & 1u)) continue;
     double tsdf = 0.0;
     int32_t W = 0;
     if (i < g.G && j < g.G && k < g.G) {
       double S = 0.0;
       for (int w = 0; w < nwords; ++w) {
-        uint32_t bits = w < kMaskWords ? vmask[cell][w] : ~0u;
+        uint32_t bits = (screen && w < kMaskWords) ? cm[cell * kMaskWords + w] : ~0u;
         bits = (uint32_t)__builtin_amdgcn_readfirstlane((int)bits);
         if (w == nwords - 1 && (T & 31)) bits &= (1u << (T & 31)) - 1u;
         fused += (uint32_t)__popc(bits);
@@ -401,25 +439,21 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
   for (int off = 32; off > 0; off >>= 1) {
     cnt += __shfl_xor(cnt, off, 64);
     fused += __shfl_xor(fused, off, 64);
-    tests += __shfl_xor(tests, off, 64);
   }
   if ((threadIdx.x & 63) == 0) {
     wave_cnt[threadIdx.x >> 6] = cnt;
     wave_fused[threadIdx.x >> 6] = fused;
-    wave_tests[threadIdx.x >> 6] = tests;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t s = 0, f = 0, n = 0;
+    uint32_t s = 0, f = 0;
     for (int w = 0; w < kThreads / 64; ++w) {
       s += wave_cnt[w];
       f += wave_fused[w];
-      n += wave_tests[w];
     }
     counts[blockIdx.x] = s;
-    work[blockIdx.x] = make_uint2(f, n);
-    uint32_t lm = 0;
-    for (int q = 0; q < kCells; ++q) lm |= live[q] ? 1u << q : 0u;
+    reinterpret_cast<uint32_t*>(work)[2 * blockIdx.x] = f;
+    if (!screen) reinterpret_cast<uint32_t*>(work)[2 * blockIdx.x + 1] = 0;  // no cell tests made
     cellmask[blockIdx.x] = lm;
   }
 }
@@ -705,12 +739,15 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   // flags[0]: depth invalid; then the band count
   void* scan_ws = nullptr;
   // layout: flags and counters (64 B) | counts [nblocks] | offsets [nblocks + 1] | work counts
-  // [nblocks] | tile view masks [nblocks][2][kMaskWords] | live-cell masks [nblocks]
+  // [nblocks] | tile view masks [nblocks][2][kMaskWords] | scattered-cell masks [nblocks] | live-cell
+  // bits [nblocks] | cell view masks [nblocks][kCells][kMaskWords]
   const size_t off_counts = 64, off_offsets = off_counts + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64;
   const size_t off_work = (off_offsets + (nblocks + 1) * sizeof(uint64_t) + 255) / 256 * 256;
   const size_t off_tmask = (off_work + nblocks * sizeof(uint2) + 255) / 256 * 256;
   const size_t off_cmask = off_tmask + nblocks * (2 * kMaskWords * sizeof(uint32_t));
-  const size_t scan_bytes = off_cmask + nblocks * sizeof(uint32_t);
+  const size_t off_live = off_cmask + nblocks * sizeof(uint32_t);
+  const size_t off_vmask = (off_live + nblocks * sizeof(uint32_t) + 255) / 256 * 256;
+  const size_t scan_bytes = off_vmask + nblocks * (kCells * kMaskWords * sizeof(uint32_t));
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
   int* dflags = (int*)scan_ws;
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
@@ -719,6 +756,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   uint2* work = (uint2*)((char*)scan_ws + off_work);
   uint32_t* tmask = (uint32_t*)((char*)scan_ws + off_tmask);
   uint32_t* cellmask = (uint32_t*)((char*)scan_ws + off_cmask);
+  uint32_t* live_bits = (uint32_t*)((char*)scan_ws + off_live);
+  uint32_t* vmask = (uint32_t*)((char*)scan_ws + off_vmask);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, ctx->stream, (uint64_t*)scan_ws, (uint64_t)8, 0ull);
 
   double* dense_t = nullptr;
@@ -775,9 +814,11 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     const int64_t waves = (int64_t)nblocks * ((std::min<int32_t>(T, kTileViews) + 63) / 64);
     BF_LAUNCH(ctx, "tile_screen", k_tile_screen, dim3((unsigned)bf_cdiv(waves, 4)), dim3(256), 0, gk, ck, T,
               (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, tmask);
+    BF_LAUNCH(ctx, "cell_screen", k_cell_screen, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T, depth_dev,
+              c2w_dev, total, pyr, dmin, dmax, tmask, vmask, live_bits, work);
   }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
-                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, pyr, dmin, dmax, tmask, work,
+                     depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, vmask, live_bits, work,
                      cellmask);
   if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
   BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal, work,
