@@ -91,6 +91,8 @@ def lib():
         L.orc_nbv_candidate_u.restype = C.c_int64
         L.orc_nbv_candidate_u.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D,
                                           _I64, C.POINTER(Utility), _D]
+        L.orc_nbv_scores.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _I64, C.c_void_p,
+                                     C.c_int32, _D, _I64, C.c_void_p]
         L.orc_nbv_argmax.restype = C.c_int32
         L.orc_nbv_argmax.argtypes = [C.c_int32, _I64]
         L.orc_features.argtypes = [C.c_int64, C.c_int32, C.c_double, _D, _I32, _I32, _I32, _D, _D,
@@ -435,33 +437,41 @@ def nbv_ray(g: Grid, keys, mu, q, o, d):
     return int(sc), int(steps.value)
 
 
-def nbv_scores(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
+def _nbv_all(g: Grid, ray_cam: Cam, keys, mu, q, cands, which, util=None, steps=False):
+    """Scores (and plain-walk visit counts) of the listed candidates, candidates in parallel."""
     keys = _c(keys, np.uint64)
     mu = _c(mu, np.float64)
     q = _c(q, np.int64)
     cands = _c(cands, np.float64).reshape(-1, 12)
-    idx = range(cands.shape[0]) if which is None else which
-    return np.array([lib().orc_nbv_candidate(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
-                                             np.ascontiguousarray(cands[c]))
-                     for c in idx], dtype=np.int64)
+    if which is not None:
+        cands = np.ascontiguousarray(cands[list(which)])
+    n = cands.shape[0]
+    sc = np.zeros(max(n, 1), dtype=np.int64)
+    st = np.zeros(max(n, 1), dtype=np.int64)
+    lib().orc_nbv_scores(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
+                         C.cast(C.byref(util), C.c_void_p) if util is not None else None, n, cands, sc,
+                         st.ctypes.data if steps else None)
+    return sc[:n], st[:n]
+
+
+def nbv_scores(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
+    """Summed-variance utility of each listed candidate (eq. 13)."""
+    return _nbv_all(g, ray_cam, keys, mu, q, cands, which)[0]
+
+
+def nbv_scores_steps(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
+    """Summed-variance utilities and plain-walk visit counts of the listed candidates."""
+    return _nbv_all(g, ray_cam, keys, mu, q, cands, which, steps=True)
 
 
 def nbv_walk_steps(g: Grid, ray_cam: Cam, keys, mu, q, cands, which=None):
     """Voxels visited by the walks of each listed candidate's rays (as nbv_scores)."""
-    keys = _c(keys, np.uint64)
-    mu = _c(mu, np.float64)
-    q = _c(q, np.int64)
-    cands = _c(cands, np.float64).reshape(-1, 12)
-    idx = range(cands.shape[0]) if which is None else which
-    return np.array([lib().orc_nbv_candidate_steps(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
-                                                   _c(cands[i], np.float64)) for i in idx], dtype=np.int64)
+    return _nbv_all(g, ray_cam, keys, mu, q, cands, which, steps=True)[1]
 
 
 def nbv_scores_var_reduction(g: Grid, ray_cam: Cam, keys, mu, s, cands, noise=(0.0012, 0.0019, 0.4),
                              which=None):
     """Candidate utilities with the expected-variance-reduction utility."""
-    keys = _c(keys, np.uint64)
-    mu = _c(mu, np.float64)
     s = _c(s, np.float64)
     u = Utility()
     u.utility = 1
@@ -469,11 +479,7 @@ def nbv_scores_var_reduction(g: Grid, ray_cam: Cam, keys, mu, s, cands, noise=(0
     u.s = s.ctypes.data
     u.smax = float(max(0.0, float(np.max(s)) if len(s) else 0.0))
     q = np.zeros(max(len(s), 1), dtype=np.int64)
-    cands = _c(cands, np.float64).reshape(-1, 12)
-    idx = range(cands.shape[0]) if which is None else which
-    return np.array([lib().orc_nbv_candidate_u(C.byref(g), C.byref(ray_cam), keys, len(keys), mu, q,
-                                               C.byref(u), np.ascontiguousarray(cands[c]))
-                     for c in idx], dtype=np.int64)
+    return _nbv_all(g, ray_cam, keys, mu, q, cands, which, util=u)[0]
 
 
 def nbv_argmax(scores) -> int:

@@ -182,6 +182,7 @@ static int64_t find_key(const uint64_t* keys, int64_t N, uint64_t key) {
 
 void orc_neighbours(int32_t G, const uint64_t* keys, int64_t N, int32_t* nbr, int32_t* deg) {
   static const int off[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t v = 0; v < N; ++v) {
     int32_t i, j, k;
     orc_morton_decode(keys[v], &i, &j, &k);
@@ -211,6 +212,8 @@ void orc_assemble(const orc_grid* g, const orc_cam* cam, int32_t T, const float*
                   const double* c2w, const orc_noise* nz, const uint64_t* keys, int64_t N,
                   double* Lambda, double* b, double* acc) {
   int64_t plane = (int64_t)cam->width * cam->height;
+  /* voxels are independent; each one's sums run over t in ascending order */
+#pragma omp parallel for schedule(dynamic, 4096)
   for (int64_t v = 0; v < N; ++v) {
     int32_t i, j, k;
     orc_morton_decode(keys[v], &i, &j, &k);
@@ -392,22 +395,31 @@ int32_t orc_probe_sign(uint64_t seed, int32_t k, int64_t i) {
 /* Hutchinson / Bekas diagonal estimator, eq. (12): solve Q u_k = z_k   */
 /* for each probe with the same PCG and average z_k * u_k.              */
 /* ------------------------------------------------------------------ */
+/* The K probe solves are independent and run in parallel (each one is the  */
+/* serial PCG above); their products z_k * u_k are then summed per voxel in */
+/* ascending k, so the result does not depend on the thread count.          */
 void orc_hutchinson(int64_t N, const int32_t* nbr, const double* diag, double lam, int32_t K,
                     uint64_t seed, double tol, int32_t max_iter, double* s_out,
                     int32_t* iters_out) {
-  double* z = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
-  double* u = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
-  for (int64_t v = 0; v < N; ++v) s_out[v] = 0.0;
+  size_t n1 = (size_t)(N > 0 ? N : 1);
+  double* zu = (double*)malloc(sizeof(double) * n1 * (size_t)(K > 0 ? K : 1));
+#pragma omp parallel for schedule(dynamic, 1)
   for (int32_t k = 0; k < K; ++k) {
+    double* z = (double*)malloc(sizeof(double) * n1);
+    double* u = (double*)malloc(sizeof(double) * n1);
     for (int64_t v = 0; v < N; ++v) z[v] = (double)orc_probe_sign(seed, k, v);
     orc_report rep;
     orc_pcg(N, nbr, diag, lam, z, NULL, tol, max_iter, u, &rep);
     if (iters_out) iters_out[k] = rep.iters;
-    for (int64_t v = 0; v < N; ++v) s_out[v] = s_out[v] + z[v] * u[v];
+    for (int64_t v = 0; v < N; ++v) zu[(size_t)k * n1 + (size_t)v] = z[v] * u[v];
+    free(z);
+    free(u);
   }
+  for (int64_t v = 0; v < N; ++v) s_out[v] = 0.0;
+  for (int32_t k = 0; k < K; ++k)
+    for (int64_t v = 0; v < N; ++v) s_out[v] = s_out[v] + zu[(size_t)k * n1 + (size_t)v];
   for (int64_t v = 0; v < N; ++v) s_out[v] = s_out[v] / (double)K;
-  free(z);
-  free(u);
+  free(zu);
 }
 
 /* ------------------------------------------------------------------ */
@@ -548,6 +560,19 @@ int64_t orc_nbv_candidate_steps(const orc_grid* g, const orc_cam* cam, const uin
       orc_nbv_ray_u(g, keys, N, mu, q, NULL, NULL, o, d, &steps);
     }
   return steps;
+}
+
+/* Utilities (or plain-walk visit counts, when steps is not NULL) of n       */
+/* candidates c2w [n][3][4], candidates in parallel.  Each is an exact       */
+/* integer sum, so the thread count cannot change a result.                  */
+void orc_nbv_scores(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                    const double* mu, const int64_t* q, const orc_utility* u, int32_t n,
+                    const double* c2w, int64_t* scores, int64_t* steps) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t c = 0; c < n; ++c) {
+    scores[c] = orc_nbv_candidate_u(g, cam, keys, N, mu, q, u, c2w + 12 * c);
+    if (steps) steps[c] = orc_nbv_candidate_steps(g, cam, keys, N, mu, q, c2w + 12 * c);
+  }
 }
 
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores) {

@@ -99,6 +99,9 @@ int64_t orc_nbv_candidate(const orc_grid* g, const orc_cam* ray_cam, const uint6
 /* Voxels visited by the walks of every ray of one candidate. */
 int64_t orc_nbv_candidate_steps(const orc_grid* g, const orc_cam* ray_cam, const uint64_t* keys, int64_t N,
                                 const double* mu, const int64_t* q, const double* P);
+void orc_nbv_scores(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                    const double* mu, const int64_t* q, const orc_utility* u, int32_t n,
+                    const double* c2w, int64_t* scores, int64_t* steps /* [n] or NULL */);
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores);
 void orc_features(int64_t N, int32_t T, double h, const double* tsdf, const int32_t* w,
                   const int32_t* nbr, const int32_t* deg, const double* Lambda, const double* acc,

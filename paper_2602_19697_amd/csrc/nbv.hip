@@ -38,7 +38,10 @@ __global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64
   }
 }
 
-// q = rint(s / max s * 2^32) >= 0, stored bitwise negated where mu <= 0.
+// q = rint(s / max s * 2^32), stored as 2q + [mu <= 0]: the low bit says the
+// walk stops at this voxel.  q is negative where the estimate s is (eq. 12's
+// Hutchinson estimate is unbiased, not positive), and the arithmetic shift
+// qs >> 1 gives it back exactly for |q| < 2^62.
 __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ s, const double* __restrict__ mu,
                                                   int64_t n, const double* __restrict__ smax,
                                                   int64_t* __restrict__ qs) {
@@ -47,7 +50,7 @@ __global__ __launch_bounds__(256) void k_quantize(const double* __restrict__ s, 
   if (v >= n) return;
   const double m = *smax;
   const int64_t q = m > 0.0 ? (int64_t)rint((s[v] / m) * kScale) : 0;
-  qs[v] = mu[v] <= 0.0 ? ~q : q;
+  qs[v] = (int64_t)((uint64_t)q << 1) | (mu[v] <= 0.0 ? 1 : 0);
 }
 
 struct ray_k {
@@ -96,7 +99,7 @@ __device__ __forceinline__ double plane_t(double org, double h, double o, double
 // voxels skipped hold no band voxel, so the visited band voxels, the utility
 // and the stopping voxel are those of the plain walk.
 //
-// SUM_VAR reads qs[v]: the quantised variance, bitwise negated when the
+// SUM_VAR reads qs[v]: twice the quantised variance, plus one when the
 // voxel's posterior mean is <= 0 (the walk stops there), so one load serves
 // both.  VAR_REDUCTION reads mu and s.
 struct Ray {
@@ -184,11 +187,8 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
       const int32_t v = cl.start + __popcll(cl.mask & ((1ull << m) - 1ull));
       if constexpr (UTIL == BF_UTILITY_SUM_VAR) {
         const int64_t qv = qs[v];
-        if (qv < 0) {
-          r.score += ~qv;
-          return false;
-        }
-        r.score += qv;
+        r.score += qv >> 1;
+        if (qv & 1) return false;
       } else {
         // expected variance reduction of one new observation at the voxel's depth
         const double x = org[0] + ((double)r.idx[0] + 0.5) * g.h;

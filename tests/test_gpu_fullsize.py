@@ -3,8 +3,8 @@
 
 Band keys, TSDF, weights, neighbours, Lambda, b and diag(Q) are compared bit
 for bit over the whole band; the FP64 mean and 32-probe variance in relative
-L2 (<= 1e-6); NBV utilities bit for bit on a sample of candidates whose rays
-the oracle walks one by one, with shared (mu, s) inputs.
+L2 (<= 1e-6); the NBV utilities of all 512 candidates and their argmax bit
+for bit with shared (mu, s) inputs, and the walk's voxel-visit count.
 """
 import numpy as np
 import pytest
@@ -65,23 +65,23 @@ def test_fullsize_mean_and_variance(full):
     assert err_mum <= 1e-4 and err_sm <= 1e-4
 
 
-def test_fullsize_nbv_sampled_bitexact(full):
+def test_fullsize_nbv_all_candidates_bitexact(full):
+    """All 512 candidate utilities (eq. 13) and the argmax, bit for bit, with
+    shared (mu, s); then the visit count of every ray of every candidate."""
     import oracle as O
     wl, ref, ctx, band, sys_ = full
     mu, _ = O.pcg(ref["nbr"], ref["diag"], wl.lam, ref["rhs"], 1e-6)
     s = O.hutchinson(ref["nbr"], ref["diag"], wl.lam, 4, 0, 1e-6)
     cands = wl.candidates()
-    scores, best = ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV),
-                                    torch.from_numpy(np.ascontiguousarray(cands)).to(gc.DEV), wl.ray_cam)
+    mu_d, s_d = torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV)
+    scores, best = ctx.bf_nbv_score(band, mu_d, s_d, torch.from_numpy(np.ascontiguousarray(cands)).to(gc.DEV),
+                                    wl.ray_cam)
     got = scores.cpu().numpy()
-    assert best == int(np.argmax(got))  # numpy argmax takes the first maximum
+    steps_gpu = ctx.bf_nbv_walk_steps()
     q = O.quantize_variance(s)
-    sample = sorted({0, 1, 255, 511, best, int(np.argmin(got))})
-    want = O.nbv_scores(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=sample)
-    print(f"[union256] NBV best={best} sample={sample} scores={got[sample]}")
-    assert np.array_equal(got[sample], want)
-    one = torch.from_numpy(np.ascontiguousarray(cands[best:best + 1])).to(gc.DEV)
-    ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV), one, wl.ray_cam)
-    steps = O.nbv_walk_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands, which=[best])[0]
-    print(f"[union256] candidate {best}: walk steps {ctx.bf_nbv_walk_steps()} (oracle {steps})")
-    assert ctx.bf_nbv_walk_steps() == steps
+    want, steps = O.nbv_scores_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands)
+    print(f"[union256] NBV best={best} (oracle {O.nbv_argmax(want)}) max={got.max()} "
+          f"walk steps {steps_gpu} (oracle {int(steps.sum())})", flush=True)
+    assert len(got) == 512 and np.array_equal(got, want)
+    assert best == O.nbv_argmax(want)
+    assert steps_gpu == int(steps.sum())

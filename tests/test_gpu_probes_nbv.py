@@ -197,3 +197,34 @@ def test_nbv_odd_ray_cameras(ctx, W, H):
     assert steps == int(O.nbv_walk_steps(ref["grid"], O.cam(rc), ref["keys"], mu, q, cands, which=[3])[0])
     sys_.free()
     band.free()
+
+
+def test_nbv_negative_variance_estimates(ctx):
+    """The Hutchinson estimate (eq. 12) is unbiased, not positive: with one probe at
+    lam = 1e6 on tiny, 344 of 3957 estimates are negative (210 of them where mu <= 0).
+    Their quantised values enter the utility with their sign, and only mu <= 0 ends
+    a ray; scores and argmax equal the oracle's bit for bit, for every candidate."""
+    import oracle as O
+    wl = gc.workload("tiny")
+    ref = gc.oracle_ref("tiny")
+    lam = 1e6
+    diag = O.precision_diag(ref["Lambda"], ref["deg"], lam, wl.eps)
+    mu, _ = O.pcg(ref["nbr"], diag, lam, ref["rhs"], 1e-10)
+    s = O.hutchinson(ref["nbr"], diag, lam, 1, 0, 1e-10)
+    assert (s < 0).sum() > 100 and ((s < 0) & (mu <= 0)).sum() > 50 and ((s < 0) & (mu > 0)).sum() > 50
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, lam=lam)
+    cands = wl.candidates()
+    scores, best = ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV),
+                                    torch.from_numpy(np.ascontiguousarray(cands)).to(gc.DEV), wl.ray_cam)
+    q = O.quantize_variance(s)
+    want = O.nbv_scores(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands)
+    got = scores.cpu().numpy()
+    print(f"[tiny lam=1e6 K=1] {int((s < 0).sum())} negative estimates; best={best} scores min={got.min()}")
+    assert np.array_equal(got, want)
+    assert best == O.nbv_argmax(want)
+    # all-negative variances: max(0, max s) = 0, every q is 0 and every score 0
+    z, b0 = ctx.bf_nbv_score(band, torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(-np.abs(s)).to(gc.DEV),
+                             torch.from_numpy(np.ascontiguousarray(cands[:8])).to(gc.DEV), wl.ray_cam)
+    assert not z.cpu().numpy().any() and b0 == 0
+    sys_.free()
+    band.free()
