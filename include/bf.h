@@ -293,6 +293,28 @@ bf_status bf_surface_metrics(bf_ctx* ctx, const double* pred_dev, int64_t n_pred
 bf_status bf_pcg_solve(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
                        const double* rhs_dev, double* x_dev, bf_solve_report* rep);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * solve as bf_pcg_solve, same kernels and results, with every temporary (the
+ * CG vectors r, z, p, q, the float correction, block partials and the solver
+ * state) in one static device array of BF_PCG_NOALLOC_BYTES per GPU.  That
+ * array is loaded with the library's code object and held until the process
+ * ends; its address is looked up once per device by bf_create.  The caller
+ * still passes rhs and x.  The call allocates nothing (no device, pinned or
+ * pooled memory, no events): the solver state is read back into host stack
+ * memory, per-kernel timing records are not taken and rep->seconds is host
+ * time.  Every call on one GPU shares that GPU's array, so calls that overlap
+ * on one GPU (from several contexts, streams or threads) race; the array keeps
+ * the last call's contents and each call initialises what it reads.
+ * Errors: as bf_pcg_solve, plus CAPACITY when the system needs more scratch
+ * than the array holds (bf_pcg_noalloc_max_n gives the largest N per
+ * precision: about 1.67M voxels in FP64, 2.79M mixed). */
+#define BF_PCG_NOALLOC_BYTES (64u << 20)
+bf_status bf_pcg_solve_noalloc(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
+                               const double* rhs_dev, double* x_dev, bf_solve_report* rep);
+/* Largest band size bf_pcg_solve_noalloc accepts in the given precision. */
+int64_t bf_pcg_noalloc_max_n(int32_t precision);
+
 /* Sec. 3.7, eq. (12), Algorithm 1 step 6: s_dev [N] = (1/K) sum_k z_k * u_k
  * with Q u_k = z_k, all K probe solves run together as one block CG whose
  * columns keep their own alpha/beta and stop independently.  logvar_dev

@@ -374,8 +374,7 @@ class Context:
                                           float(lr), float(beta1), float(beta2), float(eps)))
 
     # ---------------------------------------------------------- solves
-    def bf_pcg_solve(self, sys: System, tol, max_iter=10000, precision=L.BF_PREC_FP64, x0=None,
-                     rhs=None, check_every=0, out=None, allow_fail=False):
+    def _pcg(self, fn, sys, tol, max_iter, precision, x0, rhs, check_every, out, allow_fail):
         o = L.bf_solve_opts()
         o.tol, o.max_iter, o.precision = float(tol), int(max_iter), int(precision)
         o.use_x0 = 1 if x0 is not None else 0
@@ -384,9 +383,24 @@ class Context:
         if x0 is not None and x0.data_ptr() != x.data_ptr():
             x.copy_(x0)
         rep = L.bf_solve_report()
-        st = self.lib.bf_pcg_solve(self.handle, sys.handle, C.byref(o), _ptr(rhs), _ptr(x), C.byref(rep))
+        st = fn(self.handle, sys.handle, C.byref(o), _ptr(rhs), _ptr(x), C.byref(rep))
         self._check(st, allow=(L.BF_ERR_NOT_CONVERGED, L.BF_ERR_BREAKDOWN) if allow_fail else ())
         return x, rep.as_dict()
+
+    def bf_pcg_solve(self, sys: System, tol, max_iter=10000, precision=L.BF_PREC_FP64, x0=None,
+                     rhs=None, check_every=0, out=None, allow_fail=False):
+        return self._pcg(self.lib.bf_pcg_solve, sys, tol, max_iter, precision, x0, rhs, check_every, out,
+                         allow_fail)
+
+    def bf_pcg_solve_noalloc(self, sys: System, tol, max_iter=10000, precision=L.BF_PREC_FP64, x0=None,
+                             rhs=None, check_every=0, out=None, allow_fail=False):
+        """bf_pcg_solve with the library's static per-GPU scratch (no allocation
+        inside the call); pass `out` (and `x0` in it) to allocate nothing here either."""
+        return self._pcg(self.lib.bf_pcg_solve_noalloc, sys, tol, max_iter, precision, x0, rhs, check_every, out,
+                         allow_fail)
+
+    def bf_pcg_noalloc_max_n(self, precision=L.BF_PREC_FP64) -> int:
+        return int(self.lib.bf_pcg_noalloc_max_n(int(precision)))
 
     def bf_diag_estimate(self, sys: System, K, seed, tol, max_iter=10000, precision=L.BF_PREC_FP64,
                          logvar=None, out=None, allow_fail=False):

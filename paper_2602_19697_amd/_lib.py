@@ -132,6 +132,8 @@ SIGNATURES = {
     "bf_apply_Q": (C.c_int, [P, P, P, P]),
     "bf_features": (C.c_int, [P, P, P]),
     "bf_pcg_solve": (C.c_int, [P, P, C.POINTER(bf_solve_opts), P, P, C.POINTER(bf_solve_report)]),
+    "bf_pcg_solve_noalloc": (C.c_int, [P, P, C.POINTER(bf_solve_opts), P, P, C.POINTER(bf_solve_report)]),
+    "bf_pcg_noalloc_max_n": (C.c_int64, [C.c_int32]),
     "bf_diag_estimate": (C.c_int, [P, P, C.POINTER(bf_probe_opts), P, P,
                                    C.POINTER(bf_solve_report)]),
     "bf_nbv_score": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(bf_camera), C.c_int32,

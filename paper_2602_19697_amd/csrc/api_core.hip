@@ -170,6 +170,12 @@ bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream) {
     delete ctx;
     return BF_ERR_HIP;
   }
+  if (bf_pcg_scratch_init(ctx) != BF_OK) {
+    fprintf(stderr, "bf_create: %s\n", ctx->err);
+    (void)hipMemPoolDestroy(ctx->mempool);
+    delete ctx;
+    return BF_ERR_HIP;
+  }
   *out = ctx;
   return BF_OK;
 }

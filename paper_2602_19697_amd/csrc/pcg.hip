@@ -22,6 +22,9 @@
 // back the XCD's L2 each time.
 #include "bf_internal.h"
 
+#include <chrono>
+#include <mutex>
+
 namespace {
 
 constexpr int kThreads = 256;
@@ -350,20 +353,52 @@ __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__
   }
 }
 
+// Workspace of one solve of N rows: state | partials [nb][3] | r z p0 p1 q (V)
+// | c (float, mixed precision only).
+size_t pcg_ws_bytes(int64_t N, bool mixed) {
+  const int nb = (int)bf_round8(bf_cdiv(N, kThreads));
+  const size_t vsz = mixed ? 4 : 8;
+  return 256 + ((size_t)nb * 3 * 8 + 255) / 256 * 256 + 5 * (((size_t)N * vsz + 255) / 256 * 256) +
+         (mixed ? ((size_t)N * 4 + 255) / 256 * 256 : 0);
+}
+
+// The workspace of bf_pcg_solve_noalloc: one array per GPU, loaded with the
+// code object and kept until the process ends.  Host code never names it
+// directly: its device address comes from hipGetSymbolAddress (per device,
+// in bf_create) and is passed to the kernels like any workspace.
+constexpr size_t kNoallocBytes = (size_t)BF_PCG_NOALLOC_BYTES;
+__device__ __align__(256) char scratch[kNoallocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Disables per-kernel timing records for one call (they would allocate
+// events) and restores the setting on every return path.
+struct TimingOff {
+  bf_ctx* ctx;
+  int saved;
+  explicit TimingOff(bf_ctx* c) : ctx(c), saved(c->timing) { c->timing = 0; }
+  ~TimingOff() { ctx->timing = saved; }
+};
+
+// fixed_ws == nullptr: the context's workspace, pinned host staging and
+// pooled events (the allocating path of bf_pcg_solve).  Otherwise every
+// temporary lives in fixed_ws (pcg_ws_bytes of it), the state comes back
+// through a stack copy and the solve time is taken on the host.
 template <typename V>
 bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, const double* rhs, double* x,
-                  bf_solve_report* rep) {
+                  bf_solve_report* rep, char* fixed_ws = nullptr) {
   const int64_t N = sys->n;
   // one workgroup per 256 rows, a multiple of 8 workgroups (XCD-contiguous row ranges)
   const int nb = (int)bf_round8(bf_cdiv(N, kThreads));
   const bool mixed = sizeof(V) == 4;
-  // workspace: state | partials [nb][3] | r z p0 p1 q (V) | c (float, mixed)
+  const bool noalloc = fixed_ws != nullptr;
   const size_t st_bytes = 256;
   const size_t part_bytes = ((size_t)nb * 3 * 8 + 255) / 256 * 256;
   const size_t vec_bytes = ((size_t)N * sizeof(V) + 255) / 256 * 256;
-  const size_t c_bytes = mixed ? ((size_t)N * 4 + 255) / 256 * 256 : 0;
-  char* ws = nullptr;
-  BF_TRY(bf_ws(ctx, bf_ctx::WS_PCG, st_bytes + part_bytes + 5 * vec_bytes + c_bytes, (void**)&ws));
+  char* ws = fixed_ws;
+  if (!noalloc) BF_TRY(bf_ws(ctx, bf_ctx::WS_PCG, pcg_ws_bytes(N, mixed), (void**)&ws));
   PcgState* st = (PcgState*)ws;
   double* part = (double*)(ws + st_bytes);
   V* r = (V*)(ws + st_bytes + part_bytes);
@@ -382,9 +417,14 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   const int fb = std::min(nb, 4096);
 
   // solve-time events from the context's pool (no create / destroy per call)
-  hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
-  if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
-  BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!noalloc) {
+    e0 = bf_event_get(ctx);
+    e1 = bf_event_get(ctx);
+    if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
+    BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  }
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, ctx->stream, st, o->tol, o->max_iter, replace_every,
                      inner);
   if (!o->use_x0) hipLaunchKernelGGL(k_fill<double>, dim3(fb), dim3(256), 0, ctx->stream, x, N, 0.0);
@@ -405,8 +445,9 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   BF_TRY(bf_launch_check(ctx, "pcg init"));
 
-  PcgState* hs = nullptr;
-  BF_TRY(bf_pinned(ctx, sizeof(PcgState), (void**)&hs));
+  PcgState hs_local;
+  PcgState* hs = &hs_local;
+  if (!noalloc) BF_TRY(bf_pinned(ctx, sizeof(PcgState), (void**)&hs));
   int it = 0;
   int next = o->check_every > 0 ? o->check_every : 3;
   V* pa = p0;
@@ -443,7 +484,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
       fin_rec = ctx->recs.size();
       residual((int)MODE_REPORT, (const double*)x);
       BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
-      BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+      if (e1) BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -455,14 +496,18 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
     residual((int)MODE_REPORT, (const double*)x);
     BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
-    BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
+    if (e1) BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
   }
   float ms = 0.0f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  ctx->pool.push_back(e0);
-  ctx->pool.push_back(e1);
+  if (noalloc) {
+    ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  } else {
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    ctx->pool.push_back(e0);
+    ctx->pool.push_back(e1);
+  }
   if (ctx->timing && hs->iters >= 0 && (size_t)hs->iters < iter_rec.size())
     bf_timing_mark_idle(ctx, iter_rec[hs->iters], loop_rec_end);
   bf_status status = (bf_status)hs->status;
@@ -487,6 +532,60 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
 }
 
 }  // namespace
+
+// Called by bf_create with ctx->device current: the device address of this
+// GPU's copy of `scratch`, looked up once per device.
+bf_status bf_pcg_scratch_init(bf_ctx* ctx) {
+  if (ctx->device < 0 || ctx->device >= kMaxDevices)
+    return bf_fail(ctx, BF_ERR_INVALID_ARG, "device %d beyond the %d the library tracks", ctx->device, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[ctx->device]) {
+    void* p = nullptr;
+    BF_HIP(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return bf_fail(ctx, BF_ERR_HIP, "hipGetSymbolAddress returned no address for the solver scratch");
+    g_scratch_ptr[ctx->device] = p;
+  }
+  ctx->pcg_scratch = g_scratch_ptr[ctx->device];
+  return BF_OK;
+}
+
+extern "C" bf_status bf_pcg_solve_noalloc(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
+                                          const double* rhs_dev, double* x_dev, bf_solve_report* rep) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys && opts, "bf_pcg_solve_noalloc: NULL argument");
+  BF_CHECK(ctx, opts->tol >= 0.0 && opts->max_iter >= 0, "bf_pcg_solve_noalloc: tol and max_iter must be >= 0");
+  BF_CHECK(ctx, opts->precision == BF_PREC_FP64 || opts->precision == BF_PREC_MIXED,
+           "bf_pcg_solve_noalloc: unknown precision %d", opts->precision);
+  if (rep) *rep = bf_solve_report{};
+  if (sys->n == 0) return BF_OK;
+  BF_CHECK(ctx, x_dev, "bf_pcg_solve_noalloc: NULL x");
+  const bool mixed = opts->precision == BF_PREC_MIXED;
+  const size_t need = pcg_ws_bytes(sys->n, mixed);
+  if (need > kNoallocBytes)
+    return bf_fail(ctx, BF_ERR_CAPACITY,
+                   "bf_pcg_solve_noalloc: %lld band voxels need %zu bytes of solver scratch in %s precision; "
+                   "the static scratch holds %zu (at most %lld voxels in FP64, %lld mixed)",
+                   (long long)sys->n, need, mixed ? "mixed" : "FP64", kNoallocBytes,
+                   (long long)bf_pcg_noalloc_max_n(BF_PREC_FP64), (long long)bf_pcg_noalloc_max_n(BF_PREC_MIXED));
+  if (!ctx->pcg_scratch) return bf_fail(ctx, BF_ERR_HIP, "bf_pcg_solve_noalloc: solver scratch not initialised");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  TimingOff no_records(ctx);
+  const double* rhs = rhs_dev ? rhs_dev : sys->rhs;
+  char* ws = (char*)ctx->pcg_scratch;
+  if (!mixed) return run_pcg<double>(ctx, sys, opts, rhs, x_dev, rep, ws);
+  return run_pcg<float>(ctx, sys, opts, rhs, x_dev, rep, ws);
+}
+
+extern "C" int64_t bf_pcg_noalloc_max_n(int32_t precision) {
+  const bool mixed = precision == BF_PREC_MIXED;
+  int64_t lo = 0, hi = (int64_t)(kNoallocBytes / (mixed ? 24 : 40)) + 1;
+  while (lo < hi) {  // largest N whose workspace fits
+    const int64_t mid = lo + (hi - lo + 1) / 2;
+    if (pcg_ws_bytes(mid, mixed) <= kNoallocBytes) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 extern "C" bf_status bf_pcg_solve(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* opts,
                                   const double* rhs_dev, double* x_dev, bf_solve_report* rep) {
