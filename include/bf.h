@@ -109,7 +109,10 @@ typedef struct bf_solve_report {
   int32_t iters;            /* CG iterations (the largest over probe columns) */
   int32_t status;           /* bf_status of the solve */
   int32_t refinements;      /* FP64 residual corrections taken (mixed precision) */
-  int32_t used_warm_start;  /* 1 if the supplied start was kept */
+  int32_t used_warm_start;  /* 1 if a start was supplied and kept.  A supplied start whose FP64
+                               residual ||rhs - Q x0|| is not below ||rhs|| (no better than
+                               zero) is dropped and that solve (or probe column) runs from
+                               x = 0; this is 0 if any column's start was dropped. */
   double rel_res;           /* final FP64 ||rhs - Q x|| / ||rhs|| (max over columns) */
   double seconds;           /* device time of the solve */
   int64_t col_iters;        /* iterations summed over right-hand sides (probe columns) */
@@ -159,10 +162,27 @@ typedef struct bf_system_arrays {
 
 /* ---------------------------------------------------------------- context */
 
+/* Device memory for the arrays that bands, systems and meshes own (the
+ * objects the caller keeps and frees).  alloc returns a device pointer of at
+ * least `bytes` bytes on the context's device, usable in the order of work on
+ * `hip_stream` (the context's stream), or NULL on failure (the call then
+ * fails with BF_ERR_OOM); release hands a pointer back once the work queued on
+ * `hip_stream` before the call no longer needs it.  Both are called on the
+ * thread that makes the library call, with `user` passed through; a caller can
+ * route them to its framework's caching allocator (torch's, for instance). */
+typedef struct bf_allocator {
+  void* user;
+  void* (*alloc)(void* user, size_t bytes, void* hip_stream);
+  void (*release)(void* user, void* ptr, void* hip_stream);
+} bf_allocator;
+
 /* Create a context on HIP device `device` that orders its work on
- * `hip_stream` (a hipStream_t, NULL = the null stream).  The context owns a
- * reusable device workspace and a pinned host staging buffer. */
-bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream);
+ * `hip_stream` (a hipStream_t, NULL = the null stream).  alloc (copied; NULL =
+ * the library's own stream-ordered pool, which keeps freed memory for reuse)
+ * provides the memory of bands, systems and meshes.  The context owns
+ * reusable device workspaces (from its pool) and a pinned host staging
+ * buffer. */
+bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream, const bf_allocator* alloc);
 bf_status bf_destroy(bf_ctx* ctx);
 /* Change the stream later calls are ordered on. */
 bf_status bf_set_stream(bf_ctx* ctx, void* hip_stream);
@@ -409,6 +429,14 @@ bf_status bf_mlp_forward(bf_ctx* ctx, const float* params_dev, const float* feat
  * logvar_dev [N] = o1 (probe start for bf_diag_estimate); either may be NULL. */
 bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const float* params_dev,
                         const float* feat_dev, double* x0_dev, float* logvar_dev);
+/* Training targets of the network from the method's own solves of sys:
+ * target_dev [N][2] float = ((mu - rhs/diag) / h, log(clamp(s * diag,
+ * clamp_lo, clamp_hi))), with mu_dev [N] a converged mean (eq. 11) and s_dev
+ * [N] a Hutchinson estimate of diag(Q^-1) (eq. 12); the clamp keeps the log
+ * finite where a few-probe estimate is not positive.  Voxel-centric systems;
+ * 0 < clamp_lo <= clamp_hi.  Asynchronous. */
+bf_status bf_warm_start_targets(bf_ctx* ctx, const bf_system* sys, const double* mu_dev, const double* s_dev,
+                                double clamp_lo, double clamp_hi, float* target_dev);
 /* Gradient of L = 1/(2M) sum_m |o_m - t_m|^2 (outputs and targets in the
  * standardised units (t - out_mean) / out_std) over the batch rows idx_dev[M]
  * of feat_dev [nrows][12] / target_dev [nrows][2]; rows outside [0, nrows)

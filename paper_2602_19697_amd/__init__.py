@@ -185,10 +185,33 @@ class System:
             self.handle = None
 
 
-class Context:
-    """One bf_ctx on a torch CUDA (HIP) device, ordered on torch's current stream."""
+def _torch_allocator(idx):
+    """A bf_allocator that hands out torch's caching-allocator memory on device
+    idx (blocks are cached by torch and reused on the context's stream)."""
+    def alloc(user, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=idx, stream=int(stream or 0))
+        except Exception:  # torch raises on out-of-memory: the library reports BF_ERR_OOM
+            return None
 
-    def __init__(self, device="cuda:0", stream=None):
+    def release(user, ptr, stream):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = L.bf_allocator()
+    a.user = None
+    a.alloc = L.ALLOC_FN(alloc)
+    a.release = L.RELEASE_FN(release)
+    return a
+
+
+class Context:
+    """One bf_ctx on a torch CUDA (HIP) device, ordered on torch's current stream.
+
+    allocator="torch" (default) gives the memory of bands, systems and meshes
+    from torch's caching allocator (through the C ABI's bf_allocator hook);
+    allocator=None leaves it to the library's own stream-ordered pool."""
+
+    def __init__(self, device="cuda:0", stream=None, allocator="torch"):
         self.lib = L.load()
         self.device = torch.device(device)
         if self.device.type != "cuda":
@@ -197,8 +220,17 @@ class Context:
         self.device = torch.device("cuda", idx)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.stream = s
+        if isinstance(allocator, L.bf_allocator):
+            self._alloc = allocator  # a caller's own provider (kept alive with the context)
+        elif allocator == "torch":
+            self._alloc = _torch_allocator(idx)
+        elif allocator is None:
+            self._alloc = None
+        else:
+            raise ValueError("allocator must be 'torch', None or a bf_allocator")
         h = C.c_void_p()
-        st = self.lib.bf_create(C.byref(h), idx, C.c_void_p(s.cuda_stream))
+        st = self.lib.bf_create(C.byref(h), idx, C.c_void_p(s.cuda_stream),
+                                C.byref(self._alloc) if self._alloc is not None else None)
         if st != 0:
             raise BFError(st, "bf_create failed")
         self.handle = h
@@ -361,6 +393,12 @@ class Context:
         lv = torch.empty(sys.n, dtype=torch.float32, device=self.device) if logvar else None
         self._check(self.lib.bf_warm_start(self.handle, sys.handle, _ptr(params), _ptr(feat), _ptr(x0), _ptr(lv)))
         return x0, lv
+
+    def bf_warm_start_targets(self, sys: System, mu, s, clamp_lo=1e-3, clamp_hi=1e3, out=None):
+        tgt = out if out is not None else torch.empty((sys.n, 2), dtype=torch.float32, device=self.device)
+        self._check(self.lib.bf_warm_start_targets(self.handle, sys.handle, _ptr(mu), _ptr(s), float(clamp_lo),
+                                                   float(clamp_hi), _ptr(tgt)))
+        return tgt
 
     def bf_mlp_grad(self, params, feat, target, idx, grad=None, loss=None):
         grad = grad if grad is not None else torch.empty(L.BF_MLP_TRAIN, dtype=torch.float32, device=self.device)

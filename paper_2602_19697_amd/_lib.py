@@ -100,6 +100,14 @@ class bf_metrics(C.Structure):
                 ("precision", C.c_double * 8), ("recall", C.c_double * 8), ("fscore", C.c_double * 8)]
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class bf_allocator(C.Structure):
+    _fields_ = [("user", C.c_void_p), ("alloc", ALLOC_FN), ("release", RELEASE_FN)]
+
+
 class bf_kernel_time(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -110,7 +118,7 @@ PP = C.POINTER(C.c_void_p)
 # name: (restype, argtypes)
 SIGNATURES = {
     "bf_version": (C.c_char_p, []),
-    "bf_create": (C.c_int, [PP, C.c_int32, P]),
+    "bf_create": (C.c_int, [PP, C.c_int32, P, C.POINTER(bf_allocator)]),
     "bf_destroy": (C.c_int, [P]),
     "bf_set_stream": (C.c_int, [P, P]),
     "bf_last_error": (C.c_char_p, [P]),
@@ -147,6 +155,7 @@ SIGNATURES = {
                                     C.c_char_p, C.c_size_t]),
     "bf_mlp_forward": (C.c_int, [P, P, P, C.c_int64, P]),
     "bf_warm_start": (C.c_int, [P, P, P, P, P, P]),
+    "bf_warm_start_targets": (C.c_int, [P, P, P, P, C.c_double, C.c_double, P]),
     "bf_mlp_grad": (C.c_int, [P, P, P, P, C.c_int64, P, C.c_int64, P, P]),
     "bf_adam_step": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]),
     "bf_set_timing": (C.c_int, [P, C.c_int32]),

@@ -33,22 +33,53 @@ bf_status bf_dev_alloc(bf_ctx* ctx, void** p, size_t bytes) {
   return BF_OK;
 }
 
-bf_status bf_dev_alloc_parts(bf_ctx* ctx, void** block, std::initializer_list<bf_part> parts) {
-  size_t total = 0;
-  for (const bf_part& q : parts) total += (q.bytes + 255) / 256 * 256;
-  char* base = nullptr;
-  BF_TRY(bf_dev_alloc(ctx, (void**)&base, total));
-  *block = base;
+static void carve(char* base, std::initializer_list<bf_part> parts) {
   size_t off = 0;
   for (const bf_part& q : parts) {
     *q.p = q.bytes ? base + off : nullptr;
     off += (q.bytes + 255) / 256 * 256;
   }
+}
+
+static size_t parts_bytes(std::initializer_list<bf_part> parts) {
+  size_t total = 0;
+  for (const bf_part& q : parts) total += (q.bytes + 255) / 256 * 256;
+  return total;
+}
+
+bf_status bf_dev_alloc_parts(bf_ctx* ctx, void** block, std::initializer_list<bf_part> parts) {
+  char* base = nullptr;
+  BF_TRY(bf_dev_alloc(ctx, (void**)&base, parts_bytes(parts)));
+  *block = base;
+  carve(base, parts);
   return BF_OK;
 }
 
 void bf_dev_free(bf_ctx* ctx, void* p) {
   if (p) (void)hipFreeAsync(p, ctx->stream);
+}
+
+bf_status bf_obj_alloc(bf_ctx* ctx, void** p, size_t bytes) {
+  if (!ctx->objalloc.alloc) return bf_dev_alloc(ctx, p, bytes);
+  *p = nullptr;
+  if (bytes == 0) return BF_OK;
+  *p = ctx->objalloc.alloc(ctx->objalloc.user, bytes, (void*)ctx->stream);
+  if (!*p) return bf_fail(ctx, BF_ERR_OOM, "the caller's allocator returned no memory for %zu bytes", bytes);
+  return BF_OK;
+}
+
+bf_status bf_obj_alloc_parts(bf_ctx* ctx, void** block, std::initializer_list<bf_part> parts) {
+  char* base = nullptr;
+  BF_TRY(bf_obj_alloc(ctx, (void**)&base, parts_bytes(parts)));
+  *block = base;
+  carve(base, parts);
+  return BF_OK;
+}
+
+void bf_obj_free(bf_ctx* ctx, void* p) {
+  if (!p) return;
+  if (ctx->objalloc.release) ctx->objalloc.release(ctx->objalloc.user, p, (void*)ctx->stream);
+  else bf_dev_free(ctx, p);
 }
 
 bf_status bf_ws(bf_ctx* ctx, int slot, size_t bytes, void** out) {
@@ -145,9 +176,10 @@ bf_status bf_get_timings(bf_ctx* ctx, bf_kernel_time* out, int32_t cap, int32_t*
 
 const char* bf_version(void) { return "bayesfusion-gfx950 0.1"; }
 
-bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream) {
+bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream, const bf_allocator* alloc) {
   if (!out) return BF_ERR_INVALID_ARG;
   *out = nullptr;
+  if (alloc && (!alloc->alloc || !alloc->release)) return BF_ERR_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return BF_ERR_INVALID_ARG;
   if (hipSetDevice(device) != hipSuccess) return BF_ERR_HIP;
@@ -155,6 +187,7 @@ bf_status bf_create(bf_ctx** out, int32_t device, void* hip_stream) {
   if (!ctx) return BF_ERR_OOM;
   ctx->device = device;
   ctx->stream = (hipStream_t)hip_stream;
+  if (alloc) ctx->objalloc = *alloc;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
   hipMemPoolProps pp;
@@ -225,9 +258,9 @@ bf_status bf_band_view(const bf_band* band, bf_band_arrays* out) {
 bf_status bf_band_free(bf_ctx* ctx, bf_band* band) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   if (!band) return BF_OK;
-  bf_dev_free(ctx, band->block);
-  bf_dev_free(ctx, band->dense_tsdf);
-  bf_dev_free(ctx, band->dense_w);
+  bf_obj_free(ctx, band->block);
+  bf_obj_free(ctx, band->dense_tsdf);
+  bf_obj_free(ctx, band->dense_w);
   delete band;
   return BF_OK;
 }
@@ -252,7 +285,7 @@ bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out) {
 bf_status bf_system_free(bf_ctx* ctx, bf_system* sys) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   if (!sys) return BF_OK;
-  bf_dev_free(ctx, sys->block);
+  bf_obj_free(ctx, sys->block);
   delete sys;
   return BF_OK;
 }

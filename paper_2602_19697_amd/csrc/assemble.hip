@@ -175,7 +175,7 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
     return st;
   };
   if (N > 0) {
-    if (bf_status s = bf_dev_alloc_parts(ctx, &sys->block,
+    if (bf_status s = bf_obj_alloc_parts(ctx, &sys->block,
                                          {{(void**)&sys->Lambda, (size_t)N * 8}, {(void**)&sys->b, (size_t)N * 8},
                                           {(void**)&sys->rhs, (size_t)N * 8}, {(void**)&sys->diag, (size_t)N * 8},
                                           {(void**)&sys->dinv, (size_t)N * 8}, {(void**)&sys->diag32, (size_t)N * 4},

@@ -763,8 +763,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   double* dense_t = nullptr;
   int32_t* dense_w = nullptr;
   if (flags & BF_BAND_KEEP_DENSE) {
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->dense_tsdf, total * sizeof(double))) return fail(s);
-    if (bf_status s = bf_dev_alloc(ctx, (void**)&band->dense_w, total * sizeof(int32_t))) return fail(s);
+    if (bf_status s = bf_obj_alloc(ctx, (void**)&band->dense_tsdf, total * sizeof(double))) return fail(s);
+    if (bf_status s = bf_obj_alloc(ctx, (void**)&band->dense_w, total * sizeof(int32_t))) return fail(s);
     dense_t = band->dense_tsdf;
     dense_w = band->dense_w;
   } else {
@@ -856,7 +856,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     band->nbrick = std::max(1, band->P >> shift);
     const int64_t nbr3 = (int64_t)band->nbrick * band->nbrick * band->nbrick;
     const size_t words = ((size_t)nbr3 + 31) / 32;
-    if (bf_status s = bf_dev_alloc_parts(
+    if (bf_status s = bf_obj_alloc_parts(
             ctx, &band->block,
             {{(void**)&band->keys, N * sizeof(uint64_t)}, {(void**)&band->tsdf, N * sizeof(double)},
              {(void**)&band->w, N * sizeof(int32_t)}, {(void**)&band->nbr, N * 6 * sizeof(int32_t)},

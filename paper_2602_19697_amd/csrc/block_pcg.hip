@@ -23,8 +23,10 @@ using namespace bt;
 template <int KC>
 constexpr int kRowsPerTile = KC == 1 ? 1024 : 64;
 
-__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner, int32_t replace_every) {
+__global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner, int32_t replace_every,
+                              int32_t guard) {
   state_init(st, K, tol, max_iter, inner, replace_every);
+  if (threadIdx.x == 0) st->guard = guard;
 }
 
 // A: p = zz + beta p_old, q = Q p, per-column partial p.q.
@@ -213,17 +215,23 @@ __global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mod
   __shared__ double lds[4 * 3 * 64];
   if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
   if (mode == MODE_CHECK && st->pending == 0) return;
+  if (mode == MODE_GUARD && st->ndropped == 0) return;
   const int c = threadIdx.x % KC;
-  const bool act = mode == MODE_REPORT ? c < st->K
-                                       : (st->active[c] != 0 &&
-                                          (mode == MODE_INIT || st->check[c] == (mode == MODE_VERIFY ? 2 : 1)));
+  const bool act = mode == MODE_REPORT  ? c < st->K
+                   : mode == MODE_GUARD ? st->dropped[c] != 0
+                                        : (st->active[c] != 0 &&
+                                           (mode == MODE_INIT || st->check[c] == (mode == MODE_VERIFY ? 2 : 1)));
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
   double v3[3] = {0.0, 0.0, 0.0};
+  // GUARD: INIT of the dropped columns from x = 0 (x written as 0, r = z stored)
+  const int tmode = mode == MODE_GUARD ? (int)MODE_INIT : mode;
+  const float* lv = mode == MODE_GUARD ? nullptr : logvar;
+  const bool wx0 = mode == MODE_GUARD || write_x0 != 0, sr = mode == MODE_GUARD || store_r != 0;
   if (act)
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-      tile_resid<V, KC>(c, mode, cs, nbr, diag, lam, logvar, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
-                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, write_x0 != 0, store_r != 0);
+      tile_resid<V, KC>(c, tmode, cs, nbr, diag, lam, lv, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
+                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, wx0, sr);
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
@@ -372,6 +380,7 @@ __global__ __launch_bounds__(256) void k_bscal_R(BState* __restrict__ st, int mo
   if (mode == MODE_VERIFY && !(st->active[c] && st->check[c] == 2)) return;
   if (mode == MODE_REPORT && c >= st->K) return;
   if (mode == MODE_INIT && !st->active[c]) return;
+  if (mode == MODE_GUARD && !st->dropped[c]) return;
   double tot[3];
   col_partials_sum<KC, 3>(part, nb, c, tot, lds);
   if (threadIdx.x == 0) {
@@ -450,7 +459,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
-                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0);
+                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0, logvar ? 1 : 0);
   const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
   // FP64 from x = 0: the zero start is not written; the first B pass takes x
   // as 0 and the estimate takes a column that never iterated as 0.  (Mixed
@@ -471,6 +480,11 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
               sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part,
               zero_start ? 0 : 1, gen_start ? 0 : 1);
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
+  if (logvar) {  // columns whose start was no better than zero restart from x = 0
+    BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_GUARD,
+              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part, 1, 1);
+    BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
+  }
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
   BState* hs = nullptr;
   BF_TRY(bf_pinned(ctx, sizeof(BState), (void**)&hs));
@@ -593,7 +607,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     rep->iters = maxit;
     rep->status = status;
     rep->refinements = hs->refinements;
-    rep->used_warm_start = logvar ? 1 : 0;
+    rep->used_warm_start = (logvar && hs->ndropped == 0) ? 1 : 0;
     rep->rel_res = maxres;
     rep->seconds = ms * 1e-3;
     rep->col_iters = sumit;

@@ -20,7 +20,9 @@ constexpr int kMaxK = 64;
 // VERIFY: residual norms of the columns whose recurrence residual met the
 // tolerance (check == 2), with no stores; CHECK: the residual, stored, of the
 // columns to continue or restart from it (check == 1).
-enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2, MODE_VERIFY = 3 };
+// GUARD: after INIT with a supplied start, the columns whose start was no
+// better than zero (dropped) restart from x = 0.
+enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2, MODE_VERIFY = 3, MODE_GUARD = 4 };
 
 struct BState {
   double rho[kMaxK], alpha[kMaxK], beta[kMaxK], tol2b[kMaxK], rr_true[kMaxK], bnorm2[kMaxK], rr_ref[kMaxK];
@@ -28,7 +30,9 @@ struct BState {
   int32_t active[kMaxK], check[kMaxK], last[kMaxK], iters[kMaxK], status[kMaxK];
   int32_t nactive, any_check, max_iter, replace_every, K, refinements;
   int32_t pending;  // columns with check == 1 (a stored residual is due)
-  int32_t pad_;
+  int32_t guard;    // a start was supplied: drop it where ||z - Q u0|| >= ||z||
+  int32_t dropped[kMaxK];
+  int32_t ndropped, pad_;
 };
 
 // SplitMix64 output n (0-based) of the generator started at `start`.
@@ -50,9 +54,11 @@ __device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_
     st->rho[c] = st->alpha[c] = st->beta[c] = st->rr_true[c] = st->bnorm2[c] = st->rr_ref[c] = 0.0;
     st->tol2b[c] = tol * tol;
     st->active[c] = c < K ? 1 : 0;
-    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = 0;
+    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = st->dropped[c] = 0;
   }
   if (c == 0) {
+    st->guard = 0;
+    st->ndropped = 0;
     st->inner2 = inner * inner;
     st->nactive = K;
     st->any_check = 0;
@@ -346,9 +352,17 @@ __device__ __forceinline__ void decide_V(BState* st, int c, const double (&tot)[
 __device__ __forceinline__ void decide_R(BState* st, int c, int mode, const double (&tot)[3], int* nactive_all) {
   if (mode == MODE_REPORT) {
     st->rr_true[c] = tot[0];
-  } else if (mode == MODE_INIT) {
-    st->bnorm2[c] = tot[2];
-    st->tol2b[c] *= tot[2];
+  } else if (mode == MODE_INIT || mode == MODE_GUARD) {
+    if (mode == MODE_INIT) {
+      st->bnorm2[c] = tot[2];
+      st->tol2b[c] *= tot[2];
+      // a supplied start no better than zero is dropped; GUARD redoes INIT from x = 0
+      if (st->guard && tot[2] > 0.0 && !(tot[0] < tot[2])) {
+        st->dropped[c] = 1;
+        atomicAdd(&st->ndropped, 1);
+        return;
+      }
+    }
     st->rr_true[c] = tot[0];
     if (tot[2] == 0.0 || tot[0] <= st->tol2b[c]) {
       deactivate(st, c, 0, nactive_all);

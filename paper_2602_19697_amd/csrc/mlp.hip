@@ -435,6 +435,22 @@ __global__ __launch_bounds__(256) void k_zero(T* __restrict__ p, int64_t n) {
     p[i] = (T)0;
 }
 
+// Training targets of one band voxel from the method's own solves:
+// o0 = (mu - rhs/diag) / h, o1 = log(clamp(s * diag, lo, hi)), as float.
+__global__ __launch_bounds__(256) void k_targets(const double* __restrict__ mu, const double* __restrict__ s,
+                                                 const double* __restrict__ rhs, const double* __restrict__ diag,
+                                                 double h, double lo, double hi, int64_t n, float* __restrict__ tgt) {
+#pragma clang fp contract(off)
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const double d = diag[v];
+  const double t0 = (mu[v] - rhs[v] / d) / h;
+  const double sd = s[v] * d;
+  const double t1 = log(sd < lo ? lo : (sd > hi ? hi : sd));
+  tgt[2 * v] = (float)t0;
+  tgt[2 * v + 1] = (float)t1;
+}
+
 bf_status pack(bf_ctx* ctx, const float* params, __bf16** wt) {
   BF_TRY(bf_ws(ctx, bf_ctx::WS_MLP, NTILES * 64 * 16, (void**)wt));
   BF_LAUNCH(ctx, "mlp_pack", k_mlp_pack, dim3((NTILES * 512 + 255) / 256), dim3(256), 0, params, *wt);
@@ -473,6 +489,20 @@ extern "C" bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const floa
   BF_LAUNCH(ctx, "mlp_forward", k_mlp_forward, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev, feat_dev, n,
             (float*)nullptr, (const double*)sys->rhs, (const double*)sys->diag, sys->band->h, x0_dev, logvar_dev);
   return bf_launch_check(ctx, "k_mlp_forward");
+}
+
+extern "C" bf_status bf_warm_start_targets(bf_ctx* ctx, const bf_system* sys, const double* mu_dev,
+                                           const double* s_dev, double clamp_lo, double clamp_hi,
+                                           float* target_dev) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys && mu_dev && s_dev && target_dev, "bf_warm_start_targets: NULL argument");
+  BF_CHECK(ctx, sys->kind == BF_SYSTEM_VOXEL, "bf_warm_start_targets: voxel-centric systems only");
+  BF_CHECK(ctx, clamp_lo > 0.0 && clamp_lo <= clamp_hi, "bf_warm_start_targets: need 0 < clamp_lo <= clamp_hi");
+  if (sys->n == 0) return BF_OK;
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  BF_LAUNCH(ctx, "mlp_targets", k_targets, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, mu_dev, s_dev,
+            (const double*)sys->rhs, (const double*)sys->diag, sys->band->h, clamp_lo, clamp_hi, sys->n, target_dev);
+  return bf_launch_check(ctx, "k_targets");
 }
 
 extern "C" bf_status bf_mlp_grad(bf_ctx* ctx, const float* params_dev, const float* feat_dev,

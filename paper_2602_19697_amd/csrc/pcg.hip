@@ -32,20 +32,32 @@ constexpr int kThreads = 256;
 struct PcgState {
   double rho, alpha, beta, tol2b, bnorm2, rr, rr_true, rho_new, inner2, rr_ref;
   int32_t iters, done, check, status, last, refinements, max_iter, replace_every;
-  int32_t pad_[2];
+  int32_t guard;    // a start was supplied: drop it if ||rhs - Q x0|| >= ||rhs||
+  int32_t dropped;  // ... and it was: the solve restarts from x = 0
 };
 
-enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2 };
+// GUARD: after INIT with a supplied start that was dropped, INIT again from x = 0.
+enum { MODE_INIT = 0, MODE_CHECK = 1, MODE_REPORT = 2, MODE_GUARD = 3 };
 
-__global__ void k_state_init(PcgState* st, double tol, int32_t max_iter, int32_t replace_every, double inner) {
+__global__ void k_state_init(PcgState* st, double tol, int32_t max_iter, int32_t replace_every, double inner,
+                             int32_t guard) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     PcgState s{};
     s.tol2b = tol * tol;  // scaled by ||rhs||^2 once known
     s.max_iter = max_iter;
     s.replace_every = replace_every;
     s.inner2 = inner * inner;
+    s.guard = guard;
     *st = s;
   }
+}
+
+// x = 0 where the supplied start was dropped.
+__global__ __launch_bounds__(256) void k_zero_if_dropped(const PcgState* __restrict__ st, double* __restrict__ x,
+                                                         int64_t n) {
+  if (!st->dropped) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = 0.0;
 }
 
 template <typename V>
@@ -225,6 +237,7 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
                                                   double* __restrict__ part) {
   __shared__ double lds[16];
   if (mode == MODE_CHECK && (st->done || !st->check)) return;
+  if (mode == MODE_GUARD && !st->dropped) return;
   const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double rr = 0.0, rz = 0.0, bb = 0.0;
   if (v < n) {
@@ -271,6 +284,7 @@ __global__ __launch_bounds__(256) void k_residual27(PcgState* __restrict__ st, i
                                                     double* __restrict__ part) {
   __shared__ double lds[16];
   if (mode == MODE_CHECK && (st->done || !st->check)) return;
+  if (mode == MODE_GUARD && !st->dropped) return;
   const int64_t v = bf_xcd_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x;
   double rr = 0.0, rz = 0.0, bb = 0.0;
   if (v < n) {
@@ -312,14 +326,24 @@ __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__
                                                           const double* __restrict__ part, int nb) {
   __shared__ double lds[16];
   if (mode == MODE_CHECK && (st->done || !st->check)) return;
+  if (mode == MODE_GUARD && !st->dropped) return;
   double tot[3];
   reduce_partials<3>(part, nb, tot, lds);
   if (threadIdx.x != 0) return;
-  st->rr_true = tot[0];
-  if (mode == MODE_REPORT) return;
-  if (mode == MODE_INIT) {
+  if (mode == MODE_INIT && st->guard && tot[2] > 0.0 && !(tot[0] < tot[2])) {
+    // the supplied start is no better than zero: drop it (GUARD restarts from x = 0)
+    st->dropped = 1;
     st->bnorm2 = tot[2];
     st->tol2b = st->tol2b * tot[2];
+    return;
+  }
+  st->rr_true = tot[0];
+  if (mode == MODE_REPORT) return;
+  if (mode == MODE_INIT || mode == MODE_GUARD) {
+    if (mode == MODE_INIT) {
+      st->bnorm2 = tot[2];
+      st->tol2b = st->tol2b * tot[2];
+    }
     if (tot[2] == 0.0 || tot[0] <= st->tol2b) {
       st->done = 1;
       return;
@@ -426,7 +450,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   }
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, ctx->stream, st, o->tol, o->max_iter, replace_every,
-                     inner);
+                     inner, o->use_x0 ? 1 : 0);
   if (!o->use_x0) hipLaunchKernelGGL(k_fill<double>, dim3(fb), dim3(256), 0, ctx->stream, x, N, 0.0);
   hipLaunchKernelGGL(k_fill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N, (V)0);
   if (mixed) hipLaunchKernelGGL(k_fill<float>, dim3(fb), dim3(256), 0, ctx->stream, c, N, 0.0f);
@@ -443,6 +467,11 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   };
   residual((int)MODE_INIT, o->use_x0 ? (const double*)x : nullptr);
   BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_INIT, part, nb);
+  if (o->use_x0) {  // a start no better than zero is dropped: x = 0 and INIT again
+    hipLaunchKernelGGL(k_zero_if_dropped, dim3(fb), dim3(256), 0, ctx->stream, st, x, N);
+    residual((int)MODE_GUARD, nullptr);
+    BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
+  }
   BF_TRY(bf_launch_check(ctx, "pcg init"));
 
   PcgState hs_local;
@@ -520,7 +549,7 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
     rep->iters = hs->iters;
     rep->status = status;
     rep->refinements = mixed ? hs->refinements : 0;
-    rep->used_warm_start = o->use_x0 ? 1 : 0;
+    rep->used_warm_start = (o->use_x0 && !hs->dropped) ? 1 : 0;
     rep->rel_res = hs->bnorm2 > 0.0 ? sqrt(hs->rr_true / hs->bnorm2) : 0.0;
     rep->seconds = ms * 1e-3;
     rep->col_iters = hs->iters;

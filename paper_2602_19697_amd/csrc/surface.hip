@@ -387,8 +387,8 @@ extern "C" bf_status bf_extract_surface(bf_ctx* ctx, const bf_band* band, const 
   mesh->nv = (int64_t)pin[0] + lastc[0];
   mesh->nt = (int64_t)pin[1] + lastc[1];
   if (mesh->nv >= (1ll << 31)) return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_extract_surface: too many vertices"));
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&mesh->verts, mesh->nv * 3 * sizeof(double))) return fail(s);
-  if (bf_status s = bf_dev_alloc(ctx, (void**)&mesh->tris, mesh->nt * 3 * sizeof(int32_t))) return fail(s);
+  if (bf_status s = bf_obj_alloc(ctx, (void**)&mesh->verts, mesh->nv * 3 * sizeof(double))) return fail(s);
+  if (bf_status s = bf_obj_alloc(ctx, (void**)&mesh->tris, mesh->nt * 3 * sizeof(int32_t))) return fail(s);
   BF_LAUNCH(ctx, "surf_verts", k_surf_verts, dim3(g), dim3(kThreads), 0, S, mask, vstart, mesh->verts);
   BF_LAUNCH(ctx, "surf_tris", k_surf_tris, dim3(g), dim3(kThreads), 0, S, mask, vstart, mesh->verts, tstart,
             mesh->tris);
@@ -411,8 +411,8 @@ extern "C" bf_status bf_mesh_view(const bf_mesh* mesh, bf_mesh_arrays* out) {
 extern "C" bf_status bf_mesh_free(bf_ctx* ctx, bf_mesh* mesh) {
   if (!ctx) return BF_ERR_INVALID_ARG;
   if (!mesh) return BF_OK;
-  bf_dev_free(ctx, mesh->verts);
-  bf_dev_free(ctx, mesh->tris);
+  bf_obj_free(ctx, mesh->verts);
+  bf_obj_free(ctx, mesh->tris);
   delete mesh;
   return BF_OK;
 }

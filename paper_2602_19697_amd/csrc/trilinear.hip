@@ -339,7 +339,7 @@ extern "C" bf_status bf_assemble_trilinear(bf_ctx* ctx, const bf_band* band, con
     *out = sys;
     return BF_OK;
   }
-  if (bf_status s = bf_dev_alloc_parts(ctx, &sys->block,
+  if (bf_status s = bf_obj_alloc_parts(ctx, &sys->block,
                                        {{(void**)&sys->Lambda, (size_t)N * 8}, {(void**)&sys->b, (size_t)N * 8},
                                         {(void**)&sys->rhs, (size_t)N * 8}, {(void**)&sys->diag, (size_t)N * 8},
                                         {(void**)&sys->dinv, (size_t)N * 8}, {(void**)&sys->diag32, (size_t)N * 4},

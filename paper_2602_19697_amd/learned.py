@@ -8,7 +8,7 @@ solves: the FP64 PCG mean (tol 1e-10) and a 64-probe FP64 Hutchinson estimate
 of every training scene.  The solvers always run to their tolerance from the
 proposed start, so the network can only change how many iterations they take.
 
-    python -m paper_2602_19697_amd.learned --lam 10 --out weights.npy
+    python -m paper_2602_19697_amd.learned --lam 10 --out weights.npy [--checkpoint ck.npz [--resume]]
 """
 from __future__ import annotations
 
@@ -79,17 +79,14 @@ def scene_system(ctx: Context, wl, lam: float):
 
 
 def scene_pairs(ctx: Context, wl, lam: float, probes: int = 64, seed: int = 0):
-    """Features [N][12] (device) and targets [N][2] (host) of one scene."""
+    """Features [N][12] (device) and targets [N][2] (host) of one scene: the
+    FP64 mean (tol 1e-10) and a `probes`-probe FP64 Hutchinson estimate, turned
+    into targets by the library (bf_warm_start_targets)."""
     band, sys_ = scene_system(ctx, wl, lam)
     feat = ctx.bf_features(sys_)
     mu, _ = ctx.bf_pcg_solve(sys_, 1e-10, precision=L.BF_PREC_FP64)
     s, _ = ctx.bf_diag_estimate(sys_, probes, seed, 1e-8, precision=L.BF_PREC_FP64)
-    a = sys_.arrays()
-    rhs, diag = a["rhs"].cpu().numpy(), a["diag"].cpu().numpy()
-    mu, s = mu.cpu().numpy(), s.cpu().numpy()
-    t0 = (mu - rhs / diag) / wl.h
-    t1 = np.log(np.clip(s * diag, 1e-3, 1e3))
-    tgt = np.stack([t0, t1], axis=1).astype(np.float32)
+    tgt = ctx.bf_warm_start_targets(sys_, mu, s).cpu().numpy()
     sys_.free()
     band.free()
     return feat, tgt
@@ -102,9 +99,31 @@ def training_scenes(n_sphere: int = 100, n_union: int = 70, n_union256: int = 30
             + [("union256", 100 + s) for s in range(n_union256)])
 
 
+def save_checkpoint(path: str, params, m, v, step: int, rng: np.random.Generator, hist) -> None:
+    """Everything a resumed run needs to continue bit for bit: the FP32
+    parameters, Adam's moments, the step and the minibatch generator's state."""
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, params=params.cpu().numpy(), m=m.cpu().numpy(), v=v.cpu().numpy(), step=np.int64(step),
+             rng=np.frombuffer(json.dumps(rng.bit_generator.state).encode(), dtype=np.uint8),
+             hist=np.asarray(hist, dtype=np.float64).reshape(-1, 2))
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path: str):
+    with np.load(path, allow_pickle=False) as z:
+        state = json.loads(bytes(z["rng"]).decode())
+        return (z["params"], z["m"], z["v"], int(z["step"]), state,
+                [(int(a), float(b)) for a, b in z["hist"]])
+
+
 def train(ctx: Context, feats, tgts_host, steps: int = 3000, batch: int = 16384, lr: float = 2e-3,
-          seed: int = 0, log_every: int = 500):
-    """Adam on minibatches drawn with replacement; returns the FP32 parameters."""
+          seed: int = 0, log_every: int = 500, checkpoint: str = None, checkpoint_every: int = 500,
+          resume: bool = False, stop_at: int = None):
+    """Adam on minibatches drawn with replacement; returns the FP32 parameters.
+    With `checkpoint`, the state is saved every `checkpoint_every` steps and at
+    the end; with `resume`, training continues from that file (same results as
+    an uninterrupted run).  stop_at ends the run early after that step (an
+    interrupted run, to be resumed with the same `steps`)."""
     dev = ctx.device
     feat_host = feats.cpu().numpy()
     params = torch.from_numpy(set_scaling(init_params(seed), feat_host, tgts_host)).to(dev)
@@ -116,7 +135,16 @@ def train(ctx: Context, feats, tgts_host, steps: int = 3000, batch: int = 16384,
     rng = np.random.default_rng(seed)
     n = feats.shape[0]
     hist = []
-    for step in range(1, steps + 1):
+    start = 1
+    if resume and checkpoint and os.path.exists(checkpoint):
+        p0, m0, v0, done, state, hist = load_checkpoint(checkpoint)
+        params = torch.from_numpy(p0).to(dev)
+        m = torch.from_numpy(m0).to(dev)
+        v = torch.from_numpy(v0).to(dev)
+        rng.bit_generator.state = state
+        start = done + 1
+        print(f"[train] resumed at step {done} from {checkpoint}", file=sys.stderr, flush=True)
+    for step in range(start, steps + 1):
         idx = torch.from_numpy(rng.integers(0, n, size=batch).astype(np.int32)).to(dev)
         ctx.bf_mlp_grad(params, feats, tgts, idx, grad, loss)
         rate = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps))  # cosine decay
@@ -124,6 +152,10 @@ def train(ctx: Context, feats, tgts_host, steps: int = 3000, batch: int = 16384,
         if step % log_every == 0 or step == 1:
             hist.append((step, float(loss.item())))
             print(f"[train] step {step} loss {hist[-1][1]:.4f}", file=sys.stderr, flush=True)
+        if checkpoint and (step % checkpoint_every == 0 or step == steps):
+            save_checkpoint(checkpoint, params, m, v, step, rng, hist)
+        if stop_at is not None and step >= stop_at:
+            break
     return params.cpu().numpy(), hist
 
 
@@ -170,8 +202,7 @@ def evaluate(ctx: Context, wl, lam: float, params: np.ndarray, tol: float = 1e-6
         "start_err_learned": float(np.linalg.norm(x0_l.cpu().numpy() - mu_ref_h) / nrm)}
     (_, q0), tq0 = timed(lambda: ctx.bf_diag_estimate(sys_, probes, 0, tol, precision=precision))
     (_, ql), tql = timed(lambda: ctx.bf_diag_estimate(sys_, probes, 0, tol, precision=precision, logvar=lv))
-    diag = sys_.arrays()["diag"].cpu().numpy()
-    lv_ref = np.log(np.clip(s_ref.cpu().numpy() * diag, 1e-3, 1e3))
+    lv_ref = ctx.bf_warm_start_targets(sys_, mu_ref, s_ref)[:, 1].cpu().numpy()
     out["variance"] = {
         "iters_zero": q0["iters"], "iters_learned": ql["iters"], "ms_zero": tq0, "ms_learned": tql,
         "logvar_rmse_learned": float(np.sqrt(np.mean((lv.cpu().numpy() - lv_ref) ** 2))),
@@ -193,6 +224,8 @@ def main():
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--out", required=True)
     ap.add_argument("--report", default=None)
+    ap.add_argument("--checkpoint", default=None, help="training state file, saved every 500 steps")
+    ap.add_argument("--resume", action="store_true", help="continue from --checkpoint")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     ctx = Context(dev)
@@ -211,7 +244,8 @@ def main():
     tgts = np.concatenate(tgts)
     print(f"[data] {feats.shape[0]} voxels from {len(scenes)} scenes",
           file=sys.stderr, flush=True)
-    params, hist = train(ctx, feats, tgts, steps=args.steps, batch=args.batch, lr=args.lr)
+    params, hist = train(ctx, feats, tgts, steps=args.steps, batch=args.batch, lr=args.lr,
+                         checkpoint=args.checkpoint, resume=args.resume)
     np.save(args.out, params)
     report = {"lam": args.lam, "train_voxels": int(feats.shape[0]), "loss_history": hist, "held_out": []}
     for name, seed in (("sphere64", 1000), ("sphere64", 1001), ("union256", 1002)):

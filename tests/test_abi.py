@@ -71,3 +71,4 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(L.bf_solve_opts) == 8 + 16
     assert ctypes.sizeof(L.bf_solve_report) == 16 + 8 + 8 + 8
     assert ctypes.sizeof(L.bf_probe_opts) == 8 + 8 + 8 + 8
+

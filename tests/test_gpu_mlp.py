@@ -136,3 +136,23 @@ def test_adam_matches_oracle(ctx):
     assert np.allclose(tt.cpu().numpy(), th2, rtol=1e-6, atol=1e-7)
     assert np.allclose(tm.cpu().numpy(), m2, rtol=1e-5, atol=1e-10)
     assert np.array_equal(tt.cpu().numpy()[mlp.N_TRAIN:], th[mlp.N_TRAIN:])
+
+
+def test_training_resumes_bit_for_bit(tmp_path):
+    """A run interrupted after 10 of 20 Adam steps and resumed from its
+    checkpoint ends with the same parameters as an uninterrupted run."""
+    import paper_2602_19697_amd as bf
+    from paper_2602_19697_amd import learned
+    ctx = bf.Context(gc.DEV)
+    wl = gc.workload("sphere64")
+    feat, tgt = learned.scene_pairs(ctx, wl, 1e5, probes=4)
+    ck = str(tmp_path / "ck.npz")
+    full, hist_full = learned.train(ctx, feat, tgt, steps=20, batch=2048, log_every=5)
+    part, _ = learned.train(ctx, feat, tgt, steps=20, batch=2048, log_every=5, checkpoint=ck, checkpoint_every=10,
+                            stop_at=10)
+    assert not np.array_equal(part, full)
+    resumed, hist_res = learned.train(ctx, feat, tgt, steps=20, batch=2048, log_every=5, checkpoint=ck,
+                                      checkpoint_every=10, resume=True)
+    assert np.array_equal(resumed, full)
+    assert hist_res == hist_full
+    ctx.close()
