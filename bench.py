@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the narrow-band Bayesian SDF solve on one MI355X.
 
-One step is one pass of the whole hot path over the 256^3 union scene (3
-spheres, a rounded box and a torus; 4 mm voxels, +-4 voxel band, 40 views at
-640x480 on a 1.2 m hemisphere, sigma(z) depth noise):
-  coarse TSDF + band + hash + neighbours  ->  assembly of Lambda, b, diag(Q)
-  ->  FP64 Jacobi-PCG for the mean (tol 1e-6)  ->  32-probe Hutchinson
-  variance as one FP64 block-PCG (tol 1e-6)  ->  NBV scoring of 512 candidate
-  poses (160x120 rays each) with argmax.
+One step is one pass of the whole hot path over the 512^3 union scene (3
+spheres, a rounded box and a torus; 2 mm voxels, +-4 voxel band, 120 views at
+640x480 on a 1.2 m hemisphere, sigma(z) depth noise), the full-pass
+configuration:
+  coarse TSDF + band + key -> index map + neighbours  ->  assembly of Lambda,
+  b, diag(Q)  ->  features + network (learned start)  ->  mixed-precision
+  Jacobi-PCG for the mean from the learned start (tol 1e-6)  ->  32-probe
+  Hutchinson variance as one mixed-precision block-PCG from the learned
+  log-variance (tol 1e-6)  ->  NBV scoring of 512 candidate poses (160x120
+  rays each) with argmax.
 Inputs are synthetic and resident in device memory before timing starts.
 
 Printed: one JSON line with the metric (band voxel-PCG-iterations per second
-of step time), the dominant kernel's roofline (algorithmic bytes or flops per
-launch over its event-timed average duration), the learned/batched/mixed vs
-plain FP64 time-to-tolerance comparison, and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+of step time), the roofline of the solver iteration in its algorithmic bytes
+per voxel-column-iteration (block A + B + verify over their event-timed
+average durations), per-kernel rooflines, the 256^3 FP64 step, the
+learned/batched/mixed vs plain FP64 time-to-tolerance comparison, the solver
+kernels on a band far larger than the Infinity Cache, and the FP64 CPU oracle
+timed on a bounded sample of the same workload at one thread and at every
+host core.
 """
 from __future__ import annotations
 
@@ -100,6 +106,16 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
         return N * (s + 7 * K * s), "B", "hbm"
+    if name == "block_A_first":  # first iteration: no p_old reads
+        return N * (24 + s + 3 * K * s), "B", "hbm"
+    if name == "block_B_first":  # first iteration from zero: x and r not read
+        return N * (s + 5 * K * s), "B", "hbm"
+    if name == "block_verify":   # FP64 residual norms: nbr, diag, rhs (probe, regenerated); x64 per column
+        return N * (24 + 8 + 8 * K), "B", "hbm"
+    if name == "block_residual":  # as verify, plus r and z stored per column
+        return N * (24 + 8 + 8 * K + 2 * K * s), "B", "hbm"
+    if name == "pcg_residual":  # nbr, diag, rhs, x (FP64) -> r, z
+        return N * (24 + 8 + 8 + 8 + 2 * s), "B", "hbm"
     # screening: one tile test per (16x8x8 block tile, view of the first 256);
     # the rest of the counted tests are cell tests
     tile_tests = (-(-G // 16)) * (-(-G // 8)) ** 2 * min(T, 256)
@@ -113,6 +129,37 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
     if name == "assemble":
         return N * T * 45, "flop", "alu"
     return None
+
+
+def iteration_bytes(K, fp64):
+    """Algorithmic bytes of one CG iteration per unit of work: a band voxel for
+    one right-hand side (FP64 2-pass 120 B, mixed 72 B), or a voxel-column of a
+    K-column block solve (10 s + 32 / K with s the vector element size: the
+    matrix, 24 B of neighbours and the diagonal, amortised over the columns)."""
+    s = 8 if fp64 else 4
+    if K == 1:
+        return 120 if fp64 else 72
+    return 10 * s + 32.0 / K
+
+
+SOLVER_ITERATION = ("block_A", "block_A_first", "block_B", "block_B_first", "block_verify")
+
+
+def solver_roofline(kernels, N, K, fp64, col_iters):
+    """The block solve's iteration against HBM: voxel-column-iterations x the
+    per-unit algorithmic bytes over the summed busy time of the kernels one
+    iteration runs (A, B and the FP64 verify pass, first-iteration variants
+    included), all from HIP events on the library stream."""
+    busy_ms = sum(kernels[k]["total_ms"] for k in SOLVER_ITERATION if k in kernels)
+    if busy_ms <= 0 or col_iters <= 0:
+        return None
+    per_unit = iteration_bytes(K, fp64)
+    amount = N * col_iters * per_unit
+    ach = amount / (busy_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "kernel": "+".join(k for k in SOLVER_ITERATION if k in kernels),
+            "unit_of_work": "voxel-column-iteration", "bytes_per_unit": per_unit,
+            "units": N * col_iters, "busy_ms": busy_ms}
 
 
 def run_gpu(args):
@@ -155,6 +202,7 @@ def run_gpu(args):
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
                    tsdf_voxel_views=band.info()["tsdf_voxel_views"], tsdf_box_tests=band.info()["tsdf_box_tests"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
+                   probe_col_iters=prep["col_iters"], mean_col_iters=rep["col_iters"],
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
         sys_.free()
         band.free()
@@ -185,7 +233,7 @@ def run_gpu(args):
     # kernel table and the dominant kernel's roofline
     kernels = {}
     for name, (launches, ms) in sorted(timings.items(), key=lambda kv: -kv[1][1]):
-        kernels[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1),
+        kernels[name] = {"launches": launches, "avg_us": 1e3 * ms / max(launches, 1), "total_ms": ms,
                          "share_of_step": ms / timing_steps / ms_step}
     P = 1
     while P < wl.G:
@@ -208,9 +256,12 @@ def run_gpu(args):
                                "unit": "TFLOP/s", "frac": ach / FP64_ALU_PEAK_TOPS,
                                "algorithmic_flops_per_launch": amount}
     dominant = next(iter(kernels)) if kernels else None
+    # the block solve's iteration in the section 8(d) unit, over the timed steps' launches
+    solver = solver_roofline(kernels, info["N"], K, args.precision == "fp64", info["probe_col_iters"] * timing_steps)
     return dict(ctx=ctx, wl=wl, depth=depth, poses=poses, cands=cands, grid=grid, noise=noise,
                 info=info, value=value, ms_step=ms_step, kernels=kernels, rooflines=rooflines,
-                dominant=dominant)
+                dominant=dominant, solver_roofline=solver, precision=args.precision, learned=args.learned,
+                K=K, tol=args.tol, steps=args.steps, timing_steps=timing_steps)
 
 
 def _weights(lam):
@@ -323,48 +374,93 @@ def stream_copy_gbs():
     return 2 * COPY_BYTES * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
+def _kernel_rooflines(tm, N, K, T, G, fp64):
+    """Per-kernel HBM rooflines of the solver kernels in a timing table."""
+    out = {}
+    for kname, (launches, ms) in tm.items():
+        if launches == 0:
+            continue
+        w = algorithmic_work(kname, N, K, T, G, 0, fp64=fp64)
+        if w is None or w[2] != "hbm":
+            continue
+        gbs = w[0] / (ms * 1e-3 / launches) / 1e9
+        out[kname] = {"launches": launches, "avg_us": 1e3 * ms / launches, "algorithmic_bytes_per_launch": w[0],
+                      "achieved_GBps": gbs, "frac_of_8TBps": gbs / HBM_PEAK_GBS}
+    return out
+
+
 def solver_section(g, args):
-    """HBM rooflines of the block-PCG kernels where the working set far exceeds
-    the 256 MB Infinity Cache: the 64-probe block solve (mixed and FP64) on the
-    512^3 union scene (about 2.3M band voxels: 0.58 GB per float block vector)
-    with a strong prior (lambda = 1e5, so that it takes tens of iterations)."""
+    """The solver kernels where the working set far exceeds the 256 MB Infinity
+    Cache: the full pass's scene and views on a 1024^3 grid of 1 mm voxels
+    (several million band voxels) with a strong prior (lambda = 1e5, so that
+    CG takes tens of iterations).  The mean PCG (one right-hand side) and the 64-probe block
+    solve, each in mixed precision and FP64: iterations per second in the
+    section 8(d) unit (voxel-iterations, voxel-column-iterations), the roofline
+    of the iteration and of every solver kernel."""
     import torch
     import paper_2602_19697_amd as bf
     from synth import make_workload
+    from synth.configs import regrid
     ctx, dev = g["ctx"], g["ctx"].device
-    wl = make_workload(args.solver_workload, device=dev)
+    t0 = time.time()
+    if args.solver_workload == "union1024" and g["wl"].name == "union512":
+        wl = regrid(g["wl"], "union1024", 1024, 0.001)  # same depth maps: nothing to render
+    else:
+        wl = make_workload(args.solver_workload, device=dev)
     depth = torch.from_numpy(np.ascontiguousarray(wl.depth)).to(dev)
     poses = torch.from_numpy(np.ascontiguousarray(wl.poses)).to(dev)
     band = ctx.bf_build_band(bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band), wl.cam, depth, poses)
     lam, K, tol = 1e5, 64, 1e-6
     sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, bf.noise_struct(*wl.noise), lam, wl.eps)
     N = band.n
-    out = {"workload": wl.name, "band_voxels": N, "lambda": lam, "probes": K, "tol": tol}
+    log(f"[solver] {wl.name}: N={N} built in {time.time() - t0:.1f}s")
+    out = {"workload": wl.name, "band_voxels": N, "lambda": lam, "probes": K, "tol": tol,
+           "float_block_vector_MB": N * K * 4 / 1e6}
     for prec, name in ((bf.L.BF_PREC_MIXED, "mixed"), (bf.L.BF_PREC_FP64, "fp64")):
+        fp64 = name == "fp64"
+        # mean: one right-hand side
+        ctx.bf_pcg_solve(sys_, tol, precision=prec)  # warm-up (allocations)
+        torch.cuda.synchronize()
+        ctx.bf_get_timings()
+        ctx.bf_set_timing(True)
+        t0 = time.perf_counter()
+        _, rep = ctx.bf_pcg_solve(sys_, tol, precision=prec)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ctx.bf_set_timing(False)
+        tm = ctx.bf_get_timings()
+        busy = sum(tm.get(k, (0, 0.0))[1] for k in ("pcg_A", "pcg_B"))
+        per_unit = iteration_bytes(1, fp64)
+        mean = {"iters": rep["iters"], "wall_ms": wall * 1e3, "voxel_iters_per_s": N * rep["iters"] / wall,
+                "kernels": _kernel_rooflines(tm, N, 1, wl.T, wl.G, fp64)}
+        if busy > 0:
+            ach = N * rep["iters"] * per_unit / (busy * 1e-3) / 1e9
+            mean["iteration_roofline"] = {"bytes_per_unit": per_unit, "busy_ms_A_B": busy, "achieved_GBps": ach,
+                                          "frac_of_8TBps": ach / HBM_PEAK_GBS,
+                                          "voxel_iters_per_s_in_A_B": N * rep["iters"] / (busy * 1e-3)}
+        # the K-probe block solve
         ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)  # warm-up (allocations)
         torch.cuda.synchronize()
         ctx.bf_get_timings()
         ctx.bf_set_timing(True)
         t0 = time.perf_counter()
-        _, rep = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)
+        _, prep = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=prec)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         ctx.bf_set_timing(False)
         tm = ctx.bf_get_timings()
-        res = {"iters": rep["iters"], "column_iters": rep["col_iters"], "wall_ms": wall * 1e3,
-               "voxel_column_iters_per_s": N * rep["col_iters"] / wall}
-        for kname in ("block_A", "block_B"):
-            launches, ms = tm.get(kname, (0, 0.0))
-            if launches == 0:
-                continue
-            amount, _, _ = algorithmic_work(kname, N, K, wl.T, wl.G, 0, fp64=(name == "fp64"))
-            gbs = amount / (ms * 1e-3 / launches) / 1e9
-            res[kname] = {"launches": launches, "avg_us": 1e3 * ms / launches,
-                          "algorithmic_bytes_per_launch": amount, "achieved_GBps": gbs,
-                          "frac_of_8TBps": gbs / HBM_PEAK_GBS}
-        out[name] = res
-        log(f"[solver] {wl.name} N={N} {name}: {rep['iters']} iterations, {wall * 1e3:.1f} ms; "
-            + ", ".join(f"{k} {res[k]['achieved_GBps']:.0f} GB/s" for k in ("block_A", "block_B") if k in res))
+        kt = {k: {"total_ms": ms} for k, (launches, ms) in tm.items()}
+        block = {"iters": prep["iters"], "column_iters": prep["col_iters"], "wall_ms": wall * 1e3,
+                 "voxel_column_iters_per_s": N * prep["col_iters"] / wall,
+                 "iteration_roofline": solver_roofline(kt, N, K, fp64, prep["col_iters"]),
+                 "kernels": _kernel_rooflines(tm, N, K, wl.T, wl.G, fp64)}
+        out[name] = {"mean": mean, "block": block}
+        br = block["iteration_roofline"] or {}
+        mr = mean.get("iteration_roofline", {})
+        log(f"[solver] {wl.name} N={N} {name}: mean {rep['iters']} it {mean['wall_ms']:.1f} ms "
+            f"({mr.get('achieved_GBps', 0):.0f} GB/s in A+B); block K={K} "
+            f"{prep['iters']} it {block['wall_ms']:.1f} ms, {block['voxel_column_iters_per_s']:.3g} "
+            f"voxel-column-iters/s ({br.get('achieved', 0):.0f} GB/s in A+B+verify)")
     # time to tolerance on this large system with 32 probes (learned start trained at lambda = 1e5)
     out["time_to_tol"] = compare_solvers(ctx, sys_, lam, 32, reps=2, plain_reps=1)
     t = out["time_to_tol"]
@@ -574,31 +670,39 @@ def batch_section(g, args):
     rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
     out["mixed_rel_err_vs_fp64_max"] = {"mean": max(rel(a, b) for a, b in zip(m32, m64)),
                                         "variance": max(rel(a, b) for a, b in zip(s32, s64))}
+    # error against the FP64 oracle (its own band, FP64 PCG to 1e-10, the same
+    # seeded probes) on the smallest, two middle and the largest scene
+    if not args.no_cpu_baseline:
+        import oracle as O
+        by_size = sorted(range(len(scenes)), key=lambda i: sizes[i])
+        pick = sorted({by_size[0], by_size[len(by_size) // 3], by_size[2 * len(by_size) // 3], by_size[-1]})
+        errs = []
+        t0 = time.time()
+        for i in pick:
+            wl = make_workload(f"batchsphere{i}")
+            ref = O.full_pipeline(wl)
+            mu = O.pcg(ref["nbr"], ref["diag"], wl.lam, ref["rhs"], 1e-10)[0]
+            sv = O.hutchinson(ref["nbr"], ref["diag"], wl.lam, K, 0, 1e-10)
+            np_rel = lambda a, b: float(np.linalg.norm(a.cpu().numpy() - b) / np.linalg.norm(b))
+            errs.append({"scene": i, "band_voxels": sizes[i], "band_equal": bool(len(ref["keys"]) == sizes[i]),
+                         "mixed_mean": np_rel(m32[i], mu), "mixed_variance": np_rel(s32[i], sv),
+                         "fp64_mean": np_rel(m64[i], mu), "fp64_variance": np_rel(s64[i], sv)})
+        out["rel_err_vs_fp64_oracle"] = errs
+        log(f"[batch] vs FP64 oracle ({time.time() - t0:.1f} s): " + "; ".join(
+            f"scene {e['scene']} N={e['band_voxels']} mixed {e['mixed_mean']:.1e}/{e['mixed_variance']:.1e}"
+            for e in errs))
     for band, sy in scenes:
         sy.free()
         band.free()
     return out
 
 
-def cpu_baseline(g, args):
-    """FP64 oracle on a bounded sample of the same workload, single thread,
-    extrapolated to one whole step and expressed in voxel-PCG-iterations/s."""
-    import oracle as O
-    wl = g["wl"]
-    og = O.grid_of(wl)
-    oc = O.cam(wl.cam)
-    rng = np.random.default_rng(0)
-    depth = np.ascontiguousarray(wl.depth)
-    poses = np.ascontiguousarray(wl.poses)
-    # untimed preparation: the oracle's own band (dense TSDF uses OpenMP here)
-    t0 = time.time()
-    td, wd = O.tsdf_dense(og, oc, depth, poses)
-    keys, bt, bw = O.band(og, td, wd)
-    nbr, deg = O.neighbours(wl.G, keys)
-    log(f"[cpu] oracle band N={len(keys)} prepared in {time.time() - t0:.1f}s")
+def _oracle_stages(O, wl, og, oc, depth, poses, keys, nbr, deg, args, rng):
+    """Seconds of each oracle stage on the bounded sample, extrapolated to one
+    whole step of the timed configuration."""
     N = len(keys)
     t = {}
-    # TSDF: per-voxel cost on a random voxel sample
+    # TSDF: a random voxel sample of the grid, every view per voxel
     ns = args.cpu_tsdf_sample
     idx = rng.integers(0, wl.G, size=(ns, 3)).astype(np.int32)
     t0 = time.perf_counter()
@@ -612,7 +716,7 @@ def cpu_baseline(g, args):
     t["assembly"] = (time.perf_counter() - t0) / na * N
     Lam, b = O.assemble(og, oc, depth, poses, keys, noise=wl.noise)
     diag = O.precision_diag(Lam, deg, wl.lam, wl.eps)
-    # full mean solve
+    # the whole mean solve
     t0 = time.perf_counter()
     mu, rep = O.pcg(nbr, diag, wl.lam, b, args.tol)
     t["pcg"] = time.perf_counter() - t0
@@ -621,19 +725,59 @@ def cpu_baseline(g, args):
     t0 = time.perf_counter()
     s, its = O.hutchinson(nbr, diag, wl.lam, kp, 0, args.tol, with_iters=True)
     t["probes"] = (time.perf_counter() - t0) / kp * args.probes
-    # NBV: one candidate, extrapolated to all
+    # NBV: a few candidates, extrapolated to all
     q = O.quantize_variance(s)
     cands = wl.candidates()
+    nc = args.cpu_nbv_sample
     t0 = time.perf_counter()
-    O.nbv_scores(og, O.cam(wl.ray_cam), keys, mu, q, cands, which=[0])
-    t["nbv"] = (time.perf_counter() - t0) * len(cands)
-    t_step = sum(t.values())
+    O.nbv_scores(og, O.cam(wl.ray_cam), keys, mu, q, cands, which=list(range(0, len(cands), len(cands) // nc))[:nc])
+    t["nbv"] = (time.perf_counter() - t0) / nc * len(cands)
     work = N * (rep["iters"] + int(np.mean(its)) * args.probes)
-    return {"value": work / t_step, "unit": "voxel-PCG-iters/s", "cores": 1, "kind": "oracle",
-            "sample": (f"single-thread FP64 oracle: TSDF of {ns} random voxels x {wl.T} views, assembly of "
-                       f"{na} band voxels, the full mean PCG (N={N}), {kp} of {args.probes} probe solves "
-                       f"and NBV of 1 of {len(cands)} candidates, each extrapolated to the whole step"),
-            "extrapolated_step_s": t_step, "stage_s": t}
+    return t, work, dict(ns=ns, na=na, kp=kp, nc=nc, N=N, ncand=len(cands))
+
+
+def cpu_baseline(g, args):
+    """The FP64 oracle, as it stands, on a bounded sample of the timed step's
+    workload, extrapolated to one whole step and expressed in
+    voxel-PCG-iterations/s: once on one thread and once on every host core its
+    OpenMP loops may use (voxels, probes and candidates in parallel; the mean
+    PCG is serial).  The oracle builds its own band first (untimed)."""
+    import oracle as O
+    wl = g["wl"]
+    og = O.grid_of(wl)
+    oc = O.cam(wl.cam)
+    depth = np.ascontiguousarray(wl.depth)
+    poses = np.ascontiguousarray(wl.poses)
+    cores = O.max_threads()
+    t0 = time.time()
+    td, wd = O.tsdf_dense(og, oc, depth, poses)
+    keys, bt, bw = O.band(og, td, wd)
+    del td, wd
+    nbr, deg = O.neighbours(wl.G, keys)
+    log(f"[cpu] oracle band N={len(keys)} prepared in {time.time() - t0:.1f}s on {cores} threads")
+    runs = {}
+    for n in (1, cores):
+        O.set_threads(n)
+        t, work, smp = _oracle_stages(O, wl, og, oc, depth, poses, keys, nbr, deg, args, np.random.default_rng(0))
+        runs[n] = (t, work)
+        log(f"[cpu] {n} thread(s): extrapolated step {sum(t.values()):.1f} s " +
+            ", ".join(f"{k} {v:.2f}" for k, v in t.items()))
+    O.set_threads(cores)
+    t1, work = runs[1]
+    tn, _ = runs[cores]
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"value": work / sum(tn.values()), "unit": "voxel-PCG-iters/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle on {cores} threads: TSDF of {smp['ns']} random voxels x {wl.T} views, "
+                       f"assembly of {smp['na']} band voxels, the full mean PCG (N={smp['N']}), {smp['kp']} of "
+                       f"{args.probes} probe solves and NBV of {smp['nc']} of {smp['ncand']} candidates, each "
+                       f"extrapolated to the whole step; the same sample on one thread is single_thread"),
+            "extrapolated_step_s": sum(tn.values()), "stage_s": tn,
+            "single_thread": {"value": work / sum(t1.values()), "cores": 1, "extrapolated_step_s": sum(t1.values()),
+                              "stage_s": t1},
+            "host": {"omp_threads": cores, "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity}}
 
 
 def _scene_words(wl):
@@ -652,24 +796,29 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--timing-steps", type=int, default=2,
                     help="per-kernel HIP event timing on the last this many timed steps")
-    ap.add_argument("--workload", default="union256")
+    ap.add_argument("--workload", default="union512")
     ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--tol", type=float, default=1e-6)
-    ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64",
-                    help="solver precision of the timed step (the 256^3 configuration is FP64)")
-    ap.add_argument("--learned", action="store_true", help="start the timed solves from the learned network")
+    ap.add_argument("--precision", choices=("fp64", "mixed"), default="mixed",
+                    help="solver precision of the timed step (the 512^3 full pass is mixed)")
+    ap.add_argument("--no-learned", dest="learned", action="store_false",
+                    help="start the timed solves from zero instead of the learned network")
+    ap.add_argument("--section-workload", default="union256",
+                    help="workload of the FP64 step section and of the trilinear and surface sections")
+    ap.add_argument("--no-section-step", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-solver-roofline", action="store_true")
     ap.add_argument("--no-trilinear", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
-    ap.add_argument("--solver-workload", default="union512")
+    ap.add_argument("--solver-workload", default="union1024")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
-    ap.add_argument("--cpu-tsdf-sample", type=int, default=200000)
-    ap.add_argument("--cpu-assembly-sample", type=int, default=40000)
-    ap.add_argument("--cpu-probe-sample", type=int, default=2)
+    ap.add_argument("--cpu-tsdf-sample", type=int, default=1000000)
+    ap.add_argument("--cpu-assembly-sample", type=int, default=400000)
+    ap.add_argument("--cpu-probe-sample", type=int, default=4)
+    ap.add_argument("--cpu-nbv-sample", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -683,6 +832,14 @@ def main():
         sys.exit(2)
 
     g = run_gpu(args)
+    log(f"[bench] {g['wl'].name}: {g['ms_step']:.3f} ms/step, {g['value']:.4g} voxel-PCG-iters/s")
+    # the 256^3 FP64 step (no learned start), and the sections that run on it
+    g2 = None
+    if not args.no_section_step or not args.no_trilinear or not args.no_surface:
+        a2 = argparse.Namespace(**{**vars(args), "workload": args.section_workload, "precision": "fp64",
+                                   "learned": False, "warmup": 2})
+        g2 = run_gpu(a2)
+        log(f"[bench] {g2['wl'].name} FP64: {g2['ms_step']:.3f} ms/step")
     cmp = None if args.no_compare else time_to_tol(g, args)
     sweep = None
     if not args.no_compare:
@@ -690,23 +847,14 @@ def main():
     solver = None if args.no_solver_roofline else solver_section(g, args)
     copy_gbs = None if args.no_compare else stream_copy_gbs()
     batch = None if args.no_batch else batch_section(g, args)
-    trilinear = None if args.no_trilinear else trilinear_section(g, args)
-    surface = None if args.no_surface else surface_section(g, args)
+    trilinear = None if args.no_trilinear else trilinear_section(g2, args)
+    surface = None if args.no_surface else surface_section(g2, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
-    # The roofline is that of the longest-running kernel with a roofline
-    # claim.  The ray walk (nbv_rays) is irregular and latency-bound: it gets
-    # rays/s instead, and is named as the step's largest kernel when it is.
-    top = g["dominant"]
-    roof = None
-    if g["rooflines"]:
-        dom = max(g["rooflines"], key=lambda k: g["kernels"][k]["share_of_step"])
-        roof = dict(g["rooflines"][dom], kernel=dom, traffic=measured_traffic(dom, g["wl"].name))
-        if dom == "tsdf_count":
-            full = g["wl"].G ** 3 * g["wl"].T
-            roof["fused_voxel_views"] = g["info"]["tsdf_voxel_views"]
-            roof["screened_fraction"] = 1.0 - g["info"]["tsdf_voxel_views"] / full
-            roof["screening_tests"] = g["info"]["tsdf_box_tests"]
     wl = g["wl"]
+    roof = g["solver_roofline"]
+    if roof is not None:
+        roof = dict(roof, traffic=measured_traffic("block_iteration", wl.name))
+    top = g["dominant"]
     nbv = g["kernels"].get("nbv_rays")
     rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height
     steps = g["info"]["walk_steps"]
@@ -714,6 +862,16 @@ def main():
         "rays_per_launch": rays, "avg_ms": nbv["avg_us"] * 1e-3, "rays_per_s": rays / (nbv["avg_us"] * 1e-6),
         "dda_steps_per_launch": steps, "dda_steps_per_s": steps / (nbv["avg_us"] * 1e-6),
         "share_of_step": nbv["share_of_step"], "bound": "latency / instruction issue (no roofline claim)"}
+    section_step = None
+    if g2 is not None and not args.no_section_step:
+        w2 = g2["wl"]
+        section_step = {
+            "workload": f"{w2.name}: {_scene_words(w2)}; {w2.G}^3 grid, h={w2.h} m, {w2.T} views "
+                        f"{w2.cam.width}x{w2.cam.height}; FP64 PCG tol {args.tol} from zero, {args.probes}-probe "
+                        f"FP64 block PCG, NBV 512x160x120",
+            "ms_per_step": g2["ms_step"], "voxel_pcg_iters_per_s": g2["value"], "band_voxels": g2["info"]["N"],
+            "pcg_iters": g2["info"]["iters"], "probe_iters": g2["info"]["probe_iters"],
+            "solver_roofline": g2["solver_roofline"], "rooflines": g2["rooflines"], "kernels": g2["kernels"]}
     line = {
         "metric": "band voxel-PCG-iters/s, probe-solves/s; learned+batched vs plain time-to-1e-6",
         "value": g["value"],
@@ -727,11 +885,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"{wl.name}: {_scene_words(wl)}; {wl.G}^3 grid, "
+        "config": {"workload": f"{wl.name} full pass: {_scene_words(wl)}; {wl.G}^3 grid, "
                                f"h={wl.h} m, band +-{round(wl.band / wl.h)} voxels, {wl.T} views "
                                f"{wl.cam.width}x{wl.cam.height}; {args.precision.upper()} PCG tol {args.tol}"
                                f"{' from the learned start' if args.learned else ''}, "
-                               f"{args.probes}-probe block PCG, NBV 512x160x120",
+                               f"{args.probes}-probe {args.precision.upper()} block PCG"
+                               f"{' from the learned log-variance' if args.learned else ''}, NBV 512x160x120",
                    "band_voxels": g["info"]["N"], "pcg_iters": g["info"]["iters"],
                    "probe_iters": g["info"]["probe_iters"], "parallelism": "single GPU"},
         "probe_solves_per_s": args.probes / (g["ms_step"] * 1e-3),
@@ -740,9 +899,10 @@ def main():
         "nbv": nbv_info,
         "rooflines": g["rooflines"],
         "kernels": g["kernels"],
+        "step_fp64_union256": section_step,
         "time_to_tol": cmp,
         "time_to_tol_lambda_sweep": sweep,
-        "block_solver_roofline": solver,
+        "solver_rooflines_sized": solver,
         "stream_copy_GBps": copy_gbs,
         "batch": batch,
         "trilinear": trilinear,

@@ -54,6 +54,8 @@ def lib():
         if not os.path.exists(path):
             _build.build()
         L = C.CDLL(path)
+        L.orc_set_threads.argtypes = [C.c_int32]
+        L.orc_max_threads.restype = C.c_int32
         L.orc_morton_encode.restype = C.c_uint64
         L.orc_morton_encode.argtypes = [C.c_int32] * 3
         L.orc_morton_decode.argtypes = [C.c_uint64] + [C.POINTER(C.c_int32)] * 3
@@ -146,6 +148,15 @@ def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (every result is independent of it)."""
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
 def morton_encode(i, j, k) -> int:
     return int(lib().orc_morton_encode(int(i), int(j), int(k)))
 
@@ -165,7 +176,7 @@ def tsdf_voxel(g: Grid, cm: Cam, depth, c2w, i, j, k):
 
 
 def tsdf_points(g: Grid, cm: Cam, depth, c2w, ijk):
-    """Coarse TSDF and weight of the voxels ijk [n][3] (single thread)."""
+    """Coarse TSDF and weight of the voxels ijk [n][3]."""
     depth = _c(depth, np.float32)
     ijk = _c(ijk, np.int32).reshape(-1, 3)
     n = ijk.shape[0]

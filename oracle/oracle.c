@@ -7,8 +7,13 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the oracle's parallel loops (results do not depend on it). */
+void orc_set_threads(int32_t n) { omp_set_num_threads(n > 0 ? n : 1); }
+int32_t orc_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Morton keys.  The paper stores the band in a sparse voxel structure  */
@@ -112,9 +117,10 @@ void orc_tsdf_dense(const orc_grid* g, const orc_cam* cam, int32_t T, const floa
       }
 }
 
-/* Coarse TSDF of a list of voxels ijk [n][3] (single thread). */
+/* Coarse TSDF of a list of voxels ijk [n][3] (voxels in parallel). */
 void orc_tsdf_points(const orc_grid* g, const orc_cam* cam, int32_t T, const float* depth,
                      const double* c2w, int64_t n, const int32_t* ijk, double* tsdf, int32_t* w) {
+#pragma omp parallel for schedule(dynamic, 1024)
   for (int64_t p = 0; p < n; ++p)
     orc_tsdf_voxel(g, cam, T, depth, c2w, ijk[3 * p], ijk[3 * p + 1], ijk[3 * p + 2], &tsdf[p], &w[p]);
 }

@@ -44,6 +44,8 @@ typedef struct {
   double rel_res;      /* ||b - Q x|| / ||b|| recomputed at exit */
 } orc_report;
 
+void orc_set_threads(int32_t n);
+int32_t orc_max_threads(void);
 uint64_t orc_morton_encode(int32_t i, int32_t j, int32_t k);
 void orc_morton_decode(uint64_t key, int32_t* i, int32_t* j, int32_t* k);
 

@@ -11,6 +11,8 @@ neither is available, so these seeded analytic scenes stand in for them.
                   at 640x480 (fx=fy=525) on a 1.2 m hemisphere.
 * ``union512``  - the same generator on a 512^3 grid of 2 mm voxels, 120 views.
 * ``union512s`` - as union512 with 16 spheres, 6 rounded boxes and 6 tori (a larger band).
+* ``union1024`` - the union512 scene, views and depth maps on a 1024^3 grid of 1 mm voxels
+                  (a band of several million voxels, far beyond the 256 MB Infinity Cache).
 * ``sphere512`` - the sphere64 scene on a 512^3 grid of 2 mm voxels (tests of the 512^3 walk).
 * ``union128``  - the union generator on a 128^3 grid of 8 mm voxels, 24 views at 320x240
                   (training scenes of the warm start).
@@ -109,9 +111,18 @@ def batch_target_size(s: int) -> float:
     return float(math.exp(rng.uniform(math.log(2e4), math.log(8e5))))
 
 
+# Fraction of a sphere's 7-voxel shell that the 8 ring views bring into the band
+# (the polar caps are never seen and the band is |TSDF| <= 3h); measured 0.466-0.476
+# over batch scenes of 10k-350k voxels.
+RING_BAND_FRACTION = 0.47
+
+
 def batch_sphere(s: int, device="cpu") -> Workload:
+    """Sphere scene whose voxel edge h makes the measured band about
+    batch_target_size(s) voxels: h^2 = f 4 pi r^2 7 / N with the observed
+    fraction f = RING_BAND_FRACTION of the sphere's shell."""
     n_target = batch_target_size(s)
-    h = math.sqrt(4.0 * math.pi * 0.3 ** 2 * 7.0 / n_target)
+    h = math.sqrt(RING_BAND_FRACTION * 4.0 * math.pi * 0.3 ** 2 * 7.0 / n_target)
     G = int(math.ceil(0.96 / h))
     return sphere_workload(f"batchsphere{s}", G, h, 3, 4, Camera.centred(160, 120, 150.0, 150.0),
                            8, 1.0, s, device=device, probes=64, tol=1e-6, probe_seed=s)
@@ -126,6 +137,14 @@ def train_sphere(s: int, device="cpu") -> Workload:
     G = int(math.ceil(0.96 / h))
     return sphere_workload(f"trainsphere{s}", G, h, 3, 4, Camera.centred(160, 120, 150.0, 150.0), 8, 1.0, s,
                            radius=radius, device=device, probes=64, tol=1e-6)
+
+
+def regrid(wl: Workload, name: str, G: int, h: float) -> Workload:
+    """The same scene, views and depth maps on another grid: G^3 voxels of edge h
+    centred at the origin, with the band half-width and truncation scaled to
+    keep their size in voxels."""
+    return dataclasses.replace(wl, name=name, G=G, h=h, origin=_grid(G, h), tau=wl.tau / wl.h * h,
+                               band=wl.band / wl.h * h)
 
 
 def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
@@ -147,7 +166,9 @@ def make_workload(name: str, device="cpu", seed: int = 0) -> Workload:
     if name == "union512":
         return union_workload("union512", 512, 0.002, 120, seed, seed, device=device,
                               tol=1e-6, probes=32)
-    if name == "union512s":  # the 512^3 pass "sized" with more primitives, for a band of ~1e7 voxels
+    if name == "union1024":  # the 512^3 full pass's scene and views on a 1024^3 grid of 1 mm voxels
+        return regrid(make_workload("union512", device=device, seed=seed), "union1024", 1024, 0.001)
+    if name == "union512s":  # the 512^3 pass with more primitives (which mostly occlude each other)
         return union_workload("union512s", 512, 0.002, 120, seed, seed, device=device, tol=1e-6, probes=32,
                               primitives=dict(n_spheres=16, n_boxes=6, n_tori=6))
     if name.startswith("batchsphere"):

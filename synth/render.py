@@ -7,6 +7,8 @@ Missed pixels get depth 0 (no return).
 """
 from __future__ import annotations
 
+import sys
+
 import numpy as np
 import torch
 
@@ -35,6 +37,8 @@ def render_depth(scene, cam: Camera, poses: np.ndarray, device="cpu",
     bound = scene.bound() + 1e-3
     out = np.zeros((poses.shape[0], cam.height, cam.width), dtype=np.float64)
     for t, pose in enumerate(poses):
+        if poses.shape[0] >= 40 and t % 20 == 0:
+            print(f"[render] view {t}/{poses.shape[0]}", file=sys.stderr, flush=True)
         rot = torch.as_tensor(pose[:, :3], dtype=torch.float64, device=device)
         org = torch.as_tensor(pose[:, 3], dtype=torch.float64, device=device)
         d = dcam @ rot.T

@@ -13,6 +13,19 @@ import numpy as np
 import torch
 
 
+def _on(prim, name: str, p: torch.Tensor) -> torch.Tensor:
+    """Attribute `name` of a primitive as a tensor on p's device and dtype,
+    converted once per device (the renderer evaluates every primitive at every
+    sphere-tracing step)."""
+    cache = prim.__dict__.setdefault("_tensors", {})
+    key = (name, p.device, p.dtype)
+    t = cache.get(key)
+    if t is None:
+        t = torch.as_tensor(np.asarray(getattr(prim, name)), dtype=p.dtype, device=p.device)
+        cache[key] = t
+    return t
+
+
 def _random_rotation(rng: np.random.Generator) -> np.ndarray:
     q = rng.standard_normal(4)
     q /= np.linalg.norm(q)
@@ -33,8 +46,7 @@ class Sphere:
         return self.radius
 
     def sdf(self, p: torch.Tensor) -> torch.Tensor:
-        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
-        return torch.linalg.vector_norm(p - c, dim=-1) - self.radius
+        return torch.linalg.vector_norm(p - _on(self, "centre", p), dim=-1) - self.radius
 
 
 @dataclasses.dataclass
@@ -47,11 +59,13 @@ class RoundedBox:
     def bound(self) -> float:
         return float(np.linalg.norm(self.half))
 
+    @property
+    def core(self) -> np.ndarray:
+        return self.half - self.rounding
+
     def sdf(self, p: torch.Tensor) -> torch.Tensor:
-        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
-        rot = torch.as_tensor(self.rot, dtype=p.dtype, device=p.device)
-        q = (p - c) @ rot  # world -> local
-        b = torch.as_tensor(self.half - self.rounding, dtype=p.dtype, device=p.device)
+        q = (p - _on(self, "centre", p)) @ _on(self, "rot", p)  # world -> local
+        b = _on(self, "core", p)
         d = q.abs() - b
         outside = torch.linalg.vector_norm(d.clamp(min=0.0), dim=-1)
         inside = d.max(dim=-1).values.clamp(max=0.0)
@@ -69,9 +83,7 @@ class Torus:
         return self.major + self.minor
 
     def sdf(self, p: torch.Tensor) -> torch.Tensor:
-        c = torch.as_tensor(self.centre, dtype=p.dtype, device=p.device)
-        rot = torch.as_tensor(self.rot, dtype=p.dtype, device=p.device)
-        q = (p - c) @ rot
+        q = (p - _on(self, "centre", p)) @ _on(self, "rot", p)
         ring = torch.sqrt(q[..., 0] ** 2 + q[..., 2] ** 2) - self.major
         return torch.sqrt(ring * ring + q[..., 1] ** 2) - self.minor
 

@@ -120,3 +120,61 @@ def test_autotune_returns_a_valid_schedule(batch):
     fastest = min(table, key=lambda t: t["ms"])
     assert (best.persistent, best.rows_per_tile, best.blocks_per_cu, best.order, best.xcd_aware) == (
         fastest["persistent"], fastest["rows"], fastest["blocks_per_cu"], fastest["order"], fastest["xcd"])
+
+
+BENCH_SCENES = (23, 15, 2)  # the batch's smallest (~22k), a middle (~113k) and its largest (~775k) scene
+
+
+@pytest.fixture(scope="module")
+def bench_batch():
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    ctx = bf.Context(gc.DEV)
+    items = []
+    for s in BENCH_SCENES:
+        name = f"batchsphere{s}"
+        wl = gc.workload(name)
+        ref = gc.oracle_ref(name)
+        band, sys_, _, _ = gc.gpu_system(ctx, wl)
+        items.append(dict(wl=wl, ref=ref, band=band, sys=sys_))
+        print(f"[bench batch] {name} N={band.n} (oracle {len(ref['keys'])})", flush=True)
+    yield ctx, items
+    for it in items:
+        it["sys"].free()
+        it["band"].free()
+    ctx.close()
+
+
+def test_bench_batch_scenes_against_oracle(bench_batch):
+    """Scenes of the 32-scene bench batch, as the batch runs them: band and
+    assembly bit for bit, then the batched mean and 64-probe variance in mixed
+    precision (<= 1e-4) and FP64 (<= 1e-6) against the oracle's FP64 solves
+    with the same seeded probes."""
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    ctx, items = bench_batch
+    for it in items:
+        a, s = it["band"].arrays(), it["sys"].arrays()
+        for name in ("keys", "tsdf", "w", "nbr", "deg"):
+            assert np.array_equal(a[name].cpu().numpy(), it["ref"][name]), name
+        for name in ("Lambda", "b", "diag"):
+            assert np.array_equal(s[name].cpu().numpy(), it["ref"][name]), name
+    systems = [it["sys"] for it in items]
+    K = 64
+    refs = []
+    for it in items:
+        r, wl = it["ref"], it["wl"]
+        mu, _ = O.pcg(r["nbr"], r["diag"], wl.lam, r["rhs"], 1e-10)
+        sv = O.hutchinson(r["nbr"], r["diag"], wl.lam, K, 0, 1e-10)
+        refs.append((mu, sv))
+    sched = ctx.schedule(128, 4, bf.L.BF_ORDER_LARGEST_FIRST, 0, 0)
+    for prec, tol, bound in ((bf.L.BF_PREC_MIXED, 1e-6, 1e-4), (bf.L.BF_PREC_FP64, 1e-10, 1e-6)):
+        means, mreps = ctx.bf_pcg_solve_batched(systems, tol, precision=prec, schedule=sched)
+        vars_, vreps = ctx.bf_diag_estimate_batched(systems, K, 0, tol, precision=prec, schedule=sched)
+        for it, m, v, mr, vr, (mu, sv) in zip(items, means, vars_, mreps, vreps, refs):
+            em = gc.rel_l2(m.cpu().numpy(), mu)
+            ev = gc.rel_l2(v.cpu().numpy(), sv)
+            print(f"[{it['wl'].name} prec={prec}] mean it={mr['iters']} err {em:.2e}; K={K} it={vr['iters']} "
+                  f"err {ev:.2e}", flush=True)
+            assert mr["status"] == 0 and vr["status"] == 0
+            assert em <= bound and ev <= bound
