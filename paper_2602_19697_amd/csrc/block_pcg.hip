@@ -6,8 +6,9 @@
 // neighbour row are coalesced and the neighbour table and diagonal are read
 // once per row for all K columns.  Every column keeps its own FP64 alpha, beta
 // and stopping test (independent CGs sharing each matrix pass).  Probes z_k
-// are never stored: the SplitMix64 counter hash regenerates them in registers
-// wherever the right-hand side is needed.  Precision as in the single
+// come from the SplitMix64 counter hash; for the 7-point system their signs
+// are hashed once per solve and kept packed, one bit per column (KC/32 words
+// per row), and every pass that needs z reads those bits.  Precision as in the single
 // right-hand-side solver: FP64, or float vectors with FP64 scalars, FP64
 // folds/residuals and restarted float solves (mixed-precision iterative
 // refinement).  The per-tile work and the per-column decisions live in
@@ -204,36 +205,380 @@ __global__ __launch_bounds__(256) void k_bfold(const BState* __restrict__ st, in
     tile_fold<KC>(c, x64, cf, tile * kRowsPerTile<KC>, std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>));
 }
 
-// FP64 residual r = z - Q x for the checked columns (INIT: every active column).
-template <typename V, int KC>
-__global__ __launch_bounds__(256) void k_bresid(BState* __restrict__ st, int mode, const int32_t* __restrict__ nbr,
-                                                const double* __restrict__ diag, double lam,
-                                                const float* __restrict__ logvar, uint64_t seed,
-                                                double* __restrict__ x64, const V* __restrict__ dinv,
-                                                V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                                double* __restrict__ part, int write_x0, int store_r) {
-  __shared__ double lds[4 * 3 * 64];
-  if ((mode == MODE_CHECK || mode == MODE_VERIFY) && (st->nactive == 0 || !st->any_check)) return;
-  if (mode == MODE_CHECK && st->pending == 0) return;
-  if (mode == MODE_GUARD && st->ndropped == 0) return;
+// ---------------------------------------------------------------- 7-point probe path
+// Words of packed probe signs per row.
+template <int KC>
+constexpr int kZWords = KC > 32 ? KC / 32 : 1;
+
+// z_c[v] from the packed signs: bit c % 32 of word c / 32 set means -1.
+template <int KC>
+__device__ __forceinline__ double zsign(const uint32_t* __restrict__ zb, int64_t v, int c) {
+  const uint32_t w = zb[v * kZWords<KC> + (KC > 32 ? (c >> 5) : 0)];
+  return ((w >> (c & 31)) & 1u) ? -1.0 : 1.0;
+}
+
+// Packs the signs of the K probes (eq. 12's Rademacher vectors, SplitMix64 as
+// in the header) of every row: one hash per (row, column), gathered with a
+// wave ballot.  Columns c >= K get +1 (they never run).
+template <int KC>
+__global__ __launch_bounds__(256) void k_bzbits(uint64_t seed, int K, uint32_t* __restrict__ zb, int64_t n) {
+  constexpr int RS = kThreads / KC;
   const int c = threadIdx.x % KC;
-  const bool act = mode == MODE_REPORT  ? c < st->K
-                   : mode == MODE_GUARD ? st->dropped[c] != 0
-                                        : (st->active[c] != 0 &&
-                                           (mode == MODE_INIT || st->check[c] == (mode == MODE_VERIFY ? 2 : 1)));
+  const int lane = threadIdx.x & 63;
   const uint64_t cs = splitmix_out(seed, (uint64_t)c);
-  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  for (int64_t base = (int64_t)blockIdx.x * RS; base < n; base += (int64_t)gridDim.x * RS) {
+    const int64_t v = base + threadIdx.x / KC;  // the rows of a wave are whole (KC divides 64)
+    const bool neg = v < n && c < K && (splitmix_out(cs, (uint64_t)v) >> 63) != 0;
+    const unsigned long long m = __ballot(neg);
+    if (v >= n) continue;
+    const unsigned long long row = m >> (lane - c);
+    if constexpr (KC == 64) {
+      if (c < 2) zb[v * 2 + c] = (uint32_t)(row >> (32 * c));
+    } else {
+      if (c == 0) zb[v] = (uint32_t)(row & ((1ull << KC) - 1ull));
+    }
+  }
+}
+
+// Warm start of the probe columns, x = exp(logvar) z / diag: one weight
+// w = exp(logvar) / diag per row.  For z = +-1, (exp z) / diag and z (exp /
+// diag) are the same double, so x = +-w.
+__global__ __launch_bounds__(256) void k_bweight(const float* __restrict__ logvar, const double* __restrict__ diag,
+                                                 double* __restrict__ w, int64_t n) {
+  for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+    w[v] = exp((double)logvar[v]) / diag[v];
+}
+
+// Per-row data of one tile of R rows, staged in LDS by R threads so that the
+// KC column threads of a row read it as LDS broadcasts instead of each
+// loading it (row-uniform loads from every column lane had made the L1
+// request rate the limit of these passes).  nb: the 6 neighbours (-1: absent);
+// zs: the row's packed-sign word of the thread's 32-column group; d, di: diag,
+// 1/diag.
+template <typename V, int KC, int R>
+struct RowTile {
+  int32_t nb[6][R];
+  uint32_t zs[kZWords<KC>][R];
+  double d[R];
+  V di[R];
+  __device__ void stage(const int32_t* __restrict__ nbr, const double* __restrict__ diag, const V* __restrict__ dinv,
+                        const uint32_t* __restrict__ zb, int64_t r0, int64_t r1) {
+    for (int t = threadIdx.x; t < R; t += kThreads) {
+      const int64_t v = r0 + t < r1 ? r0 + t : r0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) nb[a][t] = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+#pragma unroll
+      for (int wd = 0; wd < kZWords<KC>; ++wd) zs[wd][t] = zb[v * kZWords<KC> + wd];
+      d[t] = diag[v];
+      di[t] = dinv[v];
+    }
+  }
+};
+
+// INIT from the warm start: x = +-w is written, and r = z - Q x is formed
+// from the neighbours' weights and packed signs (per row, staged in LDS with
+// the rest of the tile's row data) instead of gathering x back from memory.
+// The sums and stores are those of k_bres INIT with x gathered.
+template <typename V, int KC>
+__global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                                    const double* __restrict__ diag, double lam,
+                                                    const uint32_t* __restrict__ zb, const double* __restrict__ w,
+                                                    double* __restrict__ x64, const V* __restrict__ dinv,
+                                                    V* __restrict__ r, V* __restrict__ zz, int64_t n,
+                                                    double* __restrict__ part) {
+  // one column: every lane is its own row, so the row data is read directly
+  constexpr bool kStage = KC > 1;
+  constexpr int R = kRowsPerTile<KC>;
+  constexpr int RS = kThreads / KC;
+  constexpr int RT = kStage ? R : 1;
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ RowTile<V, KC, RT> rt;
+  __shared__ double wn[7][RT];                 // weights of the row (0) and its neighbours (1..6)
+  __shared__ uint32_t zn[7][kZWords<KC>][RT];  // their packed signs
+  const int c = threadIdx.x % KC;
+  const int sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
+  const bool act = st->active[c] != 0;
+  const TileWalk tw(bf_cdiv(n, R));
   double v3[3] = {0.0, 0.0, 0.0};
-  // GUARD: INIT of the dropped columns from x = 0 (x written as 0, r = z stored)
-  const int tmode = mode == MODE_GUARD ? (int)MODE_INIT : mode;
-  const float* lv = mode == MODE_GUARD ? nullptr : logvar;
-  const bool wx0 = mode == MODE_GUARD || write_x0 != 0, sr = mode == MODE_GUARD || store_r != 0;
-  if (act)
-    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-      tile_resid<V, KC>(c, tmode, cs, nbr, diag, lam, lv, x64, dinv, r, zz, tile * kRowsPerTile<KC>,
-                        std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>), v3, wx0, sr);
+  if constexpr (!kStage) {
+    if (act)
+      for (int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x; v < n; v += (int64_t)gridDim.x * kThreads) {
+        const bool neg = zb[v] & 1u;
+        const double zv = neg ? -1.0 : 1.0;
+        const double xs = neg ? -w[v] : w[v];
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const int32_t u = nbr[v * 6 + a];
+          if (u >= 0) acc += (zb[u] & 1u) ? -w[u] : w[u];
+        }
+        const double res = zv - (diag[v] * xs - lam * acc);
+        x64[v] = xs;
+        v3[0] += res * res;
+        v3[2] += zv * zv;
+        const V rv = (V)res;
+        const V zzv = rv * dinv[v];
+        r[v] = rv;
+        zz[v] = zzv;
+        v3[1] += (double)rv * (double)zzv;
+      }
+    col_block_sum<KC, 3>(v3, lds);
+    store_partials<KC, 3>(part, blockIdx.x, v3);
+    return;
+  }
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    __syncthreads();  // the previous tile's readers are done
+    rt.stage(nbr, diag, dinv, zb, r0, r1);
+    for (int t = threadIdx.x; t < R; t += kThreads) {
+      const int64_t v = r0 + t < r1 ? r0 + t : r0;
+      wn[0][t] = w[v];
+#pragma unroll
+      for (int g = 0; g < kZWords<KC>; ++g) zn[0][g][t] = zb[v * kZWords<KC> + g];
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself (its term is not added)
+        const int32_t u0 = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+        const int64_t u = u0 >= 0 ? (int64_t)u0 : v;
+        wn[1 + a][t] = w[u];
+#pragma unroll
+        for (int g = 0; g < kZWords<KC>; ++g) zn[1 + a][g][t] = zb[u * kZWords<KC> + g];
+      }
+    }
+    __syncthreads();
+    if (!act) continue;
+    for (int j = threadIdx.x / KC; j < R && r0 + j < r1; j += RS) {
+      const int64_t v = r0 + j, e = v * KC + c;
+      const bool neg = (zn[0][wd][j] >> sh) & 1u;
+      const double zv = neg ? -1.0 : 1.0;
+      const double xs = neg ? -wn[0][j] : wn[0][j];
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+        if (rt.nb[a][j] >= 0) acc += ((zn[1 + a][wd][j] >> sh) & 1u) ? -wn[1 + a][j] : wn[1 + a][j];
+      const double res = zv - (rt.d[j] * xs - lam * acc);
+      x64[e] = xs;
+      v3[0] += res * res;
+      v3[2] += zv * zv;
+      const V rv = (V)res;
+      const V zzv = rv * rt.di[j];
+      r[e] = rv;
+      zz[e] = zzv;
+      v3[1] += (double)rv * (double)zzv;
+    }
+  }
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
+}
+
+// FP64 residual r = z - Q x of the selected columns (one pass over the band):
+//   INIT   every active column; GATHER: x from x64 (a supplied start), else
+//          x = 0 (written to x64 when write_x0);
+//   GUARD  the columns whose supplied start was dropped, from x = 0;
+//   VERIFY the columns whose recurrence residual met the tolerance (check ==
+//          2), norms only;
+//   CHECK  the columns that continue or restart from it (check == 1).
+// XC (mixed precision, VERIFY): x = x64 + the float correction cf, the value a
+// fold would store, without storing it.  Sums: r.r, r.zz (stored precision),
+// z.z.  kRowsInFlight rows' gathers are issued before they are summed.
+template <typename V, int KC, int MODE, bool GATHER, bool XC>
+__global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                              const double* __restrict__ diag, double lam,
+                                              const uint32_t* __restrict__ zb, double* __restrict__ x64,
+                                              const float* __restrict__ cf, const V* __restrict__ dinv,
+                                              V* __restrict__ r, V* __restrict__ zz, int64_t n,
+                                              double* __restrict__ part, int write_x0, int store_r) {
+  constexpr int R = kRowsPerTile<KC>;
+  constexpr int RS = kThreads / KC;
+  // one column: every lane is its own row and nothing is shared, so the row
+  // data is read directly; otherwise it is staged per tile in LDS
+  constexpr bool kStage = KC > 1;
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ RowTile<V, KC, kStage ? R : 1> rt;
+  if constexpr (MODE == MODE_CHECK || MODE == MODE_VERIFY)
+    if (st->nactive == 0 || !st->any_check) return;
+  if constexpr (MODE == MODE_CHECK)
+    if (st->pending == 0) return;
+  if constexpr (MODE == MODE_GUARD)
+    if (st->ndropped == 0) return;
+  const int c = threadIdx.x % KC;
+  const int sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
+  bool act;
+  if constexpr (MODE == MODE_GUARD) act = st->dropped[c] != 0;
+  else if constexpr (MODE == MODE_INIT) act = st->active[c] != 0;
+  else act = st->active[c] != 0 && st->check[c] == (MODE == MODE_VERIFY ? 2 : 1);
+  const TileWalk tw(bf_cdiv(n, R));
+  // element (u, c) at xc[u * KC] with u * KC < 2^32 (checked by the host)
+  const double* xc = x64 + c;
+  const float* cc = XC ? cf + c : nullptr;
+  double v3[3] = {0.0, 0.0, 0.0};
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    if constexpr (kStage) {
+      __syncthreads();  // the previous tile's readers are done
+      rt.stage(nbr, diag, dinv, zb, r0, r1);
+      __syncthreads();
+    }
+    if (!act) continue;
+    // two rows in flight: their gathers are issued before they are summed
+    for (int j0 = threadIdx.x / KC; j0 < R && r0 + j0 < r1; j0 += 2 * RS) {
+      int jr[2];
+      int32_t nb[2][6];
+      double dg[2];
+      V di[2];
+      uint32_t zw[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        jr[h] = (j0 + h * RS < R && r0 + j0 + h * RS < r1) ? j0 + h * RS : j0;
+        const int64_t v = r0 + jr[h];
+        if constexpr (kStage) {
+#pragma unroll
+          for (int a = 0; a < 6; ++a) nb[h][a] = rt.nb[a][jr[h]];
+          zw[h] = rt.zs[wd][jr[h]];
+          dg[h] = rt.d[jr[h]];
+          di[h] = rt.di[jr[h]];
+        } else {
+#pragma unroll
+          for (int a = 0; a < 6; ++a) nb[h][a] = nbr[v * 6 + a];
+          zw[h] = zb[v * kZWords<KC> + wd];
+          dg[h] = diag[v];
+          di[h] = dinv[v];
+        }
+      }
+      double res[2], zv[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        zv[h] = ((zw[h] >> sh) & 1u) ? -1.0 : 1.0;
+        res[h] = zv[h];
+      }
+      if constexpr (GATHER) {
+        double xs[2], xn[2][6];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const uint32_t es = (uint32_t)(r0 + jr[h]) * (uint32_t)KC;
+          xs[h] = XC ? xc[es] + (double)cc[es] : xc[es];
+#pragma unroll
+          for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself and adds nothing
+            const uint32_t u = (uint32_t)(nb[h][a] >= 0 ? nb[h][a] : (int32_t)(r0 + jr[h])) * (uint32_t)KC;
+            xn[h][a] = XC ? xc[u] + (double)cc[u] : xc[u];
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double acc = 0.0;
+#pragma unroll
+          for (int a = 0; a < 6; ++a)
+            if (nb[h][a] >= 0) acc += xn[h][a];
+          res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (h == 1 && jr[1] == j0) break;  // no second row
+        const int64_t e = (r0 + jr[h]) * KC + c;
+        if constexpr (!GATHER)
+          if (write_x0) x64[e] = 0.0;
+        v3[0] += res[h] * res[h];
+        v3[2] += zv[h] * zv[h];
+        const V rv = (V)res[h];
+        if constexpr (MODE == MODE_VERIFY) {
+          v3[1] += (double)rv * (double)(rv * di[h]);
+        } else {
+          const V zzv = rv * di[h];
+          if (store_r) r[e] = rv;
+          zz[e] = zzv;
+          v3[1] += (double)rv * (double)zzv;
+        }
+      }
+    }
+  }
+  col_block_sum<KC, 3>(v3, lds);
+  store_partials<KC, 3>(part, blockIdx.x, v3);
+}
+
+// B of the 7-point path's first iteration from x = 0 with r = z unstored:
+// x = alpha p, r = z - alpha q (z from the packed signs), zz = r / diag.
+template <typename V, int KC>
+__global__ __launch_bounds__(256) void k_bB_gen(BState* __restrict__ st, const V* __restrict__ dinv,
+                                                const V* __restrict__ p, const V* __restrict__ q, V* __restrict__ x,
+                                                V* __restrict__ r, V* __restrict__ zz, int64_t n,
+                                                double* __restrict__ part, const uint32_t* __restrict__ zb) {
+  __shared__ double lds[4 * 3 * 64];
+  if (st->nactive == 0) return;
+  constexpr int RS = kThreads / KC;
+  const int c = threadIdx.x % KC;
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  double v2[2] = {0.0, 0.0};
+  if (st->active[c]) {
+    const V alpha = (V)st->alpha[c];
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+      const int64_t r0 = tile * kRowsPerTile<KC>, r1 = std::min<int64_t>(n, r0 + kRowsPerTile<KC>);
+      for (int64_t v = r0 + threadIdx.x / KC; v < r1; v += RS) {
+        const int64_t e = v * KC + c;
+        x[e] = (V)0 + alpha * p[e];
+        const V rv = (V)zsign<KC>(zb, v, c) - alpha * q[e];
+        const V zv = rv * dinv[v];
+        r[e] = rv;
+        zz[e] = zv;
+        v2[0] += (double)rv * (double)zv;
+        v2[1] += (double)rv * (double)rv;
+      }
+    }
+  }
+  col_block_sum<KC, 2>(v2, lds);
+  store_partials<KC, 2>(part, blockIdx.x, v2);
+}
+
+// Mixed precision, 7-point path: fold the float correction of the columns
+// that go on from a stored FP64 residual (check == 1) into x64.
+template <int KC>
+__global__ __launch_bounds__(256) void k_bfold_check(const BState* __restrict__ st, double* __restrict__ x64,
+                                                     float* __restrict__ cf, int64_t n) {
+  if (st->nactive == 0 || st->pending == 0) return;
+  const int c = threadIdx.x % KC;
+  if (!(st->active[c] && st->check[c] == 1)) return;
+  const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
+    tile_fold<KC>(c, x64, cf, tile * kRowsPerTile<KC>, std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>));
+}
+
+// s_v = (1/K) sum_k z_k[v] u_k[v] of the 7-point path, u = x64 (+ cf, mixed
+// precision: the corrections of columns that stopped after a store-free check
+// are not folded).  zero_start: a column that never iterated still has its
+// unwritten zero start.  U row groups' loads are issued before their products
+// go through LDS; one thread per row sums them in ascending k.
+template <int KC, bool XC>
+__global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ st, int zero_start,
+                                                    const double* __restrict__ x64, const float* __restrict__ cf,
+                                                    const uint32_t* __restrict__ zb, int K, int64_t n,
+                                                    double* __restrict__ s_out) {
+  constexpr int RS = kThreads / KC;
+  constexpr int U = 4;
+  __shared__ double prod[U * kThreads];
+  const int c = threadIdx.x % KC;
+  const bool zero = c < K && zero_start && st->iters[c] == 0;
+  for (int64_t r0 = blockIdx.x * (int64_t)(U * RS); r0 < n; r0 += (int64_t)gridDim.x * U * RS) {
+    double xv[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t v = r0 + j * RS + threadIdx.x / KC;
+      const int64_t e = v * KC + c;
+      xv[j] = (v < n && c < K && !zero) ? (XC ? x64[e] + (double)cf[e] : x64[e]) : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      const int64_t v = r0 + j * RS + threadIdx.x / KC;
+      prod[j * kThreads + threadIdx.x] = (v < n && c < K) ? zsign<KC>(zb, v, c) * xv[j] : 0.0;
+    }
+    __syncthreads();
+    // row r0 + t sits in group t / RS, row t % RS of it (U RS rows: 4 to 1024)
+    for (int t = threadIdx.x; t < U * RS && r0 + t < n; t += kThreads) {
+      const int base = (t / RS) * kThreads + (t % RS) * KC;
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += prod[base + k];
+      s_out[r0 + t] = acc / (double)K;
+    }
+    __syncthreads();
+  }
 }
 
 // Couplings and neighbour indices of rows [r0, r1) of one tile, staged in LDS
@@ -429,6 +774,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                     double* s_out, bf_solve_report* rep) {
   const int64_t N = sys->n;
   const bool mixed = sizeof(V) == 4;
+  const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
   const int64_t ntiles = bf_cdiv(N, kRowsPerTile<KC>);
   // a multiple of 8 workgroups so that each XCD walks a contiguous eighth of the tiles
   const int nb = (int)bf_round8(std::min<int64_t>(ntiles, 4 * (int64_t)ctx->cu_count));
@@ -436,9 +782,13 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const size_t part_bytes = ((size_t)nb * 3 * KC * 8 + 255) / 256 * 256;
   const size_t vec = ((size_t)N * KC * sizeof(V) + 255) / 256 * 256;
   const size_t vec64 = ((size_t)N * KC * 8 + 255) / 256 * 256;
-  // state | partials | x64 | r zz p0 p1 q (V) | c (float, mixed)
+  const size_t zb_bytes = tri ? 0 : ((size_t)N * kZWords<KC> * 4 + 255) / 256 * 256;
+  const size_t w_bytes = (tri || !logvar) ? 0 : ((size_t)N * 8 + 255) / 256 * 256;
+  // state | partials | x64 | r zz p0 p1 q (V) | c (float, mixed) | packed probe signs (7-point)
+  // | start weights (7-point, warm start)
   char* ws = nullptr;
-  BF_TRY(bf_ws(ctx, bf_ctx::WS_PROBE, st_bytes + part_bytes + vec64 + 5 * vec + (mixed ? vec : 0), (void**)&ws));
+  BF_TRY(bf_ws(ctx, bf_ctx::WS_PROBE,
+               st_bytes + part_bytes + vec64 + 5 * vec + (mixed ? vec : 0) + zb_bytes + w_bytes, (void**)&ws));
   BState* st = (BState*)ws;
   double* part = (double*)(ws + st_bytes);
   double* x64 = (double*)(ws + st_bytes + part_bytes);
@@ -448,11 +798,14 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   V* p1 = (V*)((char*)p0 + vec);
   V* q = (V*)((char*)p1 + vec);
   float* cf = mixed ? (float*)((char*)q + vec) : nullptr;
+  uint32_t* zb = tri ? nullptr : (uint32_t*)((char*)q + vec + (mixed ? vec : 0));
+  double* wst = w_bytes ? (double*)((char*)zb + zb_bytes) : nullptr;
   V* xin = mixed ? (V*)cf : (V*)x64;
   const V* diagV = mixed ? (const V*)sys->diag32 : (const V*)sys->diag;
   const V* dinvV = mixed ? (const V*)sys->dinv32 : (const V*)sys->dinv;
   const V lamV = (V)sys->lambda;
   const int fb = (int)std::min<int64_t>(bf_cdiv(N * KC, 256), 8192);
+  const unsigned rows_grid = (unsigned)std::min<int64_t>(bf_cdiv(N, kThreads), 8 * (int64_t)ctx->cu_count);
 
   // solve-time events from the context's pool (no create / destroy per call)
   hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
@@ -460,29 +813,38 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
                      mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0, logvar ? 1 : 0);
-  const bool tri = sys->kind == BF_SYSTEM_TRILINEAR;
   // FP64 from x = 0: the zero start is not written; the first B pass takes x
   // as 0 and the estimate takes a column that never iterated as 0.  (Mixed
   // precision folds its float corrections into x64, which must hold zeros.)
   const int zero_start = (!mixed && !logvar) ? 1 : 0;
   // ... and the initial residual r = z is not stored either: the first B pass
   // regenerates it from the probe (the 7-point system's initial pass)
-  const int gen_start = (zero_start && sys->kind != BF_SYSTEM_TRILINEAR) ? 1 : 0;
+  const int gen_start = (zero_start && !tri) ? 1 : 0;
   // the 27-point A reads the first p_old (all zeros); the 7-point one does not
   if (tri) hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
   if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   const V* offV = mixed ? (const V*)sys->off32 : (const V*)sys->off;
-  if (tri)
+  if (tri) {
     BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->nb26,
               sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
-  else
-    BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT,
-              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part,
-              zero_start ? 0 : 1, gen_start ? 0 : 1);
+  } else {
+    BF_LAUNCH(ctx, "block_probes", k_bzbits<KC>,
+              dim3((unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 16 * (int64_t)ctx->cu_count)),
+              dim3(kThreads), 0, o->seed, o->K, zb, N);
+    if (logvar) {
+      BF_LAUNCH(ctx, "block_start", k_bweight, dim3(rows_grid), dim3(kThreads), 0, logvar, sys->diag, wst, N);
+      BF_LAUNCH(ctx, "block_residual", (k_bstart_res<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                sys->diag, sys->lambda, zb, wst, x64, dinvV, r, zz, N, part);
+    } else {
+      BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_INIT, false, false>), dim3(nb), dim3(kThreads), 0, st,
+                sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, zero_start ? 0 : 1,
+                gen_start ? 0 : 1);
+    }
+  }
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   if (logvar) {  // columns whose start was no better than zero restart from x = 0
-    BF_LAUNCH(ctx, "block_residual", (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_GUARD,
-              sys->band->nbr, sys->diag, sys->lambda, logvar, o->seed, x64, dinvV, r, zz, N, part, 1, 1);
+    BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
+              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 1, 1);
     BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
   }
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
@@ -498,6 +860,19 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   V* pa = p0;
   V* pb = p1;
   std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
+  // the 7-point estimate: u = x64 (+ the float corrections, which this path folds
+  // only for columns that restart from a stored residual)
+  auto hutch = [&]() {
+    if (tri)
+      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64,
+                o->seed, o->K, N, s_out);
+    else if (mixed)
+      BF_LAUNCH(ctx, "hutch_final", (k_hutch_bits<KC, true>), dim3(hutch_grid), dim3(kThreads), 0, st, zero_start,
+                x64, cf, zb, o->K, N, s_out);
+    else
+      BF_LAUNCH(ctx, "hutch_final", (k_hutch_bits<KC, false>), dim3(hutch_grid), dim3(kThreads), 0, st, zero_start,
+                x64, cf, zb, o->K, N, s_out);
+  };
   for (;;) {
     const int upto = std::min(next, o->max_iter);
     for (; it < upto; ++it) {
@@ -534,8 +909,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       if (it == 0 && gen_start)
-        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, true>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
-                  xin, r, zz, N, part, o->seed);
+        BF_LAUNCH(ctx, "block_B_first", (k_bB_gen<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz,
+                  N, part, (const uint32_t*)zb);
       else if (it == 0 && zero_start)
         BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
                   xin, r, zz, N, part, o->seed);
@@ -543,18 +918,30 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, false, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin,
                   r, zz, N, part, o->seed);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
-      if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
-      // columns the recurrence calls converged: FP64 residual norms without
-      // stores; then the stored FP64 residual of the columns to go on from it
-      for (const int mode : {(int)MODE_VERIFY, (int)MODE_CHECK}) {
-        const char* kname = mode == MODE_VERIFY ? "block_verify" : "block_residual";
-        if (tri)
-          BF_LAUNCH(ctx, kname, (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->nb26, sys->off,
-                    sys->diag, o->seed, x64, dinvV, r, zz, N, part);
+      if (tri) {
+        if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
+        // columns the recurrence calls converged: FP64 residual norms without
+        // stores; then the stored FP64 residual of the columns to go on from it
+        for (const int mode : {(int)MODE_VERIFY, (int)MODE_CHECK}) {
+          BF_LAUNCH(ctx, mode == MODE_VERIFY ? "block_verify" : "block_residual", (k_bresid27<V, KC>), dim3(nb),
+                    dim3(kThreads), 0, st, mode, sys->nb26, sys->off, sys->diag, o->seed, x64, dinvV, r, zz, N, part);
+          BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, mode, part, nb);
+        }
+      } else {
+        // store-free FP64 residual norms of the columns the recurrence calls
+        // converged (mixed: of x64 + the float correction, unfolded); then the
+        // columns to go on from a stored FP64 residual fold (mixed) and store it
+        if (mixed)
+          BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, true>), dim3(nb), dim3(kThreads), 0, st,
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 0);
         else
-          BF_LAUNCH(ctx, kname, (k_bresid<V, KC>), dim3(nb), dim3(kThreads), 0, st, mode, sys->band->nbr,
-                    sys->diag, sys->lambda, nullptr, o->seed, x64, dinvV, r, zz, N, part, 1, 1);
-        BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, mode, part, nb);
+          BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, false>), dim3(nb), dim3(kThreads), 0, st,
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 0);
+        BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_VERIFY, part, nb);
+        if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, N);
+        BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_CHECK, true, false>), dim3(nb), dim3(kThreads), 0, st,
+                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 1);
+        BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       }
       std::swap(pa, pb);
     }
@@ -564,8 +951,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     // later batch's pass overwrites it.
     if (!mixed) {
       fin_rec = ctx->recs.size();
-      BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64,
-                o->seed, o->K, N, s_out);
+      hutch();
       BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
@@ -578,10 +964,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // a column stops only after such a check (or at INIT, or on a breakdown),
   // and its solution does not change afterwards, so no further pass is needed.
   if (mixed) {
-    BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
-    BF_LAUNCH(ctx, "hutch_final", k_hutch_final<KC>, dim3(hutch_grid), dim3(kThreads), 0, st, zero_start, x64,
-              o->seed, o->K, N,
-              s_out);
+    if (tri) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
+    hutch();
     BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -640,6 +1024,8 @@ extern "C" bf_status bf_diag_estimate(bf_ctx* ctx, const bf_system* sys, const b
            "bf_diag_estimate: no log-variance start for trilinear systems");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, s_dev, "bf_diag_estimate: NULL output");
+  BF_CHECK(ctx, sys->n <= (int64_t)(0xffffffffll / 64), "bf_diag_estimate: %lld band voxels exceed the %lld a probe "
+           "block indexes", (long long)sys->n, (long long)(0xffffffffll / 64));
   BF_HIP(ctx, hipSetDevice(ctx->device));
   if (opts->precision == BF_PREC_FP64) return dispatch_k<double>(ctx, sys, opts, logvar_dev, s_dev, rep);
   return dispatch_k<float>(ctx, sys, opts, logvar_dev, s_dev, rep);
