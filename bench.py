@@ -66,8 +66,9 @@ def copy_calibration():
 
 
 def measured_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counters, or None if there are none or its source changed since."""
+    """HBM bytes per launch of the kernel timed as `kernel` on `workload` from
+    the committed counters, or None if there are none or its source changed
+    since."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -110,8 +111,9 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + s + 3 * K * s), "B", "hbm"
     if name == "block_B_first":  # first iteration from zero: x and r not read
         return N * (s + 5 * K * s), "B", "hbm"
-    if name == "block_verify":   # FP64 residual norms: nbr, diag, rhs (probe, regenerated); x64 per column
-        return N * (24 + 8 + 8 * K), "B", "hbm"
+    if name == "block_verify":   # FP64 residual norms: nbr, diag, rhs (probe, regenerated); per column
+        # x64, and under mixed precision its float correction too
+        return N * (24 + 8 + (8 if fp64 else 12) * K), "B", "hbm"
     if name == "block_residual":  # as verify, plus r and z stored per column
         return N * (24 + 8 + 8 * K + 2 * K * s), "B", "hbm"
     if name == "pcg_residual":  # nbr, diag, rhs, x (FP64) -> r, z
@@ -249,12 +251,13 @@ def run_gpu(args):
         if unit == "B":
             ach = amount / avg_s / 1e9
             rooflines[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": amount}
+                               "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": amount,
+                               "traffic": measured_traffic(name, wl.name)}
         else:
             ach = amount / avg_s / 1e12
             rooflines[name] = {"bound": "alu", "achieved": ach, "peak": FP64_ALU_PEAK_TOPS,
                                "unit": "TFLOP/s", "frac": ach / FP64_ALU_PEAK_TOPS,
-                               "algorithmic_flops_per_launch": amount}
+                               "algorithmic_flops_per_launch": amount, "traffic": measured_traffic(name, wl.name)}
     dominant = next(iter(kernels)) if kernels else None
     # the block solve's iteration in the section 8(d) unit, over the timed steps' launches
     solver = solver_roofline(kernels, info["N"], K, args.precision == "fp64", info["probe_col_iters"] * timing_steps)
@@ -853,7 +856,13 @@ def main():
     wl = g["wl"]
     roof = g["solver_roofline"]
     if roof is not None:
-        roof = dict(roof, traffic=measured_traffic("block_iteration", wl.name))
+        # HBM bytes of the same launches (every launch the roofline times), from
+        # the committed counters of each kernel
+        per = [(measured_traffic(k, wl.name), g["kernels"][k]["launches"]) for k in SOLVER_ITERATION
+               if k in g["kernels"]]
+        traffic = None if not per or any(t is None for t, _ in per) else sum(t * n for t, n in per)
+        roof = dict(roof, traffic=traffic,
+                    traffic_per_unit=None if traffic is None else traffic / roof["units"])
     top = g["dominant"]
     nbv = g["kernels"].get("nbv_rays")
     rays = wl.n_cand * wl.ray_cam.width * wl.ray_cam.height
