@@ -96,8 +96,9 @@ TSDF_OPS_PER_VOXEL_VIEW = 35
 TSDF_OPS_PER_CELL_VIEW = 217
 
 
-def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None):
-    """(amount, unit, bound) of one launch of a timed kernel."""
+def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None, warm=False):
+    """(amount, unit, bound) of one launch of a timed kernel.  warm: the probe
+    solve starts from the log-variance start +-w (w per row) rather than 0."""
     s = 8 if fp64 else 4
     if name == "pcg_A":      # nbr, diag, z, p_old -> p_new, q
         return N * (24 + 5 * s), "B", "hbm"
@@ -109,11 +110,15 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (s + 7 * K * s), "B", "hbm"
     if name == "block_A_first":  # first iteration: no p_old reads
         return N * (24 + s + 3 * K * s), "B", "hbm"
-    if name == "block_B_first":  # first iteration from zero: x and r not read
-        return N * (s + 5 * K * s), "B", "hbm"
-    if name == "block_verify":   # FP64 residual norms: nbr, diag, rhs (probe, regenerated); per column
-        # x64, and under mixed precision its float correction too
-        return N * (24 + 8 + (8 if fp64 else 12) * K), "B", "hbm"
+    if name == "block_B_first":  # first iteration: x not read (it is 0, or the float correction's 0);
+        # r not read either in FP64 from zero (regenerated from the probe signs)
+        return N * (s + (6 if (warm or not fp64) else 5) * K * s), "B", "hbm"
+    if name == "block_verify":   # FP64 residual norms: nbr, diag, the probe signs (K/8 B); per column
+        # x64 in FP64; under mixed precision the float correction, over an FP64 part that is the
+        # start (w per row, or zero) until a column's first restart
+        if fp64:
+            return N * (24 + 8 + K / 8 + 8 * K), "B", "hbm"
+        return N * (24 + 8 + K / 8 + (8 if warm else 0) + 4 * K), "B", "hbm"
     if name == "block_residual":  # as verify, plus r and z stored per column
         return N * (24 + 8 + 8 * K + 2 * K * s), "B", "hbm"
     if name == "pcg_residual":  # nbr, diag, rhs, x (FP64) -> r, z
@@ -243,7 +248,8 @@ def run_gpu(args):
     rooflines = {}
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
-                             voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"])
+                             voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"],
+                             warm=args.learned)
         if w is None:
             continue
         amount, unit, bound = w

@@ -25,10 +25,12 @@ template <int KC>
 constexpr int kRowsPerTile = KC == 1 ? 1024 : 64;
 
 __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, double inner, int32_t replace_every,
-                              int32_t guard) {
+                              int32_t guard, int32_t xbase) {
   state_init(st, K, tol, max_iter, inner, replace_every);
   if (threadIdx.x == 0) st->guard = guard;
+  if (threadIdx.x < K) st->xbase[threadIdx.x] = xbase;
 }
+
 
 // A: p = zz + beta p_old, q = Q p, per-column partial p.q.
 //
@@ -217,6 +219,17 @@ __device__ __forceinline__ double zsign(const uint32_t* __restrict__ zb, int64_t
   return ((w >> (c & 31)) & 1u) ? -1.0 : 1.0;
 }
 
+// Element (u, c) of the FP64 part of a mixed-precision 7-point solve (see
+// BState::xbase): stored at xc[u * KC], or the warm start +-w[u] by probe c's
+// sign bit (bit sh of packed word wd), or zero.
+template <int KC>
+__device__ __forceinline__ double x_base(int xb, const double* __restrict__ xc, const double* __restrict__ w,
+                                         const uint32_t* __restrict__ zb, uint32_t u, int sh, int wd) {
+  if (xb == 0) return xc[u * (uint32_t)KC];
+  if (xb == 1) return ((zb[(size_t)u * kZWords<KC> + wd] >> sh) & 1u) ? -w[u] : w[u];
+  return 0.0;
+}
+
 // Packs the signs of the K probes (eq. 12's Rademacher vectors, SplitMix64 as
 // in the header) of every row: one hash per (row, column), gathered with a
 // wave ballot.  Columns c >= K get +1 (they never run).
@@ -285,7 +298,7 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
                                                     const uint32_t* __restrict__ zb, const double* __restrict__ w,
                                                     double* __restrict__ x64, const V* __restrict__ dinv,
                                                     V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                                    double* __restrict__ part) {
+                                                    double* __restrict__ part, int store_x) {
   // one column: every lane is its own row, so the row data is read directly
   constexpr bool kStage = KC > 1;
   constexpr int R = kRowsPerTile<KC>;
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
           if (u >= 0) acc += (zb[u] & 1u) ? -w[u] : w[u];
         }
         const double res = zv - (diag[v] * xs - lam * acc);
-        x64[v] = xs;
+        if (store_x) x64[v] = xs;
         v3[0] += res * res;
         v3[2] += zv * zv;
         const V rv = (V)res;
@@ -356,7 +369,7 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
       for (int a = 0; a < 6; ++a)
         if (rt.nb[a][j] >= 0) acc += ((zn[1 + a][wd][j] >> sh) & 1u) ? -wn[1 + a][j] : wn[1 + a][j];
       const double res = zv - (rt.d[j] * xs - lam * acc);
-      x64[e] = xs;
+      if (store_x) x64[e] = xs;
       v3[0] += res * res;
       v3[2] += zv * zv;
       const V rv = (V)res;
@@ -378,22 +391,30 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
 //          2), norms only;
 //   CHECK  the columns that continue or restart from it (check == 1).
 // XC (mixed precision, VERIFY): x = x64 + the float correction cf, the value a
-// fold would store, without storing it.  Sums: r.r, r.zz (stored precision),
+// fold would store, without storing it; x64 per BState::xbase (w: the start
+// weights).  Sums: r.r, r.zz (stored precision),
 // z.z.  kRowsInFlight rows' gathers are issued before they are summed.
 template <typename V, int KC, int MODE, bool GATHER, bool XC>
 __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                               const double* __restrict__ diag, double lam,
                                               const uint32_t* __restrict__ zb, double* __restrict__ x64,
-                                              const float* __restrict__ cf, const V* __restrict__ dinv,
-                                              V* __restrict__ r, V* __restrict__ zz, int64_t n,
-                                              double* __restrict__ part, int write_x0, int store_r) {
+                                              const float* __restrict__ cf, const double* __restrict__ w,
+                                              const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
+                                              int64_t n, double* __restrict__ part, int write_x0, int store_r) {
   constexpr int R = kRowsPerTile<KC>;
   constexpr int RS = kThreads / KC;
   // one column: every lane is its own row and nothing is shared, so the row
   // data is read directly; otherwise it is staged per tile in LDS
   constexpr bool kStage = KC > 1;
+  // mixed VERIFY from a warm start: the start weights and packed signs of each
+  // row and its neighbours are staged with the row data, so a column lane
+  // regenerates +-w from LDS and gathers only its float correction
+  constexpr bool kStageW = XC && kStage;
+  constexpr int RW = kStageW ? R : 1;
   __shared__ double lds[4 * 3 * 64];
   __shared__ RowTile<V, KC, kStage ? R : 1> rt;
+  __shared__ double wn[7][RW];
+  __shared__ uint32_t zn[7][kZWords<KC>][RW];
   if constexpr (MODE == MODE_CHECK || MODE == MODE_VERIFY)
     if (st->nactive == 0 || !st->any_check) return;
   if constexpr (MODE == MODE_CHECK)
@@ -410,12 +431,27 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   // element (u, c) at xc[u * KC] with u * KC < 2^32 (checked by the host)
   const double* xc = x64 + c;
   const float* cc = XC ? cf + c : nullptr;
+  const int xb = XC ? st->xbase[c] : 0;
   double v3[3] = {0.0, 0.0, 0.0};
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
     if constexpr (kStage) {
       __syncthreads();  // the previous tile's readers are done
       rt.stage(nbr, diag, dinv, zb, r0, r1);
+      if constexpr (kStageW)
+        if (w)
+          for (int t = threadIdx.x; t < R; t += kThreads) {
+            const int64_t v = r0 + t < r1 ? r0 + t : r0;
+            wn[0][t] = w[v];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) {  // an absent neighbour stages the row itself (never added)
+              const int32_t u0 = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+              const int64_t u = u0 >= 0 ? (int64_t)u0 : v;
+              wn[1 + a][t] = w[u];
+#pragma unroll
+              for (int g = 0; g < kZWords<KC>; ++g) zn[1 + a][g][t] = zb[u * kZWords<KC> + g];
+            }
+          }
       __syncthreads();
     }
     if (!act) continue;
@@ -454,12 +490,27 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
         double xs[2], xn[2][6];
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const uint32_t es = (uint32_t)(r0 + jr[h]) * (uint32_t)KC;
-          xs[h] = XC ? xc[es] + (double)cc[es] : xc[es];
+          const uint32_t vs = (uint32_t)(r0 + jr[h]), es = vs * (uint32_t)KC;
+          if constexpr (XC) {  // w is read only for a warm start (it is null without one)
+            double xb0 = 0.0;
+            if (xb == 0) xb0 = xc[es];
+            else if (xb == 1) xb0 = kStageW ? (((zw[h] >> sh) & 1u) ? -wn[0][jr[h]] : wn[0][jr[h]])
+                                            : (((zw[h] >> sh) & 1u) ? -w[vs] : w[vs]);
+            xs[h] = xb0 + (double)cc[es];
+          } else {
+            xs[h] = xc[es];
+          }
 #pragma unroll
           for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself and adds nothing
-            const uint32_t u = (uint32_t)(nb[h][a] >= 0 ? nb[h][a] : (int32_t)(r0 + jr[h])) * (uint32_t)KC;
-            xn[h][a] = XC ? xc[u] + (double)cc[u] : xc[u];
+            const uint32_t vu = (uint32_t)(nb[h][a] >= 0 ? nb[h][a] : (int32_t)vs), u = vu * (uint32_t)KC;
+            if constexpr (kStageW) {
+              double xb0 = 0.0;
+              if (xb == 0) xb0 = xc[u];
+              else if (xb == 1) xb0 = ((zn[1 + a][wd][jr[h]] >> sh) & 1u) ? -wn[1 + a][jr[h]] : wn[1 + a][jr[h]];
+              xn[h][a] = xb0 + (double)cc[u];
+            } else {
+              xn[h][a] = XC ? x_base<KC>(xb, xc, w, zb, vu, sh, wd) + (double)cc[u] : xc[u];
+            }
           }
         }
 #pragma unroll
@@ -529,40 +580,59 @@ __global__ __launch_bounds__(256) void k_bB_gen(BState* __restrict__ st, const V
 }
 
 // Mixed precision, 7-point path: fold the float correction of the columns
-// that go on from a stored FP64 residual (check == 1) into x64.
+// that go on from a stored FP64 residual (check == 1) into x64, storing x64
+// (x64 = base + cf, cf = 0; the base per BState::xbase, w: the start weights).
 template <int KC>
 __global__ __launch_bounds__(256) void k_bfold_check(const BState* __restrict__ st, double* __restrict__ x64,
-                                                     float* __restrict__ cf, int64_t n) {
+                                                     float* __restrict__ cf, const double* __restrict__ w,
+                                                     const uint32_t* __restrict__ zb, int64_t n) {
   if (st->nactive == 0 || st->pending == 0) return;
+  constexpr int RS = kThreads / KC;
   const int c = threadIdx.x % KC;
   if (!(st->active[c] && st->check[c] == 1)) return;
+  const int xb = st->xbase[c], sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
   const TileWalk tw(bf_cdiv(n, kRowsPerTile<KC>));
-  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
-    tile_fold<KC>(c, x64, cf, tile * kRowsPerTile<KC>, std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>));
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r1 = std::min<int64_t>(n, (tile + 1) * kRowsPerTile<KC>);
+    for (int64_t v = tile * kRowsPerTile<KC> + threadIdx.x / KC; v < r1; v += RS) {
+      const int64_t e = v * KC + c;
+      x64[e] = x_base<KC>(xb, x64 + c, w, zb, (uint32_t)v, sh, wd) + (double)cf[e];
+      cf[e] = 0.0f;
+    }
+  }
 }
 
 // s_v = (1/K) sum_k z_k[v] u_k[v] of the 7-point path, u = x64 (+ cf, mixed
 // precision: the corrections of columns that stopped after a store-free check
-// are not folded).  zero_start: a column that never iterated still has its
-// unwritten zero start.  U row groups' loads are issued before their products
-// go through LDS; one thread per row sums them in ascending k.
+// are not folded).  FP64, zero_start: a column that never iterated still has
+// its unwritten zero start.  Mixed: x64 per BState::xbase (w: the start
+// weights), and a column that never iterated has no correction (cf unwritten).
+// U row groups' loads are issued before their products go through LDS; one
+// thread per row sums them in ascending k.  (One thread per row reading its
+// columns itself was slower: 64 rows 128-256 B apart per load defeat the L1.)
 template <int KC, bool XC>
 __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ st, int zero_start,
                                                     const double* __restrict__ x64, const float* __restrict__ cf,
-                                                    const uint32_t* __restrict__ zb, int K, int64_t n,
-                                                    double* __restrict__ s_out) {
+                                                    const double* __restrict__ w, const uint32_t* __restrict__ zb,
+                                                    int K, int64_t n, double* __restrict__ s_out) {
   constexpr int RS = kThreads / KC;
   constexpr int U = 4;
   __shared__ double prod[U * kThreads];
   const int c = threadIdx.x % KC;
   const bool zero = c < K && zero_start && st->iters[c] == 0;
+  const bool nocf = c < K && st->iters[c] == 0;
+  const int xb = XC && c < K ? st->xbase[c] : 0, sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
   for (int64_t r0 = blockIdx.x * (int64_t)(U * RS); r0 < n; r0 += (int64_t)gridDim.x * U * RS) {
     double xv[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int64_t v = r0 + j * RS + threadIdx.x / KC;
       const int64_t e = v * KC + c;
-      xv[j] = (v < n && c < K && !zero) ? (XC ? x64[e] + (double)cf[e] : x64[e]) : 0.0;
+      if constexpr (XC)
+        xv[j] = (v < n && c < K) ? x_base<KC>(xb, x64 + c, w, zb, (uint32_t)v, sh, wd) + (nocf ? 0.0 : (double)cf[e])
+                                 : 0.0;
+      else
+        xv[j] = (v < n && c < K && !zero) ? x64[e] : 0.0;
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
@@ -811,18 +881,26 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   hipEvent_t e0 = bf_event_get(ctx), e1 = bf_event_get(ctx);
   if (!e0 || !e1) return bf_fail(ctx, BF_ERR_HIP, "event creation failed");
   BF_HIP(ctx, hipEventRecord(e0, ctx->stream));
+  // Mixed precision on the 7-point system keeps the FP64 part of each column
+  // implicit until its first fold: the warm start +-w (from the weights and
+  // packed signs) or zero, regenerated where it is read, so the start is never
+  // written and read back; the float correction starts unwritten (the first B
+  // pass takes it as 0, a column that never iterated has none).
+  const bool mixed7 = mixed && !tri;
   hipLaunchKernelGGL(k_bstate_init, dim3(1), dim3(64), 0, ctx->stream, st, o->K, o->tol, o->max_iter,
-                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0, logvar ? 1 : 0);
+                     mixed ? 1e-6 : 0.0, mixed ? bf_mixed_restart() : 0, logvar ? 1 : 0,
+                     mixed7 ? (logvar ? 1 : 2) : 0);
   // FP64 from x = 0: the zero start is not written; the first B pass takes x
-  // as 0 and the estimate takes a column that never iterated as 0.  (Mixed
-  // precision folds its float corrections into x64, which must hold zeros.)
+  // as 0 and the estimate takes a column that never iterated as 0.  (The
+  // trilinear mixed path folds its float corrections into x64, which must
+  // hold zeros.)
   const int zero_start = (!mixed && !logvar) ? 1 : 0;
   // ... and the initial residual r = z is not stored either: the first B pass
   // regenerates it from the probe (the 7-point system's initial pass)
   const int gen_start = (zero_start && !tri) ? 1 : 0;
   // the 27-point A reads the first p_old (all zeros); the 7-point one does not
   if (tri) hipLaunchKernelGGL(k_bfill<V>, dim3(fb), dim3(256), 0, ctx->stream, p0, N * KC, (V)0);
-  if (mixed) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
+  if (mixed && tri) hipLaunchKernelGGL(k_bfill<float>, dim3(fb), dim3(256), 0, ctx->stream, cf, N * KC, 0.0f);
   const V* offV = mixed ? (const V*)sys->off32 : (const V*)sys->off;
   if (tri) {
     BF_LAUNCH(ctx, "block_residual", (k_bresid27<V, KC>), dim3(nb), dim3(kThreads), 0, st, (int)MODE_INIT, sys->nb26,
@@ -834,17 +912,17 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     if (logvar) {
       BF_LAUNCH(ctx, "block_start", k_bweight, dim3(rows_grid), dim3(kThreads), 0, logvar, sys->diag, wst, N);
       BF_LAUNCH(ctx, "block_residual", (k_bstart_res<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                sys->diag, sys->lambda, zb, wst, x64, dinvV, r, zz, N, part);
+                sys->diag, sys->lambda, zb, wst, x64, dinvV, r, zz, N, part, mixed7 ? 0 : 1);
     } else {
       BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_INIT, false, false>), dim3(nb), dim3(kThreads), 0, st,
-                sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, zero_start ? 0 : 1,
-                gen_start ? 0 : 1);
+                sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part,
+                (zero_start || mixed7) ? 0 : 1, gen_start ? 0 : 1);
     }
   }
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   if (logvar) {  // columns whose start was no better than zero restart from x = 0
     BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
-              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 1, 1);
+              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1);
     BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
   }
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
@@ -868,10 +946,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                 o->seed, o->K, N, s_out);
     else if (mixed)
       BF_LAUNCH(ctx, "hutch_final", (k_hutch_bits<KC, true>), dim3(hutch_grid), dim3(kThreads), 0, st, zero_start,
-                x64, cf, zb, o->K, N, s_out);
+                x64, cf, wst, zb, o->K, N, s_out);
     else
       BF_LAUNCH(ctx, "hutch_final", (k_hutch_bits<KC, false>), dim3(hutch_grid), dim3(kThreads), 0, st, zero_start,
-                x64, cf, zb, o->K, N, s_out);
+                x64, cf, wst, zb, o->K, N, s_out);
   };
   for (;;) {
     const int upto = std::min(next, o->max_iter);
@@ -911,7 +989,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
       if (it == 0 && gen_start)
         BF_LAUNCH(ctx, "block_B_first", (k_bB_gen<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz,
                   N, part, (const uint32_t*)zb);
-      else if (it == 0 && zero_start)
+      else if (it == 0 && (zero_start || mixed7))
         BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
                   xin, r, zz, N, part, o->seed);
       else
@@ -933,14 +1011,16 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         // columns to go on from a stored FP64 residual fold (mixed) and store it
         if (mixed)
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, true>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 0);
         else
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 0);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_VERIFY, part, nb);
-        if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, N);
+        if (mixed)
+          BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, wst,
+                    (const uint32_t*)zb, N);
         BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_CHECK, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, dinvV, r, zz, N, part, 0, 1);
+                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 1);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       }
       std::swap(pa, pb);

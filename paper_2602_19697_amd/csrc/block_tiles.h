@@ -32,6 +32,11 @@ struct BState {
   int32_t pending;  // columns with check == 1 (a stored residual is due)
   int32_t guard;    // a start was supplied: drop it where ||z - Q u0|| >= ||z||
   int32_t dropped[kMaxK];
+  // Mixed precision, 7-point path: where column c's FP64 part x64 lives.
+  // 0: stored; 1: the warm start +-w[v] by the sign of probe c at row v,
+  // regenerated where it is read; 2: the zero start.  A column is stored (0)
+  // from its first fold on.
+  int32_t xbase[kMaxK];
   int32_t ndropped, pad_;
 };
 
@@ -54,7 +59,7 @@ __device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_
     st->rho[c] = st->alpha[c] = st->beta[c] = st->rr_true[c] = st->bnorm2[c] = st->rr_ref[c] = 0.0;
     st->tol2b[c] = tol * tol;
     st->active[c] = c < K ? 1 : 0;
-    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = st->dropped[c] = 0;
+    st->check[c] = st->last[c] = st->iters[c] = st->status[c] = st->dropped[c] = st->xbase[c] = 0;
   }
   if (c == 0) {
     st->guard = 0;
@@ -359,6 +364,7 @@ __device__ __forceinline__ void decide_R(BState* st, int c, int mode, const doub
       // a supplied start no better than zero is dropped; GUARD redoes INIT from x = 0
       if (st->guard && tot[2] > 0.0 && !(tot[0] < tot[2])) {
         st->dropped[c] = 1;
+        if (st->xbase[c] == 1) st->xbase[c] = 2;  // its x64 is the zero start now
         atomicAdd(&st->ndropped, 1);
         return;
       }
@@ -391,6 +397,7 @@ __device__ __forceinline__ void decide_R(BState* st, int c, int mode, const doub
     }
     if (st->check[c] == 1) atomicSub(&st->pending, 1);
     st->check[c] = 0;
+    st->xbase[c] = 0;  // the check's fold stored x64
   }
 }
 

@@ -12,6 +12,7 @@ training targets.
   and log(clamp(s diag)) from the method's own solves.
 """
 import ctypes as C
+import gc as pygc
 
 import numpy as np
 import pytest
@@ -37,6 +38,9 @@ def test_allocator_hook_same_bits_and_torch_accounting():
     ct = bf.Context(gc.DEV)                    # torch's caching allocator
     cp = bf.Context(gc.DEV, allocator=None)    # the library's pool
     depth, poses = gc.to_dev(wl)
+    # garbage left by earlier tests (cycles holding device tensors) must not be
+    # freed in the middle of the accounting below
+    pygc.collect()
     torch.cuda.synchronize()
     m0 = torch.cuda.memory_allocated(gc.DEV)
     bt, st = _build(ct, wl, depth, poses)

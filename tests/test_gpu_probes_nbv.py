@@ -88,6 +88,30 @@ def test_diag_estimate_warm_start(ctx):
     band.free()
 
 
+@pytest.mark.parametrize("K", [1, 16, 64])
+def test_mixed_warm_start_through_refinement(ctx, K):
+    """Mixed precision from a log-variance start keeps the start's FP64 part
+    implicit until a refinement restart stores it: at tol 1e-9 the float
+    recurrence reaches its 1e6-fold reduction first, so every column folds its
+    start and correction into x64 and continues; the result is the FP64 one."""
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    lam = 1e5
+    wl = gc.workload("sphere64")
+    ref = gc.oracle_ref("sphere64")
+    band, sys_, _, _ = gc.gpu_system(ctx, wl, lam=lam)
+    diag = O.precision_diag(ref["Lambda"], ref["deg"], lam, wl.eps)
+    s_ref = O.hutchinson(ref["nbr"], diag, lam, K, 5, 1e-12)
+    good = torch.from_numpy(np.log(np.clip(s_ref * diag, 1e-3, None)).astype(np.float32)).to(gc.DEV)
+    got, rep = ctx.bf_diag_estimate(sys_, K, 5, 1e-9, precision=bf.L.BF_PREC_MIXED, logvar=good)
+    err = gc.rel_l2(got.cpu().numpy(), s_ref)
+    print(f"[mixed start K={K}] iters={rep['iters']} refinements={rep['refinements']} err={err:.2e}", flush=True)
+    assert rep["status"] == 0 and rep["used_warm_start"] == 1 and rep["refinements"] >= K
+    assert err <= 1e-6
+    sys_.free()
+    band.free()
+
+
 def _shared_nbv_inputs(name, lam=10.0):
     import oracle as O
     wl = gc.workload(name)
