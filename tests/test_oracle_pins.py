@@ -525,3 +525,31 @@ def test_nbv_var_reduction_depth_from_geometry(orc):
         assert abs(int(got[ci]) - want) <= nvox, (ci, got[ci], want)
     # the noise model matters: a noiseless sensor gives strictly larger utilities
     assert np.all(orc.nbv_scores_var_reduction(g, cam, keys, mu, s, poses, noise=(0.0, 0.0, z0)) > got)
+
+
+def test_oracle_threads_do_not_change_results():
+    """The oracle's OpenMP loops (dense TSDF, neighbours, assembly, one solve per
+    probe, one NBV candidate per iteration) give the same bits on 1 thread and
+    on several."""
+    import oracle as O
+    from synth import make_workload
+    wl = make_workload("tiny")
+    cands = wl.candidates()[:24]
+    nthreads = max(2, min(8, O.max_threads()))
+    runs = []
+    try:
+        for t in (1, nthreads):
+            O.set_threads(t)
+            ref = O.full_pipeline(wl, with_acc=True)
+            mu, _ = O.pcg(ref["nbr"], ref["diag"], wl.lam, ref["rhs"], 1e-10)
+            s = O.hutchinson(ref["nbr"], ref["diag"], wl.lam, 8, 3, 1e-10)
+            q = O.quantize_variance(s)
+            sc, st = O.nbv_scores_steps(ref["grid"], O.cam(wl.ray_cam), ref["keys"], mu, q, cands)
+            runs.append((ref, mu, s, sc, st))
+    finally:
+        O.set_threads(O.max_threads())
+    (r1, mu1, s1, sc1, st1), (r2, mu2, s2, sc2, st2) = runs
+    for k in ("tsdf_dense", "w_dense", "keys", "tsdf", "w", "nbr", "deg", "Lambda", "b", "diag", "rhs", "acc"):
+        assert np.array_equal(r1[k], r2[k]), k
+    assert np.array_equal(mu1, mu2) and np.array_equal(s1, s2)
+    assert np.array_equal(sc1, sc2) and np.array_equal(st1, st2)
