@@ -7,6 +7,7 @@ come out as numpy; every routine is documented where it is defined in C.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -95,6 +96,7 @@ def lib():
                                           _I64, C.POINTER(Utility), _D]
         L.orc_nbv_scores.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _I64, C.c_void_p,
                                      C.c_int32, _D, _I64, C.c_void_p]
+        L.orc_pred_depth.argtypes = [C.POINTER(Grid), C.POINTER(Cam), _U64, C.c_int64, _D, _D, _F]
         L.orc_nbv_argmax.restype = C.c_int32
         L.orc_nbv_argmax.argtypes = [C.c_int32, _I64]
         L.orc_features.argtypes = [C.c_int64, C.c_int32, C.c_double, _D, _I32, _I32, _I32, _D, _D,
@@ -491,6 +493,34 @@ def nbv_scores_var_reduction(g: Grid, ray_cam: Cam, keys, mu, s, cands, noise=(0
     u.smax = float(max(0.0, float(np.max(s)) if len(s) else 0.0))
     q = np.zeros(max(len(s), 1), dtype=np.int64)
     return _nbv_all(g, ray_cam, keys, mu, q, cands, which, util=u)[0]
+
+
+def pred_depth(g: Grid, cm: Cam, keys, mu, pose):
+    """Depth map [H][W] (float32) predicted from the mean for a sensor with camera
+    cm at pose [3][4] (camera-z depth of the first band voxel with mu <= 0 on each
+    pixel's ray; 0 for none)."""
+    keys = _c(keys, np.uint64)
+    depth = np.zeros((cm.height, cm.width), dtype=np.float32)
+    lib().orc_pred_depth(C.byref(g), C.byref(cm), keys, len(keys), _c(mu, np.float64),
+                         _c(pose, np.float64).reshape(12), depth)
+    return depth
+
+
+def nbv_postview(g: Grid, cm: Cam, keys, nbr, deg, Lam, lam, eps, mu, s, pose, K, seed, tol,
+                 eps_band=math.inf, noise=(0.0012, 0.0019, 0.4), sigma2_model=0.0, lam_b=0.0, max_iter=10000):
+    """Post-view utility of one candidate (Sec. 3.8, eq. 13): the candidate's view is
+    predicted from mu, fused as one more view (its Lambda added to the system's,
+    then diag(Q') by eq. 11), s' = the Hutchinson estimate on Q' with the same
+    probes (eq. 12), and U = sum over |mu| <= eps_band of (s - s') (correctly
+    rounded sum).  Returns (U, s', the view's Lambda, the predicted depth, diag')."""
+    depth = pred_depth(g, cm, keys, mu, pose)
+    dlam, _ = assemble(g, cm, depth[None], np.asarray(pose, dtype=np.float64).reshape(1, 3, 4), keys,
+                       noise=noise, sigma2_model=sigma2_model)
+    diag_post = precision_diag(np.asarray(Lam, dtype=np.float64) + dlam, deg, lam, eps, lam_b)
+    s_post = hutchinson(nbr, diag_post, lam, K, seed, tol, max_iter)
+    sel = np.abs(np.asarray(mu)) <= eps_band
+    U = math.fsum((np.asarray(s, dtype=np.float64) - s_post)[sel])
+    return U, s_post, dlam, depth, diag_post
 
 
 def nbv_argmax(scores) -> int:

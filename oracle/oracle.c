@@ -450,10 +450,13 @@ void orc_quantize_variance(int64_t N, const double* s, int64_t* q) {
 /* quantised expected variance reduction of one new observation taken at    */
 /* the voxel's depth Z in the candidate view: s^2 / (s + sigma(Z)^2) for    */
 /* s > 0, scaled by 2^32 / max(s) and rounded to an integer.                */
-int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
-                      const int64_t* q, const orc_utility* u, const double* P, const double* o,
-                      const double* d, int64_t* steps_out) {
+/* walk_ray is that walk; *stop_out (may be NULL) receives the band index of */
+/* the voxel where it stopped (the first band voxel with mu <= 0), or -1.    */
+static int64_t walk_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
+                        const int64_t* q, const orc_utility* u, const double* P, const double* o,
+                        const double* d, int64_t* steps_out, int64_t* stop_out) {
   int32_t G = g->G;
+  if (stop_out) *stop_out = -1;
   double inv[3];
   double tnear = 0.0, tfar = INFINITY;
   for (int a = 0; a < 3; ++a) {
@@ -493,7 +496,7 @@ int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const 
     int64_t v = find_key(keys, N, orc_morton_encode(idx[0], idx[1], idx[2]));
     if (v >= 0) {
       if (u == NULL || u->utility == 0) {
-        score += q[v];
+        if (q) score += q[v];
       } else {
         double x = g->origin[0] + ((double)idx[0] + 0.5) * g->h;
         double y = g->origin[1] + ((double)idx[1] + 0.5) * g->h;
@@ -506,7 +509,10 @@ int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const 
         double term = sv > 0.0 ? (sv * sv) / (sv + sd * sd) : 0.0;
         score += u->smax > 0.0 ? (int64_t)rint((term / u->smax) * 4294967296.0) : 0;
       }
-      if (mu[v] <= 0.0) break;
+      if (mu[v] <= 0.0) {
+        if (stop_out) *stop_out = v;
+        break;
+      }
     }
     int a = 0;
     if (tn[1] < tn[a]) a = 1;
@@ -517,6 +523,12 @@ int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const 
   }
   if (steps_out) *steps_out += steps;
   return score;
+}
+
+int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
+                      const int64_t* q, const orc_utility* u, const double* P, const double* o,
+                      const double* d, int64_t* steps_out) {
+  return walk_ray(g, keys, N, mu, q, u, P, o, d, steps_out, NULL);
 }
 
 int64_t orc_nbv_ray(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
@@ -579,6 +591,40 @@ void orc_nbv_scores(const orc_grid* g, const orc_cam* cam, const uint64_t* keys,
     scores[c] = orc_nbv_candidate_u(g, cam, keys, N, mu, q, u, c2w + 12 * c);
     if (steps) steps[c] = orc_nbv_candidate_steps(g, cam, keys, N, mu, q, c2w + 12 * c);
   }
+}
+
+/* The view a sensor with camera cam would take from pose P, predicted from  */
+/* the current mean (Sec. 3.8: the post-view variance of eq. 13 needs the    */
+/* observations the candidate would add).  Pixel (row, col) looks along the  */
+/* ray of orc_nbv_candidate_u; its depth is the camera-z depth, as in eq. 2, */
+/* of the centre of the first band voxel with mu <= 0 that the walk meets,   */
+/* rounded to float like a depth map, and 0 (no return) when it meets none.  */
+void orc_pred_depth(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                    const double* mu, const double* P, float* depth) {
+  double o[3] = {P[3], P[7], P[11]};
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int32_t row = 0; row < cam->height; ++row)
+    for (int32_t col = 0; col < cam->width; ++col) {
+      double a = ((double)col - cam->cx) / cam->fx;
+      double b = ((double)row - cam->cy) / cam->fy;
+      double d[3];
+      d[0] = (P[0] * a + P[1] * b) + P[2];
+      d[1] = (P[4] * a + P[5] * b) + P[6];
+      d[2] = (P[8] * a + P[9] * b) + P[10];
+      int64_t v;
+      walk_ray(g, keys, N, mu, NULL, NULL, P, o, d, NULL, &v);
+      float z = 0.0f;
+      if (v >= 0) {
+        int32_t i, j, k;
+        orc_morton_decode(keys[v], &i, &j, &k);
+        double x = g->origin[0] + ((double)i + 0.5) * g->h;
+        double y = g->origin[1] + ((double)j + 0.5) * g->h;
+        double zz = g->origin[2] + ((double)k + 0.5) * g->h;
+        double dx = x - P[3], dy = y - P[7], dz = zz - P[11];
+        z = (float)((P[2] * dx + P[6] * dy) + P[10] * dz);
+      }
+      depth[(int64_t)row * cam->width + col] = z;
+    }
 }
 
 int32_t orc_nbv_argmax(int32_t n, const int64_t* scores) {

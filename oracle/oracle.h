@@ -88,6 +88,8 @@ typedef struct {
 } orc_utility;
 
 void orc_quantize_variance(int64_t N, const double* s, int64_t* q);
+void orc_pred_depth(const orc_grid* g, const orc_cam* cam, const uint64_t* keys, int64_t N,
+                    const double* mu, const double* P, float* depth);
 int64_t orc_nbv_ray_u(const orc_grid* g, const uint64_t* keys, int64_t N, const double* mu,
                       const int64_t* q, const orc_utility* u, const double* P, const double* o,
                       const double* d, int64_t* steps_out);
