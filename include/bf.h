@@ -223,6 +223,18 @@ bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, in
                       const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
                       const bf_prior* prior, bf_system** out);
 
+/* Sec. 3.5-3.6, eqs. (3)-(5), (10)-(11): the voxel-centric system sys with T
+ * more views appended (depth_dev [T][H][W], c2w_dev [T][3][4], noise's pose
+ * variances [T] for the new views).  Each band voxel continues its running
+ * sums (Lambda, b and the feature statistics) over the new views in order, so
+ * *out is, bit for bit, the system bf_assemble builds from all the views at
+ * once (camera and prior as sys; the band must still be alive).  *out is a new
+ * system (free with bf_system_free); sys is unchanged.  Errors: INVALID_ARG
+ * for a trilinear system, T < 0, bad camera or NULL arrays; OOM; HIP. */
+bf_status bf_assemble_more(bf_ctx* ctx, const bf_system* sys, const bf_camera* cam, int32_t T,
+                           const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                           bf_system** out);
+
 /* Sec. 3.2, eqs. (2)-(5), (7), (10)-(11): trilinear pixel-centric observation
  * rows (eq. 4, up to 8 non-zeros).  Every valid pixel (row, col) of view t
  * gives 2S+1 samples (S = samples_per_side, 0..15) along its camera ray at
@@ -359,6 +371,40 @@ bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
                        const double* s_dev, int32_t n_cand, const double* cand_c2w_dev,
                        const bf_camera* ray_cam, int32_t utility, const bf_noise* noise,
                        int64_t* scores_dev, int32_t* best_host);
+
+/* Sec. 3.8: the depth map [H][W] (float, device) that a sensor with camera
+ * cam would return from pose c2w_dev [3][4], predicted from the mean mu_dev
+ * [N]: pixel (row, col) walks the ray of bf_nbv_score's rays (direction
+ * R ((col - cx)/fx, (row - cy)/fy, 1), voxel by voxel, lowest axis first on
+ * ties) to the first band voxel with mu <= 0, and gets the camera-z depth of
+ * that voxel's centre, (R e_z) . (x - t), rounded to float; 0 (no return)
+ * when the ray leaves the grid first.  Stream-ordered.  Errors: INVALID_ARG
+ * for NULL arrays or a bad camera; HIP. */
+bf_status bf_predict_depth(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
+                           const double* c2w_dev, const bf_camera* cam, float* depth_dev);
+
+/* Sec. 3.8, eq. (13) with the post-view variance:
+ *   U(v) = sum over the band voxels with |mu| <= eps_band of (s_i - s'_i),
+ * where s' = diag(Q'^-1) and Q' is the precision once the view from candidate
+ * v has been fused.  For each of the n_sel candidates cand_idx_host[i] (into
+ * cand_c2w_dev [n_cand][3][4]) the view of sensor camera `cam` is predicted
+ * (bf_predict_depth), appended to sys as one more view (bf_assemble_more with
+ * noise's a, c, z0 and sigma2_model; the planned pose is taken as exact, no
+ * pose variance), and s' is estimated by bf_diag_estimate with opts.  Pass
+ * the seed s was estimated with, so s and s' share the probes and the
+ * difference does not carry their independent noise.  warm != 0 starts the
+ * probe solves from u0 = z clamp(s diag', 1e-3, 1e3) / diag' (a start no
+ * better than zero is dropped per column, as in bf_diag_estimate).
+ * util_host [n_sel] receives U; *best_host the candidate index (from
+ * cand_idx_host) with the largest U, the first on ties.  Optional: s_post_dev
+ * [n_sel][N] receives each s', reps_host [n_sel] each solve's report.
+ * Synchronises.  Errors: INVALID_ARG (trilinear system, eps_band < 0, an
+ * index outside [0, n_cand), NULL arrays), the errors of bf_diag_estimate. */
+bf_status bf_nbv_postview(bf_ctx* ctx, const bf_system* sys, const double* mu_dev, const double* s_dev,
+                          int32_t n_cand, const double* cand_c2w_dev, int32_t n_sel,
+                          const int32_t* cand_idx_host, const bf_camera* cam, const bf_noise* noise,
+                          const bf_probe_opts* opts, double eps_band, int32_t warm, double* util_host,
+                          int32_t* best_host, double* s_post_dev, bf_solve_report* reps_host);
 
 /* Voxel visits of the plain Amanatides-Woo walk summed over every ray of the
  * last bf_nbv_score call on ctx (voxels visited, plus voxels skipped by the

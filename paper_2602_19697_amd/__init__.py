@@ -9,6 +9,7 @@ the library; the first Context does, and fails loudly if it is not built.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import dataclasses
 
 import torch
@@ -285,6 +286,14 @@ class Context:
                                          C.byref(pr), C.byref(h)))
         return System(self, h, band.n, band)
 
+    def bf_assemble_more(self, sys: System, cam, depth, poses, noise: L.bf_noise) -> System:
+        """sys with the views depth [T][H][W] / poses [T][3][4] appended (a new system)."""
+        h = C.c_void_p()
+        self._check(self.lib.bf_assemble_more(self.handle, sys.handle, C.byref(camera_struct(cam)),
+                                              int(depth.shape[0]), _ptr(depth), _ptr(poses), C.byref(noise),
+                                              C.byref(h)))
+        return System(self, h, sys.n, sys.band)
+
     def bf_assemble_trilinear(self, band: Band, cam, depth, poses, noise: L.bf_noise, lam, eps, lam_b=0.0,
                               samples_per_side=4) -> System:
         """Trilinear pixel-centric rows (eq. 4): 2S+1 samples per pixel, 27-point Q."""
@@ -455,6 +464,35 @@ class Context:
         v = C.c_int64()
         self._check(self.lib.bf_nbv_walk_steps(self.handle, C.byref(v)))
         return int(v.value)
+
+    def bf_predict_depth(self, band: Band, mu, pose, cam):
+        """Depth map [H][W] (float32) a sensor with camera cam would see from pose [3][4]."""
+        c = camera_struct(cam)
+        depth = torch.empty((c.height, c.width), dtype=torch.float32, device=self.device)
+        self._check(self.lib.bf_predict_depth(self.handle, band.handle, _ptr(mu), _ptr(pose), C.byref(c),
+                                              _ptr(depth)))
+        return depth
+
+    def bf_nbv_postview(self, sys: System, mu, s, cands, which, cam, noise: L.bf_noise, K, seed, tol,
+                        precision=L.BF_PREC_MIXED, eps_band=None, warm=True, max_iter=10000, keep_s=False):
+        """Post-view utilities U = sum_{|mu| <= eps_band} (s - s') of the candidates `which`
+        (eq. 13); eps_band None takes every band voxel.  Returns (utilities, best
+        candidate index, s' [len(which)][N] or None, reports)."""
+        which = [int(i) for i in which]
+        n_sel = len(which)
+        idx = (C.c_int32 * max(n_sel, 1))(*which)
+        util = (C.c_double * max(n_sel, 1))()
+        reps = (L.bf_solve_report * max(n_sel, 1))()
+        best = C.c_int32(-1)
+        o = L.bf_probe_opts()
+        o.K, o.precision, o.seed, o.tol, o.max_iter = int(K), int(precision), int(seed), float(tol), int(max_iter)
+        s_post = torch.empty((n_sel, sys.n), dtype=torch.float64, device=self.device) if keep_s else None
+        eps = math.inf if eps_band is None else float(eps_band)
+        self._check(self.lib.bf_nbv_postview(self.handle, sys.handle, _ptr(mu), _ptr(s), int(cands.shape[0]),
+                                             _ptr(cands), n_sel, idx, C.byref(camera_struct(cam)), C.byref(noise),
+                                             C.byref(o), eps, 1 if warm else 0, util, C.byref(best),
+                                             _ptr(s_post), reps))
+        return [util[i] for i in range(n_sel)], int(best.value), s_post, [reps[i].as_dict() for i in range(n_sel)]
 
     def bf_nbv_score(self, band: Band, mu, s, cands, ray_cam, utility=L.BF_UTILITY_SUM_VAR, noise=None):
         n = int(cands.shape[0])

@@ -130,6 +130,7 @@ SIGNATURES = {
                               C.POINTER(bf_prior), PP]),
     "bf_assemble_trilinear": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise),
                                         C.POINTER(bf_prior), C.c_int32, PP, C.POINTER(C.c_int64)]),
+    "bf_assemble_more": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise), PP]),
     "bf_system_view": (C.c_int, [P, C.POINTER(bf_system_arrays)]),
     "bf_extract_surface": (C.c_int, [P, P, P, C.c_double, PP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "bf_mesh_view": (C.c_int, [P, C.POINTER(bf_mesh_arrays)]),
@@ -147,6 +148,9 @@ SIGNATURES = {
     "bf_nbv_score": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(bf_camera), C.c_int32,
                                C.POINTER(bf_noise), P, C.POINTER(C.c_int32)]),
     "bf_nbv_walk_steps": (C.c_int, [P, C.POINTER(C.c_int64)]),
+    "bf_predict_depth": (C.c_int, [P, P, P, P, C.POINTER(bf_camera), P]),
+    "bf_nbv_postview": (C.c_int, [P, P, P, P, C.c_int32, P, C.c_int32, P, C.POINTER(bf_camera), C.POINTER(bf_noise),
+                                  C.POINTER(bf_probe_opts), C.c_double, C.c_int32, P, C.POINTER(C.c_int32), P, P]),
     "bf_diag_estimate_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_probe_opts), C.POINTER(bf_schedule),
                                            P, C.POINTER(bf_solve_report)]),
     "bf_pcg_solve_batched": (C.c_int, [P, P, C.c_int32, C.POINTER(bf_solve_opts), C.POINTER(bf_schedule), P,

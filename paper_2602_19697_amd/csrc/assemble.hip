@@ -16,6 +16,68 @@ struct noise_k {
   const double* pose;  // [T] or null
 };
 
+// A band voxel's running sums over the views that observe it, in view order.
+struct obs_sums {
+  double L = 0.0, B = 0.0, cnt = 0.0, sy = 0.0, syy = 0.0, ss = 0.0, smin = INFINITY;
+};
+
+// One view's observation of voxel (i, j, k), eqs. (3)-(5): accepted when the
+// projective distance d = D - Z is >= -tau, y = min(d, tau), weight 1/sigma^2.
+__device__ __forceinline__ void add_view(obs_sums& a, const bf_grid_k& g, const bf_cam_k& c,
+                                         const float* __restrict__ depth_t, const double* __restrict__ pose_t,
+                                         double pose_var, const noise_k& nz, int32_t i, int32_t j, int32_t k) {
+#pragma clang fp contract(off)
+  double D, Z;
+  if (!bf_observe(g, c, depth_t, pose_t, i, j, k, D, Z)) return;
+  const double d = D - Z;
+  if (d < -g.tau) return;
+  const double y = d < g.tau ? d : g.tau;
+  const double e = D - nz.z0;
+  const double sd = nz.a + nz.c * (e * e);
+  double var = sd * sd + pose_var;
+  var = var + nz.model;
+  const double w = 1.0 / var;
+  a.L = a.L + w;
+  a.B = a.B + w * y;
+  a.cnt = a.cnt + 1.0;
+  a.sy = a.sy + y;
+  a.syy = a.syy + y * y;
+  a.ss = a.ss + sd;
+  a.smin = sd < a.smin ? sd : a.smin;
+}
+
+// Lambda, b, the anchored right-hand side, diag(Q) (eqs. 7, 10-11) and the
+// feature statistics of voxel v from its sums.
+__device__ __forceinline__ void finish_voxel(const obs_sums& a, int64_t v, int32_t dg, double tsdf_v, double lam,
+                                             double eps, double lam_b, double* __restrict__ Lambda,
+                                             double* __restrict__ b, double* __restrict__ rhs,
+                                             double* __restrict__ diag, double* __restrict__ dinv,
+                                             float* __restrict__ diag32, float* __restrict__ dinv32,
+                                             double* __restrict__ acc) {
+#pragma clang fp contract(off)
+  double dq = a.L + lam * (double)dg;
+  dq = dq + eps;
+  double h = a.B;
+  if (lam_b != 0.0 && dg < 6) {
+    dq = dq + lam_b;
+    h = h + lam_b * tsdf_v;
+  }
+  Lambda[v] = a.L;
+  b[v] = a.B;
+  rhs[v] = h;
+  diag[v] = dq;
+  const double inv = 1.0 / dq;
+  dinv[v] = inv;
+  diag32[v] = (float)dq;
+  dinv32[v] = (float)inv;
+  double* o = acc + v * 5;
+  o[0] = a.cnt;
+  o[1] = a.sy;
+  o[2] = a.syy;
+  o[3] = a.ss;
+  o[4] = a.cnt > 0.0 ? a.smin : 0.0;
+}
+
 __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32_t T,
                                                   const float* __restrict__ depth,
                                                   const double* __restrict__ poses, noise_k nz,
@@ -34,48 +96,51 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
   const int32_t i = (int32_t)bf_compact3(key), j = (int32_t)bf_compact3(key >> 1),
                 k = (int32_t)bf_compact3(key >> 2);
   const int64_t plane = (int64_t)c.W * c.H;
-  double L = 0.0, B = 0.0, cnt = 0.0, sy = 0.0, syy = 0.0, ss = 0.0, smin = INFINITY;
-  for (int32_t t = 0; t < T; ++t) {
-    double D, Z;
-    if (!bf_observe(g, c, depth + t * plane, poses + 12 * t, i, j, k, D, Z)) continue;
-    const double d = D - Z;
-    if (d < -g.tau) continue;
-    const double y = d < g.tau ? d : g.tau;
-    const double e = D - nz.z0;
-    const double sd = nz.a + nz.c * (e * e);
-    double var = sd * sd + (nz.pose ? nz.pose[t] : 0.0);
-    var = var + nz.model;
-    const double w = 1.0 / var;
-    L = L + w;
-    B = B + w * y;
-    cnt = cnt + 1.0;
-    sy = sy + y;
-    syy = syy + y * y;
-    ss = ss + sd;
-    smin = sd < smin ? sd : smin;
-  }
+  obs_sums a;
+  for (int32_t t = 0; t < T; ++t)
+    add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
   const int32_t dg = deg[v];
-  double dq = L + lam * (double)dg;
-  dq = dq + eps;
-  double h = B;
-  if (lam_b != 0.0 && dg < 6) {
-    dq = dq + lam_b;
-    h = h + lam_b * tsdf[v];
-  }
-  Lambda[v] = L;
-  b[v] = B;
-  rhs[v] = h;
-  diag[v] = dq;
-  const double inv = 1.0 / dq;
-  dinv[v] = inv;
-  diag32[v] = (float)dq;
-  dinv32[v] = (float)inv;
-  double* a = acc + v * 5;
-  a[0] = cnt;
-  a[1] = sy;
-  a[2] = syy;
-  a[3] = ss;
-  a[4] = cnt > 0.0 ? smin : 0.0;
+  finish_voxel(a, v, dg, (lam_b != 0.0 && dg < 6) ? tsdf[v] : 0.0, lam, eps, lam_b, Lambda, b, rhs, diag, dinv,
+               diag32, dinv32, acc);
+}
+
+// More views appended to an assembled system: the sums of the first views
+// come back from Lambda, b and the statistics (the running minimum of sigma
+// is "none yet" for a voxel no view observed), and the new views continue
+// them in order, so the result is that of assembling all views at once.
+__global__ __launch_bounds__(256) void k_assemble_more(bf_grid_k g, bf_cam_k c, int32_t T,
+                                                       const float* __restrict__ depth,
+                                                       const double* __restrict__ poses, noise_k nz,
+                                                       const uint64_t* __restrict__ keys,
+                                                       const double* __restrict__ tsdf,
+                                                       const int32_t* __restrict__ deg, int64_t n, double lam,
+                                                       double eps, double lam_b, const double* __restrict__ L0,
+                                                       const double* __restrict__ b0,
+                                                       const double* __restrict__ acc0,
+                                                       double* __restrict__ Lambda, double* __restrict__ b,
+                                                       double* __restrict__ rhs, double* __restrict__ diag,
+                                                       double* __restrict__ dinv, float* __restrict__ diag32,
+                                                       float* __restrict__ dinv32, double* __restrict__ acc) {
+  const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint64_t key = keys[v];
+  const int32_t i = (int32_t)bf_compact3(key), j = (int32_t)bf_compact3(key >> 1),
+                k = (int32_t)bf_compact3(key >> 2);
+  const int64_t plane = (int64_t)c.W * c.H;
+  const double* a0 = acc0 + v * 5;
+  obs_sums a;
+  a.L = L0[v];
+  a.B = b0[v];
+  a.cnt = a0[0];
+  a.sy = a0[1];
+  a.syy = a0[2];
+  a.ss = a0[3];
+  a.smin = a0[0] > 0.0 ? a0[4] : INFINITY;
+  for (int32_t t = 0; t < T; ++t)
+    add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
+  const int32_t dg = deg[v];
+  finish_voxel(a, v, dg, (lam_b != 0.0 && dg < 6) ? tsdf[v] : 0.0, lam, eps, lam_b, Lambda, b, rhs, diag, dinv,
+               diag32, dinv32, acc);
 }
 
 __global__ __launch_bounds__(256) void k_apply_Q(const int32_t* __restrict__ nbr,
@@ -191,6 +256,63 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
     if (bf_status s = bf_launch_check(ctx, "k_assemble")) return fail(s);
   }
   *out = sys;
+  return BF_OK;
+}
+
+// The system `in` with T more views appended, into out's arrays (Lambda, b,
+// rhs, diag, dinv, diag32, dinv32, acc; they may not alias in's).
+bf_status bf_assemble_more_into(bf_ctx* ctx, const bf_system* in, const bf_camera* cam, int32_t T,
+                                const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                                bf_system* out) {
+  const bf_band* band = in->band;
+  const int64_t N = in->n;
+  out->n = N;
+  out->band = band;
+  out->lambda = in->lambda;
+  out->eps = in->eps;
+  out->lambda_b = in->lambda_b;
+  out->T = in->T + T;
+  out->kind = BF_SYSTEM_VOXEL;
+  if (N == 0) return BF_OK;
+  bf_grid_k gk{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
+  bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+  noise_k nz{noise->a, noise->c, noise->z0, noise->sigma2_model, noise->sigma2_pose_dev};
+  BF_LAUNCH(ctx, "assemble_more", k_assemble_more, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, gk, ck, T,
+            depth_dev, c2w_dev, nz, band->keys, band->tsdf, band->deg, N, in->lambda, in->eps, in->lambda_b,
+            in->Lambda, in->b, in->acc, out->Lambda, out->b, out->rhs, out->diag, out->dinv, out->diag32,
+            out->dinv32, out->acc);
+  return bf_launch_check(ctx, "k_assemble_more");
+}
+
+extern "C" bf_status bf_assemble_more(bf_ctx* ctx, const bf_system* sys, const bf_camera* cam, int32_t T,
+                                      const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
+                                      bf_system** out) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys && cam && noise && out, "bf_assemble_more: NULL argument");
+  *out = nullptr;
+  BF_CHECK(ctx, sys->kind == BF_SYSTEM_VOXEL, "bf_assemble_more: voxel-centric systems only");
+  BF_CHECK(ctx, T >= 0, "bf_assemble_more: T < 0");
+  BF_CHECK(ctx, T == 0 || sys->n == 0 || (depth_dev && c2w_dev && cam->width > 0 && cam->height > 0),
+           "bf_assemble_more: bad camera or NULL depth/poses");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  bf_system* ns = new (std::nothrow) bf_system();
+  if (!ns) return bf_fail(ctx, BF_ERR_OOM, "bf_assemble_more: host allocation");
+  const int64_t N = sys->n;
+  if (N > 0) {
+    if (bf_status s = bf_obj_alloc_parts(ctx, &ns->block,
+                                         {{(void**)&ns->Lambda, (size_t)N * 8}, {(void**)&ns->b, (size_t)N * 8},
+                                          {(void**)&ns->rhs, (size_t)N * 8}, {(void**)&ns->diag, (size_t)N * 8},
+                                          {(void**)&ns->dinv, (size_t)N * 8}, {(void**)&ns->diag32, (size_t)N * 4},
+                                          {(void**)&ns->dinv32, (size_t)N * 4}, {(void**)&ns->acc, (size_t)N * 40}})) {
+      bf_system_free(ctx, ns);
+      return s;
+    }
+  }
+  if (bf_status s = bf_assemble_more_into(ctx, sys, cam, T, depth_dev, c2w_dev, noise, ns)) {
+    bf_system_free(ctx, ns);
+    return s;
+  }
+  *out = ns;
   return BF_OK;
 }
 

@@ -357,6 +357,80 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
   }
 }
 
+// The view a sensor with camera R.cam would take from pose P, predicted from
+// the mean (the observations a candidate adds, for the post-view variance of
+// eq. 13): each pixel's ray is walked voxel by voxel, the walk of
+// bf_nbv_score without jumps, to the first band voxel with mu <= 0; the
+// pixel's depth is that voxel centre's camera-z depth, rounded to float, and
+// 0 (no return) when the ray meets none.  One thread per pixel.
+__global__ __launch_bounds__(256) void k_pred_depth(ray_k R, const double* __restrict__ P,
+                                                    const bf_cell* __restrict__ cells,
+                                                    const double* __restrict__ mu,
+                                                    const uint32_t* __restrict__ bricks_g, float* __restrict__ depth) {
+#pragma clang fp contract(off)
+  __shared__ uint32_t bricks[kMaxBrickWords];
+  const int words = (R.nbrick * R.nbrick * R.nbrick + 31) / 32;
+  for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
+  __syncthreads();
+  const bf_grid_k& g = R.g;
+  const double org[3] = {g.ox, g.oy, g.oz};
+  const double o[3] = {P[3], P[7], P[11]};
+  const int bs = R.brick_shift, NB = R.nbrick, NC = R.ncell;
+  const int64_t npix = (int64_t)R.cam.W * R.cam.H;
+  for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < npix; p += (int64_t)gridDim.x * kThreads) {
+    const int32_t row = (int32_t)(p / R.cam.W), col = (int32_t)(p % R.cam.W);
+    Ray r;
+    float z = 0.0f;
+    if (ray_init(r, R, P, o, row, col)) {
+      for (int32_t it = 0; it < 3 * g.G + 3; ++it) {
+        const int32_t bit = (int32_t)((((uint32_t)r.idx[2] >> bs) * NB + ((uint32_t)r.idx[1] >> bs)) * NB +
+                                      ((uint32_t)r.idx[0] >> bs));
+        if ((bricks[bit >> 5] >> (bit & 31)) & 1u) {
+          const uint32_t c = (((uint32_t)r.idx[2] >> 2) * (uint32_t)NC + ((uint32_t)r.idx[1] >> 2)) * (uint32_t)NC +
+                             ((uint32_t)r.idx[0] >> 2);
+          const uint32_t m = (r.idx[0] & 1) | ((r.idx[1] & 1) << 1) | ((r.idx[2] & 1) << 2) |
+                             ((r.idx[0] & 2) << 2) | ((r.idx[1] & 2) << 3) | ((r.idx[2] & 2) << 4);
+          const bf_cell cl = cells[c];
+          if ((cl.mask >> m) & 1ull) {
+            const int32_t v = cl.start + __popcll(cl.mask & ((1ull << m) - 1ull));
+            if (mu[v] <= 0.0) {
+              const double x = org[0] + ((double)r.idx[0] + 0.5) * g.h;
+              const double y = org[1] + ((double)r.idx[1] + 0.5) * g.h;
+              const double zc = org[2] + ((double)r.idx[2] + 0.5) * g.h;
+              const double dx = x - P[3], dy = y - P[7], dz = zc - P[11];
+              z = (float)((P[2] * dx + P[6] * dy) + P[10] * dz);
+              break;
+            }
+          }
+        }
+        // step across the nearest plane, lowest axis on ties
+        int ax = 0;
+        double tm = r.tn[0];
+        if (r.tn[1] < tm) {
+          ax = 1;
+          tm = r.tn[1];
+        }
+        if (r.tn[2] < tm) ax = 2;
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (a == ax) {
+            r.idx[a] += r.step[a];
+            inside = r.idx[a] >= 0 && r.idx[a] < g.G;
+            r.tn[a] = plane_t(org[a], g.h, o[a], r.inv[a], r.idx[a] + (r.step[a] > 0 ? 1 : 0));
+          }
+        if (!inside) break;
+      }
+    }
+    depth[p] = z;
+  }
+}
+
+__global__ void k_zero_f32(float* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0f;
+}
+
 // Clears the scores and the walk's three workspace words (maximum variance,
 // best index and hand-out counter, visit count).
 __global__ void k_zero_i64(int64_t* p, int n, uint64_t* ws3) {
@@ -473,6 +547,33 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   *best_host = pin[0];
   ctx->nbv_walk_steps = *(const int64_t*)(pin + 2);
   return BF_OK;
+}
+
+extern "C" bf_status bf_predict_depth(bf_ctx* ctx, const bf_band* band, const double* mu_dev,
+                                      const double* c2w_dev, const bf_camera* cam, float* depth_dev) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, band && cam && c2w_dev && depth_dev, "bf_predict_depth: NULL argument");
+  BF_CHECK(ctx, cam->width > 0 && cam->height > 0 && (int64_t)cam->width * cam->height < (1ll << 31),
+           "bf_predict_depth: bad camera");
+  BF_CHECK(ctx, band->n == 0 || mu_dev, "bf_predict_depth: NULL mu");
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  const int64_t npix = (int64_t)cam->width * cam->height;
+  ray_k R{};
+  R.g = bf_grid_k{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
+  R.cam = bf_cam_k{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
+  R.brick_shift = band->brick_shift;
+  R.nbrick = band->nbrick;
+  R.nbrick3 = band->nbrick * band->nbrick * band->nbrick;
+  R.ncell = band->ncell;
+  if (band->n == 0) {  // an empty band: no ray meets a surface
+    BF_LAUNCH(ctx, "pred_depth", k_zero_f32, dim3((unsigned)std::min<int64_t>(bf_cdiv(npix, kThreads), 4096)),
+              dim3(kThreads), 0, depth_dev, npix);
+    return bf_launch_check(ctx, "k_zero_f32");
+  }
+  const unsigned grid = (unsigned)std::min<int64_t>(bf_cdiv(npix, kThreads), 8 * (int64_t)ctx->cu_count);
+  BF_LAUNCH(ctx, "pred_depth", k_pred_depth, dim3(grid), dim3(kThreads), 0, R, c2w_dev, band->cells, mu_dev,
+            band->bricks, depth_dev);
+  return bf_launch_check(ctx, "k_pred_depth");
 }
 
 extern "C" bf_status bf_nbv_walk_steps(bf_ctx* ctx, int64_t* steps) {
