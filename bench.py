@@ -551,6 +551,58 @@ def trilinear_section(g, args):
 NN_OPS_PER_PAIR = 9  # 3 differences, 3 products, 2 sums, 1 minimum (FP64)
 
 
+def postview_section(g, args, top=8):
+    """The post-view utility of eq. (13) on the headline pass: the `top`
+    candidates of the summed-variance walk are rescored with
+    U = sum (s - s') over the band voxels with |mu| <= the band half-width,
+    s' from the step's probes (same K, seed, precision and tolerance) once
+    each candidate's view, predicted from mu at the sensor's 640x480, is fused
+    as one more view; the probe solves start from s.  Times the rescoring."""
+    import torch
+    import paper_2602_19697_amd as bf
+    ctx, wl = g["ctx"], g["wl"]
+    prec = bf.L.BF_PREC_FP64 if args.precision == "fp64" else bf.L.BF_PREC_MIXED
+    K = args.probes
+    band = ctx.bf_build_band(g["grid"], wl.cam, g["depth"], g["poses"])
+    sys_ = ctx.bf_assemble(band, wl.cam, g["depth"], g["poses"], g["noise"], wl.lam, wl.eps)
+    x0 = lv = None
+    if args.learned:
+        params = torch.from_numpy(np.load(_weights(wl.lam))).to(ctx.device)
+        x0, lv = ctx.bf_warm_start(sys_, params, ctx.bf_features(sys_))
+    mu, _ = ctx.bf_pcg_solve(sys_, args.tol, precision=prec, x0=x0)
+    s, _ = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
+    scores, best = ctx.bf_nbv_score(band, mu, s, g["cands"], wl.ray_cam)
+    sc = scores.cpu().numpy()
+    which = [int(i) for i in np.argsort(-sc, kind="stable")[:top]]
+
+    def rescore():
+        return ctx.bf_nbv_postview(sys_, mu, s, g["cands"], which, wl.cam, g["noise"], K, 0, args.tol, precision=prec,
+                                   eps_band=wl.band, warm=True)
+
+    rescore()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U, pbest, _, reps = rescore()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.bf_get_timings()
+    ctx.bf_set_timing(True)
+    rescore()
+    ctx.bf_set_timing(False)
+    tm = ctx.bf_get_timings()
+    sys_.free()
+    band.free()
+    log(f"[postview] top {top}: {dt * 1e3 / top:.2f} ms per candidate; walk best {best}, post-view best {pbest}")
+    return {"workload": f"{wl.name}: the top {top} of {wl.n_cand} candidates by the summed-variance walk, rescored; "
+                        f"{K} {args.precision} probes to {args.tol} from s; predicted views at "
+                        f"{wl.cam.width}x{wl.cam.height}; Omega = band voxels with |mu| <= {wl.band} m",
+            "candidates": which, "walk_scores": [int(sc[i]) for i in which], "postview_utility": U,
+            "walk_best": int(best), "postview_best": int(pbest), "ms_per_candidate": dt * 1e3 / top,
+            "probe_iters": [r["iters"] for r in reps], "used_warm_start": [r["used_warm_start"] for r in reps],
+            "kernels_ms_per_candidate": {k: ms / top for k, (n, ms) in sorted(tm.items(), key=lambda kv: -kv[1][1])
+                                         if ms / top > 0.005}}
+
+
 def surface_section(g, args):
     """Algorithm 1 step 7 and the geometry metrics of Sec. 4.2 on the step's
     workload: marching-tetrahedra meshes of the coarse TSDF and of the mean of
@@ -821,6 +873,7 @@ def main():
     ap.add_argument("--no-solver-roofline", action="store_true")
     ap.add_argument("--no-trilinear", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
+    ap.add_argument("--no-postview", action="store_true")
     ap.add_argument("--solver-workload", default="union1024")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
@@ -858,6 +911,7 @@ def main():
     batch = None if args.no_batch else batch_section(g, args)
     trilinear = None if args.no_trilinear else trilinear_section(g2, args)
     surface = None if args.no_surface else surface_section(g2, args)
+    postview = None if args.no_postview else postview_section(g, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(g, args)
     wl = g["wl"]
     roof = g["solver_roofline"]
@@ -922,6 +976,7 @@ def main():
         "batch": batch,
         "trilinear": trilinear,
         "surface": surface,
+        "nbv_postview": postview,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

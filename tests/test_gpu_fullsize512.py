@@ -175,3 +175,34 @@ def test_union512_walk_steps(union512):
     print(f"[union512] 16 candidates: walk steps {got} (oracle {int(steps.sum())})", flush=True)
     assert np.array_equal(scores.cpu().numpy(), want)
     assert got == int(steps.sum())
+
+
+def test_union512_postview(union512):
+    """Eq. (13) with the post-view variance at full size, on the oracle's (mu, s):
+    one candidate's predicted 640x480 view bit for bit, then U and s' of the
+    mixed rescoring (32 probes started from s, as the bench runs it) against the
+    oracle's FP64 post-view solve with the same probes (<= 1e-4)."""
+    import oracle as O
+    import paper_2602_19697_amd as bf
+    wl, ref, ctx, band, sys_ = union512
+    mu, _ = O.pcg(ref["nbr"], ref["diag"], wl.lam, ref["rhs"], 1e-10)
+    s = O.hutchinson(ref["nbr"], ref["diag"], wl.lam, 32, 0, 1e-10)
+    cands = wl.candidates()
+    c = 137
+    P = np.ascontiguousarray(cands[c].reshape(3, 4))
+    mu_d, s_d = torch.from_numpy(mu).to(gc.DEV), torch.from_numpy(s).to(gc.DEV)
+    t0 = time.time()
+    want = O.pred_depth(ref["grid"], ref["cam"], ref["keys"], mu, P)
+    got = ctx.bf_predict_depth(band, mu_d, torch.from_numpy(P).to(gc.DEV), wl.cam).cpu().numpy()
+    assert np.array_equal(got, want) and (want > 0).sum() > 10000
+    U, best, s_post, reps = ctx.bf_nbv_postview(sys_, mu_d, s_d, torch.from_numpy(np.ascontiguousarray(cands)).to(gc.DEV),
+                                                [c], wl.cam, bf.noise_struct(*wl.noise), 32, 0, 1e-6,
+                                                precision=bf.L.BF_PREC_MIXED, eps_band=wl.band, warm=True, keep_s=True)
+    Uo, sp, _, _, _ = O.nbv_postview(ref["grid"], ref["cam"], ref["keys"], ref["nbr"], ref["deg"], ref["Lambda"],
+                                     wl.lam, wl.eps, mu, s, P, 32, 0, 1e-10, eps_band=wl.band, noise=wl.noise)
+    err = gc.rel_l2(s_post[0].cpu().numpy(), sp)
+    scale = float(np.abs(s)[np.abs(mu) <= wl.band].sum())
+    print(f"[union512] post-view cand {c}: {(want > 0).sum()} returns; U {U[0]:.6e} (oracle {Uo:.6e}) s' err "
+          f"{err:.2e}, probe iters {reps[0]['iters']} (oracle side {time.time() - t0:.1f} s)", flush=True)
+    assert best == c and reps[0]["status"] == 0 and reps[0]["used_warm_start"] == 1
+    assert err <= 1e-4 and abs(U[0] - Uo) <= 1e-4 * scale and Uo > 0.0
