@@ -119,6 +119,8 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         if fp64:
             return N * (24 + 8 + K / 8 + 8 * K), "B", "hbm"
         return N * (24 + 8 + K / 8 + (8 if warm else 0) + 4 * K), "B", "hbm"
+    if name == "block_start_res":  # from +-w: nbr, diag, w, signs in; per column r, zz out (+ x64 in FP64)
+        return N * (24 + 8 + 8 + K / 8 + 2 * K * s + (8 * K if fp64 else 0)), "B", "hbm"
     if name == "block_residual":  # as verify, plus r and z stored per column
         return N * (24 + 8 + 8 * K + 2 * K * s), "B", "hbm"
     if name == "pcg_residual":  # nbr, diag, rhs, x (FP64) -> r, z

@@ -59,13 +59,15 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   const V beta = (V)st->beta[c];
   // FIRST (the first iteration's launch; every active column starts there):
   // the direction is z (beta = 0) and p_old is not read, as if it held zeros
-  // (z + 0 * 0, the same value), so it needs no clearing.  A separate
-  // instantiation, so the later launches carry no switch around their loads.
+  // (z + 0 * 0, the same value), so it needs no clearing; nor is p written:
+  // it equals z, which stays where it is and serves as this iteration's p.
+  // A separate instantiation, so the later launches carry no switch around
+  // their loads.
   constexpr bool first = FIRST;
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
     if constexpr (KC == 1) {
-      if (act) tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0]);
+      if (act) tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0], !first);
     } else {
       __syncthreads();  // the previous tile's readers are done
       if (act) {
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
             const int64_t e = vr[j] * KC + c;
             const V pv = pt[(vr[j] - r0) * KC + c];
             const V qv = diag[vr[j]] * pv - lam * sacc[j];
-            p_new[e] = pv;
+            if constexpr (!FIRST) p_new[e] = pv;
             q[e] = qv;
             v1[0] += (double)pv * (double)qv;
           }
@@ -911,7 +913,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
               dim3(kThreads), 0, o->seed, o->K, zb, N);
     if (logvar) {
       BF_LAUNCH(ctx, "block_start", k_bweight, dim3(rows_grid), dim3(kThreads), 0, logvar, sys->diag, wst, N);
-      BF_LAUNCH(ctx, "block_residual", (k_bstart_res<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+      BF_LAUNCH(ctx, "block_start_res", (k_bstart_res<V, KC>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
                 sys->diag, sys->lambda, zb, wst, x64, dinvV, r, zz, N, part, mixed7 ? 0 : 1);
     } else {
       BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_INIT, false, false>), dim3(nb), dim3(kThreads), 0, st,
@@ -921,7 +923,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   }
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   if (logvar) {  // columns whose start was no better than zero restart from x = 0
-    BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
+    BF_LAUNCH(ctx, "block_guard", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
               sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1);
     BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
   }
@@ -937,6 +939,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const unsigned hutch_grid = (unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 8 * (int64_t)ctx->cu_count);
   V* pa = p0;
   V* pb = p1;
+  // the buffer holding the current zz.  The 7-point path's first iteration
+  // uses p_0 = zz_0 in place (its A does not copy it), so its B writes zz_1 to
+  // pa's buffer, and zz_0's buffer becomes the next iteration's p_old.
+  V* zc = zz;
   std::vector<size_t> iter_rec;  // timing record count at the start of each iteration
   // the 7-point estimate: u = x64 (+ the float corrections, which this path folds
   // only for columns that restart from a stored residual)
@@ -964,38 +970,45 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         case 16:
           if (it == 0)
             BF_LAUNCH(ctx, "block_A_first", (k_bA<V, KC, 16, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
           else
             BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 16, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
           break;
         case 64:
           if (it == 0)
             BF_LAUNCH(ctx, "block_A_first", (k_bA<V, KC, 64, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
           else
             BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 64, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
           break;
         default:
           if (it == 0)
             BF_LAUNCH(ctx, "block_A_first", (k_bA<V, KC, 32, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
           else
             BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zz, pa, pb, q, N, part);
+                      diagV, lamV, zc, pa, pb, q, N, part);
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
+      const bool moved = it == 0 && !tri;  // p_0 in zz_0's buffer, zz_1 to pa's
+      V* bp = moved ? zc : pb;
+      V* bz = moved ? pa : zc;
       if (it == 0 && gen_start)
-        BF_LAUNCH(ctx, "block_B_first", (k_bB_gen<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin, r, zz,
+        BF_LAUNCH(ctx, "block_B_first", (k_bB_gen<V, KC>), dim3(nb), dim3(kThreads), 0, st, dinvV, bp, q, xin, r, bz,
                   N, part, (const uint32_t*)zb);
       else if (it == 0 && (zero_start || mixed7))
-        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q,
-                  xin, r, zz, N, part, o->seed);
+        BF_LAUNCH(ctx, "block_B_first", (k_bB<V, KC, true, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, bp, q,
+                  xin, r, bz, N, part, o->seed);
       else
-        BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, false, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, pb, q, xin,
-                  r, zz, N, part, o->seed);
+        BF_LAUNCH(ctx, "block_B", (k_bB<V, KC, false, false>), dim3(nb), dim3(kThreads), 0, st, dinvV, bp, q, xin,
+                  r, bz, N, part, o->seed);
       BF_LAUNCH(ctx, "block_scalars", k_bscal_B<KC>, dim3(KC), dim3(256), 0, st, part, nb);
+      if (moved) {
+        pa = zc;  // p_0, the next iteration's p_old
+        zc = bz;
+      }
       if (tri) {
         if (mixed) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 0, x64, cf, N);
         // columns the recurrence calls converged: FP64 residual norms without
@@ -1011,19 +1024,19 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         // columns to go on from a stored FP64 residual fold (mixed) and store it
         if (mixed)
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, true>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
         else
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_VERIFY, part, nb);
         if (mixed)
           BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, wst,
                     (const uint32_t*)zb, N);
         BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_CHECK, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, 0, 1);
+                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 1);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       }
-      std::swap(pa, pb);
+      if (!moved) std::swap(pa, pb);
     }
     BF_TRY(bf_launch_check(ctx, "block pcg iteration"));
     // FP64: the estimate is formed behind every batch, so the poll that finds

@@ -147,10 +147,12 @@ struct TileWalk {
 constexpr int kRowsInFlight = 4;
 
 template <typename V, int KC>
+// store_p: write p_new (the first iteration's direction p = zz can stay
+// where zz is instead).
 __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t* __restrict__ nbr,
                                        const V* __restrict__ diag, V lam, const V* __restrict__ zz,
                                        const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
-                                       int64_t r0, int64_t r1, double& acc1) {
+                                       int64_t r0, int64_t r1, double& acc1, bool store_p = true) {
   constexpr int RS = kThreads / KC;
   constexpr int U = kRowsInFlight;
   for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
@@ -181,7 +183,7 @@ __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t*
       if (v0 + j * RS >= r1) break;
       const int64_t e = vr[j] * KC + c;
       const V qv = diag[vr[j]] * pv[j] - lam * s[j];
-      p_new[e] = pv[j];
+      if (store_p) p_new[e] = pv[j];
       q[e] = qv;
       acc1 += (double)pv[j] * (double)qv;
     }
