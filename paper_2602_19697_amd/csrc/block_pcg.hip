@@ -301,9 +301,10 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
                                                     double* __restrict__ x64, const V* __restrict__ dinv,
                                                     V* __restrict__ r, V* __restrict__ zz, int64_t n,
                                                     double* __restrict__ part, int store_x) {
-  // one column: every lane is its own row, so the row data is read directly
+  // one column: every lane is its own row, so the row data is read directly;
+  // otherwise one row per thread is staged (as in k_bres)
   constexpr bool kStage = KC > 1;
-  constexpr int R = kRowsPerTile<KC>;
+  constexpr int R = kStage ? kThreads : kRowsPerTile<KC>;
   constexpr int RS = kThreads / KC;
   constexpr int RT = kStage ? R : 1;
   __shared__ double lds[4 * 3 * 64];
@@ -403,11 +404,13 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
                                               const float* __restrict__ cf, const double* __restrict__ w,
                                               const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
                                               int64_t n, double* __restrict__ part, int write_x0, int store_r) {
-  constexpr int R = kRowsPerTile<KC>;
-  constexpr int RS = kThreads / KC;
   // one column: every lane is its own row and nothing is shared, so the row
-  // data is read directly; otherwise it is staged per tile in LDS
+  // data is read directly; otherwise it is staged per tile in LDS, one row per
+  // thread (a dependent chain of loads: neighbour indices, then the
+  // neighbours' start weights and signs), amortised over the tile's rows
   constexpr bool kStage = KC > 1;
+  constexpr int R = kStage ? kThreads : kRowsPerTile<KC>;
+  constexpr int RS = kThreads / KC;
   // mixed VERIFY from a warm start: the start weights and packed signs of each
   // row and its neighbours are staged with the row data, so a column lane
   // regenerates +-w from LDS and gathers only its float correction
