@@ -68,6 +68,7 @@ struct ray_k {
 };
 
 constexpr int kMaxBrickWords = 64 * 64 * 64 / 32;
+constexpr int kMaxTable = 256;  // ray cameras up to this many columns and rows use quotient tables
 // Defaults of the walk's tuning knobs (see ray_k); BF_NBV_JUMP_MIN,
 // BF_NBV_JUMP_BATCH and BF_NBV_REFILL_BATCH override them.  None changes a result.
 constexpr int kJumpMinDist = 1;
@@ -112,12 +113,15 @@ struct Ray {
 
 // Starts the ray through pixel (row, col) of the candidate camera at o with
 // rotation P; false when it misses the grid (utility 0).
+// ta, tb (may be null): the quotients (col - cx)/fx and (row - cy)/fy of
+// every column and row, the same values computed once per launch.
 __device__ __forceinline__ bool ray_init(Ray& r, const ray_k& R, const double* __restrict__ P, const double (&o)[3],
-                                         int32_t row, int32_t col) {
+                                         int32_t row, int32_t col, const double* ta = nullptr,
+                                         const double* tb = nullptr) {
 #pragma clang fp contract(off)
   const bf_grid_k& g = R.g;
-  const double a = ((double)col - R.cam.cx) / R.cam.fx;
-  const double b = ((double)row - R.cam.cy) / R.cam.fy;
+  const double a = ta ? ta[col] : ((double)col - R.cam.cx) / R.cam.fx;
+  const double b = tb ? tb[row] : ((double)row - R.cam.cy) / R.cam.fy;
   r.d[0] = (P[0] * a + P[1] * b) + P[2];
   r.d[1] = (P[4] * a + P[5] * b) + P[6];
   r.d[2] = (P[8] * a + P[9] * b) + P[10];
@@ -294,8 +298,16 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
                 const uint32_t* __restrict__ bricks_g, unsigned int* __restrict__ queue,
                 unsigned long long* __restrict__ walk_steps, unsigned long long* __restrict__ scores) {
   __shared__ uint32_t bricks[kMaxBrickWords];
+  __shared__ double tcol[kMaxTable], trow[kMaxTable];
   const int words = (R.nbrick * R.nbrick * R.nbrick + 31) / 32;
   for (int w = threadIdx.x; w < words; w += kThreads) bricks[w] = bricks_g[w];
+  // the pixel quotients of ray_init once per workgroup (cameras up to 256 x 256)
+  const bool tables = R.cam.W <= kMaxTable && R.cam.H <= kMaxTable;
+  if (tables) {
+#pragma clang fp contract(off)
+    for (int t = threadIdx.x; t < R.cam.W; t += kThreads) tcol[t] = ((double)t - R.cam.cx) / R.cam.fx;
+    for (int t = threadIdx.x; t < R.cam.H; t += kThreads) trow[t] = ((double)t - R.cam.cy) / R.cam.fy;
+  }
   __syncthreads();
   const double smax = *smax_p;
   const int lane = threadIdx.x & 63;
@@ -335,7 +347,8 @@ void k_nbv_rays(ray_k R, const double* __restrict__ cands, const bf_cell* __rest
           // registers across the whole walk loop (they would spill)
           const double* Pi = P;
           asm volatile("" : "+s"(Pi));
-          live = ray < nrays && row < R.cam.H && col < R.cam.W && ray_init(r, R, Pi, o, row, col);
+          live = ray < nrays && row < R.cam.H && col < R.cam.W &&
+                 ray_init(r, R, Pi, o, row, col, tables ? tcol : nullptr, tables ? trow : nullptr);
         }
         base += __popcll(need);
         continue;
