@@ -218,7 +218,11 @@ bf_status bf_band_free(bf_ctx* ctx, bf_band* band);
  * (same acceptance as the TSDF), y = min(D - Z, tau) with weight 1/sigma^2.
  * Builds Lambda, b, the anchored right-hand side and diag(Q) =
  * Lambda + lambda deg + eps (+ lambda_b on the boundary); the off-diagonal
- * entries -lambda on band edges are implicit.  Writes *out. */
+ * entries -lambda on band edges are implicit.  Writes *out.
+ * Given the depth maps and poses the band was built from (the same device
+ * arrays, T and camera, unchanged since), a screened band's per-cell view
+ * masks let each voxel skip the views proved to observe no voxel of its 4^3
+ * cell; the sums, taken in view order, are the same bits either way. */
 bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_camera* cam, int32_t T,
                       const float* depth_dev, const double* c2w_dev, const bf_noise* noise,
                       const bf_prior* prior, bf_system** out);

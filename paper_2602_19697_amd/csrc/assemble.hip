@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
                                                   double* __restrict__ Lambda, double* __restrict__ b,
                                                   double* __restrict__ rhs, double* __restrict__ diag,
                                                   double* __restrict__ dinv, float* __restrict__ diag32,
-                                                  float* __restrict__ dinv32, double* __restrict__ acc) {
+                                                  float* __restrict__ dinv32, double* __restrict__ acc,
+                                                  const uint32_t* __restrict__ vmask, int vw) {
 #pragma clang fp contract(off)
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
@@ -97,7 +98,22 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
                 k = (int32_t)bf_compact3(key >> 2);
   const int64_t plane = (int64_t)c.W * c.H;
   obs_sums a;
-  for (int32_t t = 0; t < T; ++t)
+  int32_t t0 = 0;
+  if (vmask) {
+    // the band's screen proved that a view with a clear bit observes no voxel
+    // of this voxel's cell: only the set bits are visited, in view order, so
+    // every sum is the one over all views
+    for (int q = 0; q < vw; ++q) {
+      uint32_t bits = vmask[v * vw + q];
+      while (bits) {
+        const int32_t t = 32 * q + __builtin_ctz(bits);
+        bits &= bits - 1u;
+        add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
+      }
+    }
+    t0 = 32 * vw < T ? 32 * vw : T;  // views past the masked ones
+  }
+  for (int32_t t = t0; t < T; ++t)
     add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
   const int32_t dg = deg[v];
   finish_voxel(a, v, dg, (lam_b != 0.0 && dg < 6) ? tsdf[v] : 0.0, lam, eps, lam_b, Lambda, b, rhs, diag, dinv,
@@ -249,10 +265,16 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
     bf_grid_k gk{band->G, band->h, band->origin[0], band->origin[1], band->origin[2], band->tau, band->band};
     bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
     noise_k nz{noise->a, noise->c, noise->z0, noise->sigma2_model, noise->sigma2_pose_dev};
+    // the band's view masks hold for the depth maps and poses it was built from
+    const bool masks = band->vmask && depth_dev == band->view_depth && c2w_dev == band->view_poses &&
+                       T == band->view_T && cam->width == band->view_W && cam->height == band->view_H &&
+                       cam->fx == band->view_f[0] && cam->fy == band->view_f[1] && cam->cx == band->view_f[2] &&
+                       cam->cy == band->view_f[3];
     BF_LAUNCH(ctx, "assemble", k_assemble, dim3((unsigned)bf_cdiv(N, 256)), dim3(256), 0, gk, ck, T,
                        depth_dev, c2w_dev, nz, band->keys, band->tsdf, band->deg, N, prior->lambda,
                        prior->eps, prior->lambda_b, sys->Lambda, sys->b, sys->rhs, sys->diag, sys->dinv,
-                       sys->diag32, sys->dinv32, sys->acc);
+                       sys->diag32, sys->dinv32, sys->acc, masks ? band->vmask : nullptr,
+                       masks ? band->vmask_words : 0);
     if (bf_status s = bf_launch_check(ctx, "k_assemble")) return fail(s);
   }
   *out = sys;

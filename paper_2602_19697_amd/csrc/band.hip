@@ -537,7 +537,9 @@ __global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double ban
                                                       const uint32_t* __restrict__ cellmask,
                                                       uint64_t* __restrict__ keys,
                                                       double* __restrict__ tsdf,
-                                                      int32_t* __restrict__ w) {
+                                                      int32_t* __restrict__ w,
+                                                      const uint32_t* __restrict__ cmask, int vw,
+                                                      uint32_t* __restrict__ vmask) {
   __shared__ uint32_t wave_cnt[kThreads / 64];
   if (counts[blockIdx.x] == 0) return;  // the whole block: no band voxel in the tile
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
@@ -568,6 +570,10 @@ __global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double ban
       keys[o] = m;
       tsdf[o] = t;
       w[o] = W;
+      if (vmask) {  // the screen's view mask of the voxel's cell (one wave = one cell)
+        const uint32_t* cm = cmask + (int64_t)blockIdx.x * (kCells * kMaskWords) + (it * (kThreads / 64) + wid) * kMaskWords;
+        for (int q = 0; q < vw; ++q) vmask[o * vw + q] = cm[q];
+      }
     }
     out += row;
   }
@@ -777,6 +783,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   bf_cam_k ck{cam->width, cam->height, cam->fx, cam->fy, cam->cx, cam->cy};
   // screening pyramid (off when the dense grid is kept, or when truncation does not exceed the band)
   const int screen = (!(flags & BF_BAND_KEEP_DENSE) && grid->tau > grid->band && npix > 0) ? 1 : 0;
+  // words of the per-voxel view masks kept for the assembly (views past kTileViews are never masked)
+  const int vw = screen ? (std::min<int32_t>(T, kTileViews) + 31) / 32 : 0;
   if (npix > 0 && !screen) {  // with screening the pyramid kernel validates the depth
     const int vb = (int)std::min<int64_t>(bf_cdiv(npix, 256), 8192);
     BF_LAUNCH(ctx, "validate_depth", k_validate_depth, dim3(vb), dim3(256), 0, depth_dev, npix, dflags);
@@ -861,10 +869,26 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
             {{(void**)&band->keys, N * sizeof(uint64_t)}, {(void**)&band->tsdf, N * sizeof(double)},
              {(void**)&band->w, N * sizeof(int32_t)}, {(void**)&band->nbr, N * 6 * sizeof(int32_t)},
              {(void**)&band->deg, N * sizeof(int32_t)}, {(void**)&band->cells, (size_t)nc3 * sizeof(bf_cell)},
-             {(void**)&band->bricks, words * 4}, {(void**)&band->brick_dist, (size_t)(8 * nbr3)}}))
+             {(void**)&band->bricks, words * 4}, {(void**)&band->brick_dist, (size_t)(8 * nbr3)},
+             {(void**)&band->vmask, screen ? N * vw * sizeof(uint32_t) : 0}}))
       return fail(s);
+    if (screen) {
+      band->vmask_words = vw;
+      band->view_depth = depth_dev;
+      band->view_poses = c2w_dev;
+      band->view_T = T;
+      band->view_W = cam->width;
+      band->view_H = cam->height;
+      band->view_f[0] = cam->fx;
+      band->view_f[1] = cam->fy;
+      band->view_f[2] = cam->cx;
+      band->view_f[3] = cam->cy;
+    } else {
+      band->vmask = nullptr;
+    }
     BF_LAUNCH(ctx, "band_scatter", k_band_scatter, dim3((unsigned)nblocks), dim3(kThreads), 0, total,
-                       grid->band, dense_t, dense_w, offsets, counts, cellmask, band->keys, band->tsdf, band->w);
+                       grid->band, dense_t, dense_w, offsets, counts, cellmask, band->keys, band->tsdf, band->w, vmask,
+                       vw, screen ? band->vmask : nullptr);
     if (bf_status s = bf_launch_check(ctx, "k_band_scatter")) return fail(s);
 
     const unsigned nb = (unsigned)bf_cdiv((int64_t)N, 256);

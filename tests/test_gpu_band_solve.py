@@ -88,6 +88,27 @@ def test_assembly_bitexact(ctx, name):
     band.free()
 
 
+@pytest.mark.parametrize("name", ["sphere64", "union128"])
+def test_assembly_view_masks_exact(ctx, name):
+    """The assembly of a screened band skips the views its screen proved give a
+    voxel's cell no observation, but only for the depth maps and poses the band
+    was built from: the same arrays (masks used) and a copy of them (masks not
+    used: other device arrays) give the same bits, equal to the oracle's."""
+    import paper_2602_19697_amd as bf
+    wl = gc.workload(name)
+    ref = gc.oracle_ref(name)
+    band, sys_, depth, poses = gc.gpu_system(ctx, wl)
+    other = ctx.bf_assemble(band, wl.cam, depth.clone(), poses.clone(), bf.noise_struct(*wl.noise), wl.lam, wl.eps)
+    a, b = sys_.arrays(), other.arrays()
+    for k in ("Lambda", "b", "rhs", "diag", "acc"):
+        assert torch.equal(a[k], b[k]), k
+    assert np.array_equal(a["Lambda"].cpu().numpy(), ref["Lambda"])
+    assert np.array_equal(a["acc"].cpu().numpy(), ref["acc"])
+    other.free()
+    sys_.free()
+    band.free()
+
+
 def test_assembly_anchor_bitexact(ctx):
     import oracle as O
     wl = gc.workload("sphere64")
