@@ -153,44 +153,79 @@ __device__ __forceinline__ void layer(const bf16x8* __restrict__ sw, int tbase, 
 }
 
 // Inference: physical outputs [n][2]; optionally the warm start
-// x0 = rhs/diag + h*o0 and logvar = o1.
+// x0 = rhs/diag + h*o0 and logvar = o1.  The weight tiles, biases and the
+// input and output scalings sit in LDS (the same values load_consts gives a
+// lane) and are read there in every iteration: kept in registers across the
+// loop they held the kernel to two waves per SIMD, too few to overlap the
+// chains of dependent MFMAs.
 __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ wt, const float* __restrict__ prm,
                                                      const float* __restrict__ feat, int64_t n,
                                                      float* __restrict__ out, const double* __restrict__ rhs,
                                                      const double* __restrict__ diag, double h,
                                                      double* __restrict__ x0, float* __restrict__ logvar) {
   __shared__ bf16x8 sw[NFWD * 64];
+  __shared__ float sb[3 * NH], sim[16], sii[16], so[6];
   for (int i = threadIdx.x; i < NFWD * 64; i += blockDim.x) sw[i] = wt[i];
+  for (int i = threadIdx.x; i < 3 * NH; i += blockDim.x) {
+    const int l = i / NH, u = i % NH;
+    sb[i] = prm[(l == 0 ? ob1 : (l == 1 ? ob2 : ob3)) + u];
+  }
+  if (threadIdx.x < 16) {
+    const int f = threadIdx.x;
+    sim[f] = f < NIN ? prm[oInMean + f] : 0.0f;
+    sii[f] = f < NIN ? 1.0f / prm[oInStd + f] : 0.0f;
+  }
+  if (threadIdx.x == 0) {
+    so[0] = prm[ob4];
+    so[1] = prm[ob4 + 1];
+    so[2] = prm[oOutMean];
+    so[3] = prm[oOutMean + 1];
+    so[4] = prm[oOutStd];
+    so[5] = prm[oOutStd + 1];
+  }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, col = lane & 15;
-  lane_consts k;
-  load_consts(prm, g, k);
   const int64_t ntile = (n + 15) / 16;
   for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4) {
+    // an offset of zero the compiler cannot see through: the weight reads
+    // below stay in the loop instead of being hoisted into registers
+    int z0;
+    asm volatile("s_mov_b32 %0, 0" : "=s"(z0));
+    const bf16x8* swl = sw + z0 + lane;
     const int64_t v = t * 16 + col;
     const bool valid = v < n;
-    float xs[8];
-    const bf16x8 B0 = load_input(feat, v, valid, g, k, xs);
+    bf16x8 B0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int f = 8 * g + e;
+      float x = 0.0f;
+      if (valid && f < NIN) x = (feat[v * NIN + f] - sim[f]) * sii[f];
+      B0[e] = (__bf16)x;
+    }
     f32x4 acc[4];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt) {
       f32x4 a = {0.f, 0.f, 0.f, 0.f};
-      acc[mt] = mfma(sw[(T_L1 + mt) * 64 + lane], B0, a);
+      acc[mt] = mfma(swl[(T_L1 + mt) * 64], B0, a);
     }
-    float z[16];
     bf16x8 B[2];
-    activate(acc, k.bias[0], z, B);
-    layer(sw, T_L2, lane, B, acc);
-    activate(acc, k.bias[1], z, B);
-    layer(sw, T_L3, lane, B, acc);
-    activate(acc, k.bias[2], z, B);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+      // D (+bias) -> SiLU -> the next B operands (see activate)
+      const float* bl = sb + l * NH + 4 * g;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) B[mt >> 1][(mt & 1) * 4 + j] = (__bf16)silu(acc[mt][j] + bl[16 * mt + j]);
+      if (l < 2) layer(swl - lane, l == 0 ? T_L2 : T_L3, lane, B, acc);
+    }
     f32x4 o = {0.f, 0.f, 0.f, 0.f};
-    o = mfma(sw[(T_L4 + 0) * 64 + lane], B[0], o);
-    o = mfma(sw[(T_L4 + 1) * 64 + lane], B[1], o);
+    o = mfma(swl[(T_L4 + 0) * 64], B[0], o);
+    o = mfma(swl[(T_L4 + 1) * 64], B[1], o);
     if (g == 0 && valid) {
-      const float p0 = (o[0] + k.b4[0]) * k.ostd[0] + k.omean[0];
-      const float p1 = (o[1] + k.b4[1]) * k.ostd[1] + k.omean[1];
+      const float p0 = (o[0] + so[0]) * so[4] + so[2];
+      const float p1 = (o[1] + so[1]) * so[5] + so[3];
       if (out) {
         out[2 * v] = p0;
         out[2 * v + 1] = p1;
