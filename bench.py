@@ -202,7 +202,7 @@ def run_gpu(args):
         band = ctx.bf_build_band(grid, wl.cam, depth, poses)
         sys_ = ctx.bf_assemble(band, wl.cam, depth, poses, noise, wl.lam, wl.eps)
         if params is not None:  # learned start: features -> network -> x0 and log-variance
-            x0, lv = ctx.bf_warm_start(sys_, params, ctx.bf_features(sys_))
+            x0, lv = ctx.bf_warm_start(sys_, params)  # features computed in the network's pass
         else:
             x0 = lv = None
         mu, rep = ctx.bf_pcg_solve(sys_, args.tol, precision=prec, x0=x0)
@@ -341,8 +341,7 @@ def compare_solvers(ctx, sys_, lam, K, reps=3, plain_reps=None):
         params = torch.from_numpy(np.load(path)).to(ctx.device)
 
         def learned():
-            f = ctx.bf_features(sys_)
-            x0, lv = ctx.bf_warm_start(sys_, params, f)
+            x0, lv = ctx.bf_warm_start(sys_, params)  # features computed in the network's pass
             _, r = ctx.bf_pcg_solve(sys_, tol, precision=MIXED, x0=x0)
             _, pr = ctx.bf_diag_estimate(sys_, K, 0, tol, precision=MIXED, logvar=lv)
             return [r["iters"], pr["col_iters"]]
@@ -570,7 +569,7 @@ def postview_section(g, args, top=8):
     x0 = lv = None
     if args.learned:
         params = torch.from_numpy(np.load(_weights(wl.lam))).to(ctx.device)
-        x0, lv = ctx.bf_warm_start(sys_, params, ctx.bf_features(sys_))
+        x0, lv = ctx.bf_warm_start(sys_, params)
     mu, _ = ctx.bf_pcg_solve(sys_, args.tol, precision=prec, x0=x0)
     s, _ = ctx.bf_diag_estimate(sys_, K, 0, args.tol, precision=prec, logvar=lv)
     scores, best = ctx.bf_nbv_score(band, mu, s, g["cands"], wl.ray_cam)

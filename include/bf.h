@@ -476,7 +476,9 @@ bf_status bf_features(bf_ctx* ctx, const bf_system* sys, float* feat_dev);
 bf_status bf_mlp_forward(bf_ctx* ctx, const float* params_dev, const float* feat_dev, int64_t n,
                          float* out_dev);
 /* Features -> network -> x0_dev [N] = rhs/diag + h*o0 (mean start) and
- * logvar_dev [N] = o1 (probe start for bf_diag_estimate); either may be NULL. */
+ * logvar_dev [N] = o1 (probe start for bf_diag_estimate); either may be NULL.
+ * feat_dev [N][12] as bf_features writes it, or NULL: the features are then
+ * computed in the same pass (the same values), without the [N][12] array. */
 bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const float* params_dev,
                         const float* feat_dev, double* x0_dev, float* logvar_dev);
 /* Training targets of the network from the method's own solves of sys:

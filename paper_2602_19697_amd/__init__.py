@@ -397,7 +397,8 @@ class Context:
         self._check(self.lib.bf_mlp_forward(self.handle, _ptr(params), _ptr(feat), int(feat.shape[0]), _ptr(out)))
         return out
 
-    def bf_warm_start(self, sys: System, params, feat, mean=True, logvar=True):
+    def bf_warm_start(self, sys: System, params, feat=None, mean=True, logvar=True):
+        """x0 and log-variance starts; feat None computes the features in the same pass."""
         x0 = torch.empty(sys.n, dtype=torch.float64, device=self.device) if mean else None
         lv = torch.empty(sys.n, dtype=torch.float32, device=self.device) if logvar else None
         self._check(self.lib.bf_warm_start(self.handle, sys.handle, _ptr(params), _ptr(feat), _ptr(x0), _ptr(lv)))

@@ -8,6 +8,7 @@
 // the FP64 operation order is fixed so Lambda, b and diag(Q) are reproducible
 // bit for bit.
 #include "bf_internal.h"
+#include "features.h"
 
 namespace {
 
@@ -191,7 +192,7 @@ __global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ n
   q[v] = diag[v] * p[v] + s;
 }
 
-// Features of the learned warm start, lengths in units of h (see bf_features).
+// Features of the learned warm start, lengths in units of h (features.h).
 __global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h,
                                                   const double* __restrict__ tsdf,
                                                   const int32_t* __restrict__ w,
@@ -202,30 +203,13 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h
                                                   float* __restrict__ feat) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const double* a = acc + v * 5;
-  const double cnt = a[0];
-  const double my = cnt > 0.0 ? a[1] / cnt : 0.0;
-  const double vy = cnt > 0.0 ? a[2] / cnt - my * my : 0.0;
-  const double ms = cnt > 0.0 ? a[3] / cnt : 0.0;
-  const double tv = tsdf[v];
-  float* f = feat + v * 12;
-  f[0] = (float)(tv / h);
-  f[1] = (float)log(1.0 + (double)w[v]);
-  f[2] = (float)((double)deg[v] / 6.0);
-  f[3] = (float)(cnt / (double)T);
-  f[4] = (float)(my / h);
-  f[5] = (float)(vy / (h * h));
-  f[6] = (float)(ms / h);
-  f[7] = (float)(a[4] / h);
-  f[8] = (float)log(Lambda[v] * (h * h) + 1.0);
-  const int32_t* nb = nbr + v * 6;
+  const bf_feat_in in{tsdf, Lambda, acc, w, nbr, deg, T, h};
+  float f[12];
+  bf_features_0_7(v, in, f);
+  bf_features_8_11(v, in, f + 8);
+  float* o = feat + v * 12;
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    const int32_t m = nb[2 * ax], p = nb[2 * ax + 1];
-    const double tm = m >= 0 ? tsdf[m] : tv;
-    const double tp = p >= 0 ? tsdf[p] : tv;
-    f[9 + ax] = (float)((tp - tm) / (2.0 * h));
-  }
+  for (int q = 0; q < 12; ++q) o[q] = f[q];
 }
 
 }  // namespace

@@ -15,6 +15,7 @@
 // makes those D registers exactly the next layer's B operand, so activations
 // never move between lanes; the weights are permuted once when packed.
 #include "bf_internal.h"
+#include "features.h"
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
@@ -158,8 +159,15 @@ __device__ __forceinline__ void layer(const bf16x8* __restrict__ sw, int tbase, 
 // lane) and are read there in every iteration: kept in registers across the
 // loop they held the kernel to two waves per SIMD, too few to overlap the
 // chains of dependent MFMAs.
+// FUSED: the input features are computed here from the band and the system
+// (src) instead of read from feat, the values the features kernel writes:
+// lanes 0-15 of a wave compute features 0-7 of their voxels, lanes 16-31
+// features 8-11 (features.h), the operand values those lanes hold.  (Spreading
+// the features over all four lane groups and exchanging them through LDS was
+// no faster: the pass waits on the feature loads, not on lanes.)
+template <bool FUSED>
 __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ wt, const float* __restrict__ prm,
-                                                     const float* __restrict__ feat, int64_t n,
+                                                     const float* __restrict__ feat, bf_feat_in src, int64_t n,
                                                      float* __restrict__ out, const double* __restrict__ rhs,
                                                      const double* __restrict__ diag, double h,
                                                      double* __restrict__ x0, float* __restrict__ logvar) {
@@ -196,11 +204,16 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
     const int64_t v = t * 16 + col;
     const bool valid = v < n;
     bf16x8 B0;
+    float fv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if constexpr (FUSED) {
+      if (valid && g == 0) bf_features_0_7(v, src, fv);
+      if (valid && g == 1) bf_features_8_11(v, src, fv);
+    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int f = 8 * g + e;
       float x = 0.0f;
-      if (valid && f < NIN) x = (feat[v * NIN + f] - sim[f]) * sii[f];
+      if (valid && f < NIN) x = ((FUSED ? fv[e] : feat[v * NIN + f]) - sim[f]) * sii[f];
       B0[e] = (__bf16)x;
     }
     f32x4 acc[4];
@@ -511,15 +524,16 @@ extern "C" bf_status bf_mlp_forward(bf_ctx* ctx, const float* params_dev, const 
   __bf16* wt = nullptr;
   BF_TRY(pack(ctx, params_dev, &wt));
   const unsigned grid = (unsigned)std::min<int64_t>(bf_cdiv(bf_cdiv(n, 16), 4), 8 * (int64_t)ctx->cu_count);
-  BF_LAUNCH(ctx, "mlp_forward", k_mlp_forward, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev, feat_dev, n,
-            out_dev, (const double*)nullptr, (const double*)nullptr, 0.0, (double*)nullptr, (float*)nullptr);
+  BF_LAUNCH(ctx, "mlp_forward", k_mlp_forward<false>, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev,
+            feat_dev, bf_feat_in{}, n, out_dev, (const double*)nullptr, (const double*)nullptr, 0.0, (double*)nullptr,
+            (float*)nullptr);
   return bf_launch_check(ctx, "k_mlp_forward");
 }
 
 extern "C" bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const float* params_dev,
                                    const float* feat_dev, double* x0_dev, float* logvar_dev) {
   if (!ctx) return BF_ERR_INVALID_ARG;
-  BF_CHECK(ctx, sys && params_dev && feat_dev, "bf_warm_start: NULL argument");
+  BF_CHECK(ctx, sys && params_dev, "bf_warm_start: NULL argument");
   BF_CHECK(ctx, sys->kind == BF_SYSTEM_VOXEL, "bf_warm_start: the network was trained on voxel-centric rows");
   if (sys->n == 0) return BF_OK;
   BF_CHECK(ctx, x0_dev || logvar_dev, "bf_warm_start: no output requested");
@@ -528,8 +542,17 @@ extern "C" bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const floa
   BF_TRY(pack(ctx, params_dev, &wt));
   const int64_t n = sys->n;
   const unsigned grid = (unsigned)std::min<int64_t>(bf_cdiv(bf_cdiv(n, 16), 4), 8 * (int64_t)ctx->cu_count);
-  BF_LAUNCH(ctx, "mlp_forward", k_mlp_forward, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev, feat_dev, n,
-            (float*)nullptr, (const double*)sys->rhs, (const double*)sys->diag, sys->band->h, x0_dev, logvar_dev);
+  if (feat_dev) {
+    BF_LAUNCH(ctx, "mlp_forward", k_mlp_forward<false>, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev,
+              feat_dev, bf_feat_in{}, n, (float*)nullptr, (const double*)sys->rhs, (const double*)sys->diag,
+              sys->band->h, x0_dev, logvar_dev);
+  } else {  // features computed in the same pass
+    const bf_band* b = sys->band;
+    const bf_feat_in src{b->tsdf, sys->Lambda, sys->acc, b->w, b->nbr, b->deg, sys->T, b->h};
+    BF_LAUNCH(ctx, "mlp_fused", k_mlp_forward<true>, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev,
+              (const float*)nullptr, src, n, (float*)nullptr, (const double*)sys->rhs, (const double*)sys->diag,
+              b->h, x0_dev, logvar_dev);
+  }
   return bf_launch_check(ctx, "k_mlp_forward");
 }
 

@@ -90,6 +90,9 @@ def test_warm_start_outputs(ctx, sphere_features):
     want = s["rhs"].cpu().numpy() / s["diag"].cpu().numpy() + wl.h * out[:, 0]
     assert np.allclose(x0.cpu().numpy(), want, rtol=1e-12, atol=1e-15)
     assert np.array_equal(lv.cpu().numpy(), out[:, 1].astype(np.float32))
+    # features computed in the network's pass: the same bits as through the [N][12] array
+    x0f, lvf = ctx.bf_warm_start(sys_, th, None)
+    assert torch.equal(x0f, x0) and torch.equal(lvf, lv)
 
 
 @pytest.mark.parametrize("M", [4096, 1000 + 13])
