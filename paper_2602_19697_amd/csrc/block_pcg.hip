@@ -621,8 +621,11 @@ __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ s
                                                     const double* __restrict__ w, const uint32_t* __restrict__ zb,
                                                     int K, int64_t n, double* __restrict__ s_out) {
   constexpr int RS = kThreads / KC;
-  constexpr int U = 4;
-  __shared__ double prod[U * kThreads];
+  constexpr int U = KC > 1 ? 8 : 4;
+  // a row's K products at stride PK: one double of padding per row puts the
+  // summing threads' reads (consecutive rows, the same k) in different banks
+  constexpr int PK = KC > 1 ? KC + 1 : 1;
+  __shared__ double prod[U * RS * PK];
   const int c = threadIdx.x % KC;
   const bool zero = c < K && zero_start && st->iters[c] == 0;
   const bool nocf = c < K && st->iters[c] == 0;
@@ -642,12 +645,12 @@ __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ s
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int64_t v = r0 + j * RS + threadIdx.x / KC;
-      prod[j * kThreads + threadIdx.x] = (v < n && c < K) ? zsign<KC>(zb, v, c) * xv[j] : 0.0;
+      prod[(j * RS + threadIdx.x / KC) * PK + c] = (v < n && c < K) ? zsign<KC>(zb, v, c) * xv[j] : 0.0;
     }
     __syncthreads();
-    // row r0 + t sits in group t / RS, row t % RS of it (U RS rows: 4 to 1024)
+    // row r0 + t (U RS rows: 32 to 1024)
     for (int t = threadIdx.x; t < U * RS && r0 + t < n; t += kThreads) {
-      const int base = (t / RS) * kThreads + (t % RS) * KC;
+      const int base = t * PK;
       double acc = 0.0;
       for (int k = 0; k < K; ++k) acc += prod[base + k];
       s_out[r0 + t] = acc / (double)K;
@@ -939,7 +942,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   const int stencil_kb = skb ? atoi(skb) : 32;
   int it = 0, next = 3;
   size_t fin_rec = 0;  // timing record of the last queued estimate pass (FP64)
-  const unsigned hutch_grid = (unsigned)std::min<int64_t>(bf_cdiv(N, kThreads / KC), 8 * (int64_t)ctx->cu_count);
+  const unsigned hutch_grid =
+      (unsigned)std::min<int64_t>(bf_cdiv(N, (KC > 1 ? 8 : 4) * (kThreads / KC)), 8 * (int64_t)ctx->cu_count);
   V* pa = p0;
   V* pb = p1;
   // the buffer holding the current zz.  The 7-point path's first iteration
