@@ -103,8 +103,7 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
 #pragma unroll
           for (int j = 0; j < U; ++j) {
             vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
-#pragma unroll
-            for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
+            load_nbr6(nbr, vr[j], nb[j]);
           }
           V gz[U][6], gp[U][6];
 #pragma unroll
@@ -280,8 +279,10 @@ struct RowTile {
                         const uint32_t* __restrict__ zb, int64_t r0, int64_t r1) {
     for (int t = threadIdx.x; t < R; t += kThreads) {
       const int64_t v = r0 + t < r1 ? r0 + t : r0;
+      int32_t nv[6];
+      load_nbr6(nbr, v, nv);
 #pragma unroll
-      for (int a = 0; a < 6; ++a) nb[a][t] = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+      for (int a = 0; a < 6; ++a) nb[a][t] = r0 + t < r1 ? nv[a] : -1;
 #pragma unroll
       for (int wd = 0; wd < kZWords<KC>; ++wd) zs[wd][t] = zb[v * kZWords<KC> + wd];
       d[t] = diag[v];
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
       for (int g = 0; g < kZWords<KC>; ++g) zn[0][g][t] = zb[v * kZWords<KC> + g];
 #pragma unroll
       for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself (its term is not added)
-        const int32_t u0 = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+        const int32_t u0 = rt.nb[a][t];  // staged by this thread just above
         const int64_t u = u0 >= 0 ? (int64_t)u0 : v;
         wn[1 + a][t] = w[u];
 #pragma unroll
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
             wn[0][t] = w[v];
 #pragma unroll
             for (int a = 0; a < 6; ++a) {  // an absent neighbour stages the row itself (never added)
-              const int32_t u0 = r0 + t < r1 ? nbr[v * 6 + a] : -1;
+              const int32_t u0 = rt.nb[a][t];  // staged by this thread just above
               const int64_t u = u0 >= 0 ? (int64_t)u0 : v;
               wn[1 + a][t] = w[u];
 #pragma unroll

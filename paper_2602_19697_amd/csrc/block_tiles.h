@@ -146,9 +146,22 @@ struct TileWalk {
 // compiler can issue back to back.
 constexpr int kRowsInFlight = 4;
 
-template <typename V, int KC>
+// The 6 neighbour indices of row v (24 B, 8-byte aligned: the band's arrays
+// start on 256-byte boundaries) as three 8-byte loads instead of six.
+__device__ __forceinline__ void load_nbr6(const int32_t* __restrict__ nbr, int64_t v, int32_t* nb) {
+  const int2* q = reinterpret_cast<const int2*>(nbr + v * 6);
+  const int2 a = q[0], b = q[1], c = q[2];
+  nb[0] = a.x;
+  nb[1] = a.y;
+  nb[2] = b.x;
+  nb[3] = b.y;
+  nb[4] = c.x;
+  nb[5] = c.y;
+}
+
 // store_p: write p_new (the first iteration's direction p = zz can stay
 // where zz is instead).
+template <typename V, int KC>
 __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t* __restrict__ nbr,
                                        const V* __restrict__ diag, V lam, const V* __restrict__ zz,
                                        const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
@@ -162,8 +175,7 @@ __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t*
     for (int j = 0; j < U; ++j) {
       const int64_t v = v0 + j * RS;
       vr[j] = v < r1 ? v : r0;
-#pragma unroll
-      for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
+      load_nbr6(nbr, vr[j], nb[j]);
     }
     V s[U], pv[U];
 #pragma unroll
@@ -270,8 +282,7 @@ __device__ __forceinline__ void tile_resid(int c, int mode, uint64_t cs, const i
 #pragma unroll
       for (int j = 0; j < U; ++j) {
         vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
-#pragma unroll
-        for (int t = 0; t < 6; ++t) nb[j][t] = nbr[vr[j] * 6 + t];
+        load_nbr6(nbr, vr[j], nb[j]);
       }
 #pragma unroll
       for (int j = 0; j < U; ++j) {
