@@ -42,6 +42,67 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, d
 template <typename V, int KC, int LDSKB>
 constexpr int kStencilRows = KC == 1 ? 1024 : LDSKB * 1024 / (KC * (int)sizeof(V));
 
+// The sums and stores of stencil rows [r0, r1), the tile's p staged in pt
+// (LDS): neighbour rows inside the tile come from there, the others from
+// global memory as zz + beta p_old.
+template <typename V, int KC, bool FIRST>
+__device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t* __restrict__ nbr,
+                                             const V* __restrict__ diag, const V* __restrict__ zz,
+                                             const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
+                                             const V* __restrict__ pt, int64_t r0, int64_t r1, double& acc) {
+  constexpr int RS = kThreads / KC;
+  constexpr bool first = FIRST;
+  // the gathers of neighbours outside the tile are all issued before the
+  // sums use them; an absent neighbour adds +0.0, which leaves the sum
+  // unchanged (it starts at +0.0, so it is never -0.0)
+  constexpr int U = 2;
+  for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
+    int64_t vr[U];
+    int32_t nb[U][6];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
+      load_nbr6(nbr, vr[j], nb[j]);
+    }
+    V gz[U][6], gp[U][6];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int32_t u = nb[j][t];
+        gz[j][t] = 0;
+        gp[j][t] = 0;
+        if (u >= 0 && !(u >= r0 && u < r1)) {
+          gz[j][t] = zz[(int64_t)u * KC + c];
+          gp[j][t] = first ? (V)0 : p_old[(int64_t)u * KC + c];
+        }
+      }
+    V sacc[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      sacc[j] = 0;
+#pragma unroll
+      for (int t = 0; t < 6; ++t) {
+        const int32_t u = nb[j][t];
+        const bool in = u >= r0 && u < r1;
+        const V lv = pt[(in ? u - r0 : 0) * KC + c];
+        const V gv = gz[j][t] + beta * gp[j][t];
+        sacc[j] += in ? lv : (u >= 0 ? gv : (V)0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+      if (v0 + j * RS >= r1) break;
+      const int64_t e = vr[j] * KC + c;
+      const V pv = pt[(vr[j] - r0) * KC + c];
+      const V qv = diag[vr[j]] * pv - lam * sacc[j];
+      if constexpr (!FIRST) p_new[e] = pv;
+      q[e] = qv;
+      acc += (double)pv * (double)qv;
+    }
+  }
+}
+
 template <typename V, int KC, int LDSKB, bool FIRST>
 __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
                                             const V* __restrict__ diag, V lam, const V* __restrict__ zz,
@@ -64,84 +125,67 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   // A separate instantiation, so the later launches carry no switch around
   // their loads.
   constexpr bool first = FIRST;
-  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
-    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
-    if constexpr (KC == 1) {
-      if (act) tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, r0, r1, v1[0], !first);
-    } else {
-      __syncthreads();  // the previous tile's readers are done
-      if (act) {
-        // every load of a batch of rows is issued before the first LDS store
-        constexpr int SJ = R / RS, SB = SJ < 8 ? SJ : 8;
-        static_assert(SJ % SB == 0, "staging batches must tile the rows of a thread");
-        for (int j0 = 0; j0 < SJ; j0 += SB) {
-          V za[SB], pa[SB];
+  if constexpr (KC == 1) {
+    for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
+      if (act)
+        tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, tile * R,
+                      std::min<int64_t>(n, (tile + 1) * R), v1[0], !first);
+  } else {
+    constexpr int SJ = R / RS;  // rows of a tile per thread
+    if constexpr (FIRST) {
+      // p = z: the next tile's rows of z are loaded into registers while the
+      // current tile's sums run, so staging a tile waits on no load
+      V za[SJ];
+      auto fetch = [&](int64_t tile) {
+        const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
 #pragma unroll
-          for (int j = 0; j < SB; ++j) {
-            const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
-            if (v < r1) {
-              za[j] = zz[v * KC + c];
-              pa[j] = first ? (V)0 : p_old[v * KC + c];
-            }
-          }
+        for (int j = 0; j < SJ; ++j) {
+          const int64_t v = r0 + threadIdx.x / KC + (int64_t)j * RS;
+          za[j] = v < r1 ? zz[v * KC + c] : (V)0;
+        }
+      };
+      if (act && tw.start < tw.end) fetch(tw.start);
+      for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+        const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+        __syncthreads();  // the previous tile's readers are done
+        if (act) {
 #pragma unroll
-          for (int j = 0; j < SB; ++j) {
-            const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
-            if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * pa[j];
+          for (int j = 0; j < SJ; ++j) {
+            const int64_t v = r0 + threadIdx.x / KC + (int64_t)j * RS;
+            if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * (V)0;
           }
         }
+        __syncthreads();
+        if (act && tile + tw.stride < tw.end) fetch(tile + tw.stride);
+        if (act) stencil_sums<V, KC, FIRST>(c, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, v1[0]);
       }
-      __syncthreads();
-      if (act) {
-        // the gathers of neighbours outside the tile are all issued before the
-        // sums use them; an absent neighbour adds +0.0, which leaves the sum
-        // unchanged (it starts at +0.0, so it is never -0.0)
-        constexpr int U = 2;
-        for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
-          int64_t vr[U];
-          int32_t nb[U][6];
+    } else {
+      for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+        const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+        __syncthreads();  // the previous tile's readers are done
+        if (act) {
+          // every load of a batch of rows is issued before the first LDS store
+          constexpr int SB = SJ < 8 ? SJ : 8;
+          static_assert(SJ % SB == 0, "staging batches must tile the rows of a thread");
+          for (int j0 = 0; j0 < SJ; j0 += SB) {
+            V za[SB], pa[SB];
 #pragma unroll
-          for (int j = 0; j < U; ++j) {
-            vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
-            load_nbr6(nbr, vr[j], nb[j]);
-          }
-          V gz[U][6], gp[U][6];
-#pragma unroll
-          for (int j = 0; j < U; ++j)
-#pragma unroll
-            for (int t = 0; t < 6; ++t) {
-              const int32_t u = nb[j][t];
-              gz[j][t] = 0;
-              gp[j][t] = 0;
-              if (u >= 0 && !(u >= r0 && u < r1)) {
-                gz[j][t] = zz[(int64_t)u * KC + c];
-                gp[j][t] = first ? (V)0 : p_old[(int64_t)u * KC + c];
+            for (int j = 0; j < SB; ++j) {
+              const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
+              if (v < r1) {
+                za[j] = zz[v * KC + c];
+                pa[j] = p_old[v * KC + c];
               }
             }
-          V sacc[U];
 #pragma unroll
-          for (int j = 0; j < U; ++j) {
-            sacc[j] = 0;
-#pragma unroll
-            for (int t = 0; t < 6; ++t) {
-              const int32_t u = nb[j][t];
-              const bool in = u >= r0 && u < r1;
-              const V lv = pt[(in ? u - r0 : 0) * KC + c];
-              const V gv = gz[j][t] + beta * gp[j][t];
-              sacc[j] += in ? lv : (u >= 0 ? gv : (V)0);
+            for (int j = 0; j < SB; ++j) {
+              const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
+              if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * pa[j];
             }
           }
-#pragma unroll
-          for (int j = 0; j < U; ++j) {
-            if (v0 + j * RS >= r1) break;
-            const int64_t e = vr[j] * KC + c;
-            const V pv = pt[(vr[j] - r0) * KC + c];
-            const V qv = diag[vr[j]] * pv - lam * sacc[j];
-            if constexpr (!FIRST) p_new[e] = pv;
-            q[e] = qv;
-            v1[0] += (double)pv * (double)qv;
-          }
         }
+        __syncthreads();
+        if (act) stencil_sums<V, KC, FIRST>(c, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, v1[0]);
       }
     }
   }
