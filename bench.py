@@ -187,7 +187,8 @@ def run_gpu(args):
     cands = torch.from_numpy(np.ascontiguousarray(cands_np)).to(dev)
     grid = bf.grid_struct(wl.G, wl.h, wl.origin, wl.tau, wl.band)
     noise = bf.noise_struct(*wl.noise)
-    ctx = bf.Context(dev)
+    # bands and systems from torch's caching allocator (the binding's default) or the library's pool
+    ctx = bf.Context(dev, allocator="torch" if args.allocator == "torch" else None)
     K = args.probes
 
     prec = bf.L.BF_PREC_FP64 if args.precision == "fp64" else bf.L.BF_PREC_MIXED
@@ -855,7 +856,9 @@ def main():
     # 20 timed steps (under 0.1 s): the 2 with per-kernel event timing, which
     # costs host time at every launch, then weigh 10% of the average
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the first process on a box ran its first timed steps with 2 ms/step more
+    # host idle (the same kernels): warm up longer
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--timing-steps", type=int, default=2,
                     help="per-kernel HIP event timing on the last this many timed steps")
     ap.add_argument("--workload", default="union512")
@@ -875,6 +878,8 @@ def main():
     ap.add_argument("--no-trilinear", action="store_true")
     ap.add_argument("--no-surface", action="store_true")
     ap.add_argument("--no-postview", action="store_true")
+    ap.add_argument("--allocator", choices=("pool", "torch"), default="torch",
+                    help="where bands and systems get their memory: the library's pool or torch's allocator")
     ap.add_argument("--solver-workload", default="union1024")
     ap.add_argument("--batch-scenes", type=int, default=32)
     ap.add_argument("--batch-probes", type=int, default=64)
