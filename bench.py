@@ -121,10 +121,8 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + 8 + K / 8 + (8 if warm else 0) + 4 * K), "B", "hbm"
     if name == "block_start_res":  # from +-w: nbr, diag, w, signs in; per column r, zz out (+ x64 in FP64)
         return N * (24 + 8 + 8 + K / 8 + 2 * K * s + (8 * K if fp64 else 0)), "B", "hbm"
-    if name == "block_residual":  # as verify, plus r and z stored per column
-        return N * (24 + 8 + 8 * K + 2 * K * s), "B", "hbm"
-    if name == "pcg_residual":  # nbr, diag, rhs, x (FP64) -> r, z
-        return N * (24 + 8 + 8 + 8 + 2 * s), "B", "hbm"
+    # block_residual and pcg_residual time full passes (a start residual) and
+    # checks that find nothing to do under one label: no per-launch roofline
     # screening: one tile test per (16x8x8 block tile, view of the first 256);
     # the rest of the counted tests are cell tests
     tile_tests = (-(-G // 16)) * (-(-G // 8)) ** 2 * min(T, 256)
