@@ -108,8 +108,8 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + s + 4 * K * s), "B", "hbm"
     if name == "block_B":    # dinv; per column p, q, x, r -> x, r, zz
         return N * (s + 7 * K * s), "B", "hbm"
-    if name == "block_A_first":  # first iteration: no p_old reads
-        return N * (24 + s + 3 * K * s), "B", "hbm"
+    if name == "block_A_first":  # first iteration: zz in, q out (p_0 = zz is used in place: no p_old, no p_new)
+        return N * (24 + s + 2 * K * s), "B", "hbm"
     if name == "block_B_first":  # first iteration: x not read (it is 0, or the float correction's 0);
         # r not read either in FP64 from zero (regenerated from the probe signs)
         return N * (s + (6 if (warm or not fp64) else 5) * K * s), "B", "hbm"
