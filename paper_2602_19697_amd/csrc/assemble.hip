@@ -8,7 +8,7 @@
 // the FP64 operation order is fixed so Lambda, b and diag(Q) are reproducible
 // bit for bit.
 #include "bf_internal.h"
-#include "features.h"
+#include "bf_features.h"
 
 namespace {
 
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ n
   q[v] = diag[v] * p[v] + s;
 }
 
-// Features of the learned warm start, lengths in units of h (features.h).
+// Features of the learned warm start, lengths in units of h (bf_features.h).
 __global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h,
                                                   const double* __restrict__ tsdf,
                                                   const int32_t* __restrict__ w,

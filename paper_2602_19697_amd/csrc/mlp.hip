@@ -15,7 +15,7 @@
 // makes those D registers exactly the next layer's B operand, so activations
 // never move between lanes; the weights are permuted once when packed.
 #include "bf_internal.h"
-#include "features.h"
+#include "bf_features.h"
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
@@ -162,7 +162,7 @@ __device__ __forceinline__ void layer(const bf16x8* __restrict__ sw, int tbase, 
 // FUSED: the input features are computed here from the band and the system
 // (src) instead of read from feat, the values the features kernel writes:
 // lanes 0-15 of a wave compute features 0-7 of their voxels, lanes 16-31
-// features 8-11 (features.h), the operand values those lanes hold.  (Spreading
+// features 8-11 (bf_features.h), the operand values those lanes hold.  (Spreading
 // the features over all four lane groups and exchanging them through LDS was
 // no faster: the pass waits on the feature loads, not on lanes.)
 template <bool FUSED>
