@@ -53,9 +53,13 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
   constexpr int RS = kThreads / KC;
   constexpr bool first = FIRST;
   // the gathers of neighbours outside the tile are all issued before the
-  // sums use them; an absent neighbour adds +0.0, which leaves the sum
-  // unchanged (it starts at +0.0, so it is never -0.0)
+  // sums use them.  No branch guards them: a lane with nothing to gather
+  // (neighbour absent or inside the tile) loads row 0, a line every wave
+  // reads, and takes 0, so an absent neighbour adds +0.0, which leaves the
+  // sum unchanged (it starts at +0.0, so it is never -0.0).  Row indices
+  // fit 31 bits (checked by the host).
   constexpr int U = 2;
+  const uint32_t span = (uint32_t)(r1 - r0);
   for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
     int64_t vr[U];
     int32_t nb[U][6];
@@ -70,11 +74,16 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int32_t u = nb[j][t];
-        gz[j][t] = 0;
-        gp[j][t] = 0;
-        if (u >= 0 && !(u >= r0 && u < r1)) {
-          gz[j][t] = zz[(int64_t)u * KC + c];
-          gp[j][t] = first ? (V)0 : p_old[(int64_t)u * KC + c];
+        const bool in = (uint32_t)(u - (int32_t)r0) < span;
+        const bool out = u >= 0 && !in;
+        const size_t e = (size_t)(out ? (uint32_t)u : 0u) * KC + c;
+        const V za = zz[e];
+        gz[j][t] = out ? za : (V)0;
+        if constexpr (first) {
+          gp[j][t] = 0;
+        } else {
+          const V pa = p_old[e];
+          gp[j][t] = out ? pa : (V)0;
         }
       }
     V sacc[U];
@@ -84,10 +93,10 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int32_t u = nb[j][t];
-        const bool in = u >= r0 && u < r1;
-        const V lv = pt[(in ? u - r0 : 0) * KC + c];
+        const bool in = (uint32_t)(u - (int32_t)r0) < span;
+        const V lv = pt[(in ? u - (int32_t)r0 : 0) * KC + c];
         const V gv = gz[j][t] + beta * gp[j][t];
-        sacc[j] += in ? lv : (u >= 0 ? gv : (V)0);
+        sacc[j] += in ? lv : gv;
       }
     }
 #pragma unroll
@@ -431,6 +440,126 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
 
+// The start of x at one element under BState::xbase kind k: the stored x64
+// value, the warm start +-w by the probe's sign, or zero.  sgn holds the sign
+// in bit 31 (the rest zero), so the negation is one XOR on the high word;
+// wp[wi] is read only for k == 1 (w is null without a warm start).
+__device__ __forceinline__ double xbase_at(int k, const double* __restrict__ xc, uint32_t e, uint32_t sgn,
+                                           const double* __restrict__ wp, uint32_t wi) {
+  if (k == 0) return xc[e];
+  if (k == 1) {
+    const double v = wp[wi];
+    return __hiloint2double(__double2hiint(v) ^ (int)sgn, __double2loint(v));
+  }
+  return 0.0;
+}
+
+// Bit sh of word moved to bit 31: the sign of probe sh in a packed-sign word.
+__device__ __forceinline__ uint32_t sign_bit(uint32_t word, int sh) { return (word << (31 - sh)) & 0x80000000u; }
+
+// The rows of one tile of k_bres (see there).  XBK: the start kind of x in
+// mixed precision when it is the same for every column of the wave (then the
+// choice is made at compile time), or -1 (each lane reads its column's).
+template <typename V, int KC, int MODE, bool GATHER, bool XC, int XBK, int R, int RT, int RW>
+__device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, RT>& rt, const double (&wn)[7][RW],
+                                          const uint32_t (&zn)[7][kZWords<KC>][RW],
+                                          const int32_t* __restrict__ nbr, const double* __restrict__ diag,
+                                          double lam, const uint32_t* __restrict__ zb, double* __restrict__ x64,
+                                          const float* __restrict__ cf, const double* __restrict__ w,
+                                          const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
+                                          int64_t r0, int64_t r1, int write_x0, int store_r, double (&v3)[3]) {
+  constexpr bool kStage = KC > 1;
+  constexpr bool kStageW = XC && kStage;
+  constexpr int RS = kThreads / KC;
+  const int sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
+  // element (u, c) at xc[u * KC] with u * KC < 2^32 (checked by the host)
+  const double* xc = x64 + c;
+  const float* cc = XC ? cf + c : nullptr;
+  // two rows in flight: their gathers are issued before they are summed
+  for (int j0 = threadIdx.x / KC; j0 < R && r0 + j0 < r1; j0 += 2 * RS) {
+    int jr[2];
+    int32_t nb[2][6];
+    double dg[2];
+    V di[2];
+    uint32_t zw[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      jr[h] = (j0 + h * RS < R && r0 + j0 + h * RS < r1) ? j0 + h * RS : j0;
+      const int64_t v = r0 + jr[h];
+      if constexpr (kStage) {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) nb[h][a] = rt.nb[a][jr[h]];
+        zw[h] = rt.zs[wd][jr[h]];
+        dg[h] = rt.d[jr[h]];
+        di[h] = rt.di[jr[h]];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) nb[h][a] = nbr[v * 6 + a];
+        zw[h] = zb[v * kZWords<KC> + wd];
+        dg[h] = diag[v];
+        di[h] = dinv[v];
+      }
+    }
+    double res[2], zv[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      zv[h] = ((zw[h] >> sh) & 1u) ? -1.0 : 1.0;
+      res[h] = zv[h];
+    }
+    if constexpr (GATHER) {
+      const int k = XBK >= 0 ? XBK : xbl;
+      double xs[2], xn[2][6];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint32_t vs = (uint32_t)(r0 + jr[h]), es = vs * (uint32_t)KC;
+        if constexpr (XC) {
+          const uint32_t sg = sign_bit(zw[h], sh);
+          xs[h] = (kStageW ? xbase_at(k, xc, es, sg, wn[0], (uint32_t)jr[h]) : xbase_at(k, xc, es, sg, w, vs)) +
+                  (double)cc[es];
+        } else {
+          xs[h] = xc[es];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself and adds nothing
+          const uint32_t vu = (uint32_t)(nb[h][a] >= 0 ? nb[h][a] : (int32_t)vs), u = vu * (uint32_t)KC;
+          if constexpr (kStageW) {
+            xn[h][a] = xbase_at(k, xc, u, sign_bit(zn[1 + a][wd][jr[h]], sh), wn[1 + a], (uint32_t)jr[h]) +
+                       (double)cc[u];
+          } else {
+            xn[h][a] = XC ? x_base<KC>(k, xc, w, zb, vu, sh, wd) + (double)cc[u] : xc[u];
+          }
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a)
+          if (nb[h][a] >= 0) acc += xn[h][a];
+        res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (h == 1 && jr[1] == j0) break;  // no second row
+      const int64_t e = (r0 + jr[h]) * KC + c;
+      if constexpr (!GATHER)
+        if (write_x0) x64[e] = 0.0;
+      v3[0] += res[h] * res[h];
+      v3[2] += zv[h] * zv[h];
+      const V rv = (V)res[h];
+      if constexpr (MODE == MODE_VERIFY) {
+        v3[1] += (double)rv * (double)(rv * di[h]);
+      } else {
+        const V zzv = rv * di[h];
+        if (store_r) r[e] = rv;
+        zz[e] = zzv;
+        v3[1] += (double)rv * (double)zzv;
+      }
+    }
+  }
+}
+
 // FP64 residual r = z - Q x of the selected columns (one pass over the band):
 //   INIT   every active column; GATHER: x from x64 (a supplied start), else
 //          x = 0 (written to x64 when write_x0);
@@ -455,14 +584,14 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   // neighbours' start weights and signs), amortised over the tile's rows
   constexpr bool kStage = KC > 1;
   constexpr int R = kStage ? kThreads : kRowsPerTile<KC>;
-  constexpr int RS = kThreads / KC;
+  constexpr int RT = kStage ? R : 1;
   // mixed VERIFY from a warm start: the start weights and packed signs of each
   // row and its neighbours are staged with the row data, so a column lane
   // regenerates +-w from LDS and gathers only its float correction
   constexpr bool kStageW = XC && kStage;
   constexpr int RW = kStageW ? R : 1;
   __shared__ double lds[4 * 3 * 64];
-  __shared__ RowTile<V, KC, kStage ? R : 1> rt;
+  __shared__ RowTile<V, KC, RT> rt;
   __shared__ double wn[7][RW];
   __shared__ uint32_t zn[7][kZWords<KC>][RW];
   if constexpr (MODE == MODE_CHECK || MODE == MODE_VERIFY)
@@ -472,16 +601,16 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   if constexpr (MODE == MODE_GUARD)
     if (st->ndropped == 0) return;
   const int c = threadIdx.x % KC;
-  const int sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
   bool act;
   if constexpr (MODE == MODE_GUARD) act = st->dropped[c] != 0;
   else if constexpr (MODE == MODE_INIT) act = st->active[c] != 0;
   else act = st->active[c] != 0 && st->check[c] == (MODE == MODE_VERIFY ? 2 : 1);
   const TileWalk tw(bf_cdiv(n, R));
-  // element (u, c) at xc[u * KC] with u * KC < 2^32 (checked by the host)
-  const double* xc = x64 + c;
-  const float* cc = XC ? cf + c : nullptr;
-  const int xb = XC ? st->xbase[c] : 0;
+  // the start kind of x per column, and the wave's common one (-1: they
+  // differ), a scalar that selects the rows' code once per tile
+  const int xbl = XC ? st->xbase[c] : 0;
+  const int xbf = __builtin_amdgcn_readfirstlane(xbl);
+  const int xbw = __builtin_amdgcn_readfirstlane(__ballot(act && xbl != xbf) == 0 ? xbf : -1);
   double v3[3] = {0.0, 0.0, 0.0};
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
@@ -505,92 +634,18 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
       __syncthreads();
     }
     if (!act) continue;
-    // two rows in flight: their gathers are issued before they are summed
-    for (int j0 = threadIdx.x / KC; j0 < R && r0 + j0 < r1; j0 += 2 * RS) {
-      int jr[2];
-      int32_t nb[2][6];
-      double dg[2];
-      V di[2];
-      uint32_t zw[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        jr[h] = (j0 + h * RS < R && r0 + j0 + h * RS < r1) ? j0 + h * RS : j0;
-        const int64_t v = r0 + jr[h];
-        if constexpr (kStage) {
-#pragma unroll
-          for (int a = 0; a < 6; ++a) nb[h][a] = rt.nb[a][jr[h]];
-          zw[h] = rt.zs[wd][jr[h]];
-          dg[h] = rt.d[jr[h]];
-          di[h] = rt.di[jr[h]];
-        } else {
-#pragma unroll
-          for (int a = 0; a < 6; ++a) nb[h][a] = nbr[v * 6 + a];
-          zw[h] = zb[v * kZWords<KC> + wd];
-          dg[h] = diag[v];
-          di[h] = dinv[v];
-        }
-      }
-      double res[2], zv[2];
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        zv[h] = ((zw[h] >> sh) & 1u) ? -1.0 : 1.0;
-        res[h] = zv[h];
-      }
-      if constexpr (GATHER) {
-        double xs[2], xn[2][6];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const uint32_t vs = (uint32_t)(r0 + jr[h]), es = vs * (uint32_t)KC;
-          if constexpr (XC) {  // w is read only for a warm start (it is null without one)
-            double xb0 = 0.0;
-            if (xb == 0) xb0 = xc[es];
-            else if (xb == 1) xb0 = kStageW ? (((zw[h] >> sh) & 1u) ? -wn[0][jr[h]] : wn[0][jr[h]])
-                                            : (((zw[h] >> sh) & 1u) ? -w[vs] : w[vs]);
-            xs[h] = xb0 + (double)cc[es];
-          } else {
-            xs[h] = xc[es];
-          }
-#pragma unroll
-          for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself and adds nothing
-            const uint32_t vu = (uint32_t)(nb[h][a] >= 0 ? nb[h][a] : (int32_t)vs), u = vu * (uint32_t)KC;
-            if constexpr (kStageW) {
-              double xb0 = 0.0;
-              if (xb == 0) xb0 = xc[u];
-              else if (xb == 1) xb0 = ((zn[1 + a][wd][jr[h]] >> sh) & 1u) ? -wn[1 + a][jr[h]] : wn[1 + a][jr[h]];
-              xn[h][a] = xb0 + (double)cc[u];
-            } else {
-              xn[h][a] = XC ? x_base<KC>(xb, xc, w, zb, vu, sh, wd) + (double)cc[u] : xc[u];
-            }
-          }
-        }
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          double acc = 0.0;
-#pragma unroll
-          for (int a = 0; a < 6; ++a)
-            if (nb[h][a] >= 0) acc += xn[h][a];
-          res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
-        }
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (h == 1 && jr[1] == j0) break;  // no second row
-        const int64_t e = (r0 + jr[h]) * KC + c;
-        if constexpr (!GATHER)
-          if (write_x0) x64[e] = 0.0;
-        v3[0] += res[h] * res[h];
-        v3[2] += zv[h] * zv[h];
-        const V rv = (V)res[h];
-        if constexpr (MODE == MODE_VERIFY) {
-          v3[1] += (double)rv * (double)(rv * di[h]);
-        } else {
-          const V zzv = rv * di[h];
-          if (store_r) r[e] = rv;
-          zz[e] = zzv;
-          v3[1] += (double)rv * (double)zzv;
-        }
-      }
+#define BF_BRES_ROWS(K)                                                                                        \
+  bres_rows<V, KC, MODE, GATHER, XC, K, R, RT, RW>(c, xbl, rt, wn, zn, nbr, diag, lam, zb, x64, cf, w, dinv, r, \
+                                                    zz, r0, r1, write_x0, store_r, v3)
+    if constexpr (XC && GATHER) {
+      if (xbw == 1) BF_BRES_ROWS(1);
+      else if (xbw == 0) BF_BRES_ROWS(0);
+      else if (xbw == 2) BF_BRES_ROWS(2);
+      else BF_BRES_ROWS(-1);
+    } else {
+      BF_BRES_ROWS(0);
     }
+#undef BF_BRES_ROWS
   }
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
