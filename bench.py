@@ -96,9 +96,12 @@ TSDF_OPS_PER_VOXEL_VIEW = 35
 TSDF_OPS_PER_CELL_VIEW = 217
 
 
-def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None, warm=False):
+def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None, warm=False,
+                     estimate=False):
     """(amount, unit, bound) of one launch of a timed kernel.  warm: the probe
-    solve starts from the log-variance start +-w (w per row) rather than 0."""
+    solve starts from the log-variance start +-w (w per row) rather than 0.
+    estimate: the verify pass also formed the variance estimate s (8 B per row
+    out; the separate estimate pass then had nothing to do)."""
     s = 8 if fp64 else 4
     if name == "pcg_A":      # nbr, diag, z, p_old -> p_new, q
         return N * (24 + 5 * s), "B", "hbm"
@@ -116,9 +119,10 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
     if name == "block_verify":   # FP64 residual norms: nbr, diag, the probe signs (K/8 B); per column
         # x64 in FP64; under mixed precision the float correction, over an FP64 part that is the
         # start (w per row, or zero) until a column's first restart
+        est = 8 if estimate else 0
         if fp64:
-            return N * (24 + 8 + K / 8 + 8 * K), "B", "hbm"
-        return N * (24 + 8 + K / 8 + (8 if warm else 0) + 4 * K), "B", "hbm"
+            return N * (24 + 8 + K / 8 + 8 * K + est), "B", "hbm"
+        return N * (24 + 8 + K / 8 + (8 if warm else 0) + 4 * K + est), "B", "hbm"
     if name == "block_start_res":  # from +-w: nbr, diag, w, signs in; per column r, zz out (+ x64 in FP64)
         return N * (24 + 8 + 8 + K / 8 + 2 * K * s + (8 * K if fp64 else 0)), "B", "hbm"
     # block_residual and pcg_residual time full passes (a start residual) and
@@ -247,10 +251,12 @@ def run_gpu(args):
     while P < wl.G:
         P *= 2
     rooflines = {}
+    # the verify pass formed the estimate when the estimate pass only ever found it done
+    estimate = "hutch_final" not in kernels and "hutch_final_idle" in kernels
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
                              voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"],
-                             warm=args.learned)
+                             warm=args.learned, estimate=estimate)
         if w is None:
             continue
         amount, unit, bound = w
@@ -389,7 +395,8 @@ def _kernel_rooflines(tm, N, K, T, G, fp64):
     for kname, (launches, ms) in tm.items():
         if launches == 0:
             continue
-        w = algorithmic_work(kname, N, K, T, G, 0, fp64=fp64)
+        w = algorithmic_work(kname, N, K, T, G, 0, fp64=fp64,
+                             estimate="hutch_final" not in tm and "hutch_final_idle" in tm)
         if w is None or w[2] != "hbm":
             continue
         gbs = w[0] / (ms * 1e-3 / launches) / 1e9

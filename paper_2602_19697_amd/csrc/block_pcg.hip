@@ -273,6 +273,36 @@ __device__ __forceinline__ double zsign(const uint32_t* __restrict__ zb, int64_t
   return ((w >> (c & 31)) & 1u) ? -1.0 : 1.0;
 }
 
+// A double from lane l ^ m of the lane's group (the permutation CTRL of a DPP
+// move, applied to both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of p over the KC column lanes of a row, lane c == 0's value being the
+// one used: the quad's pairs (DPP quad permutations), then the other quad of
+// 8, the other 8 of 16 (DPP mirrors), the other 16 of 32 (an LDS swizzle with
+// lane XOR 16) and the other 32 (a lane shuffle).  The estimate's one
+// summation order, in k_hutch_bits and in the VERIFY pass that forms it.
+template <int KC>
+__device__ __forceinline__ double row_sum(double p) {
+  static_assert(KC == 1 || KC == 16 || KC == 32 || KC == 64, "column blocks of 1, 16, 32 or 64");
+  if constexpr (KC >= 16) {
+    p += dpp_move<0xB1>(p);   // quad_perm [1, 0, 3, 2]
+    p += dpp_move<0x4E>(p);   // quad_perm [2, 3, 0, 1]
+    p += dpp_move<0x141>(p);  // row_half_mirror: lane 7 - l of 8
+    p += dpp_move<0x140>(p);  // row_mirror: lane 15 - l of 16
+  }
+  if constexpr (KC >= 32)
+    p += __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(p), 0x401F),
+                          __builtin_amdgcn_ds_swizzle(__double2loint(p), 0x401F));
+  if constexpr (KC >= 64) p += __shfl_xor(p, 32, 64);
+  return p;
+}
+
 // Element (u, c) of the FP64 part of a mixed-precision 7-point solve (see
 // BState::xbase): stored at xc[u * KC], or the warm start +-w[u] by probe c's
 // sign bit (bit sh of packed word wd), or zero.
@@ -467,7 +497,8 @@ __device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, R
                                           double lam, const uint32_t* __restrict__ zb, double* __restrict__ x64,
                                           const float* __restrict__ cf, const double* __restrict__ w,
                                           const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                          int64_t r0, int64_t r1, int write_x0, int store_r, double (&v3)[3]) {
+                                          int64_t r0, int64_t r1, int write_x0, int store_r, double (&v3)[3],
+                                          double* __restrict__ s_out) {
   constexpr bool kStage = KC > 1;
   constexpr bool kStageW = XC && kStage;
   constexpr int RS = kThreads / KC;
@@ -538,6 +569,17 @@ __device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, R
           if (nb[h][a] >= 0) acc += xn[h][a];
         res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
       }
+      if constexpr (MODE == MODE_VERIFY) {
+        // every column is verified here: the estimate's rows, as k_hutch_bits
+        // forms them (a row's lanes agree on whether it exists)
+        if (s_out)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            if (h == 1 && jr[1] == j0) break;
+            const double sum = row_sum<KC>(zv[h] * xs[h]);
+            if (c == 0) s_out[r0 + jr[h]] = sum / (double)KC;
+          }
+      }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -577,7 +619,8 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
                                               const uint32_t* __restrict__ zb, double* __restrict__ x64,
                                               const float* __restrict__ cf, const double* __restrict__ w,
                                               const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                              int64_t n, double* __restrict__ part, int write_x0, int store_r) {
+                                              int64_t n, double* __restrict__ part, int write_x0, int store_r,
+                                              double* __restrict__ s_fuse) {
   // one column: every lane is its own row and nothing is shared, so the row
   // data is read directly; otherwise it is staged per tile in LDS, one row per
   // thread (a dependent chain of loads: neighbour indices, then the
@@ -611,6 +654,20 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   const int xbl = XC ? st->xbase[c] : 0;
   const int xbf = __builtin_amdgcn_readfirstlane(xbl);
   const int xbw = __builtin_amdgcn_readfirstlane(__ballot(act && xbl != xbf) == 0 ? xbf : -1);
+  // VERIFY of every column of the block (K = KC, all at check 2, as when they
+  // all meet the tolerance at the same iteration): the pass also forms the
+  // estimate s from the x it reads, final unless a column fails the check
+  double* s_out = nullptr;
+  if constexpr (MODE == MODE_VERIFY && GATHER && KC > 1) {
+    if (s_fuse && st->K == KC) {
+      bool all = true;
+      for (int k = 0; k < KC; ++k) all = all && st->active[k] && st->check[k] == 2;
+      if (all) {
+        s_out = s_fuse;
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->s_fused = 1;
+      }
+    }
+  }
   double v3[3] = {0.0, 0.0, 0.0};
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
@@ -636,7 +693,7 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
     if (!act) continue;
 #define BF_BRES_ROWS(K)                                                                                        \
   bres_rows<V, KC, MODE, GATHER, XC, K, R, RT, RW>(c, xbl, rt, wn, zn, nbr, diag, lam, zb, x64, cf, w, dinv, r, \
-                                                    zz, r0, r1, write_x0, store_r, v3)
+                                                    zz, r0, r1, write_x0, store_r, v3, s_out)
     if constexpr (XC && GATHER) {
       if (xbw == 1) BF_BRES_ROWS(1);
       else if (xbw == 0) BF_BRES_ROWS(0);
@@ -712,20 +769,17 @@ __global__ __launch_bounds__(256) void k_bfold_check(const BState* __restrict__ 
 // are not folded).  FP64, zero_start: a column that never iterated still has
 // its unwritten zero start.  Mixed: x64 per BState::xbase (w: the start
 // weights), and a column that never iterated has no correction (cf unwritten).
-// U row groups' loads are issued before their products go through LDS; one
-// thread per row sums them in ascending k.  (One thread per row reading its
-// columns itself was slower: 64 rows 128-256 B apart per load defeat the L1.)
+// The KC lanes of a row sum its products with row_sum; U rows' loads are
+// issued before their sums.  Nothing to do when the last VERIFY pass formed
+// the estimate (BState::s_fused).
 template <int KC, bool XC>
 __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ st, int zero_start,
                                                     const double* __restrict__ x64, const float* __restrict__ cf,
                                                     const double* __restrict__ w, const uint32_t* __restrict__ zb,
                                                     int K, int64_t n, double* __restrict__ s_out) {
+  if (st->s_fused) return;
   constexpr int RS = kThreads / KC;
   constexpr int U = KC > 1 ? 8 : 4;
-  // a row's K products at stride PK: one double of padding per row puts the
-  // summing threads' reads (consecutive rows, the same k) in different banks
-  constexpr int PK = KC > 1 ? KC + 1 : 1;
-  __shared__ double prod[U * RS * PK];
   const int c = threadIdx.x % KC;
   const bool zero = c < K && zero_start && st->iters[c] == 0;
   const bool nocf = c < K && st->iters[c] == 0;
@@ -745,17 +799,12 @@ __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ s
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       const int64_t v = r0 + j * RS + threadIdx.x / KC;
-      prod[(j * RS + threadIdx.x / KC) * PK + c] = (v < n && c < K) ? zsign<KC>(zb, v, c) * xv[j] : 0.0;
+      // the rows of a wave are whole (KC divides 64), so a row's lanes agree on v < n
+      if (v < n) {
+        const double acc = row_sum<KC>(c < K ? zsign<KC>(zb, v, c) * xv[j] : 0.0);
+        if (c == 0) s_out[v] = acc / (double)K;
+      }
     }
-    __syncthreads();
-    // row r0 + t (U RS rows: 32 to 1024)
-    for (int t = threadIdx.x; t < U * RS && r0 + t < n; t += kThreads) {
-      const int base = t * PK;
-      double acc = 0.0;
-      for (int k = 0; k < K; ++k) acc += prod[base + k];
-      s_out[r0 + t] = acc / (double)K;
-    }
-    __syncthreads();
   }
 }
 
@@ -1024,13 +1073,13 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     } else {
       BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_INIT, false, false>), dim3(nb), dim3(kThreads), 0, st,
                 sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part,
-                (zero_start || mixed7) ? 0 : 1, gen_start ? 0 : 1);
+                (zero_start || mixed7) ? 0 : 1, gen_start ? 0 : 1, nullptr);
     }
   }
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   if (logvar) {  // columns whose start was no better than zero restart from x = 0
     BF_LAUNCH(ctx, "block_guard", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
-              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1);
+              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1, nullptr);
     BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
   }
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
@@ -1131,16 +1180,16 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         // columns to go on from a stored FP64 residual fold (mixed) and store it
         if (mixed)
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, true>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0, s_out);
         else
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0, s_out);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_VERIFY, part, nb);
         if (mixed)
           BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, wst,
                     (const uint32_t*)zb, N);
         BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_CHECK, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 1);
+                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 1, nullptr);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       }
       if (!moved) std::swap(pa, pb);
@@ -1163,8 +1212,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // The report's residual of each column is the FP64 one of its last check:
   // a column stops only after such a check (or at INIT, or on a breakdown),
   // and its solution does not change afterwards, so no further pass is needed.
+  size_t hutch_rec = fin_rec;  // timing record of the last queued estimate pass
   if (mixed) {
     if (tri) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
+    hutch_rec = ctx->recs.size();
     hutch();
     BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
@@ -1187,6 +1238,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   }
   if (status == BF_OK && hs->nactive != 0) status = BF_ERR_NOT_CONVERGED;
   if (ctx->timing && (size_t)maxit < iter_rec.size()) bf_timing_mark_idle(ctx, iter_rec[maxit], loop_rec_end);
+  // a VERIFY pass formed the estimate: the closing estimate pass found nothing to do
+  if (ctx->timing && hs->s_fused) bf_timing_mark_idle(ctx, hutch_rec, hutch_rec + 1);
   if (rep) {
     rep->iters = maxit;
     rep->status = status;

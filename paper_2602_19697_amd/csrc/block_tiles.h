@@ -37,7 +37,11 @@ struct BState {
   // regenerated where it is read; 2: the zero start.  A column is stored (0)
   // from its first fold on.
   int32_t xbase[kMaxK];
-  int32_t ndropped, pad_;
+  int32_t ndropped;
+  // 1 while the estimate s was formed by a VERIFY pass that covered every
+  // column and every column passed it (the closing estimate pass is then
+  // skipped); a failed column clears it
+  int32_t s_fused;
 };
 
 // SplitMix64 output n (0-based) of the generator started at `start`.
@@ -64,6 +68,7 @@ __device__ __forceinline__ void state_init(BState* st, int K, double tol, int32_
   if (c == 0) {
     st->guard = 0;
     st->ndropped = 0;
+    st->s_fused = 0;
     st->inner2 = inner * inner;
     st->nactive = K;
     st->any_check = 0;
@@ -364,6 +369,7 @@ __device__ __forceinline__ void decide_V(BState* st, int c, const double (&tot)[
   } else {
     st->check[c] = 1;
     atomicAdd(&st->pending, 1);
+    st->s_fused = 0;  // this column goes on: its estimate rows are not final
   }
 }
 
