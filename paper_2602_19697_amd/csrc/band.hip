@@ -458,74 +458,88 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
   }
 }
 
-// Exclusive scan of the per-block counts in one block of 1024 threads; writes
-// offsets[nb] and the total to *n_total.  Each thread sums a contiguous chunk
-// (loads unrolled so several are in flight), the 1024 chunk sums are scanned
-// with wave shuffles and one pass over the 16 wave totals, and each thread
-// then writes its chunk's offsets.  The per-block work counts (fused
-// voxel-views, cell tests) are summed into work_total[0..1] alongside.
-// Integer sums: any order is exact.
-__global__ __launch_bounds__(1024) void k_scan_counts(const uint32_t* __restrict__ counts, int64_t nb,
-                                                      uint64_t* __restrict__ offsets,
-                                                      uint64_t* __restrict__ n_total,
-                                                      const uint2* __restrict__ work,
-                                                      unsigned long long* __restrict__ work_total) {
-  __shared__ uint64_t wsum[16], wf[16], wt[16];
-  const int64_t chunk = bf_cdiv(nb, 1024);
-  const int64_t lo = threadIdx.x * chunk;
-  const int64_t hi = lo + chunk < nb ? lo + chunk : nb;
+// Exclusive scan of the per-block counts in two passes over contiguous
+// segments of them, one workgroup per segment (at most kScanBlocks): the
+// first sums each segment's counts and work counts (fused voxel-views, cell
+// tests); the second starts each segment from the sum of the segments before
+// it and scans the segment 256 counts at a time, writing offsets[nb], the
+// total to *n_total and the work totals to work_total[0..1].  Integer sums:
+// any order is exact.
+constexpr int kScanBlocks = 256;
+
+// Sum over the workgroup of 256 threads; lds holds 4 values.
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();  // lds is free
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return lds[0] + lds[1] + lds[2] + lds[3];
+}
+
+__global__ __launch_bounds__(256) void k_scan_part(const uint32_t* __restrict__ counts,
+                                                   const uint2* __restrict__ work, int64_t nb, int64_t seg,
+                                                   uint64_t* __restrict__ part) {
+  __shared__ uint64_t lds[4];
+  const int64_t lo = (int64_t)blockIdx.x * seg, hi = lo + seg < nb ? lo + seg : nb;
   uint64_t s = 0, sf = 0, st = 0;
-#pragma unroll 8
-  for (int64_t b = lo; b < hi; ++b) {
+  for (int64_t b = lo + threadIdx.x; b < hi; b += 256) {
     s += counts[b];
     const uint2 wk = work[b];
     sf += wk.x;
     st += wk.y;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    sf += __shfl_xor(sf, off, 64);
-    st += __shfl_xor(st, off, 64);
-  }
-  // inclusive scan of the chunk sums: within each wave, then across waves
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint64_t inc = s;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint64_t v = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += v;
-  }
-  if (lane == 63) wsum[wid] = inc;
-  if (lane == 0) {
-    wf[wid] = sf;
-    wt[wid] = st;
-  }
-  __syncthreads();
+  s = block_sum_u64(s, lds);
+  sf = block_sum_u64(sf, lds);
+  st = block_sum_u64(st, lds);
   if (threadIdx.x == 0) {
-    uint64_t a = 0, c = 0;
-    for (int w = 0; w < 16; ++w) {
-      a += wf[w];
-      c += wt[w];
-    }
-    work_total[0] = a;
-    work_total[1] = c;
+    part[blockIdx.x] = s;
+    part[gridDim.x + blockIdx.x] = sf;
+    part[2 * gridDim.x + blockIdx.x] = st;
   }
-  if (wid == 0) {
-    uint64_t w = lane < 16 ? wsum[lane] : 0;
+}
+
+__global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__ counts, int64_t nb, int64_t seg,
+                                                    const uint64_t* __restrict__ part,
+                                                    uint64_t* __restrict__ offsets, uint64_t* __restrict__ n_total,
+                                                    unsigned long long* __restrict__ work_total) {
+  __shared__ uint64_t lds[4], wtot[4];
+  const int G = gridDim.x, g = blockIdx.x;
+  uint64_t pre = 0;
+  for (int i = threadIdx.x; i < g; i += 256) pre += part[i];
+  pre = block_sum_u64(pre, lds);
+  if (g == 0) {
+    uint64_t sf = 0, st = 0;
+    for (int i = threadIdx.x; i < G; i += 256) {
+      sf += part[G + i];
+      st += part[2 * G + i];
+    }
+    sf = block_sum_u64(sf, lds);
+    st = block_sum_u64(st, lds);
+    if (threadIdx.x == 0) {
+      work_total[0] = sf;
+      work_total[1] = st;
+    }
+  }
+  const int64_t lo = (int64_t)g * seg, hi = lo + seg < nb ? lo + seg : nb;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t b0 = lo; b0 < hi; b0 += 256) {  // the same trip count for every thread
+    const int64_t b = b0 + threadIdx.x;
+    const uint64_t cnt = b < hi ? counts[b] : 0;
+    uint64_t inc = cnt;
 #pragma unroll
-    for (int off = 1; off < 16; off <<= 1) {
-      const uint64_t v = __shfl_up(w, off, 64);
-      if (lane >= off) w += v;
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint64_t v = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += v;
     }
-    if (lane < 16) wsum[lane] = w;  // inclusive totals through wave `lane`
+    __syncthreads();  // the previous strip's wave totals are read
+    if (lane == 63) wtot[wid] = inc;
+    __syncthreads();
+    uint64_t before = pre;
+    for (int w = 0; w < wid; ++w) before += wtot[w];
+    if (b < hi) offsets[b] = before + inc - cnt;
+    pre += wtot[0] + wtot[1] + wtot[2] + wtot[3];
   }
-  __syncthreads();
-  uint64_t run = (wid > 0 ? wsum[wid - 1] : 0) + inc - s;  // exclusive offset of this chunk
-#pragma unroll 8
-  for (int64_t b = lo; b < hi; ++b) {
-    offsets[b] = run;
-    run += counts[b];
-  }
-  if (threadIdx.x == 1023) *n_total = wsum[15];
+  if (g == G - 1 && threadIdx.x == 0) *n_total = pre;
 }
 
 // Scatter of the band voxels of one block tile in Morton order.
@@ -753,7 +767,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   const size_t off_cmask = off_tmask + nblocks * (2 * kMaskWords * sizeof(uint32_t));
   const size_t off_live = off_cmask + nblocks * sizeof(uint32_t);
   const size_t off_vmask = (off_live + nblocks * sizeof(uint32_t) + 255) / 256 * 256;
-  const size_t scan_bytes = off_vmask + nblocks * (kCells * kMaskWords * sizeof(uint32_t));
+  const size_t off_part = (off_vmask + nblocks * (kCells * kMaskWords * sizeof(uint32_t)) + 255) / 256 * 256;
+  const size_t scan_bytes = off_part + 3 * kScanBlocks * sizeof(uint64_t);
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
   int* dflags = (int*)scan_ws;
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
@@ -829,8 +844,15 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
                      depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, vmask, live_bits, work,
                      cellmask);
   if (bf_status s = bf_launch_check(ctx, "k_tsdf_count")) return fail(s);
-  BF_LAUNCH(ctx, "scan_counts", k_scan_counts, dim3(1), dim3(1024), 0, counts, nblocks, offsets, d_ntotal, work,
-            (unsigned long long*)((char*)scan_ws + 24));
+  {
+    // segments of at least 1024 counts, at most kScanBlocks of them (one, holding nothing, for an empty grid)
+    const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(kScanBlocks, bf_cdiv(nblocks, 1024)));
+    const int64_t seg = std::max<int64_t>(1, bf_cdiv(nblocks, sg));
+    uint64_t* part = (uint64_t*)((char*)scan_ws + off_part);
+    BF_LAUNCH(ctx, "scan_counts", k_scan_part, dim3(sg), dim3(256), 0, counts, work, (int64_t)nblocks, seg, part);
+    BF_LAUNCH(ctx, "scan_counts", k_scan_final, dim3(sg), dim3(256), 0, counts, (int64_t)nblocks, seg, part, offsets,
+              d_ntotal, (unsigned long long*)((char*)scan_ws + 24));
+  }
   if (bf_status s = bf_launch_check(ctx, "k_scan_counts")) return fail(s);
 
   void* pin = nullptr;

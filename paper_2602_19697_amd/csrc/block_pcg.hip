@@ -314,6 +314,23 @@ __device__ __forceinline__ double x_base(int xb, const double* __restrict__ xc, 
   return 0.0;
 }
 
+// The start of x at one element under BState::xbase kind k: the stored x64
+// value, the warm start +-w by the probe's sign, or zero.  sgn holds the sign
+// in bit 31 (the rest zero), so the negation is one XOR on the high word;
+// wp[wi] is read only for k == 1 (w is null without a warm start).
+__device__ __forceinline__ double xbase_at(int k, const double* __restrict__ xc, uint32_t e, uint32_t sgn,
+                                           const double* __restrict__ wp, uint32_t wi) {
+  if (k == 0) return xc[e];
+  if (k == 1) {
+    const double v = wp[wi];
+    return __hiloint2double(__double2hiint(v) ^ (int)sgn, __double2loint(v));
+  }
+  return 0.0;
+}
+
+// Bit sh of word moved to bit 31: the sign of probe sh in a packed-sign word.
+__device__ __forceinline__ uint32_t sign_bit(uint32_t word, int sh) { return (word << (31 - sh)) & 0x80000000u; }
+
 // Packs the signs of the K probes (eq. 12's Rademacher vectors, SplitMix64 as
 // in the header) of every row: one hash per (row, column), gathered with a
 // wave ballot.  Columns c >= K get +1 (they never run).
@@ -451,10 +468,14 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
       const bool neg = (zn[0][wd][j] >> sh) & 1u;
       const double zv = neg ? -1.0 : 1.0;
       const double xs = neg ? -wn[0][j] : wn[0][j];
+      // no branch per neighbour: an absent one adds +0.0, which leaves the sum
+      // unchanged (a sum of nonzero terms that starts at +0.0 is never -0.0)
       double acc = 0.0;
 #pragma unroll
-      for (int a = 0; a < 6; ++a)
-        if (rt.nb[a][j] >= 0) acc += ((zn[1 + a][wd][j] >> sh) & 1u) ? -wn[1 + a][j] : wn[1 + a][j];
+      for (int a = 0; a < 6; ++a) {
+        const double t = xbase_at(1, nullptr, 0u, sign_bit(zn[1 + a][wd][j], sh), wn[1 + a], (uint32_t)j);
+        acc += rt.nb[a][j] >= 0 ? t : 0.0;
+      }
       const double res = zv - (rt.d[j] * xs - lam * acc);
       if (store_x) x64[e] = xs;
       v3[0] += res * res;
@@ -469,23 +490,6 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
 }
-
-// The start of x at one element under BState::xbase kind k: the stored x64
-// value, the warm start +-w by the probe's sign, or zero.  sgn holds the sign
-// in bit 31 (the rest zero), so the negation is one XOR on the high word;
-// wp[wi] is read only for k == 1 (w is null without a warm start).
-__device__ __forceinline__ double xbase_at(int k, const double* __restrict__ xc, uint32_t e, uint32_t sgn,
-                                           const double* __restrict__ wp, uint32_t wi) {
-  if (k == 0) return xc[e];
-  if (k == 1) {
-    const double v = wp[wi];
-    return __hiloint2double(__double2hiint(v) ^ (int)sgn, __double2loint(v));
-  }
-  return 0.0;
-}
-
-// Bit sh of word moved to bit 31: the sign of probe sh in a packed-sign word.
-__device__ __forceinline__ uint32_t sign_bit(uint32_t word, int sh) { return (word << (31 - sh)) & 0x80000000u; }
 
 // The rows of one tile of k_bres (see there).  XBK: the start kind of x in
 // mixed precision when it is the same for every column of the wave (then the
