@@ -251,8 +251,8 @@ def run_gpu(args):
     while P < wl.G:
         P *= 2
     rooflines = {}
-    # the verify pass formed the estimate when the estimate pass only ever found it done
-    estimate = "hutch_final" not in kernels and "hutch_final_idle" in kernels
+    # the verify pass formed the estimate when the estimate pass never ran (or found it done)
+    estimate = "block_verify" in kernels and "hutch_final" not in kernels
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
                              voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"],
@@ -396,7 +396,7 @@ def _kernel_rooflines(tm, N, K, T, G, fp64):
         if launches == 0:
             continue
         w = algorithmic_work(kname, N, K, T, G, 0, fp64=fp64,
-                             estimate="hutch_final" not in tm and "hutch_final_idle" in tm)
+                             estimate="block_verify" in tm and "hutch_final" not in tm)
         if w is None or w[2] != "hbm":
             continue
         gbs = w[0] / (ms * 1e-3 / launches) / 1e9

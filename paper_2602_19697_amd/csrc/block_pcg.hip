@@ -1093,7 +1093,10 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   // (8: -12%, 16: -5%, 64: -34% at two workgroups per CU); BF_STENCIL_LDS_KB in {16, 32, 64} overrides
   const char* skb = getenv("BF_STENCIL_LDS_KB");
   const int stencil_kb = skb ? atoi(skb) : 32;
-  int it = 0, next = 3;
+  // iterations queued before the first poll: one from the log-variance start
+  // (a learned start often meets the tolerance at once), else three; then the
+  // batches grow (3, 7, 14, ...)
+  int it = 0, next = logvar ? 1 : 3;
   size_t fin_rec = 0;  // timing record of the last queued estimate pass (FP64)
   const unsigned hutch_grid =
       (unsigned)std::min<int64_t>(bf_cdiv(N, (KC > 1 ? 8 : 4) * (kThreads / KC)), 8 * (int64_t)ctx->cu_count);
@@ -1205,19 +1208,23 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     if (!mixed) {
       fin_rec = ctx->recs.size();
       hutch();
-      BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
+    // the solve's end, if this poll finds it done (mixed: unless a closing pass follows)
+    BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(BState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (hs->nactive == 0 || it >= o->max_iter) break;
-    next = it + std::max(it, 4);
+    next = it < 3 ? 3 : it + std::max(it, 4);
   }
   const size_t loop_rec_end = mixed ? ctx->recs.size() : fin_rec;
   // The report's residual of each column is the FP64 one of its last check:
   // a column stops only after such a check (or at INIT, or on a breakdown),
   // and its solution does not change afterwards, so no further pass is needed.
-  size_t hutch_rec = fin_rec;  // timing record of the last queued estimate pass
-  if (mixed) {
+  // timing record of the last queued estimate pass (none: mixed, until one is queued below)
+  size_t hutch_rec = mixed ? SIZE_MAX : fin_rec;
+  // Mixed: the estimate pass, unless every column stopped at a VERIFY pass
+  // that formed it (then the last poll has the final state already)
+  if (mixed && !(hs->nactive == 0 && hs->s_fused)) {
     if (tri) BF_LAUNCH(ctx, "block_fold", k_bfold<KC>, dim3(nb), dim3(kThreads), 0, st, 1, x64, cf, N);
     hutch_rec = ctx->recs.size();
     hutch();
@@ -1243,7 +1250,7 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   if (status == BF_OK && hs->nactive != 0) status = BF_ERR_NOT_CONVERGED;
   if (ctx->timing && (size_t)maxit < iter_rec.size()) bf_timing_mark_idle(ctx, iter_rec[maxit], loop_rec_end);
   // a VERIFY pass formed the estimate: the closing estimate pass found nothing to do
-  if (ctx->timing && hs->s_fused) bf_timing_mark_idle(ctx, hutch_rec, hutch_rec + 1);
+  if (ctx->timing && hs->s_fused && hutch_rec != SIZE_MAX) bf_timing_mark_idle(ctx, hutch_rec, hutch_rec + 1);
   if (rep) {
     rep->iters = maxit;
     rep->status = status;

@@ -34,6 +34,7 @@ struct PcgState {
   int32_t iters, done, check, status, last, refinements, max_iter, replace_every;
   int32_t guard;    // a start was supplied: drop it if ||rhs - Q x0|| >= ||rhs||
   int32_t dropped;  // ... and it was: the solve restarts from x = 0
+  int32_t closed;   // done was decided by a true-residual pass, so x is folded and rr_true is its residual
 };
 
 // GUARD: after INIT with a supplied start that was dropped, INIT again from x = 0.
@@ -346,6 +347,7 @@ __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__
     }
     if (tot[2] == 0.0 || tot[0] <= st->tol2b) {
       st->done = 1;
+      st->closed = 1;
       return;
     }
     st->rho = tot[1];
@@ -354,6 +356,7 @@ __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__
     if (st->max_iter <= 0) {
       st->status = BF_ERR_NOT_CONVERGED;
       st->done = 1;
+      st->closed = 1;
     }
     return;
   }
@@ -361,11 +364,14 @@ __global__ __launch_bounds__(256) void k_residual_scalars(PcgState* __restrict__
   if (!isfinite(tot[0]) || !isfinite(tot[1])) {
     st->status = BF_ERR_BREAKDOWN;
     st->done = 1;
+    st->closed = 1;
   } else if (tot[0] <= st->tol2b) {
     st->done = 1;
+    st->closed = 1;
   } else if (st->last) {
     st->status = BF_ERR_NOT_CONVERGED;
     st->done = 1;
+    st->closed = 1;
   } else {
     // FP64: continue CG from the replaced residual.  Mixed: the float
     // correction has been folded; restart the inner solve on the new residual
@@ -478,7 +484,10 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
   PcgState* hs = &hs_local;
   if (!noalloc) BF_TRY(bf_pinned(ctx, sizeof(PcgState), (void**)&hs));
   int it = 0;
-  int next = o->check_every > 0 ? o->check_every : 3;
+  // iterations queued before the first poll: one from a supplied start (a
+  // learned start often meets the tolerance at once), else three; then the
+  // batches grow (3, 7, 14, ...)
+  int next = o->check_every > 0 ? o->check_every : (o->use_x0 ? 1 : 3);
   V* pa = p0;
   V* pb = p1;
   const V lamV = (V)sys->lambda;
@@ -513,15 +522,18 @@ bf_status run_pcg(bf_ctx* ctx, const bf_system* sys, const bf_solve_opts* o, con
       fin_rec = ctx->recs.size();
       residual((int)MODE_REPORT, (const double*)x);
       BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
-      if (e1) BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     }
+    // the solve's end, if this poll finds it done (mixed: unless a closing pass follows)
+    if (e1) BF_HIP(ctx, hipEventRecord(e1, ctx->stream));
     BF_HIP(ctx, hipMemcpyAsync(hs, st, sizeof(PcgState), hipMemcpyDeviceToHost, ctx->stream));
     BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
     if (hs->done || it >= o->max_iter) break;
-    next = o->check_every > 0 ? it + o->check_every : it + std::max(it, 4);
+    next = o->check_every > 0 ? it + o->check_every : (it < 3 ? 3 : it + std::max(it, 4));
   }
   const size_t loop_rec_end = mixed ? ctx->recs.size() : fin_rec;
-  if (mixed) {
+  // Mixed: unless the solve ended at a true-residual pass (its x folded, its
+  // residual the reported one), fold what is left and take the residual.
+  if (mixed && !(hs->done && hs->closed)) {
     BF_LAUNCH(ctx, "pcg_fold", k_fold, dim3(nb), dim3(kThreads), 0, st, 1, x, c, N);
     residual((int)MODE_REPORT, (const double*)x);
     BF_LAUNCH(ctx, "pcg_scalars", k_residual_scalars, dim3(1), dim3(256), 0, st, (int)MODE_REPORT, part, nb);
