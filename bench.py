@@ -88,7 +88,7 @@ def measured_traffic(kernel, workload):
 
 # Operations per fused voxel-view of the coarse TSDF (FP64 projection, two
 # divisions, truncation, running sum) and per screening test of a (box, view)
-# pair, the box being a block tile or a 4^3 cell: one FP64 corner transform
+# pair, the box being a super tile, a block tile or a 4^3 cell: one FP64 corner transform
 # (27), box edges and Z range (22), 36 FP64 corner adds, 8 FP32 projections of
 # 12 operations (96), pixel range and pyramid bounds (31), final tests (5),
 # counted arithmetic, min/max, compare and convert operations alike.
@@ -97,7 +97,7 @@ TSDF_OPS_PER_CELL_VIEW = 217
 
 
 def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None, warm=False,
-                     estimate=False):
+                     estimate=False, tile_tests=None):
     """(amount, unit, bound) of one launch of a timed kernel.  warm: the probe
     solve starts from the log-variance start +-w (w per row) rather than 0.
     estimate: the verify pass also formed the variance estimate s (8 B per row
@@ -127,15 +127,18 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return N * (24 + 8 + 8 + K / 8 + 2 * K * s + (8 * K if fp64 else 0)), "B", "hbm"
     # block_residual and pcg_residual time full passes (a start residual) and
     # checks that find nothing to do under one label: no per-launch roofline
-    # screening: one tile test per (16x8x8 block tile, view of the first 256);
-    # the rest of the counted tests are cell tests
-    tile_tests = (-(-G // 16)) * (-(-G // 8)) ** 2 * min(T, 256)
+    # screening: one super tile test per (32x16x16 super tile, view of the first
+    # 256), block tile tests for the super tiles' undecided views, then cell
+    # tests (all counted by the kernels but the first)
+    super_tests = (-(-G // 32)) * (-(-G // 16)) ** 2 * min(T, 256)
     if name == "tsdf_count":  # fused voxel-views (counted by the kernel)
         vv = G ** 3 * T if voxel_views is None else voxel_views
         return vv * TSDF_OPS_PER_VOXEL_VIEW, "flop", "alu"
-    if name == "tile_screen":
-        return tile_tests * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
-    if name == "cell_screen" and box_tests is not None:
+    if name == "super_screen":
+        return super_tests * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
+    if name == "tile_screen" and tile_tests is not None:
+        return (tile_tests - super_tests) * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
+    if name == "cell_screen" and box_tests is not None and tile_tests is not None:
         return (box_tests - tile_tests) * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
     if name == "assemble":
         return N * T * 45, "flop", "alu"
@@ -213,6 +216,7 @@ def run_gpu(args):
         scores, best = ctx.bf_nbv_score(band, mu, s, cands, wl.ray_cam)
         out = dict(N=band.n, iters=rep["iters"], probe_iters=prep["iters"], walk_steps=ctx.bf_nbv_walk_steps(),
                    tsdf_voxel_views=band.info()["tsdf_voxel_views"], tsdf_box_tests=band.info()["tsdf_box_tests"],
+                   tsdf_tile_tests=band.info()["tsdf_tile_tests"],
                    work=band.n * (rep["col_iters"] + prep["col_iters"]), best=best,
                    probe_col_iters=prep["col_iters"], mean_col_iters=rep["col_iters"],
                    rel_res=rep["rel_res"], probe_rel_res=prep["rel_res"])
@@ -256,6 +260,7 @@ def run_gpu(args):
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
                              voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"],
+                             tile_tests=info["tsdf_tile_tests"],
                              warm=args.learned, estimate=estimate)
         if w is None:
             continue

@@ -142,7 +142,9 @@ typedef struct bf_band_arrays {
   const int32_t* dense_w;     /* [P^3] Morton-ordered dense weights, or NULL */
   int64_t tsdf_voxel_views;   /* voxel x view projections the coarse TSDF evaluated; 4^3 cells that
                                  provably hold no band voxel are skipped (not with BF_BAND_KEEP_DENSE) */
-  int64_t tsdf_box_tests;     /* (block tile or 4^3 cell, view) screening tests made for that skipping */
+  int64_t tsdf_box_tests;     /* (box, view) screening tests made for that skipping; a box is a
+                                 32x16x16 super tile, a 16x8x8 block tile or a 4^3 cell */
+  int64_t tsdf_tile_tests;    /* ... of them, those of super tiles and block tiles */
 } bf_band_arrays;
 
 typedef struct bf_system_arrays {

@@ -130,7 +130,7 @@ class Band:
         a = L.bf_band_arrays()
         self.ctx._check(self.ctx.lib.bf_band_view(self.handle, C.byref(a)))
         return {"n": int(a.n), "dense_side": int(a.dense_side), "tsdf_voxel_views": int(a.tsdf_voxel_views),
-                "tsdf_box_tests": int(a.tsdf_box_tests)}
+                "tsdf_box_tests": int(a.tsdf_box_tests), "tsdf_tile_tests": int(a.tsdf_tile_tests)}
 
     def arrays(self) -> dict:
         a = L.bf_band_arrays()
@@ -142,7 +142,7 @@ class Band:
                "nbr": _view(a.nbr, (n, 6), torch.int32, dev),
                "deg": _view(a.deg, (n,), torch.int32, dev),
                "dense_side": int(a.dense_side), "tsdf_voxel_views": int(a.tsdf_voxel_views),
-               "tsdf_box_tests": int(a.tsdf_box_tests)}
+               "tsdf_box_tests": int(a.tsdf_box_tests), "tsdf_tile_tests": int(a.tsdf_tile_tests)}
         P3 = int(a.dense_side) ** 3
         if a.dense_tsdf:
             out["dense_tsdf"] = _view(a.dense_tsdf, (P3,), torch.float64, dev)

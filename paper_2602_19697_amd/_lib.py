@@ -81,7 +81,7 @@ class bf_band_arrays(C.Structure):
     _fields_ = [("n", C.c_int64), ("dense_side", C.c_int32), ("keys", C.c_void_p),
                 ("tsdf", C.c_void_p), ("w", C.c_void_p), ("nbr", C.c_void_p), ("deg", C.c_void_p),
                 ("dense_tsdf", C.c_void_p), ("dense_w", C.c_void_p), ("tsdf_voxel_views", C.c_int64),
-                ("tsdf_box_tests", C.c_int64)]
+                ("tsdf_box_tests", C.c_int64), ("tsdf_tile_tests", C.c_int64)]
 
 
 class bf_system_arrays(C.Structure):

@@ -252,6 +252,7 @@ bf_status bf_band_view(const bf_band* band, bf_band_arrays* out) {
   out->dense_w = band->dense_w;
   out->tsdf_voxel_views = band->tsdf_voxel_views;
   out->tsdf_box_tests = band->tsdf_box_tests;
+  out->tsdf_tile_tests = band->tsdf_tile_tests;
   return BF_OK;
 }
 

@@ -227,13 +227,14 @@ __device__ int cell_view_class(const bf_grid_k& g, const bf_cam_k& c, const Pyr&
 // (taken in view order) bit for bit.  Per-view masks cover the first
 // 32 * kMaskWords views; later views are always fused.
 //
-// The screen is two-level: k_tile_screen first tests each block tile (a
-// 16 x 8 x 8 voxel box) against each of the first kTileViews views.  What
-// holds for the tile holds for each of its cells, so a tile-level kViewNone
-// needs no cell tests and a tile-level kViewFar marks the view as
-// contributing for every cell (a cell the view does not in fact observe gets
-// no observation from it in the fused loop); only the kViewMay views, and
-// views past kTileViews, are tested cell by cell (k_cell_screen).
+// The screen has three levels: k_super_screen tests each super tile (8 block
+// tiles, a 32 x 16 x 16 voxel box) against each of the first kTileViews views,
+// k_tile_screen each block tile (16 x 8 x 8) against the views its super tile
+// left undecided, and k_cell_screen each cell against those its block tile
+// left undecided, and against every view past kTileViews.  What holds for a
+// box holds for every box inside it, so a kViewNone needs no test below and a
+// kViewFar marks the view as contributing for every cell (a cell the view does
+// not in fact observe gets no observation from it in the fused loop).
 constexpr int kCells = kTile / 64;  // 4^3 cells per block tile; one wave fuses one cell
 constexpr int kMaskWords = 8;
 constexpr int kTileViews = 32 * kMaskWords;
@@ -241,35 +242,103 @@ constexpr int kViewBatch = 4;  // views whose depth loads the fused loop has in 
 constexpr int kTileI = 16, kTileJ = 8, kTileK = 8;  // Morton tile of kTile codes (x takes the low bit)
 static_assert(kTileI * kTileJ * kTileK == kTile, "block tile box");
 
-// One wave per (block tile, 64 views): the tile's kViewFar and kViewMay view
-// masks, tmask[tile][0 | 1][word], from the ballots of the lanes' tests.
-__global__ __launch_bounds__(256) void k_tile_screen(bf_grid_k g, bf_cam_k c, int32_t T, int64_t ntiles,
-                                                     const float* __restrict__ depth,
-                                                     const double* __restrict__ poses, Pyr P,
-                                                     const float* __restrict__ dmin,
-                                                     const float* __restrict__ dmax, uint32_t* __restrict__ tmask) {
+// The screen's first level: one wave per (super tile, 64 views), a super tile
+// being kSuper consecutive block tiles in Morton order (a 32 x 16 x 16 voxel
+// box): its kViewFar and kViewMay view masks, smask[sup][0 | 1][word], from
+// the ballots of the lanes' tests.
+constexpr int kSuper = 8;
+constexpr int kSupI = 2 * kTileI, kSupJ = 2 * kTileJ, kSupK = 2 * kTileK;
+constexpr int kChunks = kTileViews / 64;  // 64-view chunks of the masks
+__global__ __launch_bounds__(256) void k_super_screen(bf_grid_k g, bf_cam_k c, int32_t T, int64_t nsup,
+                                                      const float* __restrict__ depth,
+                                                      const double* __restrict__ poses, Pyr P,
+                                                      const float* __restrict__ dmin,
+                                                      const float* __restrict__ dmax, uint32_t* __restrict__ smask) {
 #pragma clang fp contract(off)
   const int32_t tv = min(T, kTileViews);
   const int nchunk = (tv + 63) >> 6;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (wave >= ntiles * nchunk) return;  // whole waves: ntiles * nchunk waves exactly
-  const int64_t tile = wave / nchunk;
+  if (wave >= nsup * nchunk) return;  // whole waves: nsup * nchunk waves exactly
+  const int64_t sup = wave / nchunk;
   const int chunk = (int)(wave % nchunk);
-  const uint64_t base = (uint64_t)tile * kTile;
-  const int32_t ti = (int32_t)bf_compact3(base), tj = (int32_t)bf_compact3(base >> 1),
-                tk = (int32_t)bf_compact3(base >> 2);
+  const uint64_t base = (uint64_t)sup * (kSuper * kTile);
+  const int32_t si = (int32_t)bf_compact3(base), sj = (int32_t)bf_compact3(base >> 1),
+                sk = (int32_t)bf_compact3(base >> 2);
   const int t = chunk * 64 + lane;
   int cls = kViewNone;
-  const bool test = t < tv && ti < g.G && tj < g.G && tk < g.G;  // else no voxel of the tile exists
+  // a super tile with no voxel in the grid needs no test; one reaching past
+  // the grid is tested as the whole box (a larger box only widens the classes)
+  const bool test = t < tv && si < g.G && sj < g.G && sk < g.G;
   if (test)
-    cls = cell_view_class(g, c, P, depth + t * ((int64_t)c.W * c.H), dmin, dmax, poses + 12 * t, t, ti, tj, tk,
-                          kTileI, kTileJ, kTileK);
+    cls = cell_view_class(g, c, P, depth + t * ((int64_t)c.W * c.H), dmin, dmax, poses + 12 * t, t, si, sj, sk,
+                          kSupI, kSupJ, kSupK);
   const uint64_t far = __ballot(cls == kViewFar), may = __ballot(cls == kViewMay);
-  uint32_t* tm = tmask + tile * (2 * kMaskWords);
+  uint32_t* sm = smask + sup * (2 * kMaskWords);
   if (lane < 2) {
-    tm[2 * chunk + lane] = (uint32_t)(far >> (32 * lane));
-    tm[kMaskWords + 2 * chunk + lane] = (uint32_t)(may >> (32 * lane));
+    sm[2 * chunk + lane] = (uint32_t)(far >> (32 * lane));
+    sm[kMaskWords + 2 * chunk + lane] = (uint32_t)(may >> (32 * lane));
+  }
+}
+
+// The second level: one wave per (super tile, 64 views) writes the block
+// tiles' masks tmask[tile][0 | 1][word].  Every voxel of a block tile is a
+// voxel of its super tile, so a view that is kViewNone or kViewFar for the
+// super tile is that for each of its block tiles; only the super tile's
+// kViewMay views are tested tile by tile, the lanes taking the (tile, view)
+// pairs in turn.  tests[tile][chunk]: the tile's tests in this chunk.
+__global__ __launch_bounds__(256) void k_tile_screen(bf_grid_k g, bf_cam_k c, int32_t T, int64_t ntiles,
+                                                     const float* __restrict__ depth,
+                                                     const double* __restrict__ poses, Pyr P,
+                                                     const float* __restrict__ dmin, const float* __restrict__ dmax,
+                                                     const uint32_t* __restrict__ smask,
+                                                     uint32_t* __restrict__ tmask, uint32_t* __restrict__ tests) {
+#pragma clang fp contract(off)
+  __shared__ int vlist[kThreads / 64][64];
+  __shared__ uint32_t res[kThreads / 64][kSuper][2][2];  // [wave][tile][far | may][word]
+  const int32_t tv = min(T, kTileViews);
+  const int nchunk = (tv + 63) >> 6;
+  const int64_t nsup = bf_cdiv(ntiles, kSuper);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6;
+  if (wave >= nsup * nchunk) return;  // whole waves; no workgroup barrier below
+  const int64_t sup = wave / nchunk;
+  const int chunk = (int)(wave % nchunk);
+  const uint32_t* sm = smask + sup * (2 * kMaskWords);
+  const uint64_t sfar = (uint64_t)sm[2 * chunk] | ((uint64_t)sm[2 * chunk + 1] << 32);
+  const uint64_t smay = (uint64_t)sm[kMaskWords + 2 * chunk] | ((uint64_t)sm[kMaskWords + 2 * chunk + 1] << 32);
+  const int m = __popcll(smay);
+  // the super tile's kViewMay views of the chunk, in view order
+  if ((smay >> lane) & 1ull) vlist[wl][__popcll(smay & ((1ull << lane) - 1ull))] = chunk * 64 + lane;
+  if (lane < kSuper * 4) (&res[wl][0][0][0])[lane] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's LDS writes are done
+  for (int q = lane; q < kSuper * m; q += 64) {
+    const int kt = q / m, t = vlist[wl][q % m];
+    const int64_t tile = sup * kSuper + kt;
+    if (tile >= ntiles) continue;
+    const uint64_t base = (uint64_t)tile * kTile;
+    const int32_t ti = (int32_t)bf_compact3(base), tj = (int32_t)bf_compact3(base >> 1),
+                  tk = (int32_t)bf_compact3(base >> 2);
+    if (ti >= g.G || tj >= g.G || tk >= g.G) continue;  // no voxel of the tile exists
+    const int cls = cell_view_class(g, c, P, depth + t * ((int64_t)c.W * c.H), dmin, dmax, poses + 12 * t, t, ti,
+                                    tj, tk, kTileI, kTileJ, kTileK);
+    const int bit = t - chunk * 64;
+    if (cls == kViewFar) atomicOr(&res[wl][kt][0][bit >> 5], 1u << (bit & 31));
+    if (cls == kViewMay) atomicOr(&res[wl][kt][1][bit >> 5], 1u << (bit & 31));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  if (lane < kSuper * 2) {
+    const int kt = lane >> 1, wd = lane & 1;
+    const int64_t tile = sup * kSuper + kt;
+    if (tile < ntiles) {
+      const uint64_t base = (uint64_t)tile * kTile;
+      const bool exists = (int32_t)bf_compact3(base) < g.G && (int32_t)bf_compact3(base >> 1) < g.G &&
+                          (int32_t)bf_compact3(base >> 2) < g.G;
+      uint32_t* tm = tmask + tile * (2 * kMaskWords);
+      tm[2 * chunk + wd] = exists ? (uint32_t)(sfar >> (32 * wd)) | res[wl][kt][0][wd] : 0u;
+      tm[kMaskWords + 2 * chunk + wd] = exists ? res[wl][kt][1][wd] : 0u;
+      if (wd == 0) tests[tile * kChunks + chunk] = exists ? (uint32_t)m : 0u;
+    }
   }
 }
 
@@ -461,9 +530,10 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
 // Exclusive scan of the per-block counts in two passes over contiguous
 // segments of them, one workgroup per segment (at most kScanBlocks): the
 // first sums each segment's counts and work counts (fused voxel-views, cell
-// tests); the second starts each segment from the sum of the segments before
-// it and scans the segment 256 counts at a time, writing offsets[nb], the
-// total to *n_total and the work totals to work_total[0..1].  Integer sums:
+// tests, block tile tests of nchunk view chunks); the second starts each
+// segment from the sum of the segments before it and scans the segment 256
+// counts at a time, writing offsets[nb], the total to *n_total and the work
+// totals to work_total[0..2].  Integer sums:
 // any order is exact.
 constexpr int kScanBlocks = 256;
 
@@ -477,24 +547,28 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* lds) {
 }
 
 __global__ __launch_bounds__(256) void k_scan_part(const uint32_t* __restrict__ counts,
-                                                   const uint2* __restrict__ work, int64_t nb, int64_t seg,
-                                                   uint64_t* __restrict__ part) {
+                                                   const uint2* __restrict__ work,
+                                                   const uint32_t* __restrict__ ttests, int nchunk, int64_t nb,
+                                                   int64_t seg, uint64_t* __restrict__ part) {
   __shared__ uint64_t lds[4];
   const int64_t lo = (int64_t)blockIdx.x * seg, hi = lo + seg < nb ? lo + seg : nb;
-  uint64_t s = 0, sf = 0, st = 0;
+  uint64_t s = 0, sf = 0, st = 0, sb = 0;
   for (int64_t b = lo + threadIdx.x; b < hi; b += 256) {
     s += counts[b];
     const uint2 wk = work[b];
     sf += wk.x;
     st += wk.y;
+    for (int q = 0; q < nchunk; ++q) sb += ttests[b * kChunks + q];
   }
   s = block_sum_u64(s, lds);
   sf = block_sum_u64(sf, lds);
   st = block_sum_u64(st, lds);
+  sb = block_sum_u64(sb, lds);
   if (threadIdx.x == 0) {
     part[blockIdx.x] = s;
     part[gridDim.x + blockIdx.x] = sf;
     part[2 * gridDim.x + blockIdx.x] = st;
+    part[3 * gridDim.x + blockIdx.x] = sb;
   }
 }
 
@@ -508,16 +582,19 @@ __global__ __launch_bounds__(256) void k_scan_final(const uint32_t* __restrict__
   for (int i = threadIdx.x; i < g; i += 256) pre += part[i];
   pre = block_sum_u64(pre, lds);
   if (g == 0) {
-    uint64_t sf = 0, st = 0;
+    uint64_t sf = 0, st = 0, sb = 0;
     for (int i = threadIdx.x; i < G; i += 256) {
       sf += part[G + i];
       st += part[2 * G + i];
+      sb += part[3 * G + i];
     }
     sf = block_sum_u64(sf, lds);
     st = block_sum_u64(st, lds);
+    sb = block_sum_u64(sb, lds);
     if (threadIdx.x == 0) {
       work_total[0] = sf;
       work_total[1] = st;
+      work_total[2] = sb;
     }
   }
   const int64_t lo = (int64_t)g * seg, hi = lo + seg < nb ? lo + seg : nb;
@@ -760,7 +837,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   void* scan_ws = nullptr;
   // layout: flags and counters (64 B) | counts [nblocks] | offsets [nblocks + 1] | work counts
   // [nblocks] | tile view masks [nblocks][2][kMaskWords] | scattered-cell masks [nblocks] | live-cell
-  // bits [nblocks] | cell view masks [nblocks][kCells][kMaskWords]
+  // bits [nblocks] | cell view masks [nblocks][kCells][kMaskWords] | scan partials [4][kScanBlocks]
+  // | super tile view masks [nsup][2][kMaskWords] | block tile test counts [nblocks][kChunks]
   const size_t off_counts = 64, off_offsets = off_counts + ((nblocks * sizeof(uint32_t) + 63) / 64) * 64;
   const size_t off_work = (off_offsets + (nblocks + 1) * sizeof(uint64_t) + 255) / 256 * 256;
   const size_t off_tmask = (off_work + nblocks * sizeof(uint2) + 255) / 256 * 256;
@@ -768,7 +846,10 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   const size_t off_live = off_cmask + nblocks * sizeof(uint32_t);
   const size_t off_vmask = (off_live + nblocks * sizeof(uint32_t) + 255) / 256 * 256;
   const size_t off_part = (off_vmask + nblocks * (kCells * kMaskWords * sizeof(uint32_t)) + 255) / 256 * 256;
-  const size_t scan_bytes = off_part + 3 * kScanBlocks * sizeof(uint64_t);
+  const int64_t nsup = bf_cdiv(nblocks, kSuper);
+  const size_t off_smask = off_part + 4 * kScanBlocks * sizeof(uint64_t);
+  const size_t off_ttests = (off_smask + nsup * (2 * kMaskWords * sizeof(uint32_t)) + 255) / 256 * 256;
+  const size_t scan_bytes = off_ttests + nblocks * (kChunks * sizeof(uint32_t));
   if (bf_status s = bf_ws(ctx, bf_ctx::WS_SCAN, scan_bytes, &scan_ws)) return fail(s);
   int* dflags = (int*)scan_ws;
   uint64_t* d_ntotal = (uint64_t*)((char*)scan_ws + 16);
@@ -778,6 +859,7 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
   uint32_t* tmask = (uint32_t*)((char*)scan_ws + off_tmask);
   uint32_t* cellmask = (uint32_t*)((char*)scan_ws + off_cmask);
   uint32_t* live_bits = (uint32_t*)((char*)scan_ws + off_live);
+  uint32_t* ttests = (uint32_t*)((char*)scan_ws + off_ttests);
   uint32_t* vmask = (uint32_t*)((char*)scan_ws + off_vmask);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, ctx->stream, (uint64_t*)scan_ws, (uint64_t)8, 0ull);
 
@@ -833,10 +915,13 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               dim3(256), 0, depth_dev, cam->width, cam->height, pyr, dmin, dmax, dflags);
     if (pyr.nl > kTileLevels + 1)
       BF_LAUNCH(ctx, "depth_pyramid", k_pyr_top, dim3((unsigned)T), dim3(1024), 0, pyr, dmin, dmax);
-    // one wave per (block tile, 64 of the first kTileViews views)
-    const int64_t waves = (int64_t)nblocks * ((std::min<int32_t>(T, kTileViews) + 63) / 64);
+    // one wave per (super tile, 64 of the first kTileViews views), in both levels
+    const int64_t waves = nsup * ((std::min<int32_t>(T, kTileViews) + 63) / 64);
+    uint32_t* smask = (uint32_t*)((char*)scan_ws + off_smask);
+    BF_LAUNCH(ctx, "super_screen", k_super_screen, dim3((unsigned)bf_cdiv(waves, 4)), dim3(256), 0, gk, ck, T, nsup,
+              depth_dev, c2w_dev, pyr, dmin, dmax, smask);
     BF_LAUNCH(ctx, "tile_screen", k_tile_screen, dim3((unsigned)bf_cdiv(waves, 4)), dim3(256), 0, gk, ck, T,
-              (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, tmask);
+              (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, smask, tmask, ttests);
     BF_LAUNCH(ctx, "cell_screen", k_cell_screen, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T, depth_dev,
               c2w_dev, total, pyr, dmin, dmax, tmask, vmask, live_bits, work);
   }
@@ -849,7 +934,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
     const int sg = (int)std::max<int64_t>(1, std::min<int64_t>(kScanBlocks, bf_cdiv(nblocks, 1024)));
     const int64_t seg = std::max<int64_t>(1, bf_cdiv(nblocks, sg));
     uint64_t* part = (uint64_t*)((char*)scan_ws + off_part);
-    BF_LAUNCH(ctx, "scan_counts", k_scan_part, dim3(sg), dim3(256), 0, counts, work, (int64_t)nblocks, seg, part);
+    BF_LAUNCH(ctx, "scan_counts", k_scan_part, dim3(sg), dim3(256), 0, counts, work, ttests,
+              screen ? (std::min<int32_t>(T, kTileViews) + 63) / 64 : 0, (int64_t)nblocks, seg, part);
     BF_LAUNCH(ctx, "scan_counts", k_scan_final, dim3(sg), dim3(256), 0, counts, (int64_t)nblocks, seg, part, offsets,
               d_ntotal, (unsigned long long*)((char*)scan_ws + 24));
   }
@@ -857,18 +943,20 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
 
   void* pin = nullptr;
   if (bf_status s = bf_pinned(ctx, 64, &pin)) return fail(s);
-  if (hipMemcpyAsync(pin, scan_ws, 40, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+  if (hipMemcpyAsync(pin, scan_ws, 48, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
       hipStreamSynchronize(ctx->stream) != hipSuccess)
     return fail(bf_fail(ctx, BF_ERR_HIP, "bf_build_band: count read-back failed"));
   if (((int*)pin)[0] & 1)
     return fail(bf_fail(ctx, BF_ERR_INVALID_ARG, "bf_build_band: depth holds NaN, inf or negative values"));
   const uint64_t N = *(uint64_t*)((char*)pin + 16);
   band->tsdf_voxel_views = *(const int64_t*)((char*)pin + 24);
-  // cell tests, plus one tile test per (block tile holding a grid voxel, screened view)
-  band->tsdf_box_tests = *(const int64_t*)((char*)pin + 32);
+  // cell tests, block tile tests, and one super tile test per (super tile
+  // holding a grid voxel, screened view)
+  band->tsdf_tile_tests = *(const int64_t*)((char*)pin + 40);
   if (screen)
-    band->tsdf_box_tests += bf_cdiv(grid->G, kTileI) * bf_cdiv(grid->G, kTileJ) * bf_cdiv(grid->G, kTileK) *
-                            (int64_t)std::min<int32_t>(T, kTileViews);
+    band->tsdf_tile_tests += bf_cdiv(grid->G, kSupI) * bf_cdiv(grid->G, kSupJ) * bf_cdiv(grid->G, kSupK) *
+                             (int64_t)std::min<int32_t>(T, kTileViews);
+  band->tsdf_box_tests = *(const int64_t*)((char*)pin + 32) + band->tsdf_tile_tests;
   if (N >= (1ull << 31) - 1)
     return fail(bf_fail(ctx, BF_ERR_CAPACITY, "bf_build_band: band of %llu voxels exceeds int32 indexing",
                         (unsigned long long)N));

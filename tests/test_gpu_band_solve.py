@@ -63,12 +63,13 @@ def test_band_screening_exact(ctx, name, seed):
     assert 0 < a["tsdf_voxel_views"] < full
     # the tile-level tests spare most cell tests
     assert 0 < a["tsdf_box_tests"] < cell_views
+    assert 0 < a["tsdf_tile_tests"] <= a["tsdf_box_tests"]
     sys_.free()
     band.free()
     # with the dense grid kept, nothing is screened
     band2, sys2, _, _ = gc.gpu_system(ctx, wl, keep_dense=True)
     assert band2.arrays()["tsdf_voxel_views"] == full
-    assert band2.arrays()["tsdf_box_tests"] == 0
+    assert band2.arrays()["tsdf_box_tests"] == 0 and band2.arrays()["tsdf_tile_tests"] == 0
     sys2.free()
     band2.free()
 
