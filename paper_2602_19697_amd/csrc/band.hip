@@ -342,61 +342,63 @@ __global__ __launch_bounds__(256) void k_tile_screen(bf_grid_k g, bf_cam_k c, in
   }
 }
 
-// Cell tests of one block tile: each cell starts with the tile's kViewFar
-// views marked, then is tested against the tile's kViewMay views (in view
-// order) and every view past kTileViews.  Writes the tile's live-cell bits
-// and, for its live cells only (the only ones read), the view masks
-// cmask[tile][cell][word]; the test count goes to the high word of work[tile].
+// Cell tests of one block tile per wave (most tiles leave few views
+// undecided): each cell starts with the tile's kViewFar views marked, then is
+// tested against the tile's kViewMay views (in view order) and every view past
+// kTileViews, the lanes taking the (cell, view) pairs in turn.  Writes the
+// tile's live-cell bits and, for its live cells only (the only ones read), the
+// view masks cmask[tile][cell][word]; the test count goes to the high word of
+// work[tile].  The waves of a workgroup share nothing.
 __global__ __launch_bounds__(256) void k_cell_screen(bf_grid_k g, bf_cam_k c, int32_t T,
                                                      const float* __restrict__ depth,
-                                                     const double* __restrict__ poses, uint64_t total, Pyr P,
-                                                     const float* __restrict__ dmin,
+                                                     const double* __restrict__ poses, uint64_t total,
+                                                     int64_t ntiles, Pyr P, const float* __restrict__ dmin,
                                                      const float* __restrict__ dmax,
                                                      const uint32_t* __restrict__ tmask,
                                                      uint32_t* __restrict__ cmask, uint32_t* __restrict__ live_bits,
                                                      uint2* __restrict__ work) {
 #pragma clang fp contract(off)
-  __shared__ int live[kCells];
-  __shared__ uint32_t vmask[kCells][kMaskWords];
-  __shared__ uint32_t may_w[kMaskWords];
-  __shared__ int may_pre[kMaskWords + 1];
-  __shared__ uint32_t wave_tests[kThreads / 64];
-  const uint64_t base = (uint64_t)blockIdx.x * kTile;
+  constexpr int NW = kThreads / 64;
+  __shared__ int live[NW][kCells];
+  __shared__ uint32_t vmask[NW][kCells][kMaskWords];
+  __shared__ int may_pre[NW][kMaskWords + 1];
+  __shared__ int mlist[NW][kTileViews];  // the tile's kViewMay views in view order
+  const int wl = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t tile = (int64_t)blockIdx.x * NW + wl;
+  if (tile >= ntiles) return;  // whole waves; no workgroup barrier below
+  const uint64_t base = (uint64_t)tile * kTile;
   const int64_t plane = (int64_t)c.W * c.H;
   const int32_t tv = min(T, kTileViews);  // views the tile screen tested
   const int tvw = (tv + 31) >> 5;
-  const uint32_t* tm = tmask + (int64_t)blockIdx.x * (2 * kMaskWords);
-  if (threadIdx.x < kCells) live[threadIdx.x] = 0;
-  if (threadIdx.x < kCells * kMaskWords) {
-    const int w = threadIdx.x % kMaskWords;
-    vmask[threadIdx.x / kMaskWords][w] = w < tvw ? tm[w] : 0u;
+  const uint32_t* tm = tmask + tile * (2 * kMaskWords);
+  if (lane < kCells) live[wl][lane] = 0;
+  for (int i = lane; i < kCells * kMaskWords; i += 64) {
+    const int w = i % kMaskWords;
+    vmask[wl][i / kMaskWords][w] = w < tvw ? tm[w] : 0u;
   }
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int w = 0; w < kMaskWords; ++w) {
-      const uint32_t mw = w < tvw ? tm[kMaskWords + w] : 0u;
-      may_w[w] = mw;
-      may_pre[w] = acc;
-      acc += __popc(mw);
-    }
-    may_pre[kMaskWords] = acc;
+  // kViewMay views per mask word, and their running count before each word
+  const uint32_t mw = lane < tvw ? tm[kMaskWords + lane] : 0u;
+  int pre = lane < kMaskWords ? __popc(mw) : 0;
+  for (int off = 1; off < kMaskWords; off <<= 1) {
+    const int v = __shfl_up(pre, off, 64);
+    if (lane >= off) pre += v;
   }
-  __syncthreads();
+  if (lane < kMaskWords) may_pre[wl][lane + 1] = pre;  // inclusive through word `lane`
+  if (lane == 0) may_pre[wl][0] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's LDS writes are done
+  for (int w = 0; w < tvw; ++w) {
+    const uint32_t word = (uint32_t)__shfl((int)mw, w, 64);
+    const int t = 32 * w + (lane & 31);
+    if (lane < 32 && ((word >> (t & 31)) & 1u))
+      mlist[wl][may_pre[wl][w] + __popc(word & ((1u << (t & 31)) - 1u))] = t;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   uint32_t tests = 0;
-  const int nm_tile = may_pre[kMaskWords];
+  const int nm_tile = may_pre[wl][kMaskWords];
   const int nm = nm_tile + (T - tv);
-  for (int e = threadIdx.x; e < kCells * nm; e += kThreads) {
+  for (int e = lane; e < kCells * nm; e += 64) {
     const int cell = e % kCells, r = e / kCells;
-    int t;
-    if (r < nm_tile) {  // the r-th set bit of the kViewMay mask
-      int w = 0;
-      while (may_pre[w + 1] <= r) ++w;
-      uint32_t x = may_w[w];
-      for (int q = r - may_pre[w]; q > 0; --q) x &= x - 1u;
-      t = 32 * w + __builtin_ctz(x);
-    } else {
-      t = tv + (r - nm_tile);
-    }
+    const int t = r < nm_tile ? mlist[wl][r] : tv + (r - nm_tile);
     const uint64_t m0 = base + (uint64_t)cell * 64;
     if (m0 >= total) continue;
     const int32_t i0 = (int32_t)bf_compact3(m0), j0 = (int32_t)bf_compact3(m0 >> 1),
@@ -404,21 +406,19 @@ __global__ __launch_bounds__(256) void k_cell_screen(bf_grid_k g, bf_cam_k c, in
     if (i0 >= g.G || j0 >= g.G || k0 >= g.G) continue;
     ++tests;
     const int cls = cell_view_class(g, c, P, depth + t * plane, dmin, dmax, poses + 12 * t, t, i0, j0, k0, 4, 4, 4);
-    if (cls != kViewNone && t < kTileViews) atomicOr(&vmask[cell][t >> 5], 1u << (t & 31));
-    if (cls == kViewMay) atomicOr(&live[cell], 1);
+    if (cls != kViewNone && t < kTileViews) atomicOr(&vmask[wl][cell][t >> 5], 1u << (t & 31));
+    if (cls == kViewMay) atomicOr(&live[wl][cell], 1);
   }
   for (int off = 32; off > 0; off >>= 1) tests += __shfl_xor(tests, off, 64);
-  if ((threadIdx.x & 63) == 0) wave_tests[threadIdx.x >> 6] = tests;
-  __syncthreads();
-  if (threadIdx.x < kCells * kMaskWords && live[threadIdx.x / kMaskWords])
-    cmask[(int64_t)blockIdx.x * (kCells * kMaskWords) + threadIdx.x] =
-        vmask[threadIdx.x / kMaskWords][threadIdx.x % kMaskWords];
-  if (threadIdx.x == 0) {
-    uint32_t lm = 0, n = 0;
-    for (int q = 0; q < kCells; ++q) lm |= live[q] ? 1u << q : 0u;
-    for (int w = 0; w < kThreads / 64; ++w) n += wave_tests[w];
-    live_bits[blockIdx.x] = lm;
-    reinterpret_cast<uint32_t*>(work)[2 * blockIdx.x + 1] = n;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int i = lane; i < kCells * kMaskWords; i += 64)
+    if (live[wl][i / kMaskWords])
+      cmask[tile * (kCells * kMaskWords) + i] = vmask[wl][i / kMaskWords][i % kMaskWords];
+  if (lane == 0) {
+    uint32_t lm = 0;
+    for (int q = 0; q < kCells; ++q) lm |= live[wl][q] ? 1u << q : 0u;
+    live_bits[tile] = lm;
+    reinterpret_cast<uint32_t*>(work)[2 * tile + 1] = tests;
   }
 }
 
@@ -922,8 +922,8 @@ extern "C" bf_status bf_build_band(bf_ctx* ctx, const bf_grid* grid, const bf_ca
               depth_dev, c2w_dev, pyr, dmin, dmax, smask);
     BF_LAUNCH(ctx, "tile_screen", k_tile_screen, dim3((unsigned)bf_cdiv(waves, 4)), dim3(256), 0, gk, ck, T,
               (int64_t)nblocks, depth_dev, c2w_dev, pyr, dmin, dmax, smask, tmask, ttests);
-    BF_LAUNCH(ctx, "cell_screen", k_cell_screen, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T, depth_dev,
-              c2w_dev, total, pyr, dmin, dmax, tmask, vmask, live_bits, work);
+    BF_LAUNCH(ctx, "cell_screen", k_cell_screen, dim3((unsigned)bf_cdiv(nblocks, kThreads / 64)), dim3(kThreads), 0,
+              gk, ck, T, depth_dev, c2w_dev, total, (int64_t)nblocks, pyr, dmin, dmax, tmask, vmask, live_bits, work);
   }
   BF_LAUNCH(ctx, "tsdf_count", k_tsdf_count, dim3((unsigned)nblocks), dim3(kThreads), 0, gk, ck, T,
                      depth_dev, c2w_dev, total, dense_t, dense_w, counts, screen, vmask, live_bits, work,
