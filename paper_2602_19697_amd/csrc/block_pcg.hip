@@ -42,15 +42,47 @@ __global__ void k_bstate_init(BState* st, int K, double tol, int32_t max_iter, d
 template <typename V, int KC, int LDSKB>
 constexpr int kStencilRows = KC == 1 ? 1024 : LDSKB * 1024 / (KC * (int)sizeof(V));
 
+// CPL adjacent columns of a row, loaded and stored as one element (8 bytes
+// for two floats).
+template <typename V, int CPL>
+struct Cols {
+  V v[CPL];
+};
+template <typename V, int CPL>
+__device__ __forceinline__ Cols<V, CPL> ldc(const V* __restrict__ p) {
+  Cols<V, CPL> r;
+  if constexpr (CPL == 2) {
+    const float2 t = *reinterpret_cast<const float2*>(p);
+    r.v[0] = t.x;
+    r.v[1] = t.y;
+  } else {
+    r.v[0] = *p;
+  }
+  return r;
+}
+template <typename V, int CPL>
+__device__ __forceinline__ void stc(V* __restrict__ p, const Cols<V, CPL>& c) {
+  if constexpr (CPL == 2) *reinterpret_cast<float2*>(p) = make_float2(c.v[0], c.v[1]);
+  else *p = c.v[0];
+}
+// Columns per thread of the stencil pass: two in single precision (the row's
+// neighbour indices, tests and addresses then serve two values), one in FP64
+// (pairs of doubles held the pass to fewer waves and ran slower).
+template <typename V>
+constexpr int kStencilCols = sizeof(V) == 4 ? 2 : 1;
+
 // The sums and stores of stencil rows [r0, r1), the tile's p staged in pt
 // (LDS): neighbour rows inside the tile come from there, the others from
-// global memory as zz + beta p_old.
-template <typename V, int KC, bool FIRST>
-__device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t* __restrict__ nbr,
+// global memory as zz + beta p_old.  A thread takes the CPL adjacent columns
+// from cc; each column's sums are those of a thread with one column.
+template <typename V, int KC, int CPL, bool FIRST>
+__device__ __forceinline__ void stencil_sums(int cc, const V (&beta)[CPL], V lam, const int32_t* __restrict__ nbr,
                                              const V* __restrict__ diag, const V* __restrict__ zz,
                                              const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
-                                             const V* __restrict__ pt, int64_t r0, int64_t r1, double& acc) {
-  constexpr int RS = kThreads / KC;
+                                             const V* __restrict__ pt, int64_t r0, int64_t r1,
+                                             double (&acc)[CPL]) {
+  typedef Cols<V, CPL> C;
+  constexpr int RS = kThreads / (KC / CPL);
   constexpr bool first = FIRST;
   // the gathers of neighbours outside the tile are all issued before the
   // sums use them.  No branch guards them: a lane with nothing to gather
@@ -60,7 +92,7 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
   // fit 31 bits (checked by the host).
   constexpr int U = 2;
   const uint32_t span = (uint32_t)(r1 - r0);
-  for (int64_t v0 = r0 + threadIdx.x / KC; v0 < r1; v0 += U * RS) {
+  for (int64_t v0 = r0 + threadIdx.x / (KC / CPL); v0 < r1; v0 += U * RS) {
     int64_t vr[U];
     int32_t nb[U][6];
 #pragma unroll
@@ -68,7 +100,7 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
       vr[j] = v0 + j * RS < r1 ? v0 + j * RS : r0;
       load_nbr6(nbr, vr[j], nb[j]);
     }
-    V gz[U][6], gp[U][6];
+    C gz[U][6], gp[U][6];
 #pragma unroll
     for (int j = 0; j < U; ++j)
 #pragma unroll
@@ -76,57 +108,71 @@ __device__ __forceinline__ void stencil_sums(int c, V beta, V lam, const int32_t
         const int32_t u = nb[j][t];
         const bool in = (uint32_t)(u - (int32_t)r0) < span;
         const bool out = u >= 0 && !in;
-        const size_t e = (size_t)(out ? (uint32_t)u : 0u) * KC + c;
-        const V za = zz[e];
-        gz[j][t] = out ? za : (V)0;
-        if constexpr (first) {
-          gp[j][t] = 0;
+        if constexpr (sizeof(V) == 8) {
+          // FP64: the gathers under a branch (faster there: a row's lanes
+          // read 256 bytes per load)
+#pragma unroll
+          for (int h = 0; h < CPL; ++h) gz[j][t].v[h] = gp[j][t].v[h] = 0;
+          if (out) {
+            const size_t e = (size_t)u * KC + cc;
+            gz[j][t] = ldc<V, CPL>(zz + e);
+            if constexpr (!first) gp[j][t] = ldc<V, CPL>(p_old + e);
+          }
         } else {
-          const V pa = p_old[e];
-          gp[j][t] = out ? pa : (V)0;
+          const size_t e = (size_t)(out ? (uint32_t)u : 0u) * KC + cc;
+          const C za = ldc<V, CPL>(zz + e);
+          C pa;
+          if constexpr (!first) pa = ldc<V, CPL>(p_old + e);
+#pragma unroll
+          for (int h = 0; h < CPL; ++h) {
+            gz[j][t].v[h] = out ? za.v[h] : (V)0;
+            gp[j][t].v[h] = first ? (V)0 : (out ? pa.v[h] : (V)0);
+          }
         }
       }
-    V sacc[U];
+    C sacc[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      sacc[j] = 0;
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) sacc[j].v[h] = 0;
 #pragma unroll
       for (int t = 0; t < 6; ++t) {
         const int32_t u = nb[j][t];
         const bool in = (uint32_t)(u - (int32_t)r0) < span;
-        const V lv = pt[(in ? u - (int32_t)r0 : 0) * KC + c];
-        const V gv = gz[j][t] + beta * gp[j][t];
-        sacc[j] += in ? lv : gv;
+        const C lv = ldc<V, CPL>(pt + (in ? u - (int32_t)r0 : 0) * KC + cc);
+#pragma unroll
+        for (int h = 0; h < CPL; ++h) {
+          const V gv = gz[j][t].v[h] + beta[h] * gp[j][t].v[h];
+          sacc[j].v[h] += in ? lv.v[h] : gv;
+        }
       }
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
       if (v0 + j * RS >= r1) break;
-      const int64_t e = vr[j] * KC + c;
-      const V pv = pt[(vr[j] - r0) * KC + c];
-      const V qv = diag[vr[j]] * pv - lam * sacc[j];
-      if constexpr (!FIRST) p_new[e] = pv;
-      q[e] = qv;
-      acc += (double)pv * (double)qv;
+      const int64_t e = vr[j] * KC + cc;
+      const C pv = ldc<V, CPL>(pt + (vr[j] - r0) * KC + cc);
+      const V d = diag[vr[j]];
+      C qv;
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) qv.v[h] = d * pv.v[h] - lam * sacc[j].v[h];
+      if constexpr (!FIRST) stc<V, CPL>(p_new + e, pv);
+      stc<V, CPL>(q + e, qv);
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) acc[h] += (double)pv.v[h] * (double)qv.v[h];
     }
   }
 }
 
+// The pass over the band (see stencil_sums); k_bA and k_bA4 launch it.
 template <typename V, int KC, int LDSKB, bool FIRST>
-__global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
-                                            const V* __restrict__ diag, V lam, const V* __restrict__ zz,
-                                            const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
-                                            int64_t n, double* __restrict__ part) {
+__device__ __forceinline__ void bA_pass(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                        const V* __restrict__ diag, V lam, const V* __restrict__ zz,
+                                        const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
+                                        int64_t n, double* __restrict__ part, double* lds, V* pt) {
   constexpr int R = kStencilRows<V, KC, LDSKB>;
-  constexpr int RS = kThreads / KC;
-  __shared__ double lds[4 * 3 * 64];
-  __shared__ V pt[KC == 1 ? 1 : R * KC];
   if (st->nactive == 0) return;
-  const int c = threadIdx.x % KC;
   const TileWalk tw(bf_cdiv(n, R));
-  double v1[1] = {0.0};
-  const bool act = st->active[c] != 0;
-  const V beta = (V)st->beta[c];
   // FIRST (the first iteration's launch; every active column starts there):
   // the direction is z (beta = 0) and p_old is not read, as if it held zeros
   // (z + 0 * 0, the same value), so it needs no clearing; nor is p written:
@@ -135,22 +181,44 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
   // their loads.
   constexpr bool first = FIRST;
   if constexpr (KC == 1) {
+    double v1[1] = {0.0};
+    const bool act = st->active[0] != 0;
+    const V beta = (V)st->beta[0];
     for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride)
       if (act)
-        tile_A<V, KC>(c, beta, first, nbr, diag, lam, zz, p_old, p_new, q, tile * R,
+        tile_A<V, KC>(0, beta, first, nbr, diag, lam, zz, p_old, p_new, q, tile * R,
                       std::min<int64_t>(n, (tile + 1) * R), v1[0], !first);
+    col_block_sum<KC, 1>(v1, lds);
+    store_partials<KC, 1>(part, blockIdx.x, v1);
   } else {
+    // a thread's columns: cc .. cc + CPL - 1 (a column that has stopped is
+    // computed along with the others; its sums are not used)
+    constexpr int CPL = kStencilCols<V>;
+    typedef Cols<V, CPL> C;
+    constexpr int KH = KC / CPL;
+    constexpr int RS = kThreads / KH;
     constexpr int SJ = R / RS;  // rows of a tile per thread
+    const int cc = CPL * (threadIdx.x % KH);
+    bool act = false;
+    V beta[CPL];
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) {
+      act = act || st->active[cc + h] != 0;
+      beta[h] = (V)st->beta[cc + h];
+    }
+    double acc[CPL];
+#pragma unroll
+    for (int h = 0; h < CPL; ++h) acc[h] = 0.0;
     if constexpr (FIRST) {
       // p = z: the next tile's rows of z are loaded into registers while the
       // current tile's sums run, so staging a tile waits on no load
-      V za[SJ];
+      C za[SJ];
       auto fetch = [&](int64_t tile) {
         const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
 #pragma unroll
         for (int j = 0; j < SJ; ++j) {
-          const int64_t v = r0 + threadIdx.x / KC + (int64_t)j * RS;
-          za[j] = v < r1 ? zz[v * KC + c] : (V)0;
+          const int64_t v = r0 + threadIdx.x / KH + (int64_t)j * RS;
+          if (v < r1) za[j] = ldc<V, CPL>(zz + v * KC + cc);
         }
       };
       if (act && tw.start < tw.end) fetch(tw.start);
@@ -160,13 +228,18 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
         if (act) {
 #pragma unroll
           for (int j = 0; j < SJ; ++j) {
-            const int64_t v = r0 + threadIdx.x / KC + (int64_t)j * RS;
-            if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * (V)0;
+            const int64_t v = r0 + threadIdx.x / KH + (int64_t)j * RS;
+            if (v < r1) {
+              C pv;
+#pragma unroll
+              for (int h = 0; h < CPL; ++h) pv.v[h] = za[j].v[h] + beta[h] * (V)0;
+              stc<V, CPL>(pt + (v - r0) * KC + cc, pv);
+            }
           }
         }
         __syncthreads();
         if (act && tile + tw.stride < tw.end) fetch(tile + tw.stride);
-        if (act) stencil_sums<V, KC, FIRST>(c, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, v1[0]);
+        if (act) stencil_sums<V, KC, CPL, FIRST>(cc, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, acc);
       }
     } else {
       for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
@@ -177,29 +250,59 @@ __global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32
           constexpr int SB = SJ < 8 ? SJ : 8;
           static_assert(SJ % SB == 0, "staging batches must tile the rows of a thread");
           for (int j0 = 0; j0 < SJ; j0 += SB) {
-            V za[SB], pa[SB];
+            C za[SB], pa[SB];
 #pragma unroll
             for (int j = 0; j < SB; ++j) {
-              const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
+              const int64_t v = r0 + threadIdx.x / KH + (int64_t)(j0 + j) * RS;
               if (v < r1) {
-                za[j] = zz[v * KC + c];
-                pa[j] = p_old[v * KC + c];
+                za[j] = ldc<V, CPL>(zz + v * KC + cc);
+                pa[j] = ldc<V, CPL>(p_old + v * KC + cc);
               }
             }
 #pragma unroll
             for (int j = 0; j < SB; ++j) {
-              const int64_t v = r0 + threadIdx.x / KC + (int64_t)(j0 + j) * RS;
-              if (v < r1) pt[(v - r0) * KC + c] = za[j] + beta * pa[j];
+              const int64_t v = r0 + threadIdx.x / KH + (int64_t)(j0 + j) * RS;
+              if (v < r1) {
+                C pv;
+#pragma unroll
+                for (int h = 0; h < CPL; ++h) pv.v[h] = za[j].v[h] + beta[h] * pa[j].v[h];
+                stc<V, CPL>(pt + (v - r0) * KC + cc, pv);
+              }
             }
           }
         }
         __syncthreads();
-        if (act) stencil_sums<V, KC, FIRST>(c, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, v1[0]);
+        if (act) stencil_sums<V, KC, CPL, FIRST>(cc, beta, lam, nbr, diag, zz, p_old, p_new, q, pt, r0, r1, acc);
       }
     }
+    // column totals: the lanes of a column group add up, then the waves
+    col_block_sum<KH, CPL>(acc, lds);
+    if (threadIdx.x < KH)
+#pragma unroll
+      for (int h = 0; h < CPL; ++h) part[(size_t)blockIdx.x * KC + CPL * threadIdx.x + h] = acc[h];
   }
-  col_block_sum<KC, 1>(v1, lds);
-  store_partials<KC, 1>(part, blockIdx.x, v1);
+}
+
+template <typename V, int KC, int LDSKB, bool FIRST>
+__global__ __launch_bounds__(256) void k_bA(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                            const V* __restrict__ diag, V lam, const V* __restrict__ zz,
+                                            const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q,
+                                            int64_t n, double* __restrict__ part) {
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ V pt[KC == 1 ? 1 : kStencilRows<V, KC, LDSKB> * KC];
+  bA_pass<V, KC, LDSKB, FIRST>(st, nbr, diag, lam, zz, p_old, p_new, q, n, part, lds, pt);
+}
+
+// The pass over 32 KB tiles with the register budget of four waves per
+// SIMD, which the tiles allow (measured faster than the compiler's choice).
+template <typename V, int KC, bool FIRST>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bA4(
+    BState* __restrict__ st, const int32_t* __restrict__ nbr, const V* __restrict__ diag, V lam,
+    const V* __restrict__ zz, const V* __restrict__ p_old, V* __restrict__ p_new, V* __restrict__ q, int64_t n,
+    double* __restrict__ part) {
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ V pt[KC == 1 ? 1 : kStencilRows<V, KC, 32> * KC];
+  bA_pass<V, KC, 32, FIRST>(st, nbr, diag, lam, zz, p_old, p_new, q, n, part, lds, pt);
 }
 
 // Per-column alpha from A's block partials (one workgroup per column).
@@ -1147,12 +1250,21 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
                       diagV, lamV, zc, pa, pb, q, N, part);
           break;
         default:
-          if (it == 0)
-            BF_LAUNCH(ctx, "block_A_first", (k_bA<V, KC, 32, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zc, pa, pb, q, N, part);
-          else
-            BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
-                      diagV, lamV, zc, pa, pb, q, N, part);
+          if constexpr (KC > 1) {
+            if (it == 0)
+              BF_LAUNCH(ctx, "block_A_first", (k_bA4<V, KC, true>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                        diagV, lamV, zc, pa, pb, q, N, part);
+            else
+              BF_LAUNCH(ctx, "block_A", (k_bA4<V, KC, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                        diagV, lamV, zc, pa, pb, q, N, part);
+          } else {
+            if (it == 0)
+              BF_LAUNCH(ctx, "block_A_first", (k_bA<V, KC, 32, true>), dim3(nb), dim3(kThreads), 0, st,
+                        sys->band->nbr, diagV, lamV, zc, pa, pb, q, N, part);
+            else
+              BF_LAUNCH(ctx, "block_A", (k_bA<V, KC, 32, false>), dim3(nb), dim3(kThreads), 0, st, sys->band->nbr,
+                        diagV, lamV, zc, pa, pb, q, N, part);
+          }
       }
       BF_LAUNCH(ctx, "block_scalars", k_bscal_A<KC>, dim3(KC), dim3(256), 0, st, part, nb);
       const bool moved = it == 0 && !tri;  // p_0 in zz_0's buffer, zz_1 to pa's
