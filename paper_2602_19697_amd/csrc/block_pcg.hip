@@ -385,24 +385,24 @@ __device__ __forceinline__ double dpp_move(double x) {
   return __hiloint2double(hi, lo);
 }
 
-// Sum of p over the KC column lanes of a row, lane c == 0's value being the
-// one used: the quad's pairs (DPP quad permutations), then the other quad of
-// 8, the other 8 of 16 (DPP mirrors), the other 16 of 32 (an LDS swizzle with
-// lane XOR 16) and the other 32 (a lane shuffle).  The estimate's one
-// summation order, in k_hutch_bits and in the VERIFY pass that forms it.
-template <int KC>
+// Sum of p over the first NL lanes of each group of NL (lane l's group:
+// l / NL), the group's first lane's value being the one used: the quad's
+// pairs (DPP quad permutations), then the other quad of 8, the other 8 of 16
+// (DPP mirrors), the other 16 of 32 (an LDS swizzle with lane XOR 16) and the
+// other 32 (a lane shuffle).  The estimate's one summation order over the
+// column pairs of a row, in k_hutch_bits and in the VERIFY pass that forms it.
+template <int NL>
 __device__ __forceinline__ double row_sum(double p) {
-  static_assert(KC == 1 || KC == 16 || KC == 32 || KC == 64, "column blocks of 1, 16, 32 or 64");
-  if constexpr (KC >= 16) {
+  static_assert(NL == 1 || NL == 8 || NL == 16 || NL == 32, "groups of 1, 8, 16 or 32 lanes");
+  if constexpr (NL >= 8) {
     p += dpp_move<0xB1>(p);   // quad_perm [1, 0, 3, 2]
     p += dpp_move<0x4E>(p);   // quad_perm [2, 3, 0, 1]
     p += dpp_move<0x141>(p);  // row_half_mirror: lane 7 - l of 8
-    p += dpp_move<0x140>(p);  // row_mirror: lane 15 - l of 16
   }
-  if constexpr (KC >= 32)
+  if constexpr (NL >= 16) p += dpp_move<0x140>(p);  // row_mirror: lane 15 - l of 16
+  if constexpr (NL >= 32)
     p += __hiloint2double(__builtin_amdgcn_ds_swizzle(__double2hiint(p), 0x401F),
                           __builtin_amdgcn_ds_swizzle(__double2loint(p), 0x401F));
-  if constexpr (KC >= 64) p += __shfl_xor(p, 32, 64);
   return p;
 }
 
@@ -604,8 +604,7 @@ __device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, R
                                           double lam, const uint32_t* __restrict__ zb, double* __restrict__ x64,
                                           const float* __restrict__ cf, const double* __restrict__ w,
                                           const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                          int64_t r0, int64_t r1, int write_x0, int store_r, double (&v3)[3],
-                                          double* __restrict__ s_out) {
+                                          int64_t r0, int64_t r1, int write_x0, int store_r, double (&v3)[3]) {
   constexpr bool kStage = KC > 1;
   constexpr bool kStageW = XC && kStage;
   constexpr int RS = kThreads / KC;
@@ -676,17 +675,6 @@ __device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, R
           if (nb[h][a] >= 0) acc += xn[h][a];
         res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
       }
-      if constexpr (MODE == MODE_VERIFY) {
-        // every column is verified here: the estimate's rows, as k_hutch_bits
-        // forms them (a row's lanes agree on whether it exists)
-        if (s_out)
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            if (h == 1 && jr[1] == j0) break;
-            const double sum = row_sum<KC>(zv[h] * xs[h]);
-            if (c == 0) s_out[r0 + jr[h]] = sum / (double)KC;
-          }
-      }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -726,8 +714,7 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
                                               const uint32_t* __restrict__ zb, double* __restrict__ x64,
                                               const float* __restrict__ cf, const double* __restrict__ w,
                                               const V* __restrict__ dinv, V* __restrict__ r, V* __restrict__ zz,
-                                              int64_t n, double* __restrict__ part, int write_x0, int store_r,
-                                              double* __restrict__ s_fuse) {
+                                              int64_t n, double* __restrict__ part, int write_x0, int store_r) {
   // one column: every lane is its own row and nothing is shared, so the row
   // data is read directly; otherwise it is staged per tile in LDS, one row per
   // thread (a dependent chain of loads: neighbour indices, then the
@@ -761,20 +748,6 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   const int xbl = XC ? st->xbase[c] : 0;
   const int xbf = __builtin_amdgcn_readfirstlane(xbl);
   const int xbw = __builtin_amdgcn_readfirstlane(__ballot(act && xbl != xbf) == 0 ? xbf : -1);
-  // VERIFY of every column of the block (K = KC, all at check 2, as when they
-  // all meet the tolerance at the same iteration): the pass also forms the
-  // estimate s from the x it reads, final unless a column fails the check
-  double* s_out = nullptr;
-  if constexpr (MODE == MODE_VERIFY && GATHER && KC > 1) {
-    if (s_fuse && st->K == KC) {
-      bool all = true;
-      for (int k = 0; k < KC; ++k) all = all && st->active[k] && st->check[k] == 2;
-      if (all) {
-        s_out = s_fuse;
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->s_fused = 1;
-      }
-    }
-  }
   double v3[3] = {0.0, 0.0, 0.0};
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
@@ -800,7 +773,7 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
     if (!act) continue;
 #define BF_BRES_ROWS(K)                                                                                        \
   bres_rows<V, KC, MODE, GATHER, XC, K, R, RT, RW>(c, xbl, rt, wn, zn, nbr, diag, lam, zb, x64, cf, w, dinv, r, \
-                                                    zz, r0, r1, write_x0, store_r, v3, s_out)
+                                                    zz, r0, r1, write_x0, store_r, v3)
     if constexpr (XC && GATHER) {
       if (xbw == 1) BF_BRES_ROWS(1);
       else if (xbw == 0) BF_BRES_ROWS(0);
@@ -813,6 +786,168 @@ __global__ __launch_bounds__(256) void k_bres(BState* __restrict__ st, const int
   }
   col_block_sum<KC, 3>(v3, lds);
   store_partials<KC, 3>(part, blockIdx.x, v3);
+}
+
+// The rows of one tile of k_bverify2 (see there) for the start kind XBK of
+// every column of the wave, or -1 (each column's own, xbl).  One row at a
+// time: with two columns per thread, its gathers are as many as two rows'
+// were with one.
+template <int KC, int XBK>
+__device__ __forceinline__ void bverify_rows(int cc, const int (&xbl)[2], const RowTile<float, KC, kThreads>& rt,
+                                             const double (&wn)[7][kThreads],
+                                             const uint32_t (&zn)[7][kZWords<KC>][kThreads], double lam,
+                                             const double* __restrict__ x64, const float* __restrict__ cf,
+                                             int64_t r0, int64_t r1, double (&v)[2][3],
+                                             double* __restrict__ s_out) {
+  constexpr int KH = KC / 2;
+  constexpr int R = kThreads, RS = kThreads / KH;
+  const int sh = cc & 31, wd = KC > 32 ? (cc >> 5) : 0;  // cc + 1: bit sh + 1 of the same word
+  for (int j = threadIdx.x / KH; j < R && r0 + j < r1; j += RS) {
+    double xs[2], xn[6][2], zv[2];
+    const uint32_t vs = (uint32_t)(r0 + j), es = vs * (uint32_t)KC + (uint32_t)cc;
+    const uint32_t zw = rt.zs[wd][j];
+    const float2 co = *reinterpret_cast<const float2*>(cf + es);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = XBK >= 0 ? XBK : xbl[q];
+      zv[q] = ((zw >> (sh + q)) & 1u) ? -1.0 : 1.0;
+      xs[q] = xbase_at(k, x64 + q, es, sign_bit(zw, sh + q), wn[0], (uint32_t)j) + (double)(q ? co.y : co.x);
+    }
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {  // an absent neighbour reads the row itself and adds nothing
+      const int32_t u0 = rt.nb[a][j];
+      const uint32_t u = (uint32_t)(u0 >= 0 ? u0 : (int32_t)vs) * (uint32_t)KC + (uint32_t)cc;
+      const float2 cn = *reinterpret_cast<const float2*>(cf + u);
+      const uint32_t zw1 = zn[1 + a][wd][j];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = XBK >= 0 ? XBK : xbl[q];
+        xn[a][q] = xbase_at(k, x64 + q, u, sign_bit(zw1, sh + q), wn[1 + a], (uint32_t)j) + (double)(q ? cn.y : cn.x);
+      }
+    }
+    const double dg = rt.d[j];
+    const float di = rt.di[j];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+        if (rt.nb[a][j] >= 0) acc += xn[a][q];
+      const double res = zv[q] - (dg * xs[q] - lam * acc);
+      v[q][0] += res * res;
+      v[q][2] += zv[q] * zv[q];
+      const float rv = (float)res;
+      v[q][1] += (double)rv * (double)(rv * di);
+    }
+    if (s_out) {  // the estimate's row, as k_hutch_bits forms it (a row's lanes agree on j)
+      double p = zv[0] * xs[0];
+      p += zv[1] * xs[1];
+      const double sum = row_sum<KH>(p);
+      if (cc == 0) s_out[r0 + j] = sum / (double)KC;
+    }
+  }
+}
+
+// VERIFY of the mixed-precision 7-point solve over column pairs: the FP64
+// residual norms of the columns whose recurrence residual met the tolerance
+// (check == 2), x = x64 (per BState::xbase) + the float correction cf, as
+// k_bres VERIFY computes them column by column; a thread takes the columns
+// cc, cc + 1 of its rows, so a row's staged data, neighbour indices and
+// addresses serve both.  When every column is verified here (K = KC, all at
+// check 2: they met the tolerance at the same iteration), the pass also forms
+// the estimate s from the x it reads; it is final unless a column fails the
+// check (BState::s_fused).
+template <int KC>
+__device__ __forceinline__ void bverify_pass(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                             const double* __restrict__ diag, double lam,
+                                             const uint32_t* __restrict__ zb, const double* __restrict__ x64,
+                                             const float* __restrict__ cf, const double* __restrict__ w,
+                                             const float* __restrict__ dinv, int64_t n, double* __restrict__ part,
+                                             double* __restrict__ s_fuse) {
+  static_assert(KC >= 16, "column pairs of a 16- to 64-column block");
+  constexpr int KH = KC / 2;
+  constexpr int R = kThreads;
+  __shared__ double lds[4 * 3 * 64];
+  __shared__ RowTile<float, KC, R> rt;
+  __shared__ double wn[7][R];
+  __shared__ uint32_t zn[7][kZWords<KC>][R];
+  if (st->nactive == 0 || !st->any_check) return;
+  const int cc = 2 * (threadIdx.x % KH);
+  bool act[2];
+  int xbl[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    act[q] = st->active[cc + q] != 0 && st->check[cc + q] == 2;
+    xbl[q] = st->xbase[cc + q];
+  }
+  const bool any = act[0] || act[1];
+  // the start kind shared by every active column of the wave (-1: they differ)
+  const int xbf = __builtin_amdgcn_readfirstlane(xbl[0]);
+  const int xbw = __builtin_amdgcn_readfirstlane(
+      __ballot((act[0] && xbl[0] != xbf) || (act[1] && xbl[1] != xbf)) == 0 ? xbf : -1);
+  double* s_out = nullptr;
+  if (s_fuse && st->K == KC) {
+    bool all = true;
+    for (int k = 0; k < KC; ++k) all = all && st->active[k] && st->check[k] == 2;
+    if (all) {
+      s_out = s_fuse;
+      if (blockIdx.x == 0 && threadIdx.x == 0) st->s_fused = 1;
+    }
+  }
+  const TileWalk tw(bf_cdiv(n, R));
+  double v[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+  for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
+    const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
+    __syncthreads();  // the previous tile's readers are done
+    rt.stage(nbr, diag, dinv, zb, r0, r1);
+    if (w)
+      for (int t = threadIdx.x; t < R; t += kThreads) {
+        const int64_t vv = r0 + t < r1 ? r0 + t : r0;
+        wn[0][t] = w[vv];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {  // an absent neighbour stages the row itself (never added)
+          const int32_t u0 = rt.nb[a][t];  // staged by this thread just above
+          const int64_t u = u0 >= 0 ? (int64_t)u0 : vv;
+          wn[1 + a][t] = w[u];
+#pragma unroll
+          for (int g = 0; g < kZWords<KC>; ++g) zn[1 + a][g][t] = zb[u * kZWords<KC> + g];
+        }
+      }
+    __syncthreads();
+    if (!any) continue;
+    if (xbw == 1) bverify_rows<KC, 1>(cc, xbl, rt, wn, zn, lam, x64, cf, r0, r1, v, s_out);
+    else if (xbw == 0) bverify_rows<KC, 0>(cc, xbl, rt, wn, zn, lam, x64, cf, r0, r1, v, s_out);
+    else if (xbw == 2) bverify_rows<KC, 2>(cc, xbl, rt, wn, zn, lam, x64, cf, r0, r1, v, s_out);
+    else bverify_rows<KC, -1>(cc, xbl, rt, wn, zn, lam, x64, cf, r0, r1, v, s_out);
+  }
+  // per-column totals, the pair's two columns in turn
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    col_block_sum<KH, 3>(v[q], lds);
+    if (threadIdx.x < KH)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) part[((size_t)blockIdx.x * 3 + i) * KC + 2 * threadIdx.x + q] = v[q][i];
+  }
+}
+
+// 16 and 32 columns: the register budget of four waves per SIMD, which their
+// LDS allows (faster than the compiler's choice of three).
+template <int KC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_bverify2(
+    BState* __restrict__ st, const int32_t* __restrict__ nbr, const double* __restrict__ diag, double lam,
+    const uint32_t* __restrict__ zb, const double* __restrict__ x64, const float* __restrict__ cf,
+    const double* __restrict__ w, const float* __restrict__ dinv, int64_t n, double* __restrict__ part,
+    double* __restrict__ s_fuse) {
+  bverify_pass<KC>(st, nbr, diag, lam, zb, x64, cf, w, dinv, n, part, s_fuse);
+}
+// 64 columns: twice the packed-sign words in LDS, at most three workgroups per CU
+__global__ __launch_bounds__(256) void k_bverify2_64(BState* __restrict__ st, const int32_t* __restrict__ nbr,
+                                                     const double* __restrict__ diag, double lam,
+                                                     const uint32_t* __restrict__ zb, const double* __restrict__ x64,
+                                                     const float* __restrict__ cf, const double* __restrict__ w,
+                                                     const float* __restrict__ dinv, int64_t n,
+                                                     double* __restrict__ part, double* __restrict__ s_fuse) {
+  bverify_pass<64>(st, nbr, diag, lam, zb, x64, cf, w, dinv, n, part, s_fuse);
 }
 
 // B of the 7-point path's first iteration from x = 0 with r = z unstored:
@@ -876,40 +1011,57 @@ __global__ __launch_bounds__(256) void k_bfold_check(const BState* __restrict__ 
 // are not folded).  FP64, zero_start: a column that never iterated still has
 // its unwritten zero start.  Mixed: x64 per BState::xbase (w: the start
 // weights), and a column that never iterated has no correction (cf unwritten).
-// The KC lanes of a row sum its products with row_sum; U rows' loads are
-// issued before their sums.  Nothing to do when the last VERIFY pass formed
-// the estimate (BState::s_fused).
+// A thread takes the column pair (cc, cc + 1) of its rows (one column for
+// KC = 1): the pair's products are added, then the row's pair sums with
+// row_sum.  U rows' loads are issued before their sums.  Nothing to do when
+// the last VERIFY pass formed the estimate (BState::s_fused).
 template <int KC, bool XC>
 __global__ __launch_bounds__(256) void k_hutch_bits(const BState* __restrict__ st, int zero_start,
                                                     const double* __restrict__ x64, const float* __restrict__ cf,
                                                     const double* __restrict__ w, const uint32_t* __restrict__ zb,
                                                     int K, int64_t n, double* __restrict__ s_out) {
   if (st->s_fused) return;
-  constexpr int RS = kThreads / KC;
+  constexpr int CP = KC > 1 ? 2 : 1;  // columns per thread
+  constexpr int KH = KC / CP;
+  constexpr int RS = kThreads / KH;
   constexpr int U = KC > 1 ? 8 : 4;
-  const int c = threadIdx.x % KC;
-  const bool zero = c < K && zero_start && st->iters[c] == 0;
-  const bool nocf = c < K && st->iters[c] == 0;
-  const int xb = XC && c < K ? st->xbase[c] : 0, sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
+  const int cc = CP * (threadIdx.x % KH);
+  bool in[CP], zero[CP], nocf[CP];
+  int xb[CP];
+#pragma unroll
+  for (int h = 0; h < CP; ++h) {
+    in[h] = cc + h < K;
+    zero[h] = in[h] && zero_start && st->iters[cc + h] == 0;
+    nocf[h] = in[h] && st->iters[cc + h] == 0;
+    xb[h] = XC && in[h] ? st->xbase[cc + h] : 0;
+  }
+  const int wd = KC > 32 ? (cc >> 5) : 0;
   for (int64_t r0 = blockIdx.x * (int64_t)(U * RS); r0 < n; r0 += (int64_t)gridDim.x * U * RS) {
-    double xv[U];
+    double xv[U][CP];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const int64_t v = r0 + j * RS + threadIdx.x / KC;
-      const int64_t e = v * KC + c;
-      if constexpr (XC)
-        xv[j] = (v < n && c < K) ? x_base<KC>(xb, x64 + c, w, zb, (uint32_t)v, sh, wd) + (nocf ? 0.0 : (double)cf[e])
-                                 : 0.0;
-      else
-        xv[j] = (v < n && c < K && !zero) ? x64[e] : 0.0;
+      const int64_t v = r0 + j * RS + threadIdx.x / KH;
+#pragma unroll
+      for (int h = 0; h < CP; ++h) {
+        const int c = cc + h;
+        const int64_t e = v * KC + c;
+        if constexpr (XC)
+          xv[j][h] = (v < n && in[h]) ? x_base<KC>(xb[h], x64 + c, w, zb, (uint32_t)v, c & 31, wd) +
+                                            (nocf[h] ? 0.0 : (double)cf[e])
+                                      : 0.0;
+        else
+          xv[j][h] = (v < n && in[h] && !zero[h]) ? x64[e] : 0.0;
+      }
     }
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-      const int64_t v = r0 + j * RS + threadIdx.x / KC;
-      // the rows of a wave are whole (KC divides 64), so a row's lanes agree on v < n
+      const int64_t v = r0 + j * RS + threadIdx.x / KH;
+      // the rows of a wave are whole (KH divides 64), so a row's lanes agree on v < n
       if (v < n) {
-        const double acc = row_sum<KC>(c < K ? zsign<KC>(zb, v, c) * xv[j] : 0.0);
-        if (c == 0) s_out[v] = acc / (double)K;
+        double p = in[0] ? zsign<KC>(zb, v, cc) * xv[j][0] : 0.0;
+        if constexpr (CP == 2) p += in[1] ? zsign<KC>(zb, v, cc + 1) * xv[j][1] : 0.0;
+        const double acc = row_sum<KH>(p);
+        if (cc == 0) s_out[v] = acc / (double)K;
       }
     }
   }
@@ -1180,13 +1332,13 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
     } else {
       BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_INIT, false, false>), dim3(nb), dim3(kThreads), 0, st,
                 sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part,
-                (zero_start || mixed7) ? 0 : 1, gen_start ? 0 : 1, nullptr);
+                (zero_start || mixed7) ? 0 : 1, gen_start ? 0 : 1);
     }
   }
   BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_INIT, part, nb);
   if (logvar) {  // columns whose start was no better than zero restart from x = 0
     BF_LAUNCH(ctx, "block_guard", (k_bres<V, KC, MODE_GUARD, false, false>), dim3(nb), dim3(kThreads), 0, st,
-              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1, nullptr);
+              sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zz, N, part, mixed7 ? 0 : 1, 1);
     BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_GUARD, part, nb);
   }
   BF_TRY(bf_launch_check(ctx, "block pcg init"));
@@ -1202,7 +1354,8 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
   int it = 0, next = logvar ? 1 : 3;
   size_t fin_rec = 0;  // timing record of the last queued estimate pass (FP64)
   const unsigned hutch_grid =
-      (unsigned)std::min<int64_t>(bf_cdiv(N, (KC > 1 ? 8 : 4) * (kThreads / KC)), 8 * (int64_t)ctx->cu_count);
+      (unsigned)std::min<int64_t>(bf_cdiv(N, (KC > 1 ? 8 : 4) * (kThreads / (KC > 1 ? KC / 2 : 1))),
+                                  8 * (int64_t)ctx->cu_count);
   V* pa = p0;
   V* pb = p1;
   // the buffer holding the current zz.  The 7-point path's first iteration
@@ -1297,18 +1450,24 @@ bf_status run_block(bf_ctx* ctx, const bf_system* sys, const bf_probe_opts* o, c
         // store-free FP64 residual norms of the columns the recurrence calls
         // converged (mixed: of x64 + the float correction, unfolded); then the
         // columns to go on from a stored FP64 residual fold (mixed) and store it
-        if (mixed)
+        if constexpr (sizeof(V) == 4 && KC == 64)
+          BF_LAUNCH(ctx, "block_verify", k_bverify2_64, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, sys->diag,
+                    sys->lambda, zb, x64, cf, wst, dinvV, N, part, s_out);
+        else if constexpr (sizeof(V) == 4 && KC > 1)
+          BF_LAUNCH(ctx, "block_verify", k_bverify2<KC>, dim3(nb), dim3(kThreads), 0, st, sys->band->nbr, sys->diag,
+                    sys->lambda, zb, x64, cf, wst, dinvV, N, part, s_out);
+        else if (mixed)
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, true>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0, s_out);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
         else
           BF_LAUNCH(ctx, "block_verify", (k_bres<V, KC, MODE_VERIFY, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0, s_out);
+                    sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 0);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_VERIFY, part, nb);
         if (mixed)
           BF_LAUNCH(ctx, "block_fold", k_bfold_check<KC>, dim3(nb), dim3(kThreads), 0, st, x64, cf, wst,
                     (const uint32_t*)zb, N);
         BF_LAUNCH(ctx, "block_residual", (k_bres<V, KC, MODE_CHECK, true, false>), dim3(nb), dim3(kThreads), 0, st,
-                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 1, nullptr);
+                  sys->band->nbr, sys->diag, sys->lambda, zb, x64, cf, wst, dinvV, r, zc, N, part, 0, 1);
         BF_LAUNCH(ctx, "block_scalars", k_bscal_R<KC>, dim3(KC), dim3(256), 0, st, (int)MODE_CHECK, part, nb);
       }
       if (!moved) std::swap(pa, pb);
