@@ -509,19 +509,15 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
   // otherwise one row per thread is staged (as in k_bres)
   constexpr bool kStage = KC > 1;
   constexpr int R = kStage ? kThreads : kRowsPerTile<KC>;
-  constexpr int RS = kThreads / KC;
   constexpr int RT = kStage ? R : 1;
   __shared__ double lds[4 * 3 * 64];
   __shared__ RowTile<V, KC, RT> rt;
   __shared__ double wn[7][RT];                 // weights of the row (0) and its neighbours (1..6)
   __shared__ uint32_t zn[7][kZWords<KC>][RT];  // their packed signs
-  const int c = threadIdx.x % KC;
-  const int sh = c & 31, wd = KC > 32 ? (c >> 5) : 0;
-  const bool act = st->active[c] != 0;
   const TileWalk tw(bf_cdiv(n, R));
-  double v3[3] = {0.0, 0.0, 0.0};
   if constexpr (!kStage) {
-    if (act)
+    double v3[3] = {0.0, 0.0, 0.0};
+    if (st->active[0] != 0)
       for (int64_t v = blockIdx.x * (int64_t)kThreads + threadIdx.x; v < n; v += (int64_t)gridDim.x * kThreads) {
         const bool neg = zb[v] & 1u;
         const double zv = neg ? -1.0 : 1.0;
@@ -546,6 +542,13 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
     store_partials<KC, 3>(part, blockIdx.x, v3);
     return;
   }
+  // a thread takes the column pair cc, cc + 1 of its rows (their bits sh,
+  // sh + 1 of the same packed-sign word), so a row's staged data serves both
+  constexpr int KH = KC > 1 ? KC / 2 : 1, RS2 = kThreads / KH;
+  const int cc = 2 * (threadIdx.x % KH);
+  const int sh = cc & 31, wd = KC > 32 ? (cc >> 5) : 0;
+  const bool any = st->active[cc] != 0 || st->active[cc + 1] != 0;
+  double v[2][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
   for (int64_t tile = tw.start; tile < tw.end; tile += tw.stride) {
     const int64_t r0 = tile * R, r1 = std::min<int64_t>(n, r0 + R);
     __syncthreads();  // the previous tile's readers are done
@@ -565,33 +568,56 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
       }
     }
     __syncthreads();
-    if (!act) continue;
-    for (int j = threadIdx.x / KC; j < R && r0 + j < r1; j += RS) {
-      const int64_t v = r0 + j, e = v * KC + c;
-      const bool neg = (zn[0][wd][j] >> sh) & 1u;
-      const double zv = neg ? -1.0 : 1.0;
-      const double xs = neg ? -wn[0][j] : wn[0][j];
+    if (!any) continue;
+    for (int j = threadIdx.x / KH; j < R && r0 + j < r1; j += RS2) {
+      const int64_t e = (r0 + j) * KC + cc;
+      const uint32_t zw = zn[0][wd][j];
+      double zv[2], xs[2], acc[2] = {0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        zv[q] = ((zw >> (sh + q)) & 1u) ? -1.0 : 1.0;
+        xs[q] = xbase_at(1, nullptr, 0u, sign_bit(zw, sh + q), wn[0], (uint32_t)j);
+      }
       // no branch per neighbour: an absent one adds +0.0, which leaves the sum
       // unchanged (a sum of nonzero terms that starts at +0.0 is never -0.0)
-      double acc = 0.0;
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        const double t = xbase_at(1, nullptr, 0u, sign_bit(zn[1 + a][wd][j], sh), wn[1 + a], (uint32_t)j);
-        acc += rt.nb[a][j] >= 0 ? t : 0.0;
+        const bool ok = rt.nb[a][j] >= 0;
+        const uint32_t zw1 = zn[1 + a][wd][j];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const double t = xbase_at(1, nullptr, 0u, sign_bit(zw1, sh + q), wn[1 + a], (uint32_t)j);
+          acc[q] += ok ? t : 0.0;
+        }
       }
-      const double res = zv - (rt.d[j] * xs - lam * acc);
-      if (store_x) x64[e] = xs;
-      v3[0] += res * res;
-      v3[2] += zv * zv;
-      const V rv = (V)res;
-      const V zzv = rv * rt.di[j];
-      r[e] = rv;
-      zz[e] = zzv;
-      v3[1] += (double)rv * (double)zzv;
+      V rv[2], zzv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double res = zv[q] - (rt.d[j] * xs[q] - lam * acc[q]);
+        v[q][0] += res * res;
+        v[q][2] += zv[q] * zv[q];
+        rv[q] = (V)res;
+        zzv[q] = rv[q] * rt.di[j];
+        v[q][1] += (double)rv[q] * (double)zzv[q];
+      }
+      if (store_x) *reinterpret_cast<double2*>(x64 + e) = make_double2(xs[0], xs[1]);
+      if constexpr (sizeof(V) == 4) {
+        *reinterpret_cast<float2*>(r + e) = make_float2(rv[0], rv[1]);
+        *reinterpret_cast<float2*>(zz + e) = make_float2(zzv[0], zzv[1]);
+      } else {
+        *reinterpret_cast<double2*>(r + e) = make_double2(rv[0], rv[1]);
+        *reinterpret_cast<double2*>(zz + e) = make_double2(zzv[0], zzv[1]);
+      }
     }
   }
-  col_block_sum<KC, 3>(v3, lds);
-  store_partials<KC, 3>(part, blockIdx.x, v3);
+  // per-column totals, the pair's two columns in turn
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    col_block_sum<KH, 3>(v[q], lds);
+    if (threadIdx.x < KH)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) part[((size_t)blockIdx.x * 3 + i) * KC + 2 * threadIdx.x + q] = v[q][i];
+  }
 }
 
 // The rows of one tile of k_bres (see there).  XBK: the start kind of x in
