@@ -193,17 +193,9 @@ __global__ __launch_bounds__(256) void k_apply_Q27(const int32_t* __restrict__ n
 }
 
 // Features of the learned warm start, lengths in units of h (bf_features.h).
-__global__ __launch_bounds__(256) void k_features(int64_t n, int32_t T, double h,
-                                                  const double* __restrict__ tsdf,
-                                                  const int32_t* __restrict__ w,
-                                                  const int32_t* __restrict__ nbr,
-                                                  const int32_t* __restrict__ deg,
-                                                  const double* __restrict__ Lambda,
-                                                  const double* __restrict__ acc,
-                                                  float* __restrict__ feat) {
+__global__ __launch_bounds__(256) void k_features(int64_t n, bf_feat_in in, float* __restrict__ feat) {
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const bf_feat_in in{tsdf, Lambda, acc, w, nbr, deg, T, h};
   float f[12];
   bf_features_0_7(v, in, f);
   bf_features_8_11(v, in, f + 8);
@@ -345,7 +337,7 @@ extern "C" bf_status bf_features(bf_ctx* ctx, const bf_system* sys, float* feat_
   BF_CHECK(ctx, feat_dev && sys->T > 0, "bf_features: NULL output or system without views");
   const bf_band* band = sys->band;
   BF_LAUNCH(ctx, "features", k_features, dim3((unsigned)bf_cdiv(sys->n, 256)), dim3(256), 0, sys->n,
-                     sys->T, band->h, band->tsdf, band->w, band->nbr, band->deg, sys->Lambda, sys->acc,
-                     feat_dev);
+            bf_feat_make(band->tsdf, sys->Lambda, sys->acc, band->w, band->nbr, band->deg, sys->T, band->h),
+            feat_dev);
   return bf_launch_check(ctx, "k_features");
 }

@@ -13,25 +13,34 @@ struct bf_feat_in {
   const int32_t *w, *nbr, *deg;
   int32_t T;
   double h;
+  // 1/h, 1/h^2, 1/(2h), 1/T: the divisions by these become products (a
+  // double-level difference that the features' rounding to float absorbs)
+  double ih, ih2, i2h, iT;
 };
+
+inline bf_feat_in bf_feat_make(const double* tsdf, const double* Lambda, const double* acc, const int32_t* w,
+                               const int32_t* nbr, const int32_t* deg, int32_t T, double h) {
+  return bf_feat_in{tsdf, Lambda, acc, w, nbr, deg, T, h, 1.0 / h, 1.0 / (h * h), 1.0 / (2.0 * h),
+                    T > 0 ? 1.0 / (double)T : 0.0};
+}
 
 // Features 0..7 of band voxel v into f[0..7].
 __device__ __forceinline__ void bf_features_0_7(int64_t v, const bf_feat_in& s, float* f) {
 #pragma clang fp contract(off)
-  const double h = s.h;
   const double* a = s.acc + v * 5;
   const double cnt = a[0];
-  const double my = cnt > 0.0 ? a[1] / cnt : 0.0;
-  const double vy = cnt > 0.0 ? a[2] / cnt - my * my : 0.0;
-  const double ms = cnt > 0.0 ? a[3] / cnt : 0.0;
-  f[0] = (float)(s.tsdf[v] / h);
+  const double rc = cnt > 0.0 ? 1.0 / cnt : 0.0;
+  const double my = a[1] * rc;
+  const double vy = cnt > 0.0 ? a[2] * rc - my * my : 0.0;
+  const double ms = a[3] * rc;
+  f[0] = (float)(s.tsdf[v] * s.ih);
   f[1] = (float)log(1.0 + (double)s.w[v]);
-  f[2] = (float)((double)s.deg[v] / 6.0);
-  f[3] = (float)(cnt / (double)s.T);
-  f[4] = (float)(my / h);
-  f[5] = (float)(vy / (h * h));
-  f[6] = (float)(ms / h);
-  f[7] = (float)(a[4] / h);
+  f[2] = (float)((double)s.deg[v] * (1.0 / 6.0));
+  f[3] = (float)(cnt * s.iT);
+  f[4] = (float)(my * s.ih);
+  f[5] = (float)(vy * s.ih2);
+  f[6] = (float)(ms * s.ih);
+  f[7] = (float)(a[4] * s.ih);
 }
 
 // Features 8..11 of band voxel v into f[0..3].
@@ -46,6 +55,6 @@ __device__ __forceinline__ void bf_features_8_11(int64_t v, const bf_feat_in& s,
     const int32_t m = nb[2 * ax], p = nb[2 * ax + 1];
     const double tm = m >= 0 ? s.tsdf[m] : tv;
     const double tp = p >= 0 ? s.tsdf[p] : tv;
-    f[1 + ax] = (float)((tp - tm) / (2.0 * h));
+    f[1 + ax] = (float)((tp - tm) * s.i2h);
   }
 }

@@ -548,7 +548,7 @@ extern "C" bf_status bf_warm_start(bf_ctx* ctx, const bf_system* sys, const floa
               sys->band->h, x0_dev, logvar_dev);
   } else {  // features computed in the same pass
     const bf_band* b = sys->band;
-    const bf_feat_in src{b->tsdf, sys->Lambda, sys->acc, b->w, b->nbr, b->deg, sys->T, b->h};
+    const bf_feat_in src = bf_feat_make(b->tsdf, sys->Lambda, sys->acc, b->w, b->nbr, b->deg, sys->T, b->h);
     BF_LAUNCH(ctx, "mlp_fused", k_mlp_forward<true>, dim3(grid), dim3(256), 0, (const bf16x8*)wt, params_dev,
               (const float*)nullptr, src, n, (float*)nullptr, (const double*)sys->rhs, (const double*)sys->diag,
               b->h, x0_dev, logvar_dev);
