@@ -93,8 +93,8 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
                                                   const uint32_t* __restrict__ vmask, int vw) {
 #pragma clang fp contract(off)
   const int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (v >= n) return;
-  const uint64_t key = keys[v];
+  const bool valid = v < n;  // every lane takes part in the wave's view loop
+  const uint64_t key = valid ? keys[v] : 0;
   const int32_t i = (int32_t)bf_compact3(key), j = (int32_t)bf_compact3(key >> 1),
                 k = (int32_t)bf_compact3(key >> 2);
   const int64_t plane = (int64_t)c.W * c.H;
@@ -103,17 +103,24 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
   if (vmask) {
     // the band's screen proved that a view with a clear bit observes no voxel
     // of this voxel's cell: only the set bits are visited, in view order, so
-    // every sum is the one over all views
+    // every sum is the one over all views.  The wave walks the union of its
+    // lanes' bits (a wave spans a few cells with similar masks), so the view,
+    // its pose and its depth map are the same for every lane
     for (int q = 0; q < vw; ++q) {
-      uint32_t bits = vmask[v * vw + q];
-      while (bits) {
-        const int32_t t = 32 * q + __builtin_ctz(bits);
-        bits &= bits - 1u;
-        add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
+      const uint32_t bits = valid ? vmask[v * vw + q] : 0u;
+      uint32_t un = bits;
+      for (int off = 32; off > 0; off >>= 1) un |= (uint32_t)__shfl_xor((int)un, off, 64);
+      un = (uint32_t)__builtin_amdgcn_readfirstlane((int)un);
+      while (un) {
+        const int32_t t = 32 * q + __builtin_ctz(un);
+        un &= un - 1u;
+        if ((bits >> (t & 31)) & 1u)
+          add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
       }
     }
     t0 = 32 * vw < T ? 32 * vw : T;  // views past the masked ones
   }
+  if (!valid) return;
   for (int32_t t = t0; t < T; ++t)
     add_view(a, g, c, depth + t * plane, poses + 12 * t, nz.pose ? nz.pose[t] : 0.0, nz, i, j, k);
   const int32_t dg = deg[v];
