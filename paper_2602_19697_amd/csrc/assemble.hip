@@ -37,7 +37,9 @@ __device__ __forceinline__ void add_view(obs_sums& a, const bf_grid_k& g, const 
   const double sd = nz.a + nz.c * (e * e);
   double var = sd * sd + pose_var;
   var = var + nz.model;
-  const double w = 1.0 / var;
+  // a positive normal variance (every realistic sensor model) takes the
+  // reciprocal sequence; anything else the plain division
+  const double w = (var >= 1e-300 && var <= 1e300) ? bf_recip(var) : 1.0 / var;
   a.L = a.L + w;
   a.B = a.B + w * y;
   a.cnt = a.cnt + 1.0;
