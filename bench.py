@@ -97,7 +97,7 @@ TSDF_OPS_PER_CELL_VIEW = 217
 
 
 def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests=None, warm=False,
-                     estimate=False, tile_tests=None):
+                     estimate=False, tile_tests=None, assembly_views=None):
     """(amount, unit, bound) of one launch of a timed kernel.  warm: the probe
     solve starts from the log-variance start +-w (w per row) rather than 0.
     estimate: the verify pass also formed the variance estimate s (8 B per row
@@ -140,8 +140,8 @@ def algorithmic_work(name, N, K, T, G, P, fp64=True, voxel_views=None, box_tests
         return (tile_tests - super_tests) * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
     if name == "cell_screen" and box_tests is not None and tile_tests is not None:
         return (box_tests - tile_tests) * TSDF_OPS_PER_CELL_VIEW, "flop", "alu"
-    if name == "assemble":
-        return N * T * 45, "flop", "alu"
+    if name == "assemble":  # the (voxel, view) pairs it goes through (its view masks skip the rest)
+        return (N * T if assembly_views is None else assembly_views) * 45, "flop", "alu"
     return None
 
 
@@ -245,6 +245,13 @@ def run_gpu(args):
         f"probe iters={info['probe_iters']} best={info['best']}")
     ms_step = 1e3 * t_total / args.steps
     value = sum(works) / t_total
+    # the (voxel, view) pairs the assembly goes through, from one more build
+    # and assembly after the timed region (the count needs a host read-back)
+    b_x = ctx.bf_build_band(grid, wl.cam, depth, poses)
+    s_x = ctx.bf_assemble(b_x, wl.cam, depth, poses, noise, wl.lam, wl.eps)
+    info["assembly_views"] = s_x.assembly_views()
+    s_x.free()
+    b_x.free()
 
     # kernel table and the dominant kernel's roofline
     kernels = {}
@@ -260,7 +267,7 @@ def run_gpu(args):
     for name, kt in kernels.items():
         w = algorithmic_work(name, info["N"], K, wl.T, wl.G, P, fp64=(args.precision == "fp64"),
                              voxel_views=info["tsdf_voxel_views"], box_tests=info["tsdf_box_tests"],
-                             tile_tests=info["tsdf_tile_tests"],
+                             tile_tests=info["tsdf_tile_tests"], assembly_views=info["assembly_views"],
                              warm=args.learned, estimate=estimate)
         if w is None:
             continue

@@ -270,6 +270,14 @@ bf_status bf_assemble_trilinear(bf_ctx* ctx, const bf_band* band, const bf_camer
 bf_status bf_system_view(const bf_system* sys, bf_system_arrays* out);
 bf_status bf_system_free(bf_ctx* ctx, bf_system* sys);
 
+/* The (band voxel, view) pairs bf_assemble went through for sys (eqs. 3-5):
+ * N T without the band's view masks, fewer with them (views the screen
+ * proved to observe nothing of a voxel's cell are skipped), counted from the
+ * band's masks, so the band must still exist.  For rates, not results.  *out
+ * is a host int64.  Synchronises with the context's stream.  Errors:
+ * INVALID_ARG (NULL argument, or a system not made by bf_assemble), HIP. */
+bf_status bf_system_assembly_views(bf_ctx* ctx, const bf_system* sys, int64_t* out);
+
 /* q_dev = Q p_dev for device vectors of N doubles (eq. 10). */
 bf_status bf_apply_Q(bf_ctx* ctx, const bf_system* sys, const double* p_dev, double* q_dev);
 

@@ -180,6 +180,12 @@ class System:
             out["nb26"] = _view(a.nb26, (26, n), torch.int32, dev).t()
         return out
 
+    def assembly_views(self) -> int:
+        """(band voxel, view) pairs the assembly went through (synchronises)."""
+        out = C.c_int64(0)
+        self.ctx._check(self.ctx.lib.bf_system_assembly_views(self.ctx.handle, self.handle, C.byref(out)))
+        return int(out.value)
+
     def free(self):
         if self.handle:
             self.ctx.lib.bf_system_free(self.ctx.handle, self.handle)

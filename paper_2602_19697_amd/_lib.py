@@ -132,6 +132,7 @@ SIGNATURES = {
                                         C.POINTER(bf_prior), C.c_int32, PP, C.POINTER(C.c_int64)]),
     "bf_assemble_more": (C.c_int, [P, P, C.POINTER(bf_camera), C.c_int32, P, P, C.POINTER(bf_noise), PP]),
     "bf_system_view": (C.c_int, [P, C.POINTER(bf_system_arrays)]),
+    "bf_system_assembly_views": (C.c_int, [P, P, C.POINTER(C.c_int64)]),
     "bf_extract_surface": (C.c_int, [P, P, P, C.c_double, PP, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "bf_mesh_view": (C.c_int, [P, C.POINTER(bf_mesh_arrays)]),
     "bf_mesh_free": (C.c_int, [P, P]),

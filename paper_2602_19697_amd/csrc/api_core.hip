@@ -1,6 +1,8 @@
 // Context, error plumbing, allocation and object views of the C ABI.
 #include "bf_internal.h"
 
+#include <vector>
+
 #include <cstdlib>
 #include <cstring>
 

@@ -10,6 +10,8 @@
 #include "bf_internal.h"
 #include "bf_features.h"
 
+#include <vector>
+
 namespace {
 
 struct noise_k {
@@ -130,6 +132,20 @@ __global__ __launch_bounds__(256) void k_assemble(bf_grid_k g, bf_cam_k c, int32
                diag32, dinv32, acc);
 }
 
+// Set bits of the band's per-voxel view masks, per workgroup (for the
+// assembly's voxel-view count; integer sums, any order is exact).
+__global__ __launch_bounds__(256) void k_popc_sum(const uint32_t* __restrict__ w, int64_t n,
+                                                  unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long lds[4];
+  unsigned long long c = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    c += (unsigned long long)__popc(w[i]);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = lds[0] + lds[1] + lds[2] + lds[3];
+}
+
 // More views appended to an assembled system: the sums of the first views
 // come back from Lambda, b and the statistics (the running minimum of sigma
 // is "none yet" for a voxel no view observed), and the new views continue
@@ -235,6 +251,7 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
   sys->eps = prior->eps;
   sys->lambda_b = prior->lambda_b;
   sys->T = T;
+  sys->masked = 0;
   const int64_t N = band->n;
   auto fail = [&](bf_status st) {
     bf_system_free(ctx, sys);
@@ -260,9 +277,41 @@ extern "C" bf_status bf_assemble(bf_ctx* ctx, const bf_band* band, const bf_came
                        prior->eps, prior->lambda_b, sys->Lambda, sys->b, sys->rhs, sys->diag, sys->dinv,
                        sys->diag32, sys->dinv32, sys->acc, masks ? band->vmask : nullptr,
                        masks ? band->vmask_words : 0);
+    sys->masked = masks ? 1 : 0;
     if (bf_status s = bf_launch_check(ctx, "k_assemble")) return fail(s);
   }
   *out = sys;
+  return BF_OK;
+}
+
+extern "C" bf_status bf_system_assembly_views(bf_ctx* ctx, const bf_system* sys, int64_t* out) {
+  if (!ctx) return BF_ERR_INVALID_ARG;
+  BF_CHECK(ctx, sys && out, "bf_system_assembly_views: NULL argument");
+  *out = 0;
+  BF_CHECK(ctx, sys->masked >= 0, "bf_system_assembly_views: the system was not made by bf_assemble");
+  const int64_t N = sys->n;
+  if (N == 0 || sys->T == 0) return BF_OK;
+  if (!sys->masked) {
+    *out = N * (int64_t)sys->T;
+    return BF_OK;
+  }
+  // every view past the masked ones, plus the masks' set bits
+  const bf_band* band = sys->band;
+  const int vw = band->vmask_words;
+  const int64_t words = N * vw;
+  const int nb = (int)std::min<int64_t>(bf_cdiv(words, 256), 1024);
+  void* ws = nullptr;
+  BF_TRY(bf_ws(ctx, bf_ctx::WS_POST, (size_t)nb * 8, &ws));
+  BF_HIP(ctx, hipSetDevice(ctx->device));
+  hipLaunchKernelGGL(k_popc_sum, dim3(nb), dim3(256), 0, ctx->stream, band->vmask, words,
+                     (unsigned long long*)ws);
+  BF_TRY(bf_launch_check(ctx, "k_popc_sum"));
+  std::vector<unsigned long long> h((size_t)nb);
+  BF_HIP(ctx, hipMemcpyAsync(h.data(), ws, h.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+  BF_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  int64_t t = 0;
+  for (const unsigned long long c : h) t += (int64_t)c;
+  *out = t + N * (int64_t)(sys->T - std::min<int32_t>(sys->T, 32 * vw));
   return BF_OK;
 }
 

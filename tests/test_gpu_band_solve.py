@@ -105,6 +105,14 @@ def test_assembly_view_masks_exact(ctx, name):
         assert torch.equal(a[k], b[k]), k
     assert np.array_equal(a["Lambda"].cpu().numpy(), ref["Lambda"])
     assert np.array_equal(a["acc"].cpu().numpy(), ref["acc"])
+    # the views gone through: every one without the masks; with them fewer,
+    # but at least every view that gave a voxel an observation
+    n, T = band.n, wl.T
+    masked, plain = sys_.assembly_views(), other.assembly_views()
+    observed = int(round(float(a["acc"][:, 0].sum().item())))
+    print(f"[{name}] assembly: {masked} of {plain} voxel-views gone through, {observed} observed", flush=True)
+    assert plain == n * T
+    assert observed <= masked < plain
     other.free()
     sys_.free()
     band.free()
