@@ -582,12 +582,12 @@ __global__ __launch_bounds__(256) void k_bstart_res(BState* __restrict__ st, con
       // unchanged (a sum of nonzero terms that starts at +0.0 is never -0.0)
 #pragma unroll
       for (int a = 0; a < 6; ++a) {
-        const bool ok = rt.nb[a][j] >= 0;
+        const double m = rt.nb[a][j] >= 0 ? 1.0 : 0.0;  // (as in bverify_rows)
         const uint32_t zw1 = zn[1 + a][wd][j];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
           const double t = xbase_at(1, nullptr, 0u, sign_bit(zw1, sh + q), wn[1 + a], (uint32_t)j);
-          acc[q] += ok ? t : 0.0;
+          acc[q] = fma(t, m, acc[q]);
         }
       }
       V rv[2], zzv[2];
@@ -853,12 +853,16 @@ __device__ __forceinline__ void bverify_rows(int cc, const int (&xbl)[2], const 
     }
     const double dg = rt.d[j];
     const float di = rt.di[j];
+    // an absent neighbour's term times 0.0: x is finite, so it adds +-0.0,
+    // which leaves the sum unchanged (one fma per column instead of a select)
+    double m[6];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) m[a] = rt.nb[a][j] >= 0 ? 1.0 : 0.0;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       double acc = 0.0;
 #pragma unroll
-      for (int a = 0; a < 6; ++a)
-        if (rt.nb[a][j] >= 0) acc += xn[a][q];
+      for (int a = 0; a < 6; ++a) acc = fma(xn[a][q], m[a], acc);
       const double res = zv[q] - (dg * xs[q] - lam * acc);
       v[q][0] += res * res;
       v[q][2] += zv[q] * zv[q];
