@@ -698,7 +698,7 @@ __device__ __forceinline__ void bres_rows(int c, int xbl, const RowTile<V, KC, R
         double acc = 0.0;
 #pragma unroll
         for (int a = 0; a < 6; ++a)
-          if (nb[h][a] >= 0) acc += xn[h][a];
+          acc = fma(xn[h][a], nb[h][a] >= 0 ? 1.0 : 0.0, acc);  // an absent neighbour adds +-0.0
         res[h] = zv[h] - (dg[h] * xs[h] - lam * acc);
       }
     }

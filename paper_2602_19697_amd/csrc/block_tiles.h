@@ -190,7 +190,7 @@ __device__ __forceinline__ void tile_A(int c, V beta, bool first, const int32_t*
       for (int t = 0; t < 6; ++t) {
         const int64_t u = nb[j][t] >= 0 ? (int64_t)nb[j][t] : vr[j];
         const V a = zz[u * KC + c] + beta * (first ? (V)0 : p_old[u * KC + c]);
-        if (nb[j][t] >= 0) s[j] += a;
+        s[j] = fma(a, nb[j][t] >= 0 ? (V)1 : (V)0, s[j]);  // an absent neighbour adds +-0 (a is finite)
       }
       const int64_t e = vr[j] * KC + c;
       pv[j] = zz[e] + beta * (first ? (V)0 : p_old[e]);

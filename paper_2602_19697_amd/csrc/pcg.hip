@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_pcg_A(PcgState* __restrict__ st, const 
     for (int t = 0; t < 6; ++t) {  // unconditional loads: an absent neighbour reads the row itself
       const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
       const V a = z[u] + beta * p_old[u];
-      if (nb[t] >= 0) s += a;
+      s = fma(a, nb[t] >= 0 ? (V)1 : (V)0, s);  // an absent neighbour adds +-0 (a is finite)
     }
     const V pv = z[v] + beta * p_old[v];
     const V qv = diag[v] * pv - lam * s;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_residual(PcgState* __restrict__ st, int
       for (int t = 0; t < 6; ++t) {
         const int64_t u = nb[t] >= 0 ? (int64_t)nb[t] : v;
         const double xu = x[u];
-        if (nb[t] >= 0) s += xu;
+        s = fma(xu, nb[t] >= 0 ? 1.0 : 0.0, s);  // an absent neighbour adds +-0
       }
       res = hv - (diag[v] * x[v] - lam * s);
     }
