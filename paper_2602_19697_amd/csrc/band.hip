@@ -486,14 +486,16 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
           }
 #pragma unroll
           for (int q = 0; q < kViewBatch; ++q) Dq[q] = px[q] >= 0 ? depth[tq[q] * plane + px[q]] : 0.0f;
+          // a view that adds nothing adds +0.0: S starts at +0.0 and a sum of
+          // doubles never gives -0.0 from a +0.0 operand, so S is unchanged;
+          // d is finite, so fmin(d, tau) is d < tau ? d : tau
 #pragma unroll
           for (int q = 0; q < kViewBatch; ++q) {
             const double D = (double)Dq[q];
-            if (px[q] < 0 || !(D > 0.0)) continue;
             const double d = D - Zq[q];
-            if (d < -g.tau) continue;
-            S = S + (d < g.tau ? d : g.tau);
-            W = W + 1;
+            const bool keep = px[q] >= 0 && D > 0.0 && !(d < -g.tau);
+            S = S + (keep ? fmin(d, g.tau) : 0.0);
+            W = W + (keep ? 1 : 0);
           }
         }
       }
