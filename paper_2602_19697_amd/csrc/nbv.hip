@@ -186,9 +186,14 @@ __device__ __forceinline__ bool ray_advance(Ray& r, const ray_k& R, int nlive, c
                        ((uint32_t)r.idx[0] >> 2);
     const uint32_t m = (r.idx[0] & 1) | ((r.idx[1] & 1) << 1) | ((r.idx[2] & 1) << 2) | ((r.idx[0] & 2) << 2) |
                        ((r.idx[1] & 2) << 3) | ((r.idx[2] & 2) << 4);
-    const bf_cell cl = cells[c];
-    if ((cl.mask >> m) & 1ull) {
-      const int32_t v = cl.start + __popcll(cl.mask & ((1ull << m) - 1ull));
+    // the cell's mask and start in one 16-byte load: read apart, the start's
+    // load would wait for the mask test, one more trip to memory per voxel
+    const uint4 cw = *reinterpret_cast<const uint4*>(cells + c);
+    int32_t start = (int32_t)cw.z;
+    asm volatile("" : "+v"(start));
+    const unsigned long long cmask = ((unsigned long long)cw.y << 32) | cw.x;
+    if ((cmask >> m) & 1ull) {
+      const int32_t v = start + __popcll(cmask & ((1ull << m) - 1ull));
       if constexpr (UTIL == BF_UTILITY_SUM_VAR) {
         const int64_t qv = qs[v];
         r.score += qv >> 1;
