@@ -50,59 +50,132 @@ struct Pyr {
   int64_t per_view;
 };
 
-// Levels 0..kTileLevels of one 32x32 pixel tile of one view, built in LDS.
-// A level-l cell holds the extremes over its 2^l x 2^l base pixels inside the
-// image, so the tile-local reduction equals the level-by-level one.
+// Levels 0..kTileLevels of one 32x32 pixel tile of one view.  A level-l cell
+// holds the extremes over its 2^l x 2^l base pixels inside the image, so the
+// tile-local reduction equals the level-by-level one (min and max are exact in
+// any order).  Thread t holds 4 adjacent pixels of row t / 8 (one 16-byte load
+// when W is a multiple of 4), so a wave holds 8 full rows: levels 1-3 combine
+// within the wave by lane exchanges (rows y ^ 1, y ^ 2, y ^ 4 are lanes ^ 8,
+// ^ 16, ^ 32; quads x ^ 4 are lanes ^ 1), and only levels 4-5 go through LDS.
 constexpr int kPyrTile = 32;
 constexpr int kTileLevels = 5;  // 32 >> 5 = 1
+__device__ __forceinline__ void pyr_pair(float& a, float& b, int lanemask) {
+  a = fminf(a, __shfl_xor(a, lanemask, 64));
+  b = fmaxf(b, __shfl_xor(b, lanemask, 64));
+}
 // The kernel reads every pixel once, so it also flags invalid depth (NaN,
 // inf or negative) as k_validate_depth does.
 __global__ __launch_bounds__(256) void k_pyr_tiles(const float* __restrict__ depth, int32_t W, int32_t H, Pyr P,
                                                    float* __restrict__ dmin, float* __restrict__ dmax,
                                                    int* __restrict__ flag) {
-  __shared__ float lo[2][kPyrTile * kPyrTile], hi[2][kPyrTile * kPyrTile];
+  __shared__ float l3lo[16], l3hi[16];
   const int t = blockIdx.z;
   const int32_t x0 = blockIdx.x * kPyrTile, y0 = blockIdx.y * kPyrTile;
   const float* D = depth + (int64_t)t * W * H;
   float* mn = dmin + (int64_t)t * P.per_view;
   float* mx = dmax + (int64_t)t * P.per_view;
-  int bad = 0;
-  for (int e = threadIdx.x; e < kPyrTile * kPyrTile; e += blockDim.x) {
-    const int32_t x = x0 + (e % kPyrTile), y = y0 + (e / kPyrTile);
-    float a = INFINITY, b = -1.0f;
-    if (x < W && y < H) {
-      const float d = D[(int64_t)y * W + x];
-      if (!(d >= 0.0f) || d == INFINITY) bad = 1;
-      if (d > 0.0f) a = b = d;
+  const int ly = threadIdx.x >> 3, lx = (threadIdx.x & 7) * 4;  // tile row, first column
+  const int32_t gy = y0 + ly, gx = x0 + lx;
+  float d[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  bool in[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) in[k] = gy < H && gx + k < W;
+  if ((W & 3) == 0) {
+    if (in[0]) {
+      const float4 v = *reinterpret_cast<const float4*>(D + (int64_t)gy * W + gx);
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
     }
-    lo[0][e] = a;
-    hi[0][e] = b;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (in[k]) d[k] = D[(int64_t)gy * W + gx + k];
+  }
+  int bad = 0;
+  float a[4], b[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (in[k] && (!(d[k] >= 0.0f) || d[k] == INFINITY)) bad = 1;
+    const bool ok = in[k] && d[k] > 0.0f;
+    a[k] = ok ? d[k] : INFINITY;
+    b[k] = ok ? d[k] : -1.0f;
   }
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
-  int cur = 0;
-  for (int l = 1; l <= kTileLevels && l < P.nl; ++l) {
-    __syncthreads();
-    const int side = kPyrTile >> l;
-    for (int e = threadIdx.x; e < side * side; e += blockDim.x) {
-      const int x = e % side, y = e / side;
-      float a = INFINITY, b = -1.0f;
+  // level 1: pixel pairs of the thread, rows y and y ^ 1
+  float a1[2], b1[2];
 #pragma unroll
-      for (int dy = 0; dy < 2; ++dy)
+  for (int h = 0; h < 2; ++h) {
+    a1[h] = fminf(a[2 * h], a[2 * h + 1]);
+    b1[h] = fmaxf(b[2 * h], b[2 * h + 1]);
+    pyr_pair(a1[h], b1[h], 8);
+  }
+  if (P.nl > 1 && (ly & 1) == 0) {
+    const int32_t cy = gy >> 1;
 #pragma unroll
-        for (int dx = 0; dx < 2; ++dx) {
-          const int q = (2 * y + dy) * kPyrTile + 2 * x + dx;
-          a = fminf(a, lo[cur][q]);
-          b = fmaxf(b, hi[cur][q]);
-        }
-      lo[cur ^ 1][y * kPyrTile + x] = a;
-      hi[cur ^ 1][y * kPyrTile + x] = b;
-      const int32_t gx = (x0 >> l) + x, gy = (y0 >> l) + y;
-      if (gx < P.w[l] && gy < P.h[l]) {
-        mn[P.off[l] + (int64_t)gy * P.w[l] + gx] = a;
-        mx[P.off[l] + (int64_t)gy * P.w[l] + gx] = b;
+    for (int h = 0; h < 2; ++h) {
+      const int32_t cx = (gx >> 1) + h;
+      if (cx < P.w[1] && cy < P.h[1]) {
+        mn[P.off[1] + (int64_t)cy * P.w[1] + cx] = a1[h];
+        mx[P.off[1] + (int64_t)cy * P.w[1] + cx] = b1[h];
       }
     }
-    cur ^= 1;
+  }
+  // level 2: the thread's 4 columns, rows y .. y ^ 3
+  float a2 = fminf(a1[0], a1[1]), b2 = fmaxf(b1[0], b1[1]);
+  pyr_pair(a2, b2, 16);
+  if (P.nl > 2 && (ly & 3) == 0) {
+    const int32_t cx = gx >> 2, cy = gy >> 2;
+    if (cx < P.w[2] && cy < P.h[2]) {
+      mn[P.off[2] + (int64_t)cy * P.w[2] + cx] = a2;
+      mx[P.off[2] + (int64_t)cy * P.w[2] + cx] = b2;
+    }
+  }
+  // level 3: quads x, x ^ 4 (lanes ^ 1) and rows y .. y ^ 7 (lanes ^ 32)
+  pyr_pair(a2, b2, 1);
+  pyr_pair(a2, b2, 32);
+  if ((threadIdx.x & 63) < 8 && (threadIdx.x & 1) == 0) {
+    if (P.nl > 3) {
+      const int32_t cx = gx >> 3, cy = gy >> 3;
+      if (cx < P.w[3] && cy < P.h[3]) {
+        mn[P.off[3] + (int64_t)cy * P.w[3] + cx] = a2;
+        mx[P.off[3] + (int64_t)cy * P.w[3] + cx] = b2;
+      }
+    }
+    // level-3 grid of the tile: 4 x 4, row = wave, column = quad / 2
+    l3lo[(threadIdx.x >> 6) * 4 + ((threadIdx.x & 7) >> 1)] = a2;
+    l3hi[(threadIdx.x >> 6) * 4 + ((threadIdx.x & 7) >> 1)] = b2;
+  }
+  __syncthreads();
+  if (threadIdx.x < 4 && P.nl > 4) {
+    // level 4: the 2 x 2 cells of 16 x 16 pixels, each over 2 x 2 level-3 cells
+    const int i = threadIdx.x & 1, j = threadIdx.x >> 1;
+    float a4 = INFINITY, b4 = -1.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = (2 * j + (q >> 1)) * 4 + 2 * i + (q & 1);
+      a4 = fminf(a4, l3lo[e]);
+      b4 = fmaxf(b4, l3hi[e]);
+    }
+    const int32_t cx = (x0 >> 4) + i, cy = (y0 >> 4) + j;
+    if (cx < P.w[4] && cy < P.h[4]) {
+      mn[P.off[4] + (int64_t)cy * P.w[4] + cx] = a4;
+      mx[P.off[4] + (int64_t)cy * P.w[4] + cx] = b4;
+    }
+    if (threadIdx.x == 0 && P.nl > 5) {
+      // level 5: the whole tile
+      float a5 = INFINITY, b5 = -1.0f;
+      for (int e = 0; e < 16; ++e) {
+        a5 = fminf(a5, l3lo[e]);
+        b5 = fmaxf(b5, l3hi[e]);
+      }
+      const int32_t cx5 = x0 >> 5, cy5 = y0 >> 5;
+      if (cx5 < P.w[5] && cy5 < P.h[5]) {
+        mn[P.off[5] + (int64_t)cy5 * P.w[5] + cx5] = a5;
+        mx[P.off[5] + (int64_t)cy5 * P.w[5] + cx5] = b5;
+      }
+    }
   }
 }
 

@@ -74,6 +74,31 @@ def test_band_screening_exact(ctx, name, seed):
     band2.free()
 
 
+@pytest.mark.parametrize("W,H", [(47, 35), (130, 97), (100, 75)])
+def test_band_odd_depth_sizes(ctx, W, H):
+    """Depth images whose width is not a multiple of 4 (the pyramid's per-pixel
+    loads) or is one (its 16-byte row loads), with sides that are not multiples
+    of its 32-pixel tiles (partial tiles on the right and bottom edges; at 130 x 97
+    levels above the tile are built too): the screened band, TSDF, weights and
+    neighbours equal the oracle's bit for bit."""
+    import oracle as O
+    from synth.configs import union_workload
+    wl = union_workload(f"union64_{W}x{H}", 64, 0.016, 12, 2, 2, width=W, height=H, f=525.0 * W / 640.0)
+    g, cm = O.grid_of(wl), O.cam(wl.cam)
+    td, wd = O.tsdf_dense(g, cm, wl.depth, wl.poses)
+    keys, bt, bw = O.band(g, td, wd)
+    nbr, deg = O.neighbours(wl.G, keys)
+    band, sys_, _, _ = gc.gpu_system(ctx, wl)
+    a = band.arrays()
+    print(f"[{W}x{H}] band {a['keys'].shape[0]} voxels, {a['tsdf_voxel_views']} voxel-views fused", flush=True)
+    assert len(keys) > 0
+    for key, want in (("keys", keys), ("tsdf", bt), ("w", bw), ("nbr", nbr), ("deg", deg)):
+        assert np.array_equal(a[key].cpu().numpy(), want), key
+    assert 0 < a["tsdf_voxel_views"] < wl.G ** 3 * wl.T
+    sys_.free()
+    band.free()
+
+
 @pytest.mark.parametrize("name", ["tiny", "sphere64"])
 def test_assembly_bitexact(ctx, name):
     wl = gc.workload(name)
