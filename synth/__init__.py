@@ -6,15 +6,6 @@ model of the paper's observation model (Sec. 3.5, eq. 5), and next-best-view
 candidate poses.  Everything it returns is plain numpy (or torch on a chosen
 device for the depth renderer) and is handed unchanged to both sides.
 """
-from .cameras import look_at, ring_poses, hemisphere_poses, sphere_candidates, Camera
-from .scenes import Sphere, RoundedBox, Torus, Scene, single_sphere, random_union, surface_points
-from .render import render_depth, add_depth_noise, sigma_depth
-from .configs import Workload, make_workload, WORKLOADS
-
-__all__ = [
-    "surface_points",
-    "look_at", "ring_poses", "hemisphere_poses", "sphere_candidates", "Camera",
-    "Sphere", "RoundedBox", "Torus", "Scene", "single_sphere", "random_union",
-    "render_depth", "add_depth_noise", "sigma_depth",
-    "Workload", "make_workload", "WORKLOADS",
-]
+from .cameras import look_at, Camera
+from .scenes import surface_points
+from .configs import Workload, make_workload
