@@ -377,11 +377,13 @@ __device__ __forceinline__ double zsign(const uint32_t* __restrict__ zb, int64_t
 }
 
 // A double from lane l ^ m of the lane's group (the permutation CTRL of a DPP
-// move, applied to both halves).
+// move, applied to both halves).  Every permutation used here stays within a
+// 16-lane row and a row's lanes are active together, so no lane keeps its old
+// value: the move takes none (no register to clear first).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 
