@@ -555,7 +555,17 @@ __global__ __launch_bounds__(256) void k_tsdf_count(bf_grid_k g, bf_cam_k c, int
 #pragma unroll
           for (int q = 0; q < kViewBatch; ++q) {
             Zq[q] = 0.0;
-            px[q] = tq[q] >= 0 ? bf_project(g, c, poses + 12 * tq[q], i, j, k, Zq[q]) : -1;
+            px[q] = -1;
+            if (tq[q] >= 0) {
+              // the whole pose in one round of scalar loads (the projection
+              // would otherwise load the rest only after its depth test)
+              double P[12];
+#pragma unroll
+              for (int e = 0; e < 12; ++e) P[e] = poses[12 * tq[q] + e];
+              asm volatile("" ::"s"(P[0]), "s"(P[1]), "s"(P[2]), "s"(P[3]), "s"(P[4]), "s"(P[5]), "s"(P[6]),
+                           "s"(P[7]), "s"(P[8]), "s"(P[9]), "s"(P[10]), "s"(P[11]));
+              px[q] = bf_project(g, c, P, i, j, k, Zq[q]);
+            }
           }
 #pragma unroll
           for (int q = 0; q < kViewBatch; ++q) Dq[q] = px[q] >= 0 ? depth[tq[q] * plane + px[q]] : 0.0f;
