@@ -716,38 +716,52 @@ __global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double ban
                                                       int32_t* __restrict__ w,
                                                       const uint32_t* __restrict__ cmask, int vw,
                                                       uint32_t* __restrict__ vmask) {
-  __shared__ uint32_t wave_cnt[kThreads / 64];
+  constexpr int NW = kThreads / 64;
+  __shared__ uint32_t wave_cnt[kItems][NW];
   if (counts[blockIdx.x] == 0) return;  // the whole block: no band voxel in the tile
   const uint64_t base = (uint64_t)blockIdx.x * kTile;
   const uint32_t lm = cellmask[blockIdx.x];  // cells whose dense values were stored
-  uint64_t out = offsets[blockIdx.x];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  // every item's loads first, then one barrier for all the wave counts
+  double t[kItems];
+  int32_t W[kItems];
+  bool sel[kItems];
+  uint32_t rank[kItems];
+#pragma unroll
   for (int it = 0; it < kItems; ++it) {
     const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
-    double t = 0.0;
-    int32_t W = 0;
-    if (m < total && ((lm >> (it * (kThreads / 64) + wid)) & 1u)) {
-      t = dense_t[m];
-      W = dense_w[m];
+    t[it] = 0.0;
+    W[it] = 0;
+    if (m < total && ((lm >> (it * NW + wid)) & 1u)) {
+      t[it] = dense_t[m];
+      W[it] = dense_w[m];
     }
-    const bool sel = m < total && W > 0 && fabs(t) <= band;
-    const uint64_t mask = __ballot(sel);
-    const uint32_t rank = __popcll(mask & ((1ull << lane) - 1ull));
-    __syncthreads();
-    if (lane == 0) wave_cnt[wid] = (uint32_t)__popcll(mask);
-    __syncthreads();
+  }
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const uint64_t m = base + (uint64_t)it * kThreads + threadIdx.x;
+    sel[it] = m < total && W[it] > 0 && fabs(t[it]) <= band;
+    const uint64_t mask = __ballot(sel[it]);
+    rank[it] = __popcll(mask & ((1ull << lane) - 1ull));
+    if (lane == 0) wave_cnt[it][wid] = (uint32_t)__popcll(mask);
+  }
+  __syncthreads();
+  uint64_t out = offsets[blockIdx.x];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
     uint32_t before = 0, row = 0;
-    for (int v = 0; v < kThreads / 64; ++v) {
-      if (v < wid) before += wave_cnt[v];
-      row += wave_cnt[v];
+#pragma unroll
+    for (int v = 0; v < NW; ++v) {
+      if (v < wid) before += wave_cnt[it][v];
+      row += wave_cnt[it][v];
     }
-    if (sel) {
-      const uint64_t o = out + before + rank;
-      keys[o] = m;
-      tsdf[o] = t;
-      w[o] = W;
+    if (sel[it]) {
+      const uint64_t o = out + before + rank[it];
+      keys[o] = base + (uint64_t)it * kThreads + threadIdx.x;
+      tsdf[o] = t[it];
+      w[o] = W[it];
       if (vmask) {  // the screen's view mask of the voxel's cell (one wave = one cell)
-        const uint32_t* cm = cmask + (int64_t)blockIdx.x * (kCells * kMaskWords) + (it * (kThreads / 64) + wid) * kMaskWords;
+        const uint32_t* cm = cmask + (int64_t)blockIdx.x * (kCells * kMaskWords) + (it * NW + wid) * kMaskWords;
         for (int q = 0; q < vw; ++q) vmask[o * vw + q] = cm[q];
       }
     }
