@@ -762,7 +762,11 @@ __global__ __launch_bounds__(256) void k_band_scatter(uint64_t total, double ban
       w[o] = W[it];
       if (vmask) {  // the screen's view mask of the voxel's cell (one wave = one cell)
         const uint32_t* cm = cmask + (int64_t)blockIdx.x * (kCells * kMaskWords) + (it * NW + wid) * kMaskWords;
-        for (int q = 0; q < vw; ++q) vmask[o * vw + q] = cm[q];
+        if ((vw & 3) == 0)  // 16-byte pieces (both arrays 16-byte aligned, rows a multiple of 16 bytes)
+          for (int q = 0; q < vw; q += 4)
+            *reinterpret_cast<uint4*>(vmask + o * vw + q) = *reinterpret_cast<const uint4*>(cm + q);
+        else
+          for (int q = 0; q < vw; ++q) vmask[o * vw + q] = cm[q];
       }
     }
     out += row;
@@ -785,15 +789,20 @@ __global__ __launch_bounds__(256) void k_neighbours(const uint64_t* __restrict__
   const uint64_t key = keys[v];
   const int32_t c[3] = {(int32_t)bf_compact3(key), (int32_t)bf_compact3(key >> 1),
                         (int32_t)bf_compact3(key >> 2)};
-  int32_t d = 0;
+  int32_t d = 0, idx[6];
 #pragma unroll
   for (int s = 0; s < 6; ++s) {
     int32_t q[3] = {c[0], c[1], c[2]};
     q[s >> 1] += (s & 1) ? 1 : -1;
-    const int32_t idx = bf_band_index(cells, ncell, G, q[0], q[1], q[2]);
-    nbr[v * 6 + s] = idx;
-    d += idx >= 0;
+    idx[s] = bf_band_index(cells, ncell, G, q[0], q[1], q[2]);
+    d += idx[s] >= 0;
   }
+  // the row's 24 bytes as three 8-byte stores (8-byte aligned: the band's
+  // arrays start on 256-byte boundaries)
+  int2* o = reinterpret_cast<int2*>(nbr + v * 6);
+  o[0] = make_int2(idx[0], idx[1]);
+  o[1] = make_int2(idx[2], idx[3]);
+  o[2] = make_int2(idx[4], idx[5]);
   deg[v] = d;
 }
 
