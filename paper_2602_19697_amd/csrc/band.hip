@@ -881,7 +881,25 @@ __global__ __launch_bounds__(256) void k_brick_oct(const uint32_t* __restrict__ 
   const int pos = (e >> (axis * lnb)) & (nb - 1);
   const int32_t stride = 1 << (axis * lnb);
   const int32_t base = e - pos * stride;
-  const uint8_t* src = axis == 0 ? nullptr : in + (vin << (3 * lnb));
+  if (axis == 0) {
+    // in = 0 on occupied bricks, 255 elsewhere: the result is the distance to
+    // the nearest occupied brick from pos on along the line (255: none), read
+    // off the line's occupancy bits.  A line starts at a multiple of nb bits.
+    uint64_t line;
+    if (lnb == 6) line = (uint64_t)bits[base >> 5] | ((uint64_t)bits[(base >> 5) + 1] << 32);
+    else line = (uint64_t)(bits[base >> 5] >> (base & 31)) & ((1ull << nb) - 1ull);  // nb <= 32: one word
+    int best;
+    if (dir > 0) {
+      const uint64_t ahead = line >> pos;
+      best = ahead ? __builtin_ctzll(ahead) : 255;
+    } else {
+      const uint64_t behind = pos == 63 ? line : line & ((2ull << pos) - 1ull);
+      best = behind ? pos - (63 - __builtin_clzll(behind)) : 255;
+    }
+    out[id] = (uint8_t)best;
+    return;
+  }
+  const uint8_t* src = in + (vin << (3 * lnb));
   // Candidates are taken 8 at a time so their loads are in flight together.
   // Taking more than needed changes nothing: max(t, .) >= t >= best once
   // t >= best, and positions outside the grid count as 255.
@@ -894,7 +912,7 @@ __global__ __launch_bounds__(256) void k_brick_oct(const uint32_t* __restrict__ 
       const int t = t0 + u;
       const int q = min(max(pos + dir * t, 0), nb - 1);  // in the grid even where unused
       const int32_t j = base + q * stride;
-      dv[u] = t >= tend ? 255 : (axis == 0 ? (((bits[j >> 5] >> (j & 31)) & 1u) ? 0 : 255) : (int)src[j]);
+      dv[u] = t >= tend ? 255 : (int)src[j];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {

@@ -25,9 +25,15 @@ constexpr double kScale = 4294967296.0;  // 2^32
 __global__ __launch_bounds__(256) void k_max(const double* __restrict__ s, int64_t n,
                                              unsigned long long* __restrict__ out_bits) {
   __shared__ double lds[kThreads / 64];
+  // four loads in flight per thread; the maximum is exact in any order
   double m = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-    m = fmax(m, s[i]);
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const double a = s[i], b = s[i + stride], c = s[i + 2 * stride], d = s[i + 3 * stride];
+    m = fmax(fmax(m, a), fmax(fmax(b, c), d));
+  }
+  for (; i < n; i += stride) m = fmax(m, s[i]);
   for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -509,7 +515,8 @@ extern "C" bf_status bf_nbv_score(bf_ctx* ctx, const bf_band* band, const double
   BF_HIP(ctx, hipSetDevice(ctx->device));
   const int64_t N = band->n;
   // workspace: smax | best | chunk counter | qs [N]
-  const int nbm = (int)std::max<int64_t>(1, std::min<int64_t>(bf_cdiv(N, kThreads), 1024));
+  // few workgroups: each ends in one atomic on the same word, and those serialise
+  const int nbm = (int)std::max<int64_t>(1, std::min<int64_t>(bf_cdiv(N, 8 * kThreads), 256));
   char* ws = nullptr;
   BF_TRY(bf_ws(ctx, bf_ctx::WS_NBV, 256 + N * 8, (void**)&ws));
   double* smax = (double*)ws;
