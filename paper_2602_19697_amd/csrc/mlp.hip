@@ -165,6 +165,7 @@ __device__ __forceinline__ void layer(const bf16x8* __restrict__ sw, int tbase, 
 // features 8-11 (bf_features.h), the operand values those lanes hold.  (Spreading
 // the features over all four lane groups and exchanging them through LDS was
 // no faster: the pass waits on the feature loads, not on lanes.)
+constexpr int kFeatPitch = 13;  // floats per voxel in the fused pass's LDS (odd: no bank conflicts)
 template <bool FUSED>
 __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ wt, const float* __restrict__ prm,
                                                      const float* __restrict__ feat, bf_feat_in src, int64_t n,
@@ -173,6 +174,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
                                                      double* __restrict__ x0, float* __restrict__ logvar) {
   __shared__ bf16x8 sw[NFWD * 64];
   __shared__ float sb[3 * NH], sim[16], sii[16], so[6];
+  __shared__ float sfeat[FUSED ? 4 : 1][FUSED ? 64 * kFeatPitch : 1];  // per wave: 64 voxels' features
   for (int i = threadIdx.x; i < NFWD * 64; i += blockDim.x) sw[i] = wt[i];
   for (int i = threadIdx.x; i < 3 * NH; i += blockDim.x) {
     const int l = i / NH, u = i % NH;
@@ -194,8 +196,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, col = lane & 15;
-  const int64_t ntile = (n + 15) / 16;
-  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4) {
+  // one 16-voxel tile: features (f(voxel, feature index)) -> network -> outputs
+  auto run_tile = [&](int64_t t, auto&& feature) {
     // an offset of zero the compiler cannot see through: the weight reads
     // below stay in the loop instead of being hoisted into registers
     int z0;
@@ -204,16 +206,11 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
     const int64_t v = t * 16 + col;
     const bool valid = v < n;
     bf16x8 B0;
-    float fv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if constexpr (FUSED) {
-      if (valid && g == 0) bf_features_0_7(v, src, fv);
-      if (valid && g == 1) bf_features_8_11(v, src, fv);
-    }
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int f = 8 * g + e;
       float x = 0.0f;
-      if (valid && f < NIN) x = ((FUSED ? fv[e] : feat[v * NIN + f]) - sim[f]) * sii[f];
+      if (valid && f < NIN) x = (feature(v, f) - sim[f]) * sii[f];
       B0[e] = (__bf16)x;
     }
     f32x4 acc[4];
@@ -246,6 +243,34 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
       if (x0) x0[v] = rhs[v] / diag[v] + h * (double)p0;
       if (logvar) logvar[v] = p1;
     }
+  };
+  if constexpr (FUSED) {
+    // every lane computes all the features of one voxel of a group of 64 (the
+    // four tiles a wave then runs), so the FP64 feature work uses the whole
+    // wave instead of a quarter of it; they pass through the wave's LDS slice
+    const int64_t ngrp = (n + 63) / 64;
+    float* fs = sfeat[wave];
+    for (int64_t gi = (int64_t)blockIdx.x * 4 + wave; gi < ngrp; gi += (int64_t)gridDim.x * 4) {
+      float fv[NIN];
+#pragma unroll
+      for (int e = 0; e < NIN; ++e) fv[e] = 0.0f;
+      const int64_t vl = gi * 64 + lane;
+      if (vl < n) {
+        bf_features_0_7(vl, src, fv);
+        bf_features_8_11(vl, src, fv + 8);
+      }
+#pragma unroll
+      for (int e = 0; e < NIN; ++e) fs[lane * kFeatPitch + e] = fv[e];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's LDS writes are done
+#pragma unroll 1
+      for (int sub = 0; sub < 4; ++sub)
+        run_tile(gi * 4 + sub, [&](int64_t v, int f) { return fs[(int)(v - gi * 64) * kFeatPitch + f]; });
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // read before the next group overwrites
+    }
+  } else {
+    const int64_t ntile = (n + 15) / 16;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4)
+      run_tile(t, [&](int64_t v, int f) { return feat[v * NIN + f]; });
   }
 }
 
