@@ -165,7 +165,7 @@ __device__ __forceinline__ void layer(const bf16x8* __restrict__ sw, int tbase, 
 // features 8-11 (bf_features.h), the operand values those lanes hold.  (Spreading
 // the features over all four lane groups and exchanging them through LDS was
 // no faster: the pass waits on the feature loads, not on lanes.)
-constexpr int kFeatPitch = 13;  // floats per voxel in the fused pass's LDS (odd: no bank conflicts)
+constexpr int kFeatPitch = 15;  // floats per voxel in the fused pass's LDS: 12 features, 2 outputs (odd: no bank conflicts)
 template <bool FUSED>
 __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ wt, const float* __restrict__ prm,
                                                      const float* __restrict__ feat, bf_feat_in src, int64_t n,
@@ -196,8 +196,9 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, col = lane & 15;
-  // one 16-voxel tile: features (f(voxel, feature index)) -> network -> outputs
-  auto run_tile = [&](int64_t t, auto&& feature) {
+  // one 16-voxel tile: features (f(voxel, feature index)) -> network ->
+  // outputs (sink(voxel, p0, p1) on the lanes of the first 16)
+  auto run_tile = [&](int64_t t, auto&& feature, auto&& sink) {
     // an offset of zero the compiler cannot see through: the weight reads
     // below stay in the loop instead of being hoisted into registers
     int z0;
@@ -233,16 +234,15 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
     f32x4 o = {0.f, 0.f, 0.f, 0.f};
     o = mfma(swl[(T_L4 + 0) * 64], B[0], o);
     o = mfma(swl[(T_L4 + 1) * 64], B[1], o);
-    if (g == 0 && valid) {
-      const float p0 = (o[0] + so[0]) * so[4] + so[2];
-      const float p1 = (o[1] + so[1]) * so[5] + so[3];
-      if (out) {
-        out[2 * v] = p0;
-        out[2 * v + 1] = p1;
-      }
-      if (x0) x0[v] = rhs[v] / diag[v] + h * (double)p0;
-      if (logvar) logvar[v] = p1;
+    if (g == 0 && valid) sink(v, (o[0] + so[0]) * so[4] + so[2], (o[1] + so[1]) * so[5] + so[3]);
+  };
+  auto write = [&](int64_t v, float p0, float p1) {
+    if (out) {
+      out[2 * v] = p0;
+      out[2 * v + 1] = p1;
     }
+    if (x0) x0[v] = rhs[v] / diag[v] + h * (double)p0;
+    if (logvar) logvar[v] = p1;
   };
   if constexpr (FUSED) {
     // every lane computes all the features of one voxel of a group of 64 (the
@@ -262,15 +262,24 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const bf16x8* __restrict__ 
 #pragma unroll
       for (int e = 0; e < NIN; ++e) fs[lane * kFeatPitch + e] = fv[e];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // the wave's LDS writes are done
+      // the network's two outputs of each voxel go back to its LDS row, and
+      // every lane then writes its own voxel's results
 #pragma unroll 1
       for (int sub = 0; sub < 4; ++sub)
-        run_tile(gi * 4 + sub, [&](int64_t v, int f) { return fs[(int)(v - gi * 64) * kFeatPitch + f]; });
+        run_tile(
+            gi * 4 + sub, [&](int64_t v, int f) { return fs[(int)(v - gi * 64) * kFeatPitch + f]; },
+            [&](int64_t v, float p0, float p1) {
+              fs[(int)(v - gi * 64) * kFeatPitch + NIN] = p0;
+              fs[(int)(v - gi * 64) * kFeatPitch + NIN + 1] = p1;
+            });
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+      if (vl < n) write(vl, fs[lane * kFeatPitch + NIN], fs[lane * kFeatPitch + NIN + 1]);
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");  // read before the next group overwrites
     }
   } else {
     const int64_t ntile = (n + 15) / 16;
     for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4)
-      run_tile(t, [&](int64_t v, int f) { return feat[v * NIN + f]; });
+      run_tile(t, [&](int64_t v, int f) { return feat[v * NIN + f]; }, write);
   }
 }
 
